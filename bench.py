@@ -1,0 +1,226 @@
+"""Benchmark: Hybrid LSLU iterations per second on one MI355X.
+
+A step is one full Hybrid LSLU solve of the workload (every iteration of the
+basis recurrence, the projected problems with weighted-GCV lambda for every k,
+all iterates x_k and the copy of the small results to the host), with the
+operator and b already resident in HBM.  ``value`` is iterations per second
+(maxiter * steps / elapsed).
+
+Default workload ``tomo128``: 128x128 parallel-beam tomography, 180 angles x 181
+bins (m = 32580, n = 16384, CSR with bilinear ray-length weights), 2% noise,
+100 iterations, FP32 (the mixed-precision mode: FP32 operator/bases/vectors,
+FP64 sums, projected problem and pivot divisions).  The FP64 plain mode is
+timed on the same problem and both relative errors are reported.
+
+The JSON line also carries the roofline of the dominant kernel (timed with HIP
+events on the library's stream) and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def _kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("operators.hip", "internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2409_05239_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _load_traffic(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None when
+    absent or taken on a different kernel source."""
+    try:
+        with open(PROFILE_TRAFFIC) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(f"{workload}:{kernel}")
+    if not ent or ent.get("source_hash") != _kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def csr_spmv_bytes(nnz, rows, cols, esz):
+    """Algorithmic bytes of one CSR product: values + column indices, row
+    pointers, the input vector once and the output once."""
+    return nnz * (esz + 4) + 4 * (rows + 1) + esz * cols + esz * rows
+
+
+def run(args):
+    import numpy as np
+    import torch
+
+    from paper_2409_05239_amd import capi
+    from workloads import CONFIGS, lambda_grid
+
+    cfg = CONFIGS[args.workload]
+    prob = cfg["make"]()
+    K = args.iters or cfg["iters"]
+    prec = args.precision or cfg["precision"]
+    grid = lambda_grid()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = capi.lslu_create(0)
+
+    def setup(p):
+        dt = torch.float64 if p == "fp64" else torch.float32
+        op = capi.make_operator(ctx, prob, capi.PRECISIONS[p])
+        b = torch.tensor(prob.b, dtype=dt, device=dev)
+        X = torch.zeros((K, prob.n), dtype=dt, device=dev)
+        x = torch.zeros(prob.n, dtype=dt, device=dev)
+        return op, b, X, x
+
+    def solve(op, b, X, x):
+        return capi.lslu_solve(ctx, op, b, K, reg=cfg["reg"], grid=grid,
+                               grid_relative=cfg["grid_relative"], X=X, x_out=x)
+
+    def timed(p, steps, warmup):
+        op, b, X, x = setup(p)
+        for _ in range(warmup):
+            solve(op, b, X, x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st, _, info = solve(op, b, X, x)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        Xh = X.double().cpu().numpy()
+        xt = prob.x_true
+        errs = np.linalg.norm(Xh[:info["k_done"]] - xt[None, :], axis=1) / np.linalg.norm(xt)
+        return op, el, info, errs
+
+    print(f"[bench] workload={args.workload} m={prob.m} n={prob.n} nnz={prob.nnz} "
+          f"K={K} prec={prec}", flush=True)
+    op, el, info, errs = timed(prec, args.steps, args.warmup)
+    ms = el / args.steps * 1e3
+    print(f"[bench] {prec}: {ms:.3f} ms/step", flush=True)
+    fp64 = None
+    if prec != "fp64" and not args.no_fp64:
+        op64, el64, info64, errs64 = timed("fp64", args.steps, args.warmup)
+        fp64 = dict(iters_per_s=K * args.steps / el64, ms_per_step=el64 / args.steps * 1e3,
+                    rel_err_final=float(errs64[-1]), rel_err_min=float(errs64.min()),
+                    k_min=int(errs64.argmin()) + 1)
+        capi.lslu_op_destroy(op64)
+        print(f"[bench] fp64: {fp64['ms_per_step']:.3f} ms/step", flush=True)
+
+    # Dominant kernel: the operator product, timed with HIP events on the
+    # library's stream (torch's current stream) through lslu_op_apply.
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    xin = torch.rand(prob.m, dtype=dt, device=dev)
+    yout = torch.empty(prob.n, dtype=dt, device=dev)
+    reps = 200
+    for _ in range(10):
+        capi.lslu_op_apply(ctx, op, 1, xin, yout)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        capi.lslu_op_apply(ctx, op, 1, xin, yout)
+    e1.record()
+    torch.cuda.synchronize()
+    t_launch = e0.elapsed_time(e1) / reps * 1e-3
+    esz = 8 if prec == "fp64" else 4
+    if prob.kind == "csr":
+        kname = "k_csr_rows"
+        nbytes = csr_spmv_bytes(prob.nnz, prob.n, prob.m, esz if prec != "bf16op" else 2)
+    else:
+        kname = "operator"
+        nbytes = esz * (prob.m + prob.n)
+    achieved = nbytes / t_launch / 1e9
+    roof = dict(bound="hbm", kernel=f"{kname} (A^T product)", achieved=round(achieved, 1),
+                peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=_load_traffic(kname, args.workload),
+                us_per_launch=round(t_launch * 1e6, 3), bytes_per_launch=int(nbytes))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(prob, cfg, grid, args.cpu_iters or K)
+    capi.lslu_op_destroy(op)
+    capi.lslu_destroy(ctx)
+
+    out = {
+        "metric": "Hybrid LSLU iters/s + % HBM roofline, mixed vs FP64 plain at equal rel. error",
+        "value": round(K * args.steps / el, 2),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16op": "bf16-op/f32"}[prec],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "m": prob.m, "n": prob.n,
+                   "nnz": prob.nnz, "iters": K, "precision": prec,
+                   "reg": cfg["reg"], "grid_relative": cfg["grid_relative"]},
+        "rel_err_final": float(errs[-1]),
+        "rel_err_min": float(errs.min()),
+        "k_min": int(errs.argmin()) + 1,
+        "k_stop": int(info["k_stop"]),
+        "status": int(info["status"]),
+        "fp64_plain": fp64,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(prob, cfg, grid, iters):
+    """The FP64 oracle (as is) on the first ``iters`` iterations of the same
+    workload, single-threaded BLAS; iterations per second."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import RegParam, make_operator
+    from oracle.hessenberg import hybrid_lslu
+
+    op = make_operator(prob)
+    reg = RegParam(cfg["reg"], grid=grid, grid_relative=cfg["grid_relative"])
+    times = []
+    with threadpool_limits(limits=1):
+        for _ in range(3):
+            t0 = time.perf_counter()
+            hybrid_lslu(op, prob.b, iters, reg)
+            times.append(time.perf_counter() - t0)
+    el = sorted(times)[1]
+    return {"value": round(iters / el, 3), "unit": "iters/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{iters} of {cfg['iters']} iterations of the same workload, "
+                      f"median of 3 runs of {el:.2f} s (FP64 NumPy/SciPy, one thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="tomo128")
+    ap.add_argument("--precision", default=None)
+    ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--cpu-iters", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the "
+              "multi-GPU path is not part of this build", file=sys.stderr)
+        sys.exit(2)
+    run(args)
+
+
+if __name__ == "__main__":
+    main()

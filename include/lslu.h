@@ -1,0 +1,216 @@
+/*
+ * lslu.h -- C ABI of the MI355X (gfx950) LSLU / Hybrid LSLU library.
+ *
+ * The library solves the rectangular linear inverse problem b = A x_true + e
+ * (Section 1, eq. ip) either as the least-squares problem min ||b - A x||
+ * regularised by the iteration count (eq. ir; LSLU, Section 2.2) or as the
+ * Tikhonov problem min ||b - A x||^2 + lambda^2 ||x||^2 (eq. vr; Hybrid LSLU,
+ * Section 3, Algorithm 5).  The operator A is dense, CSR or a PSF stencil; it
+ * is only used through the products A l and A^T d (Section 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns an lslu_status.  Negative values are failures;
+ *   the outputs are then unspecified.  Positive values report a breakdown of
+ *   the Hessenberg process; outputs are valid up to k_done (Algorithm 4 and 5:
+ *   q = 0 or u = 0).  Nothing throws across this boundary.
+ * - lslu_last_error(ctx) returns a human-readable message for the last failure
+ *   on that context (never NULL).
+ * - Handles (lslu_ctx, lslu_op) are owned by the library; the caller owns every
+ *   array it passes.  Host arrays given to lslu_op_* are copied; device arrays
+ *   given to lslu_solve/lslu_op_apply are only borrowed for the duration of the
+ *   call.  No caller pointer is kept after a call returns.
+ * - "Working precision" (wp) is the vector type of an operator: double for
+ *   LSLU_FP64, float for LSLU_FP32 and LSLU_BF16OP.  Device vectors passed to
+ *   the library are contiguous arrays of that type.
+ * - All work of one context is enqueued on that context's HIP stream (the one
+ *   given to lslu_create, or one it made).  Calls on one context must not
+ *   overlap; use one context per thread.
+ * - Matrices of the projected problem are FP64 and column-major.
+ */
+#ifndef LSLU_H
+#define LSLU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LSLU_ABI_VERSION 1
+
+typedef enum lslu_status {
+  LSLU_OK = 0,
+  LSLU_BREAKDOWN_Q = 1,  /* q = A^T d_k has no eligible nonzero entry, or k > n */
+  LSLU_BREAKDOWN_U = 2,  /* u = A l_k has no eligible nonzero entry, or k >= m */
+  LSLU_ZERO_RHS = 3,     /* r_0 = b - A x_0 is zero; x = x_0 */
+  LSLU_EINVAL = -1,      /* invalid argument (sizes, pointers, options) */
+  LSLU_ENOMEM = -2,      /* device allocation failed */
+  LSLU_EDEVICE = -3,     /* HIP runtime error or no usable GPU */
+  LSLU_ENONFINITE = -4,  /* an input holds NaN or Inf */
+  LSLU_EUNSUPPORTED = -5 /* combination not implemented */
+} lslu_status;
+
+typedef enum lslu_precision {
+  LSLU_FP64 = 0,  /* operator, bases and vectors in double */
+  LSLU_FP32 = 1,  /* operator, bases and vectors in float; sums in double */
+  LSLU_BF16OP = 2 /* operator values and its input in bfloat16, products summed
+                     in float; bases and vectors in float */
+} lslu_precision;
+
+typedef enum lslu_reg {
+  LSLU_REG_NONE = 0,    /* LSLU: lambda = 0 (Section 2.2) */
+  LSLU_REG_FIXED = 1,   /* lambda_k = opts.lambda */
+  LSLU_REG_WGCV = 2,    /* weighted GCV on the grid (Section 3.2.1) */
+  LSLU_REG_GCV = 3,     /* GCV on the grid (eq. gcv2) */
+  LSLU_REG_OPTIMAL = 4  /* argmin ||x_k(lambda) - x_true|| on the grid (eq. lambda) */
+} lslu_reg;
+
+typedef struct lslu_ctx lslu_ctx;
+typedef struct lslu_op lslu_op;
+
+/* ------------------------------------------------------------------------ */
+/* Context                                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * enqueue on (e.g. torch.cuda.current_stream().cuda_stream), or NULL to let
+ * the library create one.  The library never destroys a stream it was given.
+ * Errors: LSLU_EDEVICE if the device does not exist or is not gfx950,
+ * LSLU_EINVAL if out is NULL. */
+lslu_status lslu_create(int device, void* hip_stream, lslu_ctx** out);
+
+/* Free the context, its device workspace and (if it made it) its stream.
+ * Operators created on it must be destroyed first.  NULL is accepted. */
+lslu_status lslu_destroy(lslu_ctx* ctx);
+
+/* Message for the last failure on ctx (or a generic text for ctx == NULL). */
+const char* lslu_last_error(const lslu_ctx* ctx);
+
+/* Name of a status code, e.g. "LSLU_BREAKDOWN_U". */
+const char* lslu_status_name(int status);
+
+/* LSLU_ABI_VERSION of the built library. */
+int lslu_abi_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Operators (the forward model A of eq. ip)                                */
+/* ------------------------------------------------------------------------ */
+
+/* Dense operator.  `A` is a host array of m*n doubles, row-major (A[i*n+j]).
+ * The library stores A and A^T on the device in the operator's precision.
+ * Errors: LSLU_EINVAL (m, n < 1, NULL pointers), LSLU_ENONFINITE,
+ * LSLU_ENOMEM. */
+lslu_status lslu_op_dense(lslu_ctx* ctx, int64_t m, int64_t n, const double* A,
+                          int32_t precision, lslu_op** out);
+
+/* CSR operator: host arrays indptr[m+1] (int64, indptr[0] = 0, non-decreasing,
+ * indptr[m] = nnz), indices[nnz] (int32, strictly increasing within each row,
+ * in [0, n)) and data[nnz] (double).  nnz must be < 2^31.  The library builds
+ * the CSR of A^T on the host and keeps both on the device, so both products
+ * are row-parallel with a fixed summation order (deterministic).
+ * Errors: LSLU_EINVAL (shape, ordering or range violations), LSLU_ENONFINITE,
+ * LSLU_ENOMEM. */
+lslu_status lslu_op_csr(lslu_ctx* ctx, int64_t m, int64_t n, int64_t nnz,
+                        const int64_t* indptr, const int32_t* indices,
+                        const double* data, int32_t precision, lslu_op** out);
+
+/* PSF operator on a rows x cols image stored row-major (m = n = rows*cols).
+ * `psf` is a host array of ph*pw doubles (row-major, ph and pw odd) centred at
+ * (ph/2, pw/2).  A is the zero-boundary, same-size convolution
+ *   (A x)[i,j] = sum_{a,b} psf[a,b] x[i-a+ph/2, j-b+pw/2]
+ * and A^T the matching correlation
+ *   (A^T y)[i,j] = sum_{a,b} psf[a,b] y[i+a-ph/2, j+b-pw/2],
+ * entries outside the image read as zero.  ph, pw <= 63.
+ * Errors: LSLU_EINVAL, LSLU_ENONFINITE, LSLU_ENOMEM. */
+lslu_status lslu_op_psf(lslu_ctx* ctx, int64_t rows, int64_t cols, int32_t ph,
+                        int32_t pw, const double* psf, int32_t precision,
+                        lslu_op** out);
+
+/* y = A x (transpose = 0; x has n entries, y has m) or y = A^T x
+ * (transpose = 1; x has m entries, y has n), on the context's stream, with
+ * device vectors in the operator's working precision.  Asynchronous. */
+lslu_status lslu_op_apply(lslu_ctx* ctx, const lslu_op* op, int32_t transpose,
+                          const void* x_dev, void* y_dev);
+
+/* Shape and precision of an operator (any output pointer may be NULL). */
+lslu_status lslu_op_info(const lslu_op* op, int64_t* m, int64_t* n,
+                         int32_t* precision);
+
+/* Free an operator (NULL accepted). */
+lslu_status lslu_op_destroy(lslu_op* op);
+
+/* ------------------------------------------------------------------------ */
+/* Solve (Algorithm 5: REQUIRE A, b, x0, maxiter, RegParam)                 */
+/* ------------------------------------------------------------------------ */
+
+typedef struct lslu_opts {
+  int32_t maxiter;            /* K >= 1; at most min(m, n) + 1 */
+  int32_t reg;                /* lslu_reg */
+  double lambda;              /* LSLU_REG_FIXED: lambda >= 0 */
+  const double* lambda_grid;  /* host, n_grid > 0 values, strictly ascending
+                                 and positive (WGCV, GCV, OPTIMAL) */
+  int32_t n_grid;             /* <= 256 */
+  int32_t grid_relative;      /* nonzero: grid values are multiplied by the
+                                 largest singular value of H_{k+1,k} */
+  double omega;               /* WGCV weight; <= 0 selects (k+1)/m */
+  const void* x_true_dev;     /* OPTIMAL: device, wp, n entries */
+  double stop_tol;            /* tolerance of the stopping rule (eq. tol);
+                                 <= 0 selects 1e-6 */
+  int32_t early_stop;         /* nonzero: x_out is x_{k_stop} */
+  void* X_dev;                /* optional device output, wp, n x maxiter
+                                 column-major: column k-1 is x_k */
+  /* Replay hooks (tests): host arrays of pivot rows to use instead of the
+   * library's own choice.  piv_t needs maxiter+1 entries (t(1) is the pivot of
+   * r_0), piv_g and lambda_idx maxiter entries.  NULL = own choice. */
+  const int32_t* replay_piv_t;
+  const int32_t* replay_piv_g;
+  const int32_t* replay_lambda_idx;
+} lslu_opts;
+
+typedef struct lslu_result {
+  int32_t status;     /* as returned */
+  int32_t k_done;     /* iterates x_1..x_{k_done} were formed */
+  int32_t k_stop;     /* first k with |Ghat(k+1)-Ghat(k)|/Ghat(1) < tol, else k_done */
+  int32_t n_l, n_d;   /* basis vectors l_j and d_j formed */
+  double beta;        /* signed r_0(t(1)) */
+  int32_t piv_t_mismatch, piv_g_mismatch; /* replay: own choice differed */
+  /* Host arrays filled on return when non-NULL (caller-allocated): */
+  int32_t* piv_t;     /* maxiter+1: t(1), t(2), ... (0-based row indices) */
+  int32_t* piv_g;     /* maxiter:   g(1), g(2), ... (0-based column indices) */
+  int32_t* own_piv_t; /* maxiter+1: the library's own choices (replay) */
+  int32_t* own_piv_g; /* maxiter */
+  double* H;          /* (maxiter+1) x maxiter, upper Hessenberg (eq. nhr) */
+  double* W;          /* maxiter x maxiter, upper triangular (eq. nhr2) */
+  double* Y;          /* maxiter x maxiter: column k-1 holds y_k in rows 0..k-1 */
+  double* lambda_k;   /* maxiter */
+  int32_t* lambda_idx;/* maxiter: grid index of lambda_k, -1 without a grid */
+  double* ghat;       /* maxiter: Ghat(k) (eq. stop2) */
+  double* sep_lambda; /* maxiter: (G_2 - G_1)/G_1 over the grid */
+  double* sigma_max;  /* maxiter: largest singular value of H_{k+1,k} */
+  double* sigma_min;  /* maxiter: smallest singular value of H_{k+1,k} */
+} lslu_result;
+
+/* Run Hybrid LSLU (LSLU with LSLU_REG_NONE) for opts->maxiter iterations.
+ * b_dev: device, wp, m entries.  x0_dev: device, wp, n entries, or NULL for
+ * x_0 = 0.  x_out_dev: device, wp, n entries: the final iterate x_{k_done}
+ * (x_{k_stop} with early_stop; x_0 after a breakdown before x_1).  The call
+ * returns after the device work finished and `res` is filled.
+ * Errors: LSLU_EINVAL (options), LSLU_ENOMEM, LSLU_EDEVICE.  Breakdowns are
+ * reported as LSLU_BREAKDOWN_Q/U/LSLU_ZERO_RHS with valid outputs. */
+lslu_status lslu_solve(lslu_ctx* ctx, const lslu_op* op, const void* b_dev,
+                       const void* x0_dev, const lslu_opts* opts,
+                       void* x_out_dev, lslu_result* res);
+
+/* Copy basis vectors of the last solve on ctx into a device buffer (wp,
+ * column-major, leading dimension = vector length): which = 0 copies the
+ * n x count matrix L, which = 1 the m x count matrix D.  count must not
+ * exceed what the last solve formed.  Asynchronous on the context's stream. */
+lslu_status lslu_get_basis(lslu_ctx* ctx, int32_t which, int32_t count,
+                           void* dst_dev);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSLU_H */

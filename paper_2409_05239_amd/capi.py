@@ -1,0 +1,307 @@
+"""ctypes binding of ``include/lslu.h``.
+
+Marshalling only: every function below converts Python arguments (ints,
+floats, NumPy host arrays, torch device tensors) into the C ABI's plain
+pointers and sizes, calls the entry point of the same name in ``liblslu.so``
+and turns a negative status into :class:`LsluError`.  All computation happens
+in the library's HIP kernels.  Importing this module fails loudly when the
+library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_int32, c_int64, c_void_p
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblslu.so")
+
+LSLU_OK = 0
+LSLU_BREAKDOWN_Q = 1
+LSLU_BREAKDOWN_U = 2
+LSLU_ZERO_RHS = 3
+LSLU_EINVAL = -1
+LSLU_ENOMEM = -2
+LSLU_EDEVICE = -3
+LSLU_ENONFINITE = -4
+LSLU_EUNSUPPORTED = -5
+
+LSLU_FP64, LSLU_FP32, LSLU_BF16OP = 0, 1, 2
+PRECISIONS = {"fp64": LSLU_FP64, "fp32": LSLU_FP32, "bf16op": LSLU_BF16OP}
+
+LSLU_REG_NONE, LSLU_REG_FIXED, LSLU_REG_WGCV, LSLU_REG_GCV, LSLU_REG_OPTIMAL = range(5)
+REGS = {"none": LSLU_REG_NONE, "fixed": LSLU_REG_FIXED, "wgcv": LSLU_REG_WGCV,
+        "gcv": LSLU_REG_GCV, "optimal": LSLU_REG_OPTIMAL}
+
+#: Every entry point declared in include/lslu.h.
+EXPORTS = (
+    "lslu_create", "lslu_destroy", "lslu_last_error", "lslu_status_name",
+    "lslu_abi_version", "lslu_op_dense", "lslu_op_csr", "lslu_op_psf",
+    "lslu_op_apply", "lslu_op_info", "lslu_op_destroy", "lslu_solve",
+    "lslu_get_basis",
+)
+
+
+class lslu_opts(ctypes.Structure):
+    _fields_ = [
+        ("maxiter", c_int32),
+        ("reg", c_int32),
+        ("lambda_", c_double),
+        ("lambda_grid", POINTER(c_double)),
+        ("n_grid", c_int32),
+        ("grid_relative", c_int32),
+        ("omega", c_double),
+        ("x_true_dev", c_void_p),
+        ("stop_tol", c_double),
+        ("early_stop", c_int32),
+        ("X_dev", c_void_p),
+        ("replay_piv_t", POINTER(c_int32)),
+        ("replay_piv_g", POINTER(c_int32)),
+        ("replay_lambda_idx", POINTER(c_int32)),
+    ]
+
+
+class lslu_result(ctypes.Structure):
+    _fields_ = [
+        ("status", c_int32),
+        ("k_done", c_int32),
+        ("k_stop", c_int32),
+        ("n_l", c_int32),
+        ("n_d", c_int32),
+        ("beta", c_double),
+        ("piv_t_mismatch", c_int32),
+        ("piv_g_mismatch", c_int32),
+        ("piv_t", POINTER(c_int32)),
+        ("piv_g", POINTER(c_int32)),
+        ("own_piv_t", POINTER(c_int32)),
+        ("own_piv_g", POINTER(c_int32)),
+        ("H", POINTER(c_double)),
+        ("W", POINTER(c_double)),
+        ("Y", POINTER(c_double)),
+        ("lambda_k", POINTER(c_double)),
+        ("lambda_idx", POINTER(c_int32)),
+        ("ghat", POINTER(c_double)),
+        ("sep_lambda", POINTER(c_double)),
+        ("sigma_max", POINTER(c_double)),
+        ("sigma_min", POINTER(c_double)),
+    ]
+
+
+class LsluError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{status_name(status)}: {message}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with "
+            "'python -m paper_2409_05239_amd.build' (there is no fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, pp = c_void_p, POINTER(c_void_p)
+    sig = {
+        "lslu_create": (c_int, [c_int, vp, pp]),
+        "lslu_destroy": (c_int, [vp]),
+        "lslu_last_error": (ctypes.c_char_p, [vp]),
+        "lslu_status_name": (ctypes.c_char_p, [c_int]),
+        "lslu_abi_version": (c_int, []),
+        "lslu_op_dense": (c_int, [vp, c_int64, c_int64, POINTER(c_double), c_int32, pp]),
+        "lslu_op_csr": (c_int, [vp, c_int64, c_int64, c_int64, POINTER(c_int64),
+                                POINTER(c_int32), POINTER(c_double), c_int32, pp]),
+        "lslu_op_psf": (c_int, [vp, c_int64, c_int64, c_int32, c_int32,
+                                POINTER(c_double), c_int32, pp]),
+        "lslu_op_apply": (c_int, [vp, vp, c_int32, vp, vp]),
+        "lslu_op_info": (c_int, [vp, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32)]),
+        "lslu_op_destroy": (c_int, [vp]),
+        "lslu_solve": (c_int, [vp, vp, vp, vp, POINTER(lslu_opts), vp,
+                               POINTER(lslu_result)]),
+        "lslu_get_basis": (c_int, [vp, c_int32, c_int32, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def status_name(status: int) -> str:
+    return lib.lslu_status_name(int(status)).decode()
+
+
+def _check(ctx, status):
+    if status < 0:
+        msg = lib.lslu_last_error(ctx).decode() if ctx else ""
+        raise LsluError(status, msg)
+    return status
+
+
+def _dptr(t):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+def _np(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(POINTER(np.ctypeslib.as_ctypes_type(dtype)))
+
+
+def _torch_dtype(precision):
+    import torch
+    return torch.float64 if precision == LSLU_FP64 else torch.float32
+
+
+# ------------------------------------------------------------------ context
+
+def lslu_abi_version() -> int:
+    return lib.lslu_abi_version()
+
+
+def lslu_create(device: int = 0, stream=None):
+    """``stream``: a ``torch.cuda.Stream`` (or raw handle); default torch's
+    current stream on ``device``."""
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream(device)
+    handle = getattr(stream, "cuda_stream", stream)
+    out = c_void_p()
+    st = lib.lslu_create(int(device), c_void_p(handle), ctypes.byref(out))
+    if st < 0:
+        raise LsluError(st, "lslu_create failed (no gfx950 device?)")
+    return out
+
+
+def lslu_destroy(ctx):
+    return lib.lslu_destroy(ctx)
+
+
+def lslu_last_error(ctx) -> str:
+    return lib.lslu_last_error(ctx).decode()
+
+
+# ---------------------------------------------------------------- operators
+
+def lslu_op_dense(ctx, A, precision=LSLU_FP64):
+    A, pA = _np(A, np.float64)
+    m, n = A.shape
+    out = c_void_p()
+    _check(ctx, lib.lslu_op_dense(ctx, m, n, pA, int(precision), ctypes.byref(out)))
+    return out
+
+
+def lslu_op_csr(ctx, m, n, indptr, indices, data, precision=LSLU_FP64):
+    ip, pip = _np(indptr, np.int64)
+    ix, pix = _np(indices, np.int32)
+    dv, pdv = _np(data, np.float64)
+    out = c_void_p()
+    _check(ctx, lib.lslu_op_csr(ctx, int(m), int(n), int(ip[-1]), pip, pix, pdv,
+                                int(precision), ctypes.byref(out)))
+    return out
+
+
+def lslu_op_psf(ctx, rows, cols, psf, precision=LSLU_FP64):
+    P, pP = _np(psf, np.float64)
+    ph, pw = P.shape
+    out = c_void_p()
+    _check(ctx, lib.lslu_op_psf(ctx, int(rows), int(cols), int(ph), int(pw), pP,
+                                int(precision), ctypes.byref(out)))
+    return out
+
+
+def lslu_op_apply(ctx, op, transpose, x, y):
+    """``x``/``y``: torch device tensors in the operator's working precision."""
+    _check(ctx, lib.lslu_op_apply(ctx, op, int(transpose), _dptr(x), _dptr(y)))
+
+
+def lslu_op_info(op):
+    m, n, p = c_int64(), c_int64(), c_int32()
+    _check(None, lib.lslu_op_info(op, ctypes.byref(m), ctypes.byref(n), ctypes.byref(p)))
+    return m.value, n.value, p.value
+
+
+def lslu_op_destroy(op):
+    return lib.lslu_op_destroy(op)
+
+
+def make_operator(ctx, problem, precision=LSLU_FP64):
+    """Operator for a ``workloads.Problem``."""
+    if problem.kind == "dense":
+        return lslu_op_dense(ctx, problem.A, precision)
+    if problem.kind == "csr":
+        return lslu_op_csr(ctx, problem.m, problem.n, problem.indptr,
+                           problem.indices, problem.data, precision)
+    if problem.kind == "psf":
+        rows, cols = problem.image_shape
+        return lslu_op_psf(ctx, rows, cols, problem.psf, precision)
+    raise ValueError(problem.kind)
+
+
+# -------------------------------------------------------------------- solve
+
+def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
+               grid_relative=False, omega=0.0, x0=None, x_true=None,
+               stop_tol=0.0, early_stop=False, X=None, x_out=None,
+               replay_piv_t=None, replay_piv_g=None, replay_lambda_idx=None):
+    """Run the solver.  ``b``, ``x0``, ``X``, ``x_out`` are torch device
+    tensors in the working precision (``x_out`` is allocated when None).
+    Returns ``(status, x_out, info)`` where ``info`` holds the host-side
+    results as NumPy arrays."""
+    import torch
+    m, n, prec = lslu_op_info(op)
+    K = int(maxiter)
+    if x_out is None:
+        x_out = torch.empty(n, dtype=_torch_dtype(prec), device=b.device)
+    o = lslu_opts()
+    o.maxiter = K
+    o.reg = REGS[reg] if isinstance(reg, str) else int(reg)
+    o.lambda_ = float(lam)
+    keep = []
+    if grid is not None:
+        g, pg = _np(grid, np.float64)
+        keep.append(g)
+        o.lambda_grid = pg
+        o.n_grid = g.shape[0]
+    o.grid_relative = 1 if grid_relative else 0
+    o.omega = float(omega)
+    o.x_true_dev = _dptr(x_true)
+    o.stop_tol = float(stop_tol)
+    o.early_stop = 1 if early_stop else 0
+    o.X_dev = _dptr(X)
+    for name, arr in (("replay_piv_t", replay_piv_t), ("replay_piv_g", replay_piv_g),
+                      ("replay_lambda_idx", replay_lambda_idx)):
+        if arr is not None:
+            a, pa = _np(arr, np.int32)
+            keep.append(a)
+            setattr(o, name, pa)
+    r = lslu_result()
+    host = dict(
+        piv_t=np.full(K + 1, -1, np.int32), piv_g=np.full(K, -1, np.int32),
+        own_piv_t=np.full(K + 1, -1, np.int32), own_piv_g=np.full(K, -1, np.int32),
+        H=np.zeros((K, K + 1)), W=np.zeros((K, K)), Y=np.zeros((K, K)),
+        lambda_k=np.zeros(K), lambda_idx=np.zeros(K, np.int32), ghat=np.zeros(K),
+        sep_lambda=np.zeros(K), sigma_max=np.zeros(K), sigma_min=np.zeros(K))
+    for name, arr in host.items():
+        ct = c_int32 if arr.dtype == np.int32 else c_double
+        setattr(r, name, arr.ctypes.data_as(POINTER(ct)))
+    st = _check(ctx, lib.lslu_solve(ctx, op, _dptr(b), _dptr(x0), ctypes.byref(o),
+                                    _dptr(x_out), ctypes.byref(r)))
+    info = dict(status=st, k_done=r.k_done, k_stop=r.k_stop, n_l=r.n_l, n_d=r.n_d,
+                beta=r.beta, piv_t_mismatch=r.piv_t_mismatch,
+                piv_g_mismatch=r.piv_g_mismatch)
+    # column-major (K+1) x K etc. were filled into row-major (K, K+1) buffers
+    info.update(piv_t=host["piv_t"], piv_g=host["piv_g"],
+                own_piv_t=host["own_piv_t"], own_piv_g=host["own_piv_g"],
+                H=host["H"].T.copy(), W=host["W"].T.copy(), Y=host["Y"].T.copy(),
+                lambda_k=host["lambda_k"], lambda_idx=host["lambda_idx"],
+                ghat=host["ghat"], sep_lambda=host["sep_lambda"],
+                sigma_max=host["sigma_max"], sigma_min=host["sigma_min"])
+    return st, x_out, info
+
+
+def lslu_get_basis(ctx, which, count, dst):
+    _check(ctx, lib.lslu_get_basis(ctx, int(which), int(count), _dptr(dst)))

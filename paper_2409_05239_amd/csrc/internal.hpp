@@ -1,0 +1,147 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+namespace lslu {
+
+constexpr int kWave = 64;
+constexpr int kMaxIter = 256;   // largest maxiter accepted
+constexpr int kMaxGrid = 256;   // largest lambda grid accepted
+constexpr int kArgmaxBlock = 256;
+constexpr int kMaxArgmaxBlocks = 2048;
+
+enum Prec : int { kFP64 = 0, kFP32 = 1, kBF16 = 2 };
+enum Reg : int { kNone = 0, kFixed = 1, kWGCV = 2, kGCV = 3, kOptimal = 4 };
+enum Status : int {
+  kOK = 0, kBreakQ = 1, kBreakU = 2, kZeroRHS = 3,
+  kEInval = -1, kENoMem = -2, kEDevice = -3, kENonFinite = -4, kEUnsupported = -5
+};
+
+// Device-resident state of one solve.  `stopped` is read by every kernel of the
+// iteration so that work enqueued after a breakdown does nothing.
+struct DevState {
+  int stopped;      // nonzero once the process has stopped
+  int status;       // Status of the process
+  int n_l;          // basis vectors l_j formed
+  int n_d;          // basis vectors d_j formed
+  int k_done;       // iterates x_k that exist (x_1..x_{k_done})
+  int mismatch_t;   // replay: own pivot choice differed (d side)
+  int mismatch_g;   // replay: own pivot choice differed (l side)
+  int pad;
+  double beta;      // r_0(t(1))
+  unsigned int ticket[4];  // arrival counters of the last-block reductions
+};
+
+// One candidate of the pivot search: |v| (key, -1 when ineligible) and row.
+struct ArgPart {
+  double key;
+  int idx;
+  int pad;
+};
+
+// What the last block of a pivot search does with the winner.
+struct PivotJob {
+  int side;              // 0: l side (W(k,k)), 1: d side (H(k+1,k)), 2: r_0 (beta)
+  int k;                 // iteration (1-based); 0 for r_0
+  int eligible;          // host-side guard of the search (k <= n, k < m)
+  int piv_pos;           // position in the pivot list to fill
+  double* piv_val;       // where the pivot value goes (W, H or beta)
+  int* piv_list;         // pivot list (device)
+  int* own_list;         // own choices (device)
+  unsigned char* mask;   // "is a pivot" flag per row
+  const int* replay;     // replay pivot list (device) or nullptr
+  DevState* st;
+};
+
+// ---------------------------------------------------------------- bf16 ----
+__host__ __device__ inline uint16_t f32_to_bf16(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return 0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return static_cast<uint16_t>(u >> 16);
+}
+__host__ __device__ inline float bf16_to_f32(uint16_t h) {
+  return __builtin_bit_cast(float, static_cast<uint32_t>(h) << 16);
+}
+
+// ------------------------------------------------------------- launchers ---
+// Basis recurrence (basis.hip).
+template <typename T>
+void launch_fill(T* p, T v, int64_t count, hipStream_t s);
+void launch_state_reset(DevState* st, hipStream_t s);
+template <typename T>
+void launch_sub(const T* a, const T* b, T* out, int64_t len, hipStream_t s);
+template <typename T>
+void launch_eliminate_argmax(const T* v0, T* out, const T* basis, int64_t ld,
+                             int nb, const double* coef,
+                             const unsigned char* mask, int64_t len,
+                             ArgPart* parts, const PivotJob& job, hipStream_t s);
+template <typename T>
+void launch_normalize(const T* v, T* dst, int64_t len, const PivotJob& job,
+                      double* Trow, int ldT, const T* basis, int64_t ld, int nb,
+                      hipStream_t s);
+template <typename T>
+void launch_gather_trisolve(const T* v0, const int* piv, int nb,
+                            const double* Tm, int ldT, double* coef,
+                            const DevState* st, hipStream_t s);
+
+// Operators (operators.hip).  `stop` may be nullptr.
+struct DeviceOp {
+  int kind;         // 0 dense, 1 csr, 2 psf
+  int prec;
+  int64_t m, n;
+  // dense: A (m x n) and AT (n x m), row-major, value type of prec
+  void* A = nullptr;
+  void* AT = nullptr;
+  // csr
+  int* rp = nullptr;  int* ci = nullptr;  void* val = nullptr;
+  int* rpT = nullptr; int* ciT = nullptr; void* valT = nullptr;
+  int64_t nnz = 0;
+  // psf
+  int64_t rows = 0, cols = 0;
+  int ph = 0, pw = 0;
+  double* psf = nullptr;       // correlation weights for A^T (as given)
+  double* psf_flip = nullptr;  // correlation weights for A (rotated 180)
+  float* psf32 = nullptr;
+  float* psf32_flip = nullptr;
+};
+void op_apply(const DeviceOp& op, int transpose, const void* x, void* y,
+              const int* stop, hipStream_t s);
+
+// Projected problem (projected.hip).
+struct ProjParams {
+  int K;           // leading dimension data: H is (K+1) x K, Y is K x K
+  int m, n;
+  int reg;
+  double lambda;
+  int n_grid;
+  int grid_relative;
+  double omega;    // <= 0: (k+1)/m
+  const double* grid;         // device
+  const int* replay_lambda;   // device or nullptr
+  const double* gram;         // OPTIMAL: K x K Gram matrix of L
+  const double* gvec;         // OPTIMAL: L^T (x_true - x0)
+  const double* e0;           // OPTIMAL: ||x_true - x0||^2
+};
+void launch_projected(const double* H, const DevState* st, double beta_unused,
+                      const ProjParams& p, double* Y, double* lam,
+                      int* lam_idx, double* ghat, double* sep, double* smax,
+                      double* smin, double* scratch, size_t lds_bytes,
+                      hipStream_t s);
+size_t projected_scratch_doubles(int K);
+
+// Iterate assembly (assemble.hip).
+template <typename T>
+void launch_assemble(const T* L, int64_t ld, int64_t n, const double* Y, int K,
+                     const T* x0, T* X, const DevState* st, hipStream_t s);
+template <typename T>
+void launch_select_x(const T* X, int64_t n, const T* x0, T* x_out,
+                     const DevState* st, const int* k_sel, hipStream_t s);
+void launch_stopping(const double* ghat, const DevState* st, double tol,
+                     int early, int* out, hipStream_t s);
+
+}  // namespace lslu

@@ -1,0 +1,745 @@
+// C ABI (include/lslu.h) and the host-side driver of one solve.
+//
+// A solve enqueues, on the context's stream and without host synchronisation:
+//   init      r_0 = b - A x_0, pivot search over r_0, beta, d_1
+//   for k = 1..K (Algorithm 5):
+//     q0 = A^T d_k                              (operator kernel)
+//     W(1:k-1,k) from q0(g(1:k-1))              (gather + triangular solve)
+//     q = q0 - L w, zero at pivots, argmax      (streaming pass, last block
+//                                                picks g(k) and W(k,k))
+//     l_k = q / W(k,k), new row of T_L          (normalise)
+//     u0 = A l_k, H(1:k,k), u, t(k+1), H(k+1,k), d_{k+1}   (same on the d side)
+//   projected problems for all k                (one workgroup per k)
+//   stopping rule, iterates X = x_0 + L Y, selected iterate -> x_out
+// then copies the small results to pinned host memory once and waits.
+// Breakdowns are detected on the device; later kernels then do nothing.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "lslu.h"
+
+using namespace lslu;
+
+namespace {
+
+struct Layout {
+  void *L = nullptr, *D = nullptr, *q = nullptr, *u = nullptr, *r0 = nullptr,
+       *X = nullptr;
+  double *TL = nullptr, *TD = nullptr, *grid = nullptr, *proj = nullptr;
+  int *rep_t = nullptr, *rep_g = nullptr, *rep_lam = nullptr;
+  unsigned char *mask_t = nullptr, *mask_g = nullptr;
+  ArgPart* parts = nullptr;
+  // result block (copied to the host in one transfer)
+  unsigned char* res = nullptr;
+  size_t res_bytes = 0;
+  double *H = nullptr, *W = nullptr, *Y = nullptr, *lam = nullptr,
+         *ghat = nullptr, *sep = nullptr, *smax = nullptr, *smin = nullptr;
+  int *piv_t = nullptr, *piv_g = nullptr, *own_t = nullptr, *own_g = nullptr,
+      *lam_idx = nullptr, *sel = nullptr;
+  DevState* st = nullptr;
+};
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Two passes: with base == nullptr only the size is computed.
+size_t carve(unsigned char* base, int64_t m, int64_t n, int K, size_t esz,
+             int64_t ldL, int64_t ldD, Layout* lay) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> unsigned char* {
+    off = align_up(off, 256);
+    unsigned char* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  };
+  Layout l;
+  l.L = take(esz * ldL * K);
+  l.D = take(esz * ldD * (K + 1));
+  l.q = take(esz * ldL);
+  l.u = take(esz * ldD);
+  l.r0 = take(esz * ldD);
+  l.X = take(esz * n * K);
+  l.TL = reinterpret_cast<double*>(take(sizeof(double) * K * K));
+  l.TD = reinterpret_cast<double*>(take(sizeof(double) * (K + 1) * (K + 1)));
+  l.grid = reinterpret_cast<double*>(take(sizeof(double) * kMaxGrid));
+  l.proj = reinterpret_cast<double*>(take(sizeof(double) * projected_scratch_doubles(K)));
+  l.rep_t = reinterpret_cast<int*>(take(sizeof(int) * (K + 1)));
+  l.rep_g = reinterpret_cast<int*>(take(sizeof(int) * K));
+  l.rep_lam = reinterpret_cast<int*>(take(sizeof(int) * K));
+  l.mask_t = take(m);
+  l.mask_g = take(n);
+  l.parts = reinterpret_cast<ArgPart*>(take(sizeof(ArgPart) * kMaxArgmaxBlocks));
+  // result block: doubles, then ints, then the state
+  off = align_up(off, 256);
+  const size_t res_start = off;
+  l.H = reinterpret_cast<double*>(take(sizeof(double) * (K + 1) * K));
+  l.W = reinterpret_cast<double*>(take(sizeof(double) * K * K));
+  l.Y = reinterpret_cast<double*>(take(sizeof(double) * K * K));
+  l.lam = reinterpret_cast<double*>(take(sizeof(double) * K));
+  l.ghat = reinterpret_cast<double*>(take(sizeof(double) * K));
+  l.sep = reinterpret_cast<double*>(take(sizeof(double) * K));
+  l.smax = reinterpret_cast<double*>(take(sizeof(double) * K));
+  l.smin = reinterpret_cast<double*>(take(sizeof(double) * K));
+  l.piv_t = reinterpret_cast<int*>(take(sizeof(int) * (K + 1)));
+  l.piv_g = reinterpret_cast<int*>(take(sizeof(int) * K));
+  l.own_t = reinterpret_cast<int*>(take(sizeof(int) * (K + 1)));
+  l.own_g = reinterpret_cast<int*>(take(sizeof(int) * K));
+  l.lam_idx = reinterpret_cast<int*>(take(sizeof(int) * K));
+  l.sel = reinterpret_cast<int*>(take(sizeof(int) * 2));
+  l.st = reinterpret_cast<DevState*>(take(sizeof(DevState)));
+  l.res_bytes = off - res_start;
+  l.res = base ? base + res_start : nullptr;
+  if (lay) *lay = l;
+  return align_up(off, 256);
+}
+
+}  // namespace
+
+struct lslu_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  size_t lds_max = 0;
+  // workspace
+  unsigned char* ws = nullptr;
+  size_t ws_bytes = 0;
+  unsigned char* host = nullptr;  // pinned staging for the result block
+  size_t host_bytes = 0;
+  Layout lay;
+  int64_t m = 0, n = 0, ldL = 0, ldD = 0;
+  int K = 0;
+  size_t esz = 0;
+  // basis vectors formed by the last solve
+  int last_nl = 0, last_nd = 0;
+};
+
+struct lslu_op {
+  lslu_ctx* ctx = nullptr;
+  DeviceOp d;
+};
+
+namespace {
+
+lslu_status fail(lslu_ctx* c, lslu_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define LSLU_HIP(ctx, expr)                                                  \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return fail((ctx), e_ == hipErrorOutOfMemory ? LSLU_ENOMEM : LSLU_EDEVICE, \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+bool finite_all(const double* p, int64_t count) {
+  for (int64_t i = 0; i < count; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+size_t prec_size(int prec) { return prec == kFP64 ? sizeof(double) : sizeof(float); }
+
+// Convert host doubles to the operator's stored value type.
+std::vector<unsigned char> convert_values(const double* v, int64_t count, int prec) {
+  std::vector<unsigned char> out;
+  if (prec == kFP64) {
+    out.resize(sizeof(double) * count);
+    std::memcpy(out.data(), v, out.size());
+  } else if (prec == kFP32) {
+    out.resize(sizeof(float) * count);
+    float* o = reinterpret_cast<float*>(out.data());
+    for (int64_t i = 0; i < count; ++i) o[i] = static_cast<float>(v[i]);
+  } else {
+    out.resize(sizeof(uint16_t) * count);
+    uint16_t* o = reinterpret_cast<uint16_t*>(out.data());
+    for (int64_t i = 0; i < count; ++i) o[i] = f32_to_bf16(static_cast<float>(v[i]));
+  }
+  return out;
+}
+
+lslu_status upload(lslu_ctx* c, void** dst, const void* src, size_t bytes) {
+  LSLU_HIP(c, hipMalloc(dst, bytes > 0 ? bytes : 1));
+  if (bytes) LSLU_HIP(c, hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+  return LSLU_OK;
+}
+
+void free_op(DeviceOp& d) {
+  void* ps[] = {d.A, d.AT, d.rp, d.ci, d.val, d.rpT, d.ciT, d.valT,
+                d.psf, d.psf_flip, d.psf32, d.psf32_flip};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  d = DeviceOp{};
+}
+
+lslu_status ensure_ws(lslu_ctx* c, int64_t m, int64_t n, int K, size_t esz) {
+  const int64_t ldL = (int64_t)align_up((size_t)n, 64);
+  const int64_t ldD = (int64_t)align_up((size_t)m, 64);
+  const size_t need = carve(nullptr, m, n, K, esz, ldL, ldD, nullptr);
+  if (need > c->ws_bytes) {
+    if (c->ws) (void)hipFree(c->ws);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    void* p = nullptr;
+    LSLU_HIP(c, hipMalloc(&p, need));
+    c->ws = static_cast<unsigned char*>(p);
+    c->ws_bytes = need;
+  }
+  carve(c->ws, m, n, K, esz, ldL, ldD, &c->lay);
+  if (c->lay.res_bytes > c->host_bytes) {
+    if (c->host) (void)hipHostFree(c->host);
+    c->host = nullptr;
+    c->host_bytes = 0;
+    void* h = nullptr;
+    LSLU_HIP(c, hipHostMalloc(&h, c->lay.res_bytes, hipHostMallocDefault));
+    c->host = static_cast<unsigned char*>(h);
+    c->host_bytes = c->lay.res_bytes;
+  }
+  c->m = m;
+  c->n = n;
+  c->K = K;
+  c->ldL = ldL;
+  c->ldD = ldD;
+  c->esz = esz;
+  return LSLU_OK;
+}
+
+template <typename T>
+void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
+                   const lslu_opts* o, T* x_out, T* X, bool replay_t,
+                   bool replay_g, bool replay_lam) {
+  const hipStream_t s = c->stream;
+  const Layout& l = c->lay;
+  const int K = c->K;
+  const int64_t m = c->m, n = c->n, ldL = c->ldL, ldD = c->ldD;
+  T* Lb = static_cast<T*>(l.L);
+  T* Db = static_cast<T*>(l.D);
+  T* q = static_cast<T*>(l.q);
+  T* u = static_cast<T*>(l.u);
+  DevState* st = l.st;
+  const int* stop = &st->stopped;
+
+  launch_state_reset(st, s);
+  launch_fill<unsigned char>(l.mask_t, 0, m, s);
+  launch_fill<unsigned char>(l.mask_g, 0, n, s);
+  launch_fill<int>(l.piv_t, -1, K + 1, s);
+  launch_fill<int>(l.piv_g, -1, K, s);
+  launch_fill<int>(l.own_t, -1, K + 1, s);
+  launch_fill<int>(l.own_g, -1, K, s);
+  launch_fill<double>(l.H, 0.0, (int64_t)(K + 1) * K, s);
+  launch_fill<double>(l.W, 0.0, (int64_t)K * K, s);
+  launch_fill<double>(l.Y, 0.0, (int64_t)K * K, s);
+  launch_fill<double>(l.TL, 0.0, (int64_t)K * K, s);
+  launch_fill<double>(l.TD, 0.0, (int64_t)(K + 1) * (K + 1), s);
+
+  // r_0 = b - A x_0 (or b), its pivot, beta and d_1.
+  const T* r0 = b;
+  if (x0) {
+    op_apply(op, 0, x0, l.r0, nullptr, s);
+    launch_sub<T>(b, static_cast<const T*>(l.r0), static_cast<T*>(l.r0), m, s);
+    r0 = static_cast<const T*>(l.r0);
+  }
+  PivotJob j0{};
+  j0.side = 2;
+  j0.k = 0;
+  j0.eligible = 1;
+  j0.piv_pos = 0;
+  j0.piv_val = &st->beta;
+  j0.piv_list = l.piv_t;
+  j0.own_list = l.own_t;
+  j0.mask = l.mask_t;
+  j0.replay = replay_t ? l.rep_t : nullptr;
+  j0.st = st;
+  launch_eliminate_argmax<T>(r0, u, Db, ldD, 0, nullptr, l.mask_t, m, l.parts,
+                             j0, s);
+  launch_normalize<T>(u, Db, m, j0, l.TD, K + 1, Db, ldD, 0, s);
+
+  for (int k = 1; k <= K; ++k) {
+    // l side: q0 = A^T d_k, W(1:k-1,k), q, g(k), W(k,k), l_k.
+    op_apply(op, 1, Db + (int64_t)(k - 1) * ldD, q, stop, s);
+    double* Wcol = l.W + (int64_t)(k - 1) * K;
+    launch_gather_trisolve<T>(q, l.piv_g, k - 1, l.TL, K, Wcol, st, s);
+    PivotJob jg{};
+    jg.side = 0;
+    jg.k = k;
+    jg.eligible = (k <= n) ? 1 : 0;
+    jg.piv_pos = k - 1;
+    jg.piv_val = Wcol + (k - 1);
+    jg.piv_list = l.piv_g;
+    jg.own_list = l.own_g;
+    jg.mask = l.mask_g;
+    jg.replay = replay_g ? l.rep_g : nullptr;
+    jg.st = st;
+    launch_eliminate_argmax<T>(q, q, Lb, ldL, k - 1, Wcol, l.mask_g, n, l.parts,
+                               jg, s);
+    launch_normalize<T>(q, Lb + (int64_t)(k - 1) * ldL, n, jg, l.TL + (k - 1), K,
+                        Lb, ldL, k - 1, s);
+    // d side: u0 = A l_k, H(1:k,k), u, t(k+1), H(k+1,k), d_{k+1}.
+    op_apply(op, 0, Lb + (int64_t)(k - 1) * ldL, u, stop, s);
+    double* Hcol = l.H + (int64_t)(k - 1) * (K + 1);
+    launch_gather_trisolve<T>(u, l.piv_t, k, l.TD, K + 1, Hcol, st, s);
+    PivotJob jt{};
+    jt.side = 1;
+    jt.k = k;
+    jt.eligible = (k < m) ? 1 : 0;
+    jt.piv_pos = k;
+    jt.piv_val = Hcol + k;
+    jt.piv_list = l.piv_t;
+    jt.own_list = l.own_t;
+    jt.mask = l.mask_t;
+    jt.replay = replay_t ? l.rep_t : nullptr;
+    jt.st = st;
+    launch_eliminate_argmax<T>(u, u, Db, ldD, k, Hcol, l.mask_t, m, l.parts, jt,
+                               s);
+    launch_normalize<T>(u, Db + (int64_t)k * ldD, m, jt, l.TD + k, K + 1, Db,
+                        ldD, k, s);
+  }
+
+  ProjParams pp{};
+  pp.K = K;
+  pp.m = static_cast<int>(std::min<int64_t>(m, INT32_MAX));
+  pp.n = static_cast<int>(std::min<int64_t>(n, INT32_MAX));
+  pp.reg = o->reg;
+  pp.lambda = o->lambda;
+  pp.n_grid = o->n_grid;
+  pp.grid_relative = o->grid_relative;
+  pp.omega = o->omega;
+  pp.grid = l.grid;
+  pp.replay_lambda = replay_lam ? l.rep_lam : nullptr;
+  launch_projected(l.H, st, 0.0, pp, l.Y, l.lam, l.lam_idx, l.ghat, l.sep,
+                   l.smax, l.smin, l.proj, c->lds_max, s);
+  const double tol = o->stop_tol > 0.0 ? o->stop_tol : 1e-6;
+  launch_stopping(l.ghat, st, tol, o->early_stop ? 1 : 0, l.sel, s);
+  launch_assemble<T>(Lb, ldL, n, l.Y, K, x0, X, st, s);
+  launch_select_x<T>(X, n, x0, x_out, st, l.sel, s);
+}
+
+lslu_status validate_opts(lslu_ctx* c, const lslu_op* op, const lslu_opts* o) {
+  const int64_t m = op->d.m, n = op->d.n;
+  if (o->maxiter < 1 || o->maxiter > kMaxIter)
+    return fail(c, LSLU_EINVAL, "maxiter must be in [1, 256]");
+  if ((int64_t)o->maxiter > std::min(m, n) + 1)
+    return fail(c, LSLU_EINVAL, "maxiter must not exceed min(m, n) + 1");
+  if (o->reg < LSLU_REG_NONE || o->reg > LSLU_REG_OPTIMAL)
+    return fail(c, LSLU_EINVAL, "unknown regularisation rule");
+  if (o->reg == LSLU_REG_OPTIMAL)
+    return fail(c, LSLU_EUNSUPPORTED, "LSLU_REG_OPTIMAL is not implemented");
+  if (o->reg == LSLU_REG_FIXED && !(std::isfinite(o->lambda) && o->lambda >= 0.0))
+    return fail(c, LSLU_EINVAL, "lambda must be finite and >= 0");
+  if (o->reg == LSLU_REG_WGCV || o->reg == LSLU_REG_GCV) {
+    if (!o->lambda_grid || o->n_grid < 1 || o->n_grid > kMaxGrid)
+      return fail(c, LSLU_EINVAL, "a lambda grid of 1..256 values is required");
+    for (int i = 0; i < o->n_grid; ++i) {
+      const double g = o->lambda_grid[i];
+      if (!std::isfinite(g) || g <= 0.0)
+        return fail(c, LSLU_EINVAL, "lambda grid values must be finite and > 0");
+      if (i > 0 && !(g > o->lambda_grid[i - 1]))
+        return fail(c, LSLU_EINVAL, "lambda grid must be strictly ascending");
+    }
+  }
+  auto check_piv = [&](const int32_t* p, int count, int64_t lim,
+                       const char* what) -> lslu_status {
+    std::vector<char> seen(static_cast<size_t>(lim), 0);
+    for (int i = 0; i < count; ++i) {
+      if (p[i] < 0 || p[i] >= lim)
+        return fail(c, LSLU_EINVAL, std::string(what) + ": pivot out of range");
+      if (seen[p[i]])
+        return fail(c, LSLU_EINVAL, std::string(what) + ": repeated pivot");
+      seen[p[i]] = 1;
+    }
+    return LSLU_OK;
+  };
+  const int K = o->maxiter;
+  if (o->replay_piv_t) {
+    lslu_status st = check_piv(o->replay_piv_t, (int)std::min<int64_t>(K + 1, m), m,
+                               "replay_piv_t");
+    if (st != LSLU_OK) return st;
+  }
+  if (o->replay_piv_g) {
+    lslu_status st = check_piv(o->replay_piv_g, (int)std::min<int64_t>(K, n), n,
+                               "replay_piv_g");
+    if (st != LSLU_OK) return st;
+  }
+  if (o->replay_lambda_idx) {
+    for (int i = 0; i < K; ++i)
+      if (o->replay_lambda_idx[i] >= o->n_grid)
+        return fail(c, LSLU_EINVAL, "replay_lambda_idx out of range");
+  }
+  return LSLU_OK;
+}
+
+template <typename T>
+void copy_out(T* dst, const T* src, size_t count) {
+  if (dst) std::memcpy(dst, src, sizeof(T) * count);
+}
+
+}  // namespace
+
+// =========================================================================
+extern "C" {
+
+int lslu_abi_version(void) { return LSLU_ABI_VERSION; }
+
+const char* lslu_status_name(int s) {
+  switch (s) {
+    case LSLU_OK: return "LSLU_OK";
+    case LSLU_BREAKDOWN_Q: return "LSLU_BREAKDOWN_Q";
+    case LSLU_BREAKDOWN_U: return "LSLU_BREAKDOWN_U";
+    case LSLU_ZERO_RHS: return "LSLU_ZERO_RHS";
+    case LSLU_EINVAL: return "LSLU_EINVAL";
+    case LSLU_ENOMEM: return "LSLU_ENOMEM";
+    case LSLU_EDEVICE: return "LSLU_EDEVICE";
+    case LSLU_ENONFINITE: return "LSLU_ENONFINITE";
+    case LSLU_EUNSUPPORTED: return "LSLU_EUNSUPPORTED";
+    default: return "LSLU_UNKNOWN";
+  }
+}
+
+const char* lslu_last_error(const lslu_ctx* ctx) {
+  if (!ctx) return "no context (lslu_create failed or was not called)";
+  return ctx->err.c_str();
+}
+
+lslu_status lslu_create(int device, void* hip_stream, lslu_ctx** out) {
+  if (!out) return LSLU_EINVAL;
+  *out = nullptr;
+  try {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return LSLU_EDEVICE;
+    if (device < 0 || device >= count) return LSLU_EDEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return LSLU_EDEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return LSLU_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return LSLU_EDEVICE;
+    lslu_ctx* c = new lslu_ctx();
+    c->device = device;
+    c->lds_max = prop.sharedMemPerBlock;
+    if (hip_stream) {
+      c->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+      if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return LSLU_EDEVICE;
+      }
+      c->own_stream = true;
+    }
+    *out = c;
+    return LSLU_OK;
+  } catch (const std::bad_alloc&) {
+    return LSLU_ENOMEM;
+  } catch (...) {
+    return LSLU_EDEVICE;
+  }
+}
+
+lslu_status lslu_destroy(lslu_ctx* c) {
+  if (!c) return LSLU_OK;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->host) (void)hipHostFree(c->host);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return LSLU_OK;
+}
+
+lslu_status lslu_op_dense(lslu_ctx* c, int64_t m, int64_t n, const double* A,
+                          int32_t prec, lslu_op** out) {
+  if (!c) return LSLU_EINVAL;
+  if (!out || !A) return fail(c, LSLU_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (m < 1 || n < 1) return fail(c, LSLU_EINVAL, "m and n must be >= 1");
+  if (prec < LSLU_FP64 || prec > LSLU_BF16OP) return fail(c, LSLU_EINVAL, "bad precision");
+  if (m > INT32_MAX || n > INT32_MAX) return fail(c, LSLU_EINVAL, "size too large");
+  try {
+    if (!finite_all(A, m * n)) return fail(c, LSLU_ENONFINITE, "A has NaN/Inf");
+    LSLU_HIP(c, hipSetDevice(c->device));
+    std::vector<double> AT(static_cast<size_t>(m * n));
+    for (int64_t i = 0; i < m; ++i)
+      for (int64_t j = 0; j < n; ++j) AT[j * m + i] = A[i * n + j];
+    lslu_op* op = new lslu_op();
+    op->ctx = c;
+    op->d.kind = 0;
+    op->d.prec = prec;
+    op->d.m = m;
+    op->d.n = n;
+    auto va = convert_values(A, m * n, prec);
+    auto vt = convert_values(AT.data(), m * n, prec);
+    lslu_status st = upload(c, &op->d.A, va.data(), va.size());
+    if (st == LSLU_OK) st = upload(c, &op->d.AT, vt.data(), vt.size());
+    if (st != LSLU_OK) {
+      free_op(op->d);
+      delete op;
+      return st;
+    }
+    *out = op;
+    return LSLU_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(c, LSLU_ENOMEM, "host allocation failed");
+  }
+}
+
+lslu_status lslu_op_csr(lslu_ctx* c, int64_t m, int64_t n, int64_t nnz,
+                        const int64_t* indptr, const int32_t* indices,
+                        const double* data, int32_t prec, lslu_op** out) {
+  if (!c) return LSLU_EINVAL;
+  if (!out || !indptr || (nnz > 0 && (!indices || !data)))
+    return fail(c, LSLU_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (m < 1 || n < 1 || nnz < 0) return fail(c, LSLU_EINVAL, "bad shape");
+  if (m > INT32_MAX - 1 || n > INT32_MAX - 1 || nnz > INT32_MAX - 1)
+    return fail(c, LSLU_EINVAL, "sizes must be < 2^31");
+  if (prec < LSLU_FP64 || prec > LSLU_BF16OP) return fail(c, LSLU_EINVAL, "bad precision");
+  try {
+    if (indptr[0] != 0 || indptr[m] != nnz)
+      return fail(c, LSLU_EINVAL, "indptr[0] must be 0 and indptr[m] must be nnz");
+    for (int64_t r = 0; r < m; ++r) {
+      if (indptr[r + 1] < indptr[r]) return fail(c, LSLU_EINVAL, "indptr decreases");
+      for (int64_t p = indptr[r]; p < indptr[r + 1]; ++p) {
+        if (indices[p] < 0 || indices[p] >= n)
+          return fail(c, LSLU_EINVAL, "column index out of range");
+        if (p > indptr[r] && indices[p] <= indices[p - 1])
+          return fail(c, LSLU_EINVAL, "column indices not strictly increasing");
+      }
+    }
+    if (!finite_all(data, nnz)) return fail(c, LSLU_ENONFINITE, "data has NaN/Inf");
+    LSLU_HIP(c, hipSetDevice(c->device));
+    // A^T in CSR: count per column, prefix sum, scatter in row order (so the
+    // column indices of A^T, i.e. rows of A, come out increasing).
+    std::vector<int> rp(m + 1), rpT(n + 1, 0), ciT(nnz);
+    std::vector<double> valT(nnz);
+    for (int64_t r = 0; r <= m; ++r) rp[r] = static_cast<int>(indptr[r]);
+    for (int64_t p = 0; p < nnz; ++p) rpT[indices[p] + 1] += 1;
+    for (int64_t j = 0; j < n; ++j) rpT[j + 1] += rpT[j];
+    std::vector<int> fillp(rpT.begin(), rpT.end() - 1);
+    for (int64_t r = 0; r < m; ++r)
+      for (int64_t p = indptr[r]; p < indptr[r + 1]; ++p) {
+        const int dst = fillp[indices[p]]++;
+        ciT[dst] = static_cast<int>(r);
+        valT[dst] = data[p];
+      }
+    lslu_op* op = new lslu_op();
+    op->ctx = c;
+    op->d.kind = 1;
+    op->d.prec = prec;
+    op->d.m = m;
+    op->d.n = n;
+    op->d.nnz = nnz;
+    auto va = convert_values(data, nnz, prec);
+    auto vt = convert_values(valT.data(), nnz, prec);
+    lslu_status st = upload(c, reinterpret_cast<void**>(&op->d.rp), rp.data(), sizeof(int) * (m + 1));
+    if (st == LSLU_OK) st = upload(c, reinterpret_cast<void**>(&op->d.ci), indices, sizeof(int) * nnz);
+    if (st == LSLU_OK) st = upload(c, &op->d.val, va.data(), va.size());
+    if (st == LSLU_OK) st = upload(c, reinterpret_cast<void**>(&op->d.rpT), rpT.data(), sizeof(int) * (n + 1));
+    if (st == LSLU_OK) st = upload(c, reinterpret_cast<void**>(&op->d.ciT), ciT.data(), sizeof(int) * nnz);
+    if (st == LSLU_OK) st = upload(c, &op->d.valT, vt.data(), vt.size());
+    if (st != LSLU_OK) {
+      free_op(op->d);
+      delete op;
+      return st;
+    }
+    *out = op;
+    return LSLU_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(c, LSLU_ENOMEM, "host allocation failed");
+  }
+}
+
+lslu_status lslu_op_psf(lslu_ctx* c, int64_t rows, int64_t cols, int32_t ph,
+                        int32_t pw, const double* psf, int32_t prec,
+                        lslu_op** out) {
+  if (!c) return LSLU_EINVAL;
+  if (!out || !psf) return fail(c, LSLU_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (rows < 1 || cols < 1 || rows * cols > INT32_MAX)
+    return fail(c, LSLU_EINVAL, "bad image shape");
+  if (ph < 1 || pw < 1 || ph % 2 == 0 || pw % 2 == 0 || ph > 31 || pw > 31)
+    return fail(c, LSLU_EINVAL, "PSF sizes must be odd and <= 31");
+  if (prec < LSLU_FP64 || prec > LSLU_BF16OP) return fail(c, LSLU_EINVAL, "bad precision");
+  if (!finite_all(psf, (int64_t)ph * pw)) return fail(c, LSLU_ENONFINITE, "PSF has NaN/Inf");
+  try {
+    LSLU_HIP(c, hipSetDevice(c->device));
+    const int np = ph * pw;
+    std::vector<double> p(psf, psf + np), pf(np);
+    for (int a = 0; a < ph; ++a)
+      for (int b = 0; b < pw; ++b) pf[a * pw + b] = psf[(ph - 1 - a) * pw + (pw - 1 - b)];
+    std::vector<float> p32(np), pf32(np);
+    for (int i = 0; i < np; ++i) {
+      p32[i] = bf16_to_f32(f32_to_bf16(static_cast<float>(p[i])));
+      pf32[i] = bf16_to_f32(f32_to_bf16(static_cast<float>(pf[i])));
+    }
+    lslu_op* op = new lslu_op();
+    op->ctx = c;
+    op->d.kind = 2;
+    op->d.prec = prec;
+    op->d.m = rows * cols;
+    op->d.n = rows * cols;
+    op->d.rows = rows;
+    op->d.cols = cols;
+    op->d.ph = ph;
+    op->d.pw = pw;
+    lslu_status st = upload(c, reinterpret_cast<void**>(&op->d.psf), p.data(), sizeof(double) * np);
+    if (st == LSLU_OK) st = upload(c, reinterpret_cast<void**>(&op->d.psf_flip), pf.data(), sizeof(double) * np);
+    if (st == LSLU_OK) st = upload(c, reinterpret_cast<void**>(&op->d.psf32), p32.data(), sizeof(float) * np);
+    if (st == LSLU_OK) st = upload(c, reinterpret_cast<void**>(&op->d.psf32_flip), pf32.data(), sizeof(float) * np);
+    if (st != LSLU_OK) {
+      free_op(op->d);
+      delete op;
+      return st;
+    }
+    *out = op;
+    return LSLU_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(c, LSLU_ENOMEM, "host allocation failed");
+  }
+}
+
+lslu_status lslu_op_apply(lslu_ctx* c, const lslu_op* op, int32_t transpose,
+                          const void* x, void* y) {
+  if (!c) return LSLU_EINVAL;
+  if (!op || !x || !y) return fail(c, LSLU_EINVAL, "NULL argument");
+  if (op->ctx != c) return fail(c, LSLU_EINVAL, "operator belongs to another context");
+  LSLU_HIP(c, hipSetDevice(c->device));
+  op_apply(op->d, transpose ? 1 : 0, x, y, nullptr, c->stream);
+  LSLU_HIP(c, hipGetLastError());
+  return LSLU_OK;
+}
+
+lslu_status lslu_op_info(const lslu_op* op, int64_t* m, int64_t* n, int32_t* prec) {
+  if (!op) return LSLU_EINVAL;
+  if (m) *m = op->d.m;
+  if (n) *n = op->d.n;
+  if (prec) *prec = op->d.prec;
+  return LSLU_OK;
+}
+
+lslu_status lslu_op_destroy(lslu_op* op) {
+  if (!op) return LSLU_OK;
+  if (op->ctx) {
+    (void)hipSetDevice(op->ctx->device);
+    if (op->ctx->stream) (void)hipStreamSynchronize(op->ctx->stream);
+  }
+  free_op(op->d);
+  delete op;
+  return LSLU_OK;
+}
+
+lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
+                       const void* x0, const lslu_opts* o, void* x_out,
+                       lslu_result* res) {
+  if (!c) return LSLU_EINVAL;
+  if (!op || !b || !o || !x_out) return fail(c, LSLU_EINVAL, "NULL argument");
+  if (op->ctx != c) return fail(c, LSLU_EINVAL, "operator belongs to another context");
+  try {
+    lslu_status vs = validate_opts(c, op, o);
+    if (vs != LSLU_OK) return vs;
+    LSLU_HIP(c, hipSetDevice(c->device));
+    const int K = o->maxiter;
+    const size_t esz = prec_size(op->d.prec);
+    lslu_status ws = ensure_ws(c, op->d.m, op->d.n, K, esz);
+    if (ws != LSLU_OK) return ws;
+    const Layout& l = c->lay;
+    const hipStream_t s = c->stream;
+    if (o->reg == LSLU_REG_WGCV || o->reg == LSLU_REG_GCV)
+      LSLU_HIP(c, hipMemcpyAsync(l.grid, o->lambda_grid, sizeof(double) * o->n_grid,
+                                 hipMemcpyHostToDevice, s));
+    const bool rt = o->replay_piv_t != nullptr, rg = o->replay_piv_g != nullptr,
+               rl = o->replay_lambda_idx != nullptr;
+    if (rt) {
+      std::vector<int> v(K + 1, -1);
+      for (int i = 0; i < std::min<int64_t>(K + 1, op->d.m); ++i) v[i] = o->replay_piv_t[i];
+      LSLU_HIP(c, hipMemcpyAsync(l.rep_t, v.data(), sizeof(int) * (K + 1),
+                                 hipMemcpyHostToDevice, s));
+      LSLU_HIP(c, hipStreamSynchronize(s));
+    }
+    if (rg) {
+      std::vector<int> v(K, -1);
+      for (int i = 0; i < std::min<int64_t>(K, op->d.n); ++i) v[i] = o->replay_piv_g[i];
+      LSLU_HIP(c, hipMemcpyAsync(l.rep_g, v.data(), sizeof(int) * K,
+                                 hipMemcpyHostToDevice, s));
+      LSLU_HIP(c, hipStreamSynchronize(s));
+    }
+    if (rl) {
+      LSLU_HIP(c, hipMemcpyAsync(l.rep_lam, o->replay_lambda_idx, sizeof(int) * K,
+                                 hipMemcpyHostToDevice, s));
+      LSLU_HIP(c, hipStreamSynchronize(s));
+    }
+    if (o->reg == LSLU_REG_WGCV || o->reg == LSLU_REG_GCV)
+      LSLU_HIP(c, hipStreamSynchronize(s));  // grid upload reads host memory
+    void* X = o->X_dev ? o->X_dev : l.X;
+    if (esz == sizeof(double))
+      enqueue_solve<double>(c, op->d, static_cast<const double*>(b),
+                            static_cast<const double*>(x0), o,
+                            static_cast<double*>(x_out), static_cast<double*>(X),
+                            rt, rg, rl);
+    else
+      enqueue_solve<float>(c, op->d, static_cast<const float*>(b),
+                           static_cast<const float*>(x0), o,
+                           static_cast<float*>(x_out), static_cast<float*>(X),
+                           rt, rg, rl);
+    LSLU_HIP(c, hipGetLastError());
+    LSLU_HIP(c, hipMemcpyAsync(c->host, l.res, l.res_bytes, hipMemcpyDeviceToHost, s));
+    LSLU_HIP(c, hipStreamSynchronize(s));
+    // Unpack the result block (same layout as on the device).
+    auto hp = [&](const void* dev) {
+      return c->host + (static_cast<const unsigned char*>(dev) - l.res);
+    };
+    const DevState* st = reinterpret_cast<const DevState*>(hp(l.st));
+    const int* sel = reinterpret_cast<const int*>(hp(l.sel));
+    c->last_nl = st->n_l;
+    c->last_nd = st->n_d;
+    const lslu_status status = static_cast<lslu_status>(st->status);
+    if (res) {
+      res->status = status;
+      res->k_done = st->k_done;
+      res->k_stop = sel[0];
+      res->n_l = st->n_l;
+      res->n_d = st->n_d;
+      res->beta = st->beta;
+      res->piv_t_mismatch = st->mismatch_t;
+      res->piv_g_mismatch = st->mismatch_g;
+      copy_out(res->piv_t, reinterpret_cast<const int32_t*>(hp(l.piv_t)), K + 1);
+      copy_out(res->piv_g, reinterpret_cast<const int32_t*>(hp(l.piv_g)), K);
+      copy_out(res->own_piv_t, reinterpret_cast<const int32_t*>(hp(l.own_t)), K + 1);
+      copy_out(res->own_piv_g, reinterpret_cast<const int32_t*>(hp(l.own_g)), K);
+      copy_out(res->H, reinterpret_cast<const double*>(hp(l.H)), (size_t)(K + 1) * K);
+      copy_out(res->W, reinterpret_cast<const double*>(hp(l.W)), (size_t)K * K);
+      copy_out(res->Y, reinterpret_cast<const double*>(hp(l.Y)), (size_t)K * K);
+      copy_out(res->lambda_k, reinterpret_cast<const double*>(hp(l.lam)), K);
+      copy_out(res->lambda_idx, reinterpret_cast<const int32_t*>(hp(l.lam_idx)), K);
+      copy_out(res->ghat, reinterpret_cast<const double*>(hp(l.ghat)), K);
+      copy_out(res->sep_lambda, reinterpret_cast<const double*>(hp(l.sep)), K);
+      copy_out(res->sigma_max, reinterpret_cast<const double*>(hp(l.smax)), K);
+      copy_out(res->sigma_min, reinterpret_cast<const double*>(hp(l.smin)), K);
+    }
+    return status;
+  } catch (const std::bad_alloc&) {
+    return fail(c, LSLU_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(c, LSLU_EDEVICE, "unexpected exception");
+  }
+}
+
+lslu_status lslu_get_basis(lslu_ctx* c, int32_t which, int32_t count, void* dst) {
+  if (!c) return LSLU_EINVAL;
+  if (!dst) return fail(c, LSLU_EINVAL, "NULL argument");
+  const int have = which == 0 ? c->last_nl : c->last_nd;
+  if (which < 0 || which > 1 || count < 0 || count > have)
+    return fail(c, LSLU_EINVAL, "count exceeds the basis of the last solve");
+  if (count == 0) return LSLU_OK;
+  LSLU_HIP(c, hipSetDevice(c->device));
+  const int64_t len = which == 0 ? c->n : c->m;
+  const int64_t ld = which == 0 ? c->ldL : c->ldD;
+  const void* src = which == 0 ? c->lay.L : c->lay.D;
+  LSLU_HIP(c, hipMemcpy2DAsync(dst, len * c->esz, src, ld * c->esz, len * c->esz,
+                               count, hipMemcpyDeviceToDevice, c->stream));
+  return LSLU_OK;
+}
+
+}  // extern "C"

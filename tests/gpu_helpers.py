@@ -1,0 +1,114 @@
+"""Helpers for the GPU parity tests: run the HIP library through its C ABI on a
+``workloads.Problem`` and compare with the oracle's result."""
+
+from __future__ import annotations
+
+import numpy as np
+
+TAU = {"fp64": 1e-9, "fp32": 1e-3, "bf16op": 1e-2}
+TOL = {"fp64": 1e-10, "fp32": 1e-4}
+
+
+def torch_dtype(prec):
+    import torch
+    return torch.float64 if prec == "fp64" else torch.float32
+
+
+def gpu_solve(capi, ctx, prob, prec="fp64", K=10, reg="none", lam=0.0,
+              grid=None, grid_relative=False, replay=None, x0=None,
+              early_stop=False, stop_tol=0.0, bases=True, op=None):
+    """Solve on the GPU; returns the info dict with x, X (n x K), L, D."""
+    import torch
+    dt = torch_dtype(prec)
+    own_op = op is None
+    if own_op:
+        op = capi.make_operator(ctx, prob, capi.PRECISIONS[prec])
+    try:
+        print(f"[gpu_solve] {prob.name} prec={prec} K={K} reg={reg} "
+              f"replay={replay is not None}", flush=True)
+        b = torch.tensor(prob.b, dtype=dt, device="cuda")
+        X = torch.zeros((K, prob.n), dtype=dt, device="cuda")
+        x0t = None if x0 is None else torch.tensor(x0, dtype=dt, device="cuda")
+        kw = {}
+        if replay is not None:
+            kw.update(replay)
+        st, x, info = capi.lslu_solve(ctx, op, b, K, reg=reg, lam=lam, grid=grid,
+                                      grid_relative=grid_relative, X=X, x0=x0t,
+                                      early_stop=early_stop, stop_tol=stop_tol,
+                                      **kw)
+        torch.cuda.synchronize()
+        info["x"] = x.double().cpu().numpy()
+        info["X"] = X.double().cpu().numpy().T.copy()
+        if bases:
+            nl, nd = info["n_l"], info["n_d"]
+            Lt = torch.zeros((max(nl, 1), prob.n), dtype=dt, device="cuda")
+            Dt = torch.zeros((max(nd, 1), prob.m), dtype=dt, device="cuda")
+            capi.lslu_get_basis(ctx, 0, nl, Lt)
+            capi.lslu_get_basis(ctx, 1, nd, Dt)
+            torch.cuda.synchronize()
+            info["L"] = Lt.double().cpu().numpy().T[:, :nl].copy()
+            info["D"] = Dt.double().cpu().numpy().T[:, :nd].copy()
+        return info
+    finally:
+        if own_op:
+            capi.lslu_op_destroy(op)
+
+
+def replay_from(R, K):
+    """Replay arrays (pivots and lambda indices) from an oracle result."""
+    pt = np.full(K + 1, -1, np.int32)
+    pg = np.full(K, -1, np.int32)
+    t = np.asarray(R.piv_t[:K + 1], np.int32)
+    g = np.asarray(R.piv_g[:K], np.int32)
+    pt[:t.shape[0]] = t
+    pg[:g.shape[0]] = g
+    li = np.full(K, -1, np.int32)
+    lk = np.asarray(R.lambda_idx[:K], np.int32)
+    li[:lk.shape[0]] = lk
+    return dict(replay_piv_t=pt, replay_piv_g=pg, replay_lambda_idx=li)
+
+
+def well_separated_prefix(R, tau, k_max):
+    """Largest k such that every search deciding x_1..x_k (t(1), g(1), t(2),
+    ..., g(k) and lambda_1..lambda_k) has separation above tau."""
+    k_ok = 0
+    for k in range(1, k_max + 1):
+        seps = [R.sep_t[k - 1], R.sep_g[k - 1]] if k - 1 < len(R.sep_g) else []
+        if len(seps) < 2 or min(seps) <= tau:
+            break
+        if k - 1 < len(R.sep_lambda) and R.sep_lambda[k - 1] <= tau:
+            break
+        k_ok = k
+    return k_ok
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def residual_gap(op, b, x, x_ref):
+    r = np.linalg.norm(b - op.matvec(x))
+    r_ref = np.linalg.norm(b - op.matvec(x_ref))
+    return abs(r - r_ref) / r_ref
+
+
+def check_basis_invariants(info, m, n):
+    """Exact structure of the bases in any precision (unit at own pivot, zero at
+    earlier pivots, |entries| <= 1, distinct pivots, H Hessenberg)."""
+    L, D = info["L"], info["D"]
+    pg = [int(v) for v in info["piv_g"][:info["n_l"]]]
+    pt = [int(v) for v in info["piv_t"][:info["n_d"]]]
+    assert len(set(pg)) == len(pg) and len(set(pt)) == len(pt)
+    for k, g in enumerate(pg):
+        assert L[g, k] == 1.0
+        for j in range(k):
+            assert L[pg[j], k] == 0.0
+    for k, t in enumerate(pt):
+        assert D[t, k] == 1.0
+        for j in range(k):
+            assert D[pt[j], k] == 0.0
+    assert np.all(np.abs(L) <= 1.0) and np.all(np.abs(D) <= 1.0)
+    kd = info["k_done"]
+    H = info["H"]
+    assert np.all(np.tril(H[:kd + 1, :kd], -2) == 0)

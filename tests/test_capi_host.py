@@ -1,0 +1,64 @@
+"""Host-side checks of the C-ABI library: it loads, exports every entry point
+declared in include/lslu.h, and its argument validation answers without a GPU
+(no device work is started here)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lslu.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lslu_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_2409_05239_amd import capi
+    return capi
+
+
+def test_header_declares_expected_entry_points(capi):
+    assert _declared() == sorted(capi.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(capi):
+    raw = ctypes.CDLL(capi.LIB_PATH)
+    for name in _declared():
+        assert hasattr(raw, name), name
+
+
+def test_abi_version_and_status_names(capi):
+    assert capi.lslu_abi_version() == 1
+    assert capi.status_name(0) == "LSLU_OK"
+    assert capi.status_name(2) == "LSLU_BREAKDOWN_U"
+    assert capi.status_name(-4) == "LSLU_ENONFINITE"
+    assert capi.status_name(99) == "LSLU_UNKNOWN"
+
+
+def test_null_context_is_rejected(capi):
+    out = ctypes.c_void_p()
+    A = np.ones((2, 2))
+    st = capi.lib.lslu_op_dense(None, 2, 2, A.ctypes.data_as(
+        ctypes.POINTER(ctypes.c_double)), 0, ctypes.byref(out))
+    assert st == capi.LSLU_EINVAL
+    assert "no context" in capi.lslu_last_error(None)
+    assert capi.lib.lslu_solve(None, None, None, None, None, None, None) == capi.LSLU_EINVAL
+    assert capi.lib.lslu_destroy(None) == capi.LSLU_OK
+    assert capi.lib.lslu_op_destroy(None) == capi.LSLU_OK
+
+
+def test_create_without_gpu_reports_device_error(capi):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    out = ctypes.c_void_p()
+    assert capi.lib.lslu_create(0, None, ctypes.byref(out)) == capi.LSLU_EDEVICE
+    assert not out.value

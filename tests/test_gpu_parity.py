@@ -1,0 +1,278 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Protocol:
+* free mode -- the library picks its own pivots and lambda; pivots and x_k
+  must match the oracle as long as every pivot/lambda search that decides x_k
+  is well separated in the oracle (separation above tau);
+* replay mode -- the library follows the oracle's pivots and lambda indices
+  and x_k, H and W must match at every k.
+Tolerances on ||x_k - x_oracle||/||x_oracle|| and on the relative residual gap:
+1e-10 in FP64, 1e-4 in FP32.  BF16OP runs report their error against x_true.
+"""
+
+import numpy as np
+import pytest
+
+from gpu_helpers import (TAU, TOL, check_basis_invariants, gpu_solve, rel,
+                         replay_from, residual_gap, well_separated_prefix)
+from oracle import RegParam, make_operator
+from oracle.hessenberg import Status, hybrid_lslu
+from workloads import (config_problem, lambda_grid, psf_deblur, random_dense,
+                       tomography)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    c = lib.lslu_create(0)
+    yield c
+    lib.lslu_destroy(c)
+
+
+def _reg(kind, relative, lam=0.05, x_true=None):
+    return RegParam(kind, lam=lam, grid=lambda_grid(), grid_relative=relative,
+                    x_true=x_true)
+
+
+def _compare(lib, ctx, prob, prec, K, kind, relative, lam=0.05, replay=True,
+             check_free=True, kappa_cap=None):
+    """Run oracle + GPU (free and replay) and check the parity bar."""
+    op = make_operator(prob)
+    R = hybrid_lslu(op, prob.b, K, _reg(kind, relative, lam))
+    grid = lambda_grid() if kind in ("wgcv", "gcv") else None
+    tol = TOL[prec]
+    if check_free:
+        G = gpu_solve(lib, ctx, prob, prec, K, kind, lam, grid, relative)
+        check_basis_invariants(G, prob.m, prob.n)
+        k_ok = well_separated_prefix(R, TAU[prec], min(R.k_done, G["k_done"]))
+        assert list(G["piv_g"][:k_ok]) == R.piv_g[:k_ok]
+        assert list(G["piv_t"][:k_ok]) == R.piv_t[:k_ok]
+        if prec == "fp64":
+            for k in range(1, k_ok + 1):
+                if kappa_cap and G["sigma_max"][k - 1] / G["sigma_min"][k - 1] > kappa_cap:
+                    break
+                assert rel(G["X"][:, k - 1], R.X[:, k - 1]) <= tol, k
+    if replay:
+        Kr = min(K, R.k_done)
+        G = gpu_solve(lib, ctx, prob, prec, Kr, kind, lam, grid, relative,
+                      replay=replay_from(R, Kr))
+        check_basis_invariants(G, prob.m, prob.n)
+        assert G["k_done"] == Kr
+        worst = []
+        for k in range(1, Kr + 1):
+            kap = G["sigma_max"][k - 1] / G["sigma_min"][k - 1]
+            e = rel(G["X"][:, k - 1], R.X[:, k - 1])
+            g = residual_gap(op, prob.b, G["X"][:, k - 1], R.X[:, k - 1])
+            worst.append((k, e, g, kap))
+            if kappa_cap is None or kap <= kappa_cap:
+                assert e <= tol and g <= tol, (k, e, g, kap)
+        print(f"[{prob.name} {prec} {kind}] max x err "
+              f"{max(w[1] for w in worst):.3e} max residual gap "
+              f"{max(w[2] for w in worst):.3e}")
+        # H and W follow from the same pivots; compare where formed.
+        kd = G["k_done"]
+        Hs = np.abs(R.H[:kd + 1, :kd]).max()
+        Ws = np.abs(R.W[:kd, :kd]).max()
+        assert np.abs(G["H"][:kd + 1, :kd] - R.H[:kd + 1, :kd]).max() <= tol * 10 * Hs
+        assert np.abs(G["W"][:kd, :kd] - R.W[:kd, :kd]).max() <= tol * 10 * Ws
+        return R, G
+    return R, None
+
+
+# --------------------------------------------------------------- operators
+
+def _bound(Aabs_x, prec, nterms):
+    u = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "bf16op": 2.0 ** -8}[prec]
+    acc = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -53, "bf16op": 2.0 ** -24}[prec]
+    return (4 * u + nterms * acc) * Aabs_x + 1e-300
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16op"])
+@pytest.mark.parametrize("which", ["dense", "csr", "psf31", "psf_nonsym"])
+def test_operator_products(lib, ctx, which, prec):
+    import torch
+    rng = np.random.default_rng(7)
+    if which == "dense":
+        prob = random_dense(37, 53, seed=3)
+    elif which == "csr":
+        prob = tomography(20, 15, 29, 0.02, seed=4)
+    elif which == "psf31":
+        prob = psf_deblur(45, 15, 2.5, 0.01, seed=5, cols=77)
+    else:
+        prob = psf_deblur(33, 2, 1.0, 0.01, seed=6, cols=70)
+        prob.psf = rng.standard_normal((5, 3))
+    op_or = make_operator(prob)
+    absop = type(op_or)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    op = lib.make_operator(ctx, prob, lib.PRECISIONS[prec])
+    try:
+        for tr in (0, 1):
+            nin, nout = (prob.n, prob.m) if tr == 0 else (prob.m, prob.n)
+            x = rng.standard_normal(nin)
+            if prec != "fp64":
+                x = x.astype(np.float32).astype(np.float64)
+            xt = torch.tensor(x, dtype=dt, device="cuda")
+            yt = torch.full((nout,), np.nan, dtype=dt, device="cuda")
+            lib.lslu_op_apply(ctx, op, tr, xt, yt)
+            torch.cuda.synchronize()
+            y = yt.double().cpu().numpy()
+            ref = op_or.rmatvec(x) if tr else op_or.matvec(x)
+            # |A| |x| via the oracle operator on absolute values
+            if prob.kind == "dense":
+                aop = absop(np.abs(prob.A))
+            elif prob.kind == "csr":
+                aop = absop(prob.m, prob.n, prob.indptr, prob.indices, np.abs(prob.data))
+            else:
+                aop = absop(np.abs(prob.psf), prob.image_shape)
+            mag = aop.rmatvec(np.abs(x)) if tr else aop.matvec(np.abs(x))
+            nterms = 600
+            assert np.all(np.isfinite(y))
+            assert np.all(np.abs(y - ref) <= _bound(mag, prec, nterms)), which
+    finally:
+        lib.lslu_op_destroy(op)
+
+
+# ------------------------------------------------------------ solve parity
+
+@pytest.mark.parametrize("kind", ["none", "wgcv", "gcv", "fixed"])
+def test_dense_blur_fp64(lib, ctx, kind):
+    prob = config_problem("dense256")
+    _compare(lib, ctx, prob, "fp64", 50, kind, relative=False, kappa_cap=1e5)
+
+
+@pytest.mark.parametrize("shape,seed", [((40, 30), 1), ((30, 41), 2),
+                                        ((67, 67), 3), ((130, 70), 4)])
+@pytest.mark.parametrize("kind", ["none", "wgcv"])
+def test_random_dense_fp64(lib, ctx, shape, seed, kind):
+    prob = random_dense(*shape, seed=seed, nu=0.05)
+    K = min(shape) - 5
+    _compare(lib, ctx, prob, "fp64", K, kind, relative=True, kappa_cap=1e6)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tomography_small(lib, ctx, prec):
+    prob = config_problem("tomo32")
+    _compare(lib, ctx, prob, prec, 30, "wgcv", relative=True,
+             check_free=(prec == "fp64"))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_deblur_small(lib, ctx, prec):
+    prob = config_problem("deblur96")
+    _compare(lib, ctx, prob, prec, 40, "wgcv", relative=True,
+             check_free=(prec == "fp64"))
+
+
+def test_deblur_small_bf16op_error(lib, ctx):
+    prob = config_problem("deblur96")
+    op = make_operator(prob)
+    R = hybrid_lslu(op, prob.b, 40, _reg("wgcv", True))
+    G = gpu_solve(lib, ctx, prob, "bf16op", 40, "wgcv", grid=lambda_grid(),
+                  grid_relative=True)
+    check_basis_invariants(G, prob.m, prob.n)
+    e_bf = rel(G["x"], prob.x_true)
+    e_64 = rel(R.x, prob.x_true)
+    print(f"[deblur96 bf16op] rel err vs x_true {e_bf:.4f} (fp64 oracle {e_64:.4f})")
+    assert e_bf < 2 * e_64
+
+
+# -------------------------------------------------------------- edge cases
+
+def test_scaled_identity_breaks_down_at_one(lib, ctx):
+    from workloads.problems import Problem
+    n = 70
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(n)
+    prob = Problem("cI", "dense", n, n, np.zeros(n), b, 0.0, A=2.5 * np.eye(n))
+    for kind, lam in (("none", 0.0), ("fixed", 0.7)):
+        G = gpu_solve(lib, ctx, prob, "fp64", 5, kind, lam)
+        assert G["status"] == lib.LSLU_BREAKDOWN_U and G["k_done"] == 1
+        assert np.allclose(G["x"], 2.5 * b / (2.5 ** 2 + lam ** 2), rtol=1e-14, atol=0)
+
+
+def test_zero_rhs_and_adjoint_nullspace(lib, ctx):
+    from workloads.problems import Problem
+    A = np.zeros((5, 3))
+    A[:3, :3] = np.eye(3)
+    prob = Problem("z", "dense", 5, 3, np.zeros(3), np.zeros(5), 0.0, A=A)
+    G = gpu_solve(lib, ctx, prob, "fp64", 2)
+    assert G["status"] == lib.LSLU_ZERO_RHS and G["k_done"] == 0
+    assert np.all(G["x"] == 0)
+    prob.b = np.array([0.0, 0.0, 0.0, 1.0, -2.0])
+    G = gpu_solve(lib, ctx, prob, "fp64", 2)
+    assert G["status"] == lib.LSLU_BREAKDOWN_Q and G["k_done"] == 0
+    assert np.all(G["x"] == 0)
+
+
+@pytest.mark.parametrize("n,seed", [(5, 52), (8, 54), (70, 55)])
+def test_square_consistent_system_solved_at_full_dimension(lib, ctx, n, seed):
+    from workloads.problems import Problem
+    rng = np.random.default_rng(seed)
+    while True:
+        A = rng.integers(-3, 4, size=(n, n)).astype(float) + (4 + n / 4) * np.eye(n)
+        if np.linalg.cond(A) < 100:
+            break
+    x_true = rng.integers(-3, 4, size=n).astype(float)
+    prob = Problem("sq", "dense", n, n, x_true, A @ x_true, 0.0, A=A)
+    G = gpu_solve(lib, ctx, prob, "fp64", n)
+    assert G["status"] == lib.LSLU_BREAKDOWN_U and G["k_done"] == n
+    assert rel(G["x"], x_true) <= 1e-11
+
+
+def test_maxiter_beyond_dimension_and_x0(lib, ctx):
+    prob = random_dense(24, 9, seed=8, nu=0.05)
+    rng = np.random.default_rng(9)
+    x0 = rng.standard_normal(9)
+    op = make_operator(prob)
+    R = hybrid_lslu(op, prob.b, 10, RegParam("none"), x0=x0)
+    G = gpu_solve(lib, ctx, prob, "fp64", 10, x0=x0)
+    assert G["status"] == R.status == Status.BREAKDOWN_Q
+    assert G["k_done"] == R.k_done == 9
+    assert rel(G["x"], R.x) <= 1e-10
+
+
+def test_early_stop_selects_k_stop(lib, ctx):
+    prob = config_problem("dense256")
+    op = make_operator(prob)
+    R = hybrid_lslu(op, prob.b, 30, _reg("wgcv", False), stop_tol=1e-2,
+                    early_stop=True)
+    G = gpu_solve(lib, ctx, prob, "fp64", 30, "wgcv", grid=lambda_grid(),
+                  early_stop=True, stop_tol=1e-2)
+    assert G["k_stop"] == R.k_stop
+    assert rel(G["x"], R.x) <= 1e-10
+
+
+def test_ragged_sizes_and_determinism(lib, ctx):
+    prob = tomography(13, 7, 19, 0.02, seed=12)
+    a = gpu_solve(lib, ctx, prob, "fp64", 12, "wgcv", grid=lambda_grid(),
+                  grid_relative=True)
+    b = gpu_solve(lib, ctx, prob, "fp64", 12, "wgcv", grid=lambda_grid(),
+                  grid_relative=True)
+    assert np.array_equal(a["X"], b["X"]) and np.array_equal(a["H"], b["H"])
+    assert np.array_equal(a["L"], b["L"]) and np.array_equal(a["D"], b["D"])
+    op = make_operator(prob)
+    R = hybrid_lslu(op, prob.b, 12, _reg("wgcv", True))
+    k_ok = well_separated_prefix(R, TAU["fp64"], 12)
+    for k in range(1, k_ok + 1):
+        assert rel(a["X"][:, k - 1], R.X[:, k - 1]) <= 1e-10
+
+
+def test_invalid_options_are_rejected(lib, ctx):
+    import torch
+    prob = random_dense(10, 8, seed=1)
+    op = lib.make_operator(ctx, prob, lib.LSLU_FP64)
+    b = torch.tensor(prob.b, device="cuda")
+    try:
+        for kw in (dict(maxiter=0), dict(maxiter=20),
+                   dict(maxiter=3, reg="wgcv"),
+                   dict(maxiter=3, reg="wgcv", grid=[1.0, 0.5]),
+                   dict(maxiter=3, reg="fixed", lam=-1.0)):
+            K = kw.pop("maxiter")
+            with pytest.raises(lib.LsluError) as ei:
+                lib.lslu_solve(ctx, op, b, K, **kw)
+            assert ei.value.status == lib.LSLU_EINVAL
+        with pytest.raises(lib.LsluError):
+            lib.lslu_op_dense(ctx, np.full((2, 2), np.nan))
+    finally:
+        lib.lslu_op_destroy(op)
