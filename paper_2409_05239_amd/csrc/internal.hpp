@@ -33,7 +33,6 @@ struct DevState {
   int mismatch_g;   // replay: own pivot choice differed (l side)
   int pad;
   double beta;      // r_0(t(1))
-  unsigned int ticket[4];  // arrival counters of the last-block reductions
 };
 
 // One candidate of the pivot search: |v| (key, -1 when ineligible) and row.
@@ -43,7 +42,7 @@ struct ArgPart {
   int pad;
 };
 
-// What the last block of a pivot search does with the winner.
+// How the pivot of one search is recorded.
 struct PivotJob {
   int side;              // 0: l side (W(k,k)), 1: d side (H(k+1,k)), 2: r_0 (beta)
   int k;                 // iteration (1-based); 0 for r_0
@@ -79,15 +78,15 @@ template <typename T>
 void launch_eliminate_argmax(const T* v0, T* out, const T* basis, int64_t ld,
                              int nb, const double* coef,
                              const unsigned char* mask, int64_t len,
-                             ArgPart* parts, const PivotJob& job, hipStream_t s);
+                             ArgPart* parts, const DevState* st, hipStream_t s);
 template <typename T>
-void launch_normalize(const T* v, T* dst, int64_t len, const PivotJob& job,
-                      double* Trow, int ldT, const T* basis, int64_t ld, int nb,
-                      hipStream_t s);
+void launch_pivot_normalize(const T* v, T* dst, int64_t len,
+                            const ArgPart* parts, const PivotJob& job, T* Tpack,
+                            const T* basis, int64_t ld, int nb, hipStream_t s);
 template <typename T>
-void launch_gather_trisolve(const T* v0, const int* piv, int nb,
-                            const double* Tm, int ldT, double* coef,
-                            const DevState* st, hipStream_t s);
+void launch_gather_trisolve(const T* v0, const int* piv, int nb, const T* Tp,
+                            double* coef, const DevState* st, size_t lds_bytes,
+                            hipStream_t s);
 
 // Operators (operators.hip).  `stop` may be nullptr.
 struct DeviceOp {

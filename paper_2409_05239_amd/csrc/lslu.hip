@@ -5,9 +5,9 @@
 //   for k = 1..K (Algorithm 5):
 //     q0 = A^T d_k                              (operator kernel)
 //     W(1:k-1,k) from q0(g(1:k-1))              (gather + triangular solve)
-//     q = q0 - L w, zero at pivots, argmax      (streaming pass, last block
-//                                                picks g(k) and W(k,k))
-//     l_k = q / W(k,k), new row of T_L          (normalise)
+//     q = q0 - L w, zero at pivots, argmax      (streaming pass, per-block
+//                                                candidates)
+//     g(k), W(k,k), l_k = q / W(k,k), T_L row   (pivot + normalise)
 //     u0 = A l_k, H(1:k,k), u, t(k+1), H(k+1,k), d_{k+1}   (same on the d side)
 //   projected problems for all k                (one workgroup per k)
 //   stopping rule, iterates X = x_0 + L Y, selected iterate -> x_out
@@ -30,7 +30,8 @@ namespace {
 struct Layout {
   void *L = nullptr, *D = nullptr, *q = nullptr, *u = nullptr, *r0 = nullptr,
        *X = nullptr;
-  double *TL = nullptr, *TD = nullptr, *grid = nullptr, *proj = nullptr;
+  void *TL = nullptr, *TD = nullptr;  // pivot-row triangles, basis precision
+  double *grid = nullptr, *proj = nullptr;
   int *rep_t = nullptr, *rep_g = nullptr, *rep_lam = nullptr;
   unsigned char *mask_t = nullptr, *mask_g = nullptr;
   ArgPart* parts = nullptr;
@@ -63,8 +64,8 @@ size_t carve(unsigned char* base, int64_t m, int64_t n, int K, size_t esz,
   l.u = take(esz * ldD);
   l.r0 = take(esz * ldD);
   l.X = take(esz * n * K);
-  l.TL = reinterpret_cast<double*>(take(sizeof(double) * K * K));
-  l.TD = reinterpret_cast<double*>(take(sizeof(double) * (K + 1) * (K + 1)));
+  l.TL = take(esz * K * (K + 1) / 2);        // packed rows, strict lower
+  l.TD = take(esz * (K + 1) * (K + 2) / 2);
   l.grid = reinterpret_cast<double*>(take(sizeof(double) * kMaxGrid));
   l.proj = reinterpret_cast<double*>(take(sizeof(double) * projected_scratch_doubles(K)));
   l.rep_t = reinterpret_cast<int*>(take(sizeof(int) * (K + 1)));
@@ -235,8 +236,10 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
   launch_fill<double>(l.H, 0.0, (int64_t)(K + 1) * K, s);
   launch_fill<double>(l.W, 0.0, (int64_t)K * K, s);
   launch_fill<double>(l.Y, 0.0, (int64_t)K * K, s);
-  launch_fill<double>(l.TL, 0.0, (int64_t)K * K, s);
-  launch_fill<double>(l.TD, 0.0, (int64_t)(K + 1) * (K + 1), s);
+  T* TL = static_cast<T*>(l.TL);
+  T* TD = static_cast<T*>(l.TD);
+  launch_fill<T>(TL, T(0), (int64_t)K * (K + 1) / 2, s);
+  launch_fill<T>(TD, T(0), (int64_t)(K + 1) * (K + 2) / 2, s);
 
   // r_0 = b - A x_0 (or b), its pivot, beta and d_1.
   const T* r0 = b;
@@ -257,14 +260,14 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
   j0.replay = replay_t ? l.rep_t : nullptr;
   j0.st = st;
   launch_eliminate_argmax<T>(r0, u, Db, ldD, 0, nullptr, l.mask_t, m, l.parts,
-                             j0, s);
-  launch_normalize<T>(u, Db, m, j0, l.TD, K + 1, Db, ldD, 0, s);
+                             st, s);
+  launch_pivot_normalize<T>(u, Db, m, l.parts, j0, TD, Db, ldD, 0, s);
 
   for (int k = 1; k <= K; ++k) {
     // l side: q0 = A^T d_k, W(1:k-1,k), q, g(k), W(k,k), l_k.
     op_apply(op, 1, Db + (int64_t)(k - 1) * ldD, q, stop, s);
     double* Wcol = l.W + (int64_t)(k - 1) * K;
-    launch_gather_trisolve<T>(q, l.piv_g, k - 1, l.TL, K, Wcol, st, s);
+    launch_gather_trisolve<T>(q, l.piv_g, k - 1, TL, Wcol, st, c->lds_max, s);
     PivotJob jg{};
     jg.side = 0;
     jg.k = k;
@@ -277,13 +280,13 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
     jg.replay = replay_g ? l.rep_g : nullptr;
     jg.st = st;
     launch_eliminate_argmax<T>(q, q, Lb, ldL, k - 1, Wcol, l.mask_g, n, l.parts,
-                               jg, s);
-    launch_normalize<T>(q, Lb + (int64_t)(k - 1) * ldL, n, jg, l.TL + (k - 1), K,
-                        Lb, ldL, k - 1, s);
+                               st, s);
+    launch_pivot_normalize<T>(q, Lb + (int64_t)(k - 1) * ldL, n, l.parts, jg,
+                              TL, Lb, ldL, k - 1, s);
     // d side: u0 = A l_k, H(1:k,k), u, t(k+1), H(k+1,k), d_{k+1}.
     op_apply(op, 0, Lb + (int64_t)(k - 1) * ldL, u, stop, s);
     double* Hcol = l.H + (int64_t)(k - 1) * (K + 1);
-    launch_gather_trisolve<T>(u, l.piv_t, k, l.TD, K + 1, Hcol, st, s);
+    launch_gather_trisolve<T>(u, l.piv_t, k, TD, Hcol, st, c->lds_max, s);
     PivotJob jt{};
     jt.side = 1;
     jt.k = k;
@@ -295,10 +298,10 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
     jt.mask = l.mask_t;
     jt.replay = replay_t ? l.rep_t : nullptr;
     jt.st = st;
-    launch_eliminate_argmax<T>(u, u, Db, ldD, k, Hcol, l.mask_t, m, l.parts, jt,
+    launch_eliminate_argmax<T>(u, u, Db, ldD, k, Hcol, l.mask_t, m, l.parts, st,
                                s);
-    launch_normalize<T>(u, Db + (int64_t)k * ldD, m, jt, l.TD + k, K + 1, Db,
-                        ldD, k, s);
+    launch_pivot_normalize<T>(u, Db + (int64_t)k * ldD, m, l.parts, jt, TD, Db,
+                              ldD, k, s);
   }
 
   ProjParams pp{};

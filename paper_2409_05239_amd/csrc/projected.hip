@@ -1,23 +1,27 @@
 // The projected problem of Hybrid LSLU, in FP64 on the device.
 //
-// For each iteration k (one workgroup per k, all k in one launch: the basis
-// does not depend on lambda, so these solves are independent of each other
-// and of the recurrence):
+// For every iteration k (one workgroup per k, all k in one launch: the basis
+// does not depend on lambda, so the K projected problems are independent of
+// each other and of the recurrence) this kernel computes lambda_k, y_k and
+// Ghat(k) for the (k+1) x k Hessenberg matrix H = H_{k+1,k} and beta.
 //
-//   * SVD of H_{k+1,k} = U Sigma V^T by one-sided Jacobi applied to the
-//     columns of M = H^T (k rows, k+1 columns): right rotations J make the
-//     columns of M J orthogonal, so J = U and the columns of M J are
-//     sigma_i v_i (one of them vanishes).  Only the first row of J is kept:
-//     c = U^T e_1 (Section 3.2.1, eq. gcv2).
-//   * lambda_k by the chosen rule on the grid: weighted GCV with omega =
-//     (k+1)/m, GCV (omega = 1), a fixed value or none (Section 3.2.1);
-//   * y_k = beta sum_i sigma_i c_i / (sigma_i^2 + lambda^2) v_i (eq. TSP
-//     solved through the SVD, Section 3.2.1 eq. 4);
-//   * Ghat(k) (eq. stop2).
-//
-// Jacobi pairs follow a round-robin tournament; each wavefront rotates one
-// disjoint pair at a time.  Everything is in a fixed order, so results do not
-// depend on timing.
+//  1. Householder bidiagonalisation H = P [B; 0] Q^T with B upper bidiagonal
+//     (diagonal d, superdiagonal e), g = P^T beta e_1 (k+1 entries).  The
+//     right reflectors are kept for the back-transformation y = Q z.
+//  2. The parameter rules use the residual/trace forms that define them
+//     (Section 3.2.1, eq. gcv1 and eq. wgcv_projected1; eq. stop1 for Ghat):
+//        ||(I - H H_lam^+) beta e_1||^2 = ||g_1:k - B z_lam||^2 + g_{k+1}^2
+//        trace(H H_lam^+)               = k - lam^2 trace((B^T B + lam^2 I)^-1)
+//     with z_lam = argmin ||g_1:k - B z||^2 + lam^2 ||z||^2 computed by Elden's
+//     O(k) Givens elimination of [B; lam I] into an upper bidiagonal R, and
+//     trace((B^T B + lam^2 I)^-1) = ||R^-1||_F^2 from a recurrence of positive
+//     terms.  One thread per grid value of lambda.
+//  3. sigma_1 (for the relative grid and reports) and sigma_min by parallel
+//     multisection of Sturm counts of B^T B.
+//  4. y_k = Q z_{lambda_k}.
+// In exact arithmetic these equal the SVD expressions of Section 3.2.1
+// (eq. gcv2, the SVD form of weighted GCV, eq. stop2 and the filtered SVD
+// solution for y).
 #include <cfloat>
 #include <climits>
 
@@ -27,13 +31,16 @@ namespace lslu {
 
 namespace {
 
-constexpr int kProjThreads = 256;
-constexpr int kProjWaves = kProjThreads / kWave;
-constexpr int kMaxSweeps = 40;
+constexpr int kPT = 256;            // threads per projected problem
+constexpr int kSectRounds1 = 8;     // multisection rounds for sigma_1
+constexpr int kSectRoundsMin = 8;   // multisection rounds for sigma_min
+constexpr size_t kStaticLds = 24 * 1024;  // bound on the static LDS below
 
-// Doubles of working storage per projected problem (sized for k = K).
-__host__ __device__ inline size_t proj_per_k(int K) {
-  return (size_t)K * (K + 1) + 2 * (size_t)(K + 1) + 2 * kMaxGrid + K;
+// Working matrix A ((k+1) x k, leading dimension k+1).
+__host__ __device__ inline size_t proj_a_doubles(int k) { return (size_t)(k + 1) * k; }
+// Global scratch per problem: A (when not in LDS) and 3 vectors per lambda.
+__host__ __device__ inline size_t proj_scratch_per_k(int K) {
+  return proj_a_doubles(K) + (size_t)3 * K * kMaxGrid;
 }
 
 __device__ inline double wave_sum_d(double v) {
@@ -42,152 +49,310 @@ __device__ inline double wave_sum_d(double v) {
   return v;
 }
 
-// Round-robin (circle method) pairing of Np (even) players, round r.
-__device__ inline void rr_pair(int Np, int r, int i, int& a, int& b) {
-  auto pos = [&](int x) { return x == 0 ? 0 : ((x - 1 + r) % (Np - 1)) + 1; };
-  a = pos(i);
-  b = pos(Np - 1 - i);
+// sum_i u[i] * x[i*stride], i < len, with four independent partial sums so the
+// loads of consecutive terms overlap.
+__device__ inline double dot_unrolled(const double* u, const double* x, int len,
+                                      int stride) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int i = 0;
+  for (; i + 4 <= len; i += 4) {
+    const double x0 = x[(size_t)i * stride], x1 = x[(size_t)(i + 1) * stride];
+    const double x2 = x[(size_t)(i + 2) * stride], x3 = x[(size_t)(i + 3) * stride];
+    s0 = fma(u[i], x0, s0);
+    s1 = fma(u[i + 1], x1, s1);
+    s2 = fma(u[i + 2], x2, s2);
+    s3 = fma(u[i + 3], x3, s3);
+  }
+  for (; i < len; ++i) s0 = fma(u[i], x[(size_t)i * stride], s0);
+  return (s0 + s1) + (s2 + s3);
 }
 
-__global__ __launch_bounds__(kProjThreads) void k_projected(
-    const double* __restrict__ H, const DevState* __restrict__ st,
-    ProjParams p, double* __restrict__ Y, double* __restrict__ lam_out,
-    int* __restrict__ lam_idx_out, double* __restrict__ ghat_out,
-    double* __restrict__ sep_out, double* __restrict__ smax_out,
-    double* __restrict__ smin_out, double* __restrict__ scratch, int use_lds) {
-  extern __shared__ double lds[];
-  const int k = blockIdx.x + 1;
-  if (k > st->k_done) return;
-  const double beta = st->beta;
-  const int K = p.K;
-  const int N = k + 1;        // columns of M
-  const int Np = N + (N & 1); // padded to even
-  double* base = use_lds ? lds : scratch + (size_t)(k - 1) * proj_per_k(K);
-  double* M = base;                 // k x N, column c = row c of H
-  double* f = M + (size_t)k * N;    // first row of J (length N)
-  double* nrm = f + N;              // column norms (length N)
-  double* gv = nrm + N;             // grid values of the rule (kMaxGrid)
-  double* glam = gv + kMaxGrid;     // grid lambdas (kMaxGrid)
-  double* ybuf = glam + kMaxGrid;   // y (length k)
-  __shared__ int s_rot;
-  __shared__ int s_order[kMaxIter + 2];
-  __shared__ double s_lam;
-  __shared__ int s_lidx;
-  __shared__ double s_sep;
-
-  const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1);
-  const int wv = tid / kWave;
-  for (int e = tid; e < k * N; e += kProjThreads) {
-    const int c = e / k, r = e - c * k;  // M(r, c) = H(c, r)
-    M[e] = H[(size_t)r * (K + 1) + c];
+// Number of eigenvalues of the tridiagonal T = B^T B (diagonal a,
+// off-diagonal b) below x, from the signs of its LDL^T pivots.
+__device__ inline int sturm_count(const double* a, const double* b, int k,
+                                  double x, double pivmin) {
+  double q = a[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int cnt = q < 0.0;
+  for (int i = 1; i < k; ++i) {
+    q = (a[i] - x) - (b[i - 1] * b[i - 1]) / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
   }
-  for (int c = tid; c < N; c += kProjThreads) f[c] = (c == 0) ? 1.0 : 0.0;
+  return cnt;
+}
+
+// Elden: Givens rotations reduce [B; lam I] with right-hand side [g; 0] to an
+// upper bidiagonal R (diagonal rho, superdiagonal f) with right-hand side q.
+// Each step eliminates the damping entry against row i of B, then merges the
+// fill it leaves in column i+1 into the next damping row.  Returns
+// trace((B^T B + lam^2 I)^-1) = ||R^-1||_F^2 (0 when lam == 0).
+__device__ inline double elden_forward(const double* d, const double* e,
+                                       const double* g, int k, double lam,
+                                       double* rho, double* f, double* q) {
+  double mu = lam, h = 0.0, S = 1.0, tr = 0.0, fprev = 0.0, rprev = 1.0;
+  for (int i = 0; i < k; ++i) {
+    const double di = d[i];
+    const double ei = (i + 1 < k) ? e[i] : 0.0;
+    double c = 1.0, s = 0.0, r = di;
+    if (mu != 0.0) {
+      r = sqrt(di * di + mu * mu);
+      c = di / r;
+      s = mu / r;
+    }
+    const double fi = c * ei;
+    rho[i] = r;
+    f[i] = fi;
+    q[i] = c * g[i] + s * h;
+    const double hp = c * h - s * g[i];
+    if (lam != 0.0) {
+      if (i > 0) {
+        const double a = fprev / rprev;
+        S = 1.0 + a * a * S;
+      }
+      tr += S / (r * r);
+    }
+    fprev = fi;
+    rprev = r;
+    if (i + 1 < k) {
+      const double fill = -s * ei;
+      const double mup = sqrt(lam * lam + fill * fill);
+      if (mup != 0.0) {
+        h = (fill / mup) * hp;
+        mu = mup;
+      } else {
+        h = 0.0;
+        mu = 0.0;
+      }
+    }
+  }
+  return tr;
+}
+
+// Back substitution R z = q; returns ||g - B z||^2 (z stored when non-null).
+__device__ inline double elden_backward(const double* d, const double* e,
+                                        const double* g, int k,
+                                        const double* rho, const double* f,
+                                        const double* q, double* z) {
+  double znext = 0.0, mis = 0.0;
+  for (int i = k - 1; i >= 0; --i) {
+    double zi, ri;
+    if (i + 1 < k) {
+      zi = (q[i] - f[i] * znext) / rho[i];
+      ri = g[i] - d[i] * zi - e[i] * znext;
+    } else {
+      zi = q[i] / rho[i];
+      ri = g[i] - d[i] * zi;
+    }
+    mis += ri * ri;
+    if (z) z[i] = zi;
+    znext = zi;
+  }
+  return mis;
+}
+
+__global__ __launch_bounds__(kPT) void k_projected(
+    const double* __restrict__ H, const DevState* __restrict__ st,
+    ProjParams p, int k_first, int a_in_lds, double* __restrict__ Y,
+    double* __restrict__ lam_out, int* __restrict__ lam_idx_out,
+    double* __restrict__ ghat_out, double* __restrict__ sep_out,
+    double* __restrict__ smax_out, double* __restrict__ smin_out,
+    double* __restrict__ scratch) {
+  extern __shared__ double lds_a[];
+  __shared__ double g[kMaxIter + 1], vb[kMaxIter + 1], taur[kMaxIter];
+  __shared__ double d[kMaxIter], e[kMaxIter], ta[kMaxIter], tb[kMaxIter];
+  __shared__ double zy[kMaxIter], gv[kMaxGrid];
+  __shared__ int s_cnt[kPT];
+  __shared__ double s_tau, s_lo, s_hi, s_sig1, s_lam, s_sep;
+  __shared__ int s_lidx;
+
+  const int k = k_first + blockIdx.x;
+  if (k > st->k_done) return;
+  const int K = p.K;
+  const double beta = st->beta;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const int lda = k + 1;
+  double* blk = scratch + (size_t)(k - 1) * proj_scratch_per_k(K);
+  double* A = a_in_lds ? lds_a : blk;
+  double* lamscr = blk + proj_a_doubles(K);  // 3*K doubles per grid value
+
+  // 1. Load H (column-major, leading dimension K+1) into A; g = beta e_1.
+  for (int idx = tid; idx < (k + 1) * k; idx += kPT) {
+    const int c = idx / (k + 1), r = idx - c * (k + 1);
+    A[(size_t)c * lda + r] = H[(size_t)c * (K + 1) + r];
+  }
+  for (int r = tid; r <= k; r += kPT) g[r] = (r == 0) ? beta : 0.0;
   __syncthreads();
 
-  const double tol = DBL_EPSILON * sqrt((double)k);
-  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
-    if (tid == 0) s_rot = 0;
+  // 2. Householder bidiagonalisation (upper bidiagonal B).
+  for (int j = 0; j < k; ++j) {
+    // Left reflector annihilating A(j+1:k, j).
+    if (wv == 0) {
+      double s2 = 0.0;
+      for (int r = j + 1 + lane; r <= k; r += kWave) {
+        const double x = A[(size_t)j * lda + r];
+        s2 = fma(x, x, s2);
+      }
+      s2 = wave_sum_d(s2);
+      const double alpha = A[(size_t)j * lda + j];
+      double tau = 0.0, bet = alpha, scal = 0.0;
+      if (s2 != 0.0) {
+        bet = -copysign(sqrt(alpha * alpha + s2), alpha);
+        tau = (bet - alpha) / bet;
+        scal = 1.0 / (alpha - bet);
+      }
+      for (int r = j + 1 + lane; r <= k; r += kWave)
+        vb[r - j] = A[(size_t)j * lda + r] * scal;
+      if (lane == 0) {
+        vb[0] = 1.0;
+        s_tau = tau;
+        A[(size_t)j * lda + j] = bet;
+      }
+    }
     __syncthreads();
-    for (int r = 0; r < Np - 1; ++r) {
-      for (int pi = wv; pi < Np / 2; pi += kProjWaves) {
-        int a, b;
-        rr_pair(Np, r, pi, a, b);
-        if (a >= N || b >= N) continue;
-        double* ca = M + (size_t)a * k;
-        double* cb = M + (size_t)b * k;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = lane; i < k; i += kWave) {
-          const double x = ca[i], y = cb[i];
-          al = fma(x, x, al);
-          be = fma(y, y, be);
-          ga = fma(x, y, ga);
+    {
+      const double tau = s_tau;
+      const int ncol = k - 1 - j;  // columns j+1..k-1, then g
+      if (tau != 0.0) {
+        for (int t = tid; t <= ncol; t += kPT) {
+          double* col = (t < ncol) ? A + (size_t)(j + 1 + t) * lda : g;
+          const double w = tau * dot_unrolled(vb, col + j, k + 1 - j, 1);
+#pragma unroll 8
+          for (int r = j; r <= k; ++r) col[r] = fma(-w, vb[r - j], col[r]);
         }
-        al = wave_sum_d(al);
-        be = wave_sum_d(be);
-        ga = wave_sum_d(ga);
-        if (ga == 0.0 || al == 0.0 || be == 0.0) continue;
-        if (fabs(ga) <= tol * sqrt(al) * sqrt(be)) continue;
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + t * t);
-        const double sn = cs * t;
-        for (int i = lane; i < k; i += kWave) {
-          const double x = ca[i], y = cb[i];
-          ca[i] = cs * x - sn * y;
-          cb[i] = sn * x + cs * y;
+      }
+    }
+    __syncthreads();
+    if (j + 2 >= k) continue;  // at most one entry right of the diagonal
+    // Right reflector annihilating A(j, j+2:k-1).
+    if (wv == 0) {
+      double s2 = 0.0;
+      for (int c = j + 2 + lane; c < k; c += kWave) {
+        const double x = A[(size_t)c * lda + j];
+        s2 = fma(x, x, s2);
+      }
+      s2 = wave_sum_d(s2);
+      const double alpha = A[(size_t)(j + 1) * lda + j];
+      double tau = 0.0, bet = alpha, scal = 0.0;
+      if (s2 != 0.0) {
+        bet = -copysign(sqrt(alpha * alpha + s2), alpha);
+        tau = (bet - alpha) / bet;
+        scal = 1.0 / (alpha - bet);
+      }
+      for (int c = j + 2 + lane; c < k; c += kWave) {
+        const double v = A[(size_t)c * lda + j] * scal;
+        vb[c - j - 1] = v;
+        A[(size_t)c * lda + j] = v;  // kept for y = Q z
+      }
+      if (lane == 0) {
+        vb[0] = 1.0;
+        s_tau = tau;
+        taur[j] = tau;
+        A[(size_t)(j + 1) * lda + j] = bet;
+      }
+    }
+    __syncthreads();
+    {
+      const double tau = s_tau;
+      const int nrow = k - j;  // rows j+1..k
+      if (tau != 0.0) {
+        for (int t = tid; t < nrow; t += kPT) {
+          const int r = j + 1 + t;
+          double* row = A + (size_t)(j + 1) * lda + r;  // A(r, j+1), stride lda
+          const double w = tau * dot_unrolled(vb, row, k - 1 - j, lda);
+#pragma unroll 8
+          for (int c = 0; c < k - 1 - j; ++c)
+            row[(size_t)c * lda] = fma(-w, vb[c], row[(size_t)c * lda]);
         }
-        if (lane == 0) {
-          const double x = f[a], y = f[b];
-          f[a] = cs * x - sn * y;
-          f[b] = sn * x + cs * y;
-          s_rot = 1;
-        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < k; i += kPT) {
+    d[i] = A[(size_t)i * lda + i];
+    e[i] = (i + 1 < k) ? A[(size_t)(i + 1) * lda + i] : 0.0;
+  }
+  __syncthreads();
+  for (int i = tid; i < k; i += kPT) {  // T = B^T B
+    ta[i] = d[i] * d[i] + (i > 0 ? e[i - 1] * e[i - 1] : 0.0);
+    tb[i] = (i + 1 < k) ? d[i] * e[i] : 0.0;
+  }
+  __syncthreads();
+  const double gk1 = g[k];  // = +-beta c_{k+1}
+
+  // 3. sigma_1^2 and sigma_min^2 by multisection of the eigenvalue count.
+  double pivmin = DBL_MIN, gers = 0.0;
+  for (int i = 0; i < k; ++i) {
+    const double bl = i > 0 ? fabs(tb[i - 1]) : 0.0, br = fabs(tb[i]);
+    gers = fmax(gers, ta[i] + bl + br);
+    pivmin = fmax(pivmin, DBL_MIN * tb[i] * tb[i]);
+  }
+  for (int which = 0; which < 2; ++which) {
+    // which 0: first x with count k (largest); which 1: first x with count 1.
+    if (tid == 0) {
+      s_lo = 0.0;
+      s_hi = gers * (1.0 + 4.0 * DBL_EPSILON) + pivmin;
+    }
+    __syncthreads();
+    const int target = which == 0 ? k : 1;
+    const int rounds = which == 0 ? kSectRounds1 : kSectRoundsMin;
+    for (int rd = 0; rd < rounds; ++rd) {
+      const double lo = s_lo, hi = s_hi;
+      const double step = (hi - lo) / (double)(kPT + 1);
+      s_cnt[tid] = sturm_count(ta, tb, k, lo + step * (tid + 1), pivmin);
+      __syncthreads();
+      if (tid == 0) {
+        int t = 0;
+        while (t < kPT && s_cnt[t] < target) ++t;
+        s_lo = (t == 0) ? lo : lo + step * t;
+        s_hi = (t == kPT) ? hi : lo + step * (t + 1);
       }
       __syncthreads();
     }
-    const int rot = s_rot;
-    __syncthreads();
-    if (!rot) break;
-  }
-
-  // Column norms, then order the columns by decreasing norm (ties: column).
-  for (int c = wv; c < N; c += kProjWaves) {
-    const double* cc = M + (size_t)c * k;
-    double s = 0.0;
-    for (int i = lane; i < k; i += kWave) s = fma(cc[i], cc[i], s);
-    s = wave_sum_d(s);
-    if (lane == 0) nrm[c] = sqrt(s);
-  }
-  __syncthreads();
-  for (int c = tid; c < N; c += kProjThreads) {
-    int rank = 0;
-    const double v = nrm[c];
-    for (int c2 = 0; c2 < N; ++c2) {
-      const double v2 = nrm[c2];
-      rank += (v2 > v) || (v2 == v && c2 < c);
+    if (tid == 0) {
+      const double val = sqrt(0.5 * (s_lo + s_hi));
+      if (which == 0) {
+        smax_out[k - 1] = val;
+        s_sig1 = val;
+      } else {
+        smin_out[k - 1] = val;
+      }
     }
-    s_order[rank] = c;
+    __syncthreads();
   }
-  __syncthreads();
-  const double sig1 = nrm[s_order[0]];
-  const double cnull = f[s_order[k]];  // c_{k+1}
+  const double sig1 = s_sig1;
 
-  // Parameter choice on the grid.
+  // 4. Parameter choice on the grid: one thread per grid value.
   const int reg = p.reg;
   if (reg == kWGCV || reg == kGCV) {
     const double omega =
         (reg == kGCV) ? 1.0 : (p.omega > 0.0 ? p.omega : (double)(k + 1) / p.m);
-    for (int g = tid; g < p.n_grid; g += kProjThreads) {
-      const double lam = p.grid_relative ? p.grid[g] * sig1 : p.grid[g];
-      const double l2 = lam * lam;
-      double num = 0.0, den = 0.0;
-      for (int i = 0; i < k; ++i) {
-        const int c = s_order[i];
-        const double s2 = nrm[c] * nrm[c];
-        const double fi = l2 / (s2 + l2);
-        const double t = fi * f[c];
-        num += t * t;
-        den += ((1.0 - omega) * s2 + l2) / (s2 + l2);
-      }
-      num = (double)k * beta * beta * (num + cnull * cnull);
-      den = 1.0 + den;
-      gv[g] = num / (den * den);
-      glam[g] = lam;
+    for (int gi = tid; gi < p.n_grid; gi += kPT) {
+      const double lam = p.grid_relative ? p.grid[gi] * sig1 : p.grid[gi];
+      double* rho = lamscr + (size_t)gi * 3 * K;
+      double* ff = rho + K;
+      double* qq = ff + K;
+      const double tr = elden_forward(d, e, g, k, lam, rho, ff, qq);
+      const double mis = elden_backward(d, e, g, k, rho, ff, qq, nullptr);
+      const double num = (double)k * (mis + gk1 * gk1);
+      // trace(I - omega H H_lam^+) = (k+1) - omega (k - lam^2 tr)
+      const double den = (double)(k + 1) - omega * ((double)k - lam * lam * tr);
+      gv[gi] = num / (den * den);
     }
     __syncthreads();
     if (tid == 0) {
       int bi = 0;
-      for (int g = 1; g < p.n_grid; ++g)
-        if (gv[g] < gv[bi]) bi = g;
+      for (int gi = 1; gi < p.n_grid; ++gi)
+        if (gv[gi] < gv[bi]) bi = gi;
       double g2 = INFINITY;
-      for (int g = 0; g < p.n_grid; ++g)
-        if (g != bi && gv[g] < g2) g2 = gv[g];
+      for (int gi = 0; gi < p.n_grid; ++gi)
+        if (gi != bi && gv[gi] < g2) g2 = gv[gi];
       double sep = INFINITY;
-      if (p.n_grid > 1) sep = gv[bi] > 0.0 ? (g2 - gv[bi]) / gv[bi] : (g2 > 0.0 ? INFINITY : 0.0);
+      if (p.n_grid > 1)
+        sep = gv[bi] > 0.0 ? (g2 - gv[bi]) / gv[bi] : (g2 > 0.0 ? INFINITY : 0.0);
       int use = bi;
       if (p.replay_lambda && p.replay_lambda[k - 1] >= 0) use = p.replay_lambda[k - 1];
-      s_lam = glam[use];
+      s_lam = p.grid_relative ? p.grid[use] * sig1 : p.grid[use];
       s_lidx = use;
       s_sep = sep;
     }
@@ -197,57 +362,75 @@ __global__ __launch_bounds__(kProjThreads) void k_projected(
     s_sep = INFINITY;
   }
   __syncthreads();
-  const double lam = s_lam;
-  const double l2 = lam * lam;
 
-  // y_k = beta * sum_i c_i/(sigma_i^2 + lambda^2) * (sigma_i v_i).
-  for (int r = tid; r < k; r += kProjThreads) {
-    double acc = 0.0;
-    for (int i = 0; i < k; ++i) {
-      const int c = s_order[i];
-      const double s2 = nrm[c] * nrm[c];
-      const double den = s2 + l2;
-      if (den > 0.0) acc += (f[c] / den) * M[(size_t)c * k + r];
-    }
-    ybuf[r] = beta * acc;
-  }
-  __syncthreads();
-  for (int r = tid; r < K; r += kProjThreads)
-    Y[(size_t)(k - 1) * K + r] = (r < k) ? ybuf[r] : 0.0;
+  // 5. z for lambda_k and Ghat(k) (thread 0), then y = Q z (wavefront 0).
   if (tid == 0) {
-    double num = 0.0, den = 0.0;
-    for (int i = 0; i < k; ++i) {
-      const int c = s_order[i];
-      const double s2 = nrm[c] * nrm[c];
-      const double fi = (s2 + l2 > 0.0) ? l2 / (s2 + l2) : 0.0;
-      num += (fi * f[c]) * (fi * f[c]);
-      den += fi;
-    }
-    num = (double)p.n * beta * beta * (num + cnull * cnull);
-    den = (double)(p.m - k) + den;
+    const double lam = s_lam;
+    double* rho = lamscr;  // grid slot 0 is free again
+    double* ff = rho + K;
+    double* qq = ff + K;
+    const double tr = elden_forward(d, e, g, k, lam, rho, ff, qq);
+    const double mis = elden_backward(d, e, g, k, rho, ff, qq, zy);
+    const double num = (double)p.n * (mis + gk1 * gk1);
+    const double den = (double)(p.m - k) + lam * lam * tr;
     ghat_out[k - 1] = (den == 0.0) ? NAN : num / (den * den);
     lam_out[k - 1] = lam;
     lam_idx_out[k - 1] = s_lidx;
     sep_out[k - 1] = s_sep;
-    smax_out[k - 1] = sig1;
-    smin_out[k - 1] = nrm[s_order[k - 1]];
   }
+  __syncthreads();
+  if (wv == 0) {
+    for (int j = k - 3; j >= 0; --j) {
+      const double tau = taur[j];
+      if (tau == 0.0) continue;
+      // reflector vector u = [1 at j+1; A(j, j+2:k-1)]
+      double w = 0.0;
+      for (int c = j + 1 + lane; c < k; c += kWave) {
+        const double u = (c == j + 1) ? 1.0 : A[(size_t)c * lda + j];
+        w = fma(u, zy[c], w);
+      }
+      w = wave_sum_d(w) * tau;
+      for (int c = j + 1 + lane; c < k; c += kWave) {
+        const double u = (c == j + 1) ? 1.0 : A[(size_t)c * lda + j];
+        zy[c] = fma(-w, u, zy[c]);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+  for (int r = tid; r < K; r += kPT)
+    Y[(size_t)(k - 1) * K + r] = (r < k) ? zy[r] : 0.0;
 }
 
 }  // namespace
 
-// Per-k scratch when the working set does not fit in LDS: k*(k+1) + 2(k+1)
-// + 2*kMaxGrid + k doubles, bounded by the K case, times K problems.
-size_t projected_scratch_doubles(int K) { return proj_per_k(K) * (size_t)K; }
+size_t projected_scratch_doubles(int K) { return proj_scratch_per_k(K) * (size_t)K; }
 
 void launch_projected(const double* H, const DevState* st, double,
                       const ProjParams& p, double* Y, double* lam, int* lam_idx,
                       double* ghat, double* sep, double* smax, double* smin,
                       double* scratch, size_t lds_bytes, hipStream_t s) {
-  const size_t per = proj_per_k(p.K) * sizeof(double);
-  const int use_lds = (lds_bytes > 0 && per <= lds_bytes) ? 1 : 0;
-  k_projected<<<p.K, kProjThreads, use_lds ? per : 0, s>>>(
-      H, st, p, Y, lam, lam_idx, ghat, sep, smax, smin, scratch, use_lds);
+  // Problems whose working matrix fits in LDS keep it there; the others use
+  // their slice of global scratch.
+  int k_lds = 0;
+  while (k_lds < p.K &&
+         proj_a_doubles(k_lds + 1) * sizeof(double) + kStaticLds <= lds_bytes)
+    ++k_lds;
+  if (k_lds > 0) {
+    const size_t dyn = proj_a_doubles(k_lds) * sizeof(double);
+    if (dyn > 64 * 1024)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_projected),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)dyn);
+    k_projected<<<k_lds, kPT, dyn, s>>>(H, st, p, 1, 1, Y, lam, lam_idx, ghat,
+                                        sep, smax, smin, scratch);
+  }
+  if (k_lds < p.K) {
+    k_projected<<<p.K - k_lds, kPT, 0, s>>>(H, st, p, k_lds + 1, 0, Y, lam,
+                                            lam_idx, ghat, sep, smax, smin,
+                                            scratch);
+  }
 }
 
 }  // namespace lslu

@@ -112,3 +112,23 @@ def check_basis_invariants(info, m, n):
     kd = info["k_done"]
     H = info["H"]
     assert np.all(np.tril(H[:kd + 1, :kd], -2) == 0)
+
+
+def check_relations(info, op, prec):
+    """A L_k = D_{k+1} H_{k+1,k} and A^T D_k = L_k W_k (eq. nhr, eq. nhr2) for
+    the bases and coefficients the GPU produced, to rounding of the working
+    precision."""
+    u = 2.0 ** -53 if prec == "fp64" else 2.0 ** -24
+    k = min(info["n_l"], info["n_d"] - 1)
+    if k < 1:
+        return
+    L, D = info["L"][:, :k], info["D"][:, :k + 1]
+    H, W = info["H"][:k + 1, :k], info["W"][:k, :k]
+    AL = np.stack([op.matvec(L[:, j]) for j in range(k)], axis=1)
+    ATD = np.stack([op.rmatvec(D[:, j]) for j in range(k)], axis=1)
+    r1 = np.linalg.norm(AL - D @ H)
+    s1 = np.linalg.norm(AL) + np.linalg.norm(D) * np.linalg.norm(H)
+    r2 = np.linalg.norm(ATD - L @ W)
+    s2 = np.linalg.norm(ATD) + np.linalg.norm(L) * np.linalg.norm(W)
+    assert r1 <= 10 * k * u * s1, (r1 / s1, k)
+    assert r2 <= 10 * k * u * s2, (r2 / s2, k)

@@ -13,8 +13,9 @@ Tolerances on ||x_k - x_oracle||/||x_oracle|| and on the relative residual gap:
 import numpy as np
 import pytest
 
-from gpu_helpers import (TAU, TOL, check_basis_invariants, gpu_solve, rel,
-                         replay_from, residual_gap, well_separated_prefix)
+from gpu_helpers import (TAU, TOL, check_basis_invariants, check_relations,
+                         gpu_solve, rel, replay_from, residual_gap,
+                         well_separated_prefix)
 from oracle import RegParam, make_operator
 from oracle.hessenberg import Status, hybrid_lslu
 from workloads import (config_problem, lambda_grid, psf_deblur, random_dense,
@@ -70,12 +71,16 @@ def _compare(lib, ctx, prob, prec, K, kind, relative, lam=0.05, replay=True,
         print(f"[{prob.name} {prec} {kind}] max x err "
               f"{max(w[1] for w in worst):.3e} max residual gap "
               f"{max(w[2] for w in worst):.3e}")
-        # H and W follow from the same pivots; compare where formed.
+        # The GPU's own H, W, L, D satisfy the Hessenberg relations to the
+        # rounding of its working precision; in FP64 H and W also match the
+        # oracle's entry by entry.
+        check_relations(G, op, prec)
         kd = G["k_done"]
-        Hs = np.abs(R.H[:kd + 1, :kd]).max()
-        Ws = np.abs(R.W[:kd, :kd]).max()
-        assert np.abs(G["H"][:kd + 1, :kd] - R.H[:kd + 1, :kd]).max() <= tol * 10 * Hs
-        assert np.abs(G["W"][:kd, :kd] - R.W[:kd, :kd]).max() <= tol * 10 * Ws
+        if prec == "fp64":
+            Hs = np.abs(R.H[:kd + 1, :kd]).max()
+            Ws = np.abs(R.W[:kd, :kd]).max()
+            assert np.abs(G["H"][:kd + 1, :kd] - R.H[:kd + 1, :kd]).max() <= tol * 10 * Hs
+            assert np.abs(G["W"][:kd, :kd] - R.W[:kd, :kd]).max() <= tol * 10 * Ws
         return R, G
     return R, None
 
