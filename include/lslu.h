@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LSLU_ABI_VERSION 1
+#define LSLU_ABI_VERSION 2
 
 typedef enum lslu_status {
   LSLU_OK = 0,
@@ -166,7 +166,15 @@ typedef struct lslu_opts {
   const int32_t* replay_piv_t;
   const int32_t* replay_piv_g;
   const int32_t* replay_lambda_idx;
+  int32_t flags;              /* bitwise OR of lslu_flag values; 0 = default */
 } lslu_opts;
+
+/* lslu_opts.flags */
+typedef enum lslu_flag {
+  /* Enqueue every kernel directly instead of replaying the context's cached
+   * HIP graph of the solve.  Results are identical either way. */
+  LSLU_FLAG_EAGER = 1
+} lslu_flag;
 
 typedef struct lslu_result {
   int32_t status;     /* as returned */
@@ -192,6 +200,11 @@ typedef struct lslu_result {
 } lslu_result;
 
 /* Run Hybrid LSLU (LSLU with LSLU_REG_NONE) for opts->maxiter iterations.
+ * The device work of a solve is captured once into a HIP graph owned by the
+ * context and replayed by later calls with the same operator, sizes, device
+ * pointers and options (the lambda grid and replay arrays are re-uploaded
+ * when they change); any other change re-captures it.  The graph holds no
+ * memset nodes.
  * b_dev: device, wp, m entries.  x0_dev: device, wp, n entries, or NULL for
  * x_0 = 0.  x_out_dev: device, wp, n entries: the final iterate x_{k_done}
  * (x_{k_stop} with early_stop; x_0 after a breakdown before x_1).  The call

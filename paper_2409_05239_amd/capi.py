@@ -61,7 +61,11 @@ class lslu_opts(ctypes.Structure):
         ("replay_piv_t", POINTER(c_int32)),
         ("replay_piv_g", POINTER(c_int32)),
         ("replay_lambda_idx", POINTER(c_int32)),
+        ("flags", c_int32),
     ]
+
+
+LSLU_FLAG_EAGER = 1
 
 
 class lslu_result(ctypes.Structure):
@@ -246,7 +250,8 @@ def make_operator(ctx, problem, precision=LSLU_FP64):
 def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
                grid_relative=False, omega=0.0, x0=None, x_true=None,
                stop_tol=0.0, early_stop=False, X=None, x_out=None,
-               replay_piv_t=None, replay_piv_g=None, replay_lambda_idx=None):
+               replay_piv_t=None, replay_piv_g=None, replay_lambda_idx=None,
+               eager=False):
     """Run the solver.  ``b``, ``x0``, ``X``, ``x_out`` are torch device
     tensors in the working precision (``x_out`` is allocated when None).
     Returns ``(status, x_out, info)`` where ``info`` holds the host-side
@@ -272,6 +277,7 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
     o.stop_tol = float(stop_tol)
     o.early_stop = 1 if early_stop else 0
     o.X_dev = _dptr(X)
+    o.flags = LSLU_FLAG_EAGER if eager else 0
     for name, arr in (("replay_piv_t", replay_piv_t), ("replay_piv_g", replay_piv_g),
                       ("replay_lambda_idx", replay_lambda_idx)):
         if arr is not None:

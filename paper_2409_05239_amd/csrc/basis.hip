@@ -374,18 +374,20 @@ void launch_gather_trisolve(const T* v0, const int* piv, int nb, const T* Tp,
                             double* coef, const DevState* st, size_t lds_bytes,
                             hipStream_t s) {
   if (nb <= 0) return;
-  static bool attr_set = false;
-  if (!attr_set && lds_bytes > 8 * 1024) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_gather_trisolve<T, true>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              static_cast<int>(lds_bytes - 8 * 1024));
-    attr_set = true;
-  }
   const size_t need = sizeof(T) * (size_t)nb * (nb - 1) / 2;
   if (need + 8 * 1024 <= lds_bytes)
     k_gather_trisolve<T, true><<<1, kTriThreads, need, s>>>(v0, piv, nb, Tp, coef, st);
   else
     k_gather_trisolve<T, false><<<1, kTriThreads, 0, s>>>(v0, piv, nb, Tp, coef, st);
+}
+
+void basis_init_attributes(size_t lds_bytes) {
+  if (lds_bytes <= 8 * 1024) return;
+  const int dyn = static_cast<int>(lds_bytes - 8 * 1024);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_gather_trisolve<double, true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_gather_trisolve<float, true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
 }
 
 #define LSLU_INST(T)                                                          \

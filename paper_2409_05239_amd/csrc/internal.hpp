@@ -133,6 +133,11 @@ void launch_projected(const double* H, const DevState* st, double beta_unused,
                       hipStream_t s);
 size_t projected_scratch_doubles(int K);
 
+// One-time kernel attributes (dynamic LDS limits), set at context creation so
+// that no attribute call happens while a solve is being captured.
+void basis_init_attributes(size_t lds_bytes);
+void projected_init_attributes(size_t lds_bytes);
+
 // Iterate assembly (assemble.hip).
 template <typename T>
 void launch_assemble(const T* L, int64_t ld, int64_t n, const double* Y, int K,

@@ -117,6 +117,13 @@ struct lslu_ctx {
   size_t esz = 0;
   // basis vectors formed by the last solve
   int last_nl = 0, last_nd = 0;
+  // captured solve (replayed while the key matches)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<double> gkey;
+  // last uploaded lambda grid and replay arrays (skipped when unchanged)
+  std::vector<double> up_grid;
+  std::vector<int> up_rep;
 };
 
 struct lslu_op {
@@ -179,11 +186,20 @@ void free_op(DeviceOp& d) {
   d = DeviceOp{};
 }
 
+void drop_graph(lslu_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->gkey.clear();
+}
+
 lslu_status ensure_ws(lslu_ctx* c, int64_t m, int64_t n, int K, size_t esz) {
   const int64_t ldL = (int64_t)align_up((size_t)n, 64);
   const int64_t ldD = (int64_t)align_up((size_t)m, 64);
   const size_t need = carve(nullptr, m, n, K, esz, ldL, ldD, nullptr);
   if (need > c->ws_bytes) {
+    drop_graph(c);
     if (c->ws) (void)hipFree(c->ws);
     c->ws = nullptr;
     c->ws_bytes = 0;
@@ -423,6 +439,8 @@ lslu_status lslu_create(int device, void* hip_stream, lslu_ctx** out) {
     lslu_ctx* c = new lslu_ctx();
     c->device = device;
     c->lds_max = prop.sharedMemPerBlock;
+    basis_init_attributes(c->lds_max);
+    projected_init_attributes(c->lds_max);
     if (hip_stream) {
       c->stream = static_cast<hipStream_t>(hip_stream);
     } else {
@@ -445,6 +463,7 @@ lslu_status lslu_destroy(lslu_ctx* c) {
   if (!c) return LSLU_OK;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  drop_graph(c);
   if (c->ws) (void)hipFree(c->ws);
   if (c->host) (void)hipHostFree(c->host);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -649,43 +668,79 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
     if (ws != LSLU_OK) return ws;
     const Layout& l = c->lay;
     const hipStream_t s = c->stream;
-    if (o->reg == LSLU_REG_WGCV || o->reg == LSLU_REG_GCV)
-      LSLU_HIP(c, hipMemcpyAsync(l.grid, o->lambda_grid, sizeof(double) * o->n_grid,
-                                 hipMemcpyHostToDevice, s));
     const bool rt = o->replay_piv_t != nullptr, rg = o->replay_piv_g != nullptr,
                rl = o->replay_lambda_idx != nullptr;
-    if (rt) {
-      std::vector<int> v(K + 1, -1);
-      for (int i = 0; i < std::min<int64_t>(K + 1, op->d.m); ++i) v[i] = o->replay_piv_t[i];
-      LSLU_HIP(c, hipMemcpyAsync(l.rep_t, v.data(), sizeof(int) * (K + 1),
-                                 hipMemcpyHostToDevice, s));
-      LSLU_HIP(c, hipStreamSynchronize(s));
+    // Small host inputs: uploaded only when they changed (pageable copies
+    // synchronise with the host).
+    {
+      std::vector<double> grid;
+      if (o->reg == LSLU_REG_WGCV || o->reg == LSLU_REG_GCV)
+        grid.assign(o->lambda_grid, o->lambda_grid + o->n_grid);
+      // the cached copy is tied to the device buffer, which moves with the
+      // workspace layout
+      grid.push_back(static_cast<double>(reinterpret_cast<uintptr_t>(l.grid)));
+      if (grid.size() > 1 && grid != c->up_grid) {
+        LSLU_HIP(c, hipMemcpyAsync(l.grid, grid.data(), sizeof(double) * (grid.size() - 1),
+                                   hipMemcpyHostToDevice, s));
+        LSLU_HIP(c, hipStreamSynchronize(s));
+      }
+      c->up_grid = grid;
+      std::vector<int> rep(3 * (K + 1) + 2, -1);
+      const uintptr_t rp = reinterpret_cast<uintptr_t>(l.rep_t);
+      rep[3 * (K + 1)] = static_cast<int>(rp & 0x7fffffff);
+      rep[3 * (K + 1) + 1] = static_cast<int>((rp >> 31) & 0x7fffffff);
+      for (int i = 0; rt && i < std::min<int64_t>(K + 1, op->d.m); ++i) rep[i] = o->replay_piv_t[i];
+      for (int i = 0; rg && i < std::min<int64_t>(K, op->d.n); ++i) rep[(K + 1) + i] = o->replay_piv_g[i];
+      for (int i = 0; rl && i < K; ++i) rep[2 * (K + 1) + i] = o->replay_lambda_idx[i];
+      if ((rt || rg || rl) && rep != c->up_rep) {
+        LSLU_HIP(c, hipMemcpyAsync(l.rep_t, rep.data(), sizeof(int) * (K + 1),
+                                   hipMemcpyHostToDevice, s));
+        LSLU_HIP(c, hipMemcpyAsync(l.rep_g, rep.data() + (K + 1), sizeof(int) * K,
+                                   hipMemcpyHostToDevice, s));
+        LSLU_HIP(c, hipMemcpyAsync(l.rep_lam, rep.data() + 2 * (K + 1), sizeof(int) * K,
+                                   hipMemcpyHostToDevice, s));
+        LSLU_HIP(c, hipStreamSynchronize(s));
+        c->up_rep = rep;
+      }
     }
-    if (rg) {
-      std::vector<int> v(K, -1);
-      for (int i = 0; i < std::min<int64_t>(K, op->d.n); ++i) v[i] = o->replay_piv_g[i];
-      LSLU_HIP(c, hipMemcpyAsync(l.rep_g, v.data(), sizeof(int) * K,
-                                 hipMemcpyHostToDevice, s));
-      LSLU_HIP(c, hipStreamSynchronize(s));
-    }
-    if (rl) {
-      LSLU_HIP(c, hipMemcpyAsync(l.rep_lam, o->replay_lambda_idx, sizeof(int) * K,
-                                 hipMemcpyHostToDevice, s));
-      LSLU_HIP(c, hipStreamSynchronize(s));
-    }
-    if (o->reg == LSLU_REG_WGCV || o->reg == LSLU_REG_GCV)
-      LSLU_HIP(c, hipStreamSynchronize(s));  // grid upload reads host memory
     void* X = o->X_dev ? o->X_dev : l.X;
-    if (esz == sizeof(double))
-      enqueue_solve<double>(c, op->d, static_cast<const double*>(b),
-                            static_cast<const double*>(x0), o,
-                            static_cast<double*>(x_out), static_cast<double*>(X),
-                            rt, rg, rl);
-    else
-      enqueue_solve<float>(c, op->d, static_cast<const float*>(b),
-                           static_cast<const float*>(x0), o,
-                           static_cast<float*>(x_out), static_cast<float*>(X),
-                           rt, rg, rl);
+    auto enqueue = [&]() {
+      if (esz == sizeof(double))
+        enqueue_solve<double>(c, op->d, static_cast<const double*>(b),
+                              static_cast<const double*>(x0), o,
+                              static_cast<double*>(x_out), static_cast<double*>(X),
+                              rt, rg, rl);
+      else
+        enqueue_solve<float>(c, op->d, static_cast<const float*>(b),
+                             static_cast<const float*>(x0), o,
+                             static_cast<float*>(x_out), static_cast<float*>(X),
+                             rt, rg, rl);
+    };
+    if (o->flags & LSLU_FLAG_EAGER) {
+      enqueue();
+    } else {
+      // Everything the captured kernels bake in: pointers, sizes, options.
+      std::vector<double> key = {
+          (double)(uintptr_t)op, (double)(uintptr_t)b, (double)(uintptr_t)x0,
+          (double)(uintptr_t)x_out, (double)(uintptr_t)X, (double)(uintptr_t)c->ws,
+          (double)K, (double)o->reg, o->lambda, (double)o->n_grid,
+          (double)o->grid_relative, o->omega, o->stop_tol, (double)o->early_stop,
+          (double)rt, (double)rg, (double)rl};
+      if (!c->gexec || key != c->gkey) {
+        drop_graph(c);
+        LSLU_HIP(c, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+        enqueue();
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(s, &g);
+        if (ce != hipSuccess || !g)
+          return fail(c, LSLU_EDEVICE, std::string("graph capture failed: ") +
+                                           hipGetErrorString(ce));
+        c->graph = g;
+        LSLU_HIP(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+        c->gkey = key;
+      }
+      LSLU_HIP(c, hipGraphLaunch(c->gexec, s));
+    }
     LSLU_HIP(c, hipGetLastError());
     LSLU_HIP(c, hipMemcpyAsync(c->host, l.res, l.res_bytes, hipMemcpyDeviceToHost, s));
     LSLU_HIP(c, hipStreamSynchronize(s));

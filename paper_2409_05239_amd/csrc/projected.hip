@@ -407,6 +407,13 @@ __global__ __launch_bounds__(kPT) void k_projected(
 
 size_t projected_scratch_doubles(int K) { return proj_scratch_per_k(K) * (size_t)K; }
 
+void projected_init_attributes(size_t lds_bytes) {
+  if (lds_bytes <= kStaticLds) return;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_projected),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            static_cast<int>(lds_bytes - kStaticLds));
+}
+
 void launch_projected(const double* H, const DevState* st, double,
                       const ProjParams& p, double* Y, double* lam, int* lam_idx,
                       double* ghat, double* sep, double* smax, double* smin,
@@ -419,10 +426,6 @@ void launch_projected(const double* H, const DevState* st, double,
     ++k_lds;
   if (k_lds > 0) {
     const size_t dyn = proj_a_doubles(k_lds) * sizeof(double);
-    if (dyn > 64 * 1024)
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_projected),
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)dyn);
     k_projected<<<k_lds, kPT, dyn, s>>>(H, st, p, 1, 1, Y, lam, lam_idx, ghat,
                                         sep, smax, smin, scratch);
   }

@@ -281,3 +281,34 @@ def test_invalid_options_are_rejected(lib, ctx):
             lib.lslu_op_dense(ctx, np.full((2, 2), np.nan))
     finally:
         lib.lslu_op_destroy(op)
+
+
+def test_graph_replays_match_eager(lib, ctx):
+    """The captured graph of a solve, replayed several times with eager solves
+    and other device work in between, gives bit-identical results each time."""
+    import torch
+    prob = config_problem("tomo32")
+    op = lib.make_operator(ctx, prob, lib.LSLU_FP64)
+    grid = lambda_grid()
+    try:
+        b = torch.tensor(prob.b, dtype=torch.float64, device="cuda")
+        kw = dict(op=op, b=b, grid=grid, grid_relative=True, bases=False)
+        ref = gpu_solve(lib, ctx, prob, "fp64", 20, "wgcv", eager=True, **kw)
+        for rep in range(4):
+            G = gpu_solve(lib, ctx, prob, "fp64", 20, "wgcv", **kw)
+            assert np.array_equal(G["X"], ref["X"]) and np.array_equal(G["H"], ref["H"])
+            assert np.array_equal(G["lambda_k"], ref["lambda_k"])
+            assert list(G["piv_t"]) == list(ref["piv_t"])
+            # other work in between: an eager solve of a different problem and
+            # a torch kernel overwriting b, then b restored
+            other = random_dense(30, 20, seed=rep)
+            gpu_solve(lib, ctx, other, "fp64", 5, eager=True, bases=False)
+            b.mul_(3.0)
+            torch.cuda.synchronize()
+            b.copy_(torch.tensor(prob.b, dtype=torch.float64, device="cuda"))
+        # a changed right-hand side in the same buffer is picked up by replays
+        b.mul_(2.0)
+        G2 = gpu_solve(lib, ctx, prob, "fp64", 20, "wgcv", **kw)
+        assert np.allclose(G2["X"], 2.0 * ref["X"], rtol=1e-12, atol=0)
+    finally:
+        lib.lslu_op_destroy(op)
