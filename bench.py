@@ -106,6 +106,14 @@ def run(args):
 
     print(f"[bench] workload={args.workload} m={prob.m} n={prob.n} nnz={prob.nnz} "
           f"K={K} prec={prec}", flush=True)
+    if args.calibrate_copy:
+        # A plain device copy of known size (256 MiB read + 256 MiB written),
+        # used to scale the FETCH_SIZE / WRITE_SIZE counters.
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     op, el, info, errs = timed(prec, args.steps, args.warmup)
     ms = el / args.steps * 1e3
     print(f"[bench] {prec}: {ms:.3f} ms/step", flush=True)
@@ -214,6 +222,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 256 MiB device copy first (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the "
