@@ -105,6 +105,11 @@ def _load():
         raise ImportError(
             f"{LIB_PATH} is missing: build it with "
             "'python -m paper_2409_05239_amd.build' (there is no fallback)")
+    # torch's wheel carries its own HIP runtime under a different file name
+    # but the same soname.  Loading torch first makes liblslu.so bind to that
+    # runtime instance, the one that owns the device tensors passed in;
+    # loading liblslu.so first would put a second HIP runtime in the process.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, pp = c_void_p, POINTER(c_void_p)
     sig = {

@@ -1,0 +1,198 @@
+"""GPU checks at the full sizes of the measured workloads.
+
+* tomo128 (CSR 32580 x 16384, 100 iterations): the FP64 oracle runs the whole
+  solve; the FP32 library follows its pivots and lambda indices (replay) and
+  must satisfy the Hessenberg relations at every k; the FP64 library runs
+  free and matches the pivots over the well-separated prefix.  x_k matches
+  the oracle to the stated 1e-4 (FP32) / 1e-10 (FP64) while the problem's
+  forward sensitivity allows it, and to 10 k u s_k beyond, s_k measured on
+  the oracle (``sensitivity.py``).
+* deblur1024 (31x31 PSF on 1024^2, 150 iterations): the oracle cannot run the
+  whole solve in a test, so it checks what it can compute piece by piece --
+  the exact pivot structure of the bases, the Hessenberg relations at sampled
+  pixels (the PSF product of one pixel is a 31x31 neighbourhood sum), the
+  projected problem re-solved by the oracle from the library's H and beta,
+  x_k at sampled pixels from the library's L and y_k, and bit-identical
+  repeats.
+"""
+
+import numpy as np
+import pytest
+
+from gpu_helpers import (TAU, check_basis_invariants, check_relations,
+                         gpu_solve, pivot_prefix, rel, replay_from,
+                         residual_gap)
+from oracle import RegParam, make_operator
+from oracle.hessenberg import hybrid_lslu
+from oracle.projected import projected_svd, select_lambda, tikhonov_coeffs
+from sensitivity import forward_sensitivity, step_tolerances
+from workloads import config_problem, lambda_grid
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    c = lib.lslu_create(0)
+    yield c
+    lib.lslu_destroy(c)
+
+
+@pytest.fixture(scope="module")
+def tomo():
+    prob = config_problem("tomo128")
+    reg = RegParam("wgcv", grid=lambda_grid(), grid_relative=True)
+    R = hybrid_lslu(make_operator(prob), prob.b, 100, reg)
+    sens = forward_sensitivity(prob, R, reg, 100)
+    return prob, R, sens
+
+
+def test_tomo128_fp32_replay_full(lib, ctx, tomo):
+    """FP32 following the oracle's pivots and lambda indices for 100 steps.
+
+    What holds at any k is the backward-error statement -- the Hessenberg
+    relations to FP32 rounding -- and the exact pivot structure.  Forward
+    parity with the FP64 oracle is held to the stated 1e-4 wherever the
+    problem's forward sensitivity allows it and to 10 k u s_k beyond (see
+    ``sensitivity.py``): the LU-type bases of this problem turn a relative
+    perturbation of 1e-9 into ~1e-6 by k = 16 and ~3e-5 by k = 79."""
+    prob, R, sens = tomo
+    K = min(100, R.k_done)
+    G = gpu_solve(lib, ctx, prob, "fp32", K, "wgcv", grid=lambda_grid(),
+                  grid_relative=True, replay=replay_from(R, K))
+    # The imposed pivot need not be the FP32 vector's largest entry once the
+    # two precisions have drifted apart, so only the exact structure holds.
+    check_basis_invariants(G, prob.m, prob.n, bound=np.inf)
+    op = make_operator(prob)
+    check_relations(G, op, "fp32")
+    assert G["k_stop"] == R.k_stop
+    tol = step_tolerances(sens[:K], 2.0 ** -24, 1e-4)
+    errs = np.array([rel(G["X"][:, k], R.X[:, k]) for k in range(K)])
+    gaps = np.array([residual_gap(op, prob.b, G["X"][:, k], R.X[:, k]) for k in range(K)])
+    k_stated = int(np.argmax(tol > 1e-4)) if np.any(tol > 1e-4) else K
+    print(f"[tomo128 fp32 replay] stated 1e-4 applies for k <= {k_stated}; "
+          f"max err there {errs[:k_stated].max():.2e}; max err/tol over all k "
+          f"{(errs / tol).max():.2f}; max residual gap/tol {(gaps / tol).max():.2f}")
+    assert k_stated >= 10
+    bad = [(k + 1, errs[k], tol[k]) for k in range(K) if errs[k] > tol[k]]
+    assert not bad, bad[:5]
+    assert np.all(gaps <= tol)
+    # Equal reconstruction error where it is decided: at the error minimum
+    # and at the stopping index the FP32 run matches the FP64 oracle.
+    e64 = [rel(R.X[:, k], prob.x_true) for k in range(K)]
+    e32 = [rel(G["X"][:, k], prob.x_true) for k in range(K)]
+    kmin = int(np.argmin(e64))
+    assert abs(e32[kmin] - e64[kmin]) <= 1e-4 * e64[kmin]
+    assert abs(e32[R.k_stop - 1] - e64[R.k_stop - 1]) <= 1e-2 * e64[R.k_stop - 1]
+
+
+def test_tomo128_fp64_free_full(lib, ctx, tomo):
+    prob, R, sens = tomo
+    G = gpu_solve(lib, ctx, prob, "fp64", 100, "wgcv", grid=lambda_grid(),
+                  grid_relative=True, bases=False)
+    k_piv = pivot_prefix(R, TAU["fp64"], min(R.k_done, G["k_done"]))
+    print(f"[tomo128 fp64 free] pivots well separated up to k = {k_piv}")
+    assert k_piv >= 90
+    assert list(G["piv_g"][:k_piv]) == R.piv_g[:k_piv]
+    assert list(G["piv_t"][:k_piv]) == R.piv_t[:k_piv]
+    # The bases never depend on lambda, so x_k is decided by the pivots up to
+    # g(k) and by lambda_k alone.  The weighted GCV function of this problem
+    # is flat at the small-lambda end (neighbouring grid values differ by
+    # ~1e-10 relative), so lambda_k may be a near-tie: where the two sides
+    # pick different grid points that must be one, and x_k is then not unique.
+    tol = step_tolerances(sens[:k_piv], 2.0 ** -53, 1e-10)
+    k_stated = int(np.argmax(tol > 1e-10)) if np.any(tol > 1e-10) else k_piv
+    same, worst = 0, 0.0
+    for k in range(1, k_piv + 1):
+        if G["lambda_idx"][k - 1] != R.lambda_idx[k - 1]:
+            assert R.sep_lambda[k - 1] <= TAU["fp64"], k
+            continue
+        same += 1
+        e = rel(G["X"][:, k - 1], R.X[:, k - 1])
+        worst = max(worst, e / tol[k - 1])
+        assert e <= tol[k - 1], (k, e, tol[k - 1])
+    print(f"[tomo128 fp64 free] x_k compared at {same} of {k_piv} steps; stated "
+          f"1e-10 applies for k <= {k_stated}; max err/tol {worst:.2f}")
+    assert same >= k_piv // 2
+
+
+def _psf_at(img_stack, P, pix, rows, cols, transpose):
+    """(A v)(pix) or (A^T v)(pix) for every image in img_stack (count x rows x
+    cols), from the definition: zero-boundary convolution / correlation."""
+    ph, pw = P.shape
+    ch, cw = ph // 2, pw // 2
+    W = P if transpose else P[::-1, ::-1]  # correlation weights
+    out = np.zeros((img_stack.shape[0], len(pix)))
+    pad = np.pad(img_stack, ((0, 0), (ch, ch), (cw, cw)))
+    for t, p in enumerate(pix):
+        i, j = divmod(int(p), cols)
+        patch = pad[:, i:i + ph, j:j + pw]
+        out[:, t] = np.einsum("kab,ab->k", patch, W)
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_deblur1024_sampled(lib, ctx, prec):
+    prob = config_problem("deblur1024")
+    rows, cols = prob.image_shape
+    K = 150
+    grid = lambda_grid()
+    G = gpu_solve(lib, ctx, prob, prec, K, "wgcv", grid=grid, grid_relative=True)
+    assert G["status"] == lib.LSLU_OK and G["k_done"] == K
+    L, D = G["L"], G["D"]
+    # exact structure
+    pg = [int(v) for v in G["piv_g"][:K]]
+    pt = [int(v) for v in G["piv_t"][:K + 1]]
+    assert len(set(pg)) == K and len(set(pt)) == K + 1
+    for k in range(K):
+        assert L[pg[k], k] == 1.0 and D[pt[k], k] == 1.0
+        assert np.all(L[pg[:k], k] == 0.0) and np.all(D[pt[:k], k] == 0.0)
+    assert np.abs(L).max() <= 1.0 and np.abs(D).max() <= 1.0
+    # relations at sampled pixels: A L_k = D_{k+1} H, A^T D_k = L_k W_k
+    rng = np.random.default_rng(5)
+    pix = np.concatenate([rng.integers(0, prob.n, 48), pg[:8], [0, prob.n - 1]])
+    H, W = G["H"][:K + 1, :K], G["W"][:K, :K]
+    u = 2.0 ** -53 if prec == "fp64" else 2.0 ** -24
+    AL = _psf_at(L.T.reshape(K, rows, cols), prob.psf, pix, rows, cols, False)
+    DH = (D[pix, :K + 1] @ H).T
+    mag = (np.abs(D[pix, :K + 1]) @ np.abs(H)).T + np.abs(AL)
+    assert np.all(np.abs(AL - DH) <= 20 * K * u * (mag + 1e-300))
+    ATD = _psf_at(D[:, :K].T.reshape(K, rows, cols), prob.psf, pix, rows, cols, True)
+    LW = (L[pix, :K] @ W).T
+    mag = (np.abs(L[pix, :K]) @ np.abs(W)).T + np.abs(ATD)
+    assert np.all(np.abs(ATD - LW) <= 20 * K * u * (mag + 1e-300))
+    # projected problem re-solved by the oracle from the library's H and beta
+    reg = RegParam("wgcv", grid=grid, grid_relative=True)
+    beta = G["beta"]
+    worst_y = 0.0
+    for k in (1, 2, 5, 20, 50, 100, 149, 150):
+        s, c, V = projected_svd(H[:k + 1, :k])
+        lam, li, sep, _ = select_lambda(reg, k, prob.m, beta, s, c, V, None, None)
+        if sep > 1e-9:
+            assert G["lambda_idx"][k - 1] == li, k
+        y = tikhonov_coeffs(beta, s, c, V, G["lambda_k"][k - 1])
+        worst_y = max(worst_y, rel(G["Y"][:k, k - 1], y))
+        # x_k at sampled pixels from the library's own L and y_k
+        xs = L[pix, :k] @ G["Y"][:k, k - 1]
+        assert np.allclose(G["X"][pix, k - 1], xs, rtol=1e-5 if prec == "fp32" else 1e-12,
+                           atol=1e-6 * np.abs(xs).max() if prec == "fp32" else 1e-14)
+    print(f"[deblur1024 {prec}] max y_k error vs oracle projected solve {worst_y:.2e}")
+    assert worst_y <= 1e-9
+    e = rel(G["x"], prob.x_true)
+    print(f"[deblur1024 {prec}] rel err vs x_true at k=150: {e:.4f}")
+    # bit-identical repeat
+    G2 = gpu_solve(lib, ctx, prob, prec, K, "wgcv", grid=grid, grid_relative=True,
+                   bases=False)
+    assert np.array_equal(G2["X"], G["X"]) and np.array_equal(G2["H"], G["H"])
+
+
+def test_deblur1024_bf16op_structure_and_error(lib, ctx):
+    prob = config_problem("deblur1024")
+    K = 150
+    G = gpu_solve(lib, ctx, prob, "bf16op", K, "wgcv", grid=lambda_grid(),
+                  grid_relative=True, bases=False)
+    assert G["status"] == lib.LSLU_OK and G["k_done"] == K
+    errs = [rel(G["X"][:, k], prob.x_true) for k in range(K)]
+    print(f"[deblur1024 bf16op] rel err vs x_true: min {min(errs):.4f} at k={int(np.argmin(errs)) + 1}, "
+          f"final {errs[-1]:.4f}")
+    assert min(errs) < 0.5
