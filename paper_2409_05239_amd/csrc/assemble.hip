@@ -17,7 +17,7 @@ constexpr int kAsmBlock = 256;
 
 template <typename T>
 __global__ __launch_bounds__(kAsmBlock) void k_assemble(
-    const T* __restrict__ L, int64_t ld, int64_t n, const double* __restrict__ Y,
+    const T* __restrict__ L, int64_t rs, int64_t cs, int64_t n, const double* __restrict__ Y,
     int K, const T* __restrict__ x0, T* __restrict__ X,
     const DevState* __restrict__ st) {
   const int kd = st->k_done;
@@ -31,7 +31,7 @@ __global__ __launch_bounds__(kAsmBlock) void k_assemble(
   for (int c = 0; c < kChunk; ++c) acc[c] = 0.0;
   const int jmax = k0 + kc;  // y_{k0+kc} has k0+kc entries
   for (int j = 0; j < jmax; ++j) {
-    const double l = static_cast<double>(L[(int64_t)j * ld + r]);
+    const double l = static_cast<double>(L[r * rs + (int64_t)j * cs]);
 #pragma unroll
     for (int c = 0; c < kChunk; ++c) {
       // y_{k0+c+1} has entries j = 0 .. k0+c
@@ -75,11 +75,12 @@ __global__ void k_select_x(const T* __restrict__ X, int64_t n,
 }  // namespace
 
 template <typename T>
-void launch_assemble(const T* L, int64_t ld, int64_t n, const double* Y, int K,
-                     const T* x0, T* X, const DevState* st, hipStream_t s) {
+void launch_assemble(const T* L, int64_t rs, int64_t cs, int64_t n,
+                     const double* Y, int K, const T* x0, T* X,
+                     const DevState* st, hipStream_t s) {
   dim3 grid((unsigned)((n + kAsmBlock - 1) / kAsmBlock),
             (unsigned)((K + kChunk - 1) / kChunk));
-  k_assemble<T><<<grid, kAsmBlock, 0, s>>>(L, ld, n, Y, K, x0, X, st);
+  k_assemble<T><<<grid, kAsmBlock, 0, s>>>(L, rs, cs, n, Y, K, x0, X, st);
 }
 
 void launch_stopping(const double* ghat, const DevState* st, double tol,
@@ -95,10 +96,10 @@ void launch_select_x(const T* X, int64_t n, const T* x0, T* x_out,
   k_select_x<T><<<(unsigned)g, 256, 0, s>>>(X, n, x0, x_out, k_sel);
 }
 
-template void launch_assemble<double>(const double*, int64_t, int64_t,
+template void launch_assemble<double>(const double*, int64_t, int64_t, int64_t,
                                       const double*, int, const double*,
                                       double*, const DevState*, hipStream_t);
-template void launch_assemble<float>(const float*, int64_t, int64_t,
+template void launch_assemble<float>(const float*, int64_t, int64_t, int64_t,
                                      const double*, int, const float*, float*,
                                      const DevState*, hipStream_t);
 template void launch_select_x<double>(const double*, int64_t, const double*,

@@ -1,0 +1,275 @@
+// Device helpers shared by the operator and recurrence kernels: value access
+// per precision mode, fixed-order reductions, the pivot order, and row access
+// to the operator (one row of A or A^T for dense and CSR, one pixel of the PSF
+// correlation) summed by an aligned group of G lanes.
+#pragma once
+
+#include <climits>
+#include <type_traits>
+
+#include "internal.hpp"
+
+namespace lslu {
+
+// ----------------------------------------------------------- value access --
+template <typename V>
+struct ValTraits;
+template <>
+struct ValTraits<double> {
+  __device__ static double get(double v) { return v; }
+};
+template <>
+struct ValTraits<float> {
+  __device__ static float get(float v) { return v; }
+};
+template <>
+struct ValTraits<uint16_t> {
+  __device__ static float get(uint16_t v) { return bf16_to_f32(v); }
+};
+
+// Vector entry as seen by a product: in the BF16 operator mode the input is
+// rounded to bfloat16 (bf16 x bf16 products are exact in float).
+template <bool kBf16, typename T>
+__device__ inline auto in_val(T v) {
+  if constexpr (kBf16)
+    return bf16_to_f32(f32_to_bf16(static_cast<float>(v)));
+  else
+    return v;
+}
+
+// ------------------------------------------------------------ reductions --
+// Sum over the G lanes of an aligned lane group, fixed xor butterfly: the
+// result does not depend on timing.
+template <int G, typename Acc>
+__device__ inline Acc group_sum(Acc v) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__device__ inline double readlane_d(double v, int lane) {
+  uint64_t u = __builtin_bit_cast(uint64_t, v);
+  uint32_t lo = static_cast<uint32_t>(
+      __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(u)), lane));
+  uint32_t hi = static_cast<uint32_t>(
+      __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(u >> 32)), lane));
+  return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// Total order of every pivot search: larger |v| first, then the smaller row
+// (ties go to the smallest index).  Ineligible rows carry key -1.
+__device__ inline bool better(double ka, int ia, double kb, int ib) {
+  return ka > kb || (ka == kb && ia < ib);
+}
+
+__device__ inline void wave_argmax(double& key, int& idx) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    double ok = __shfl_xor(key, off);
+    int oi = __shfl_xor(idx, off);
+    if (better(ok, oi, key, idx)) {
+      key = ok;
+      idx = oi;
+    }
+  }
+}
+
+// Block-wide argmax; the result is returned to every thread.
+template <int BLOCK>
+__device__ inline void block_argmax(double& key, int& idx) {
+  __shared__ double sk[BLOCK / kWave];
+  __shared__ int si[BLOCK / kWave];
+  wave_argmax(key, idx);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    sk[w] = key;
+    si[w] = idx;
+  }
+  __syncthreads();
+  key = sk[0];
+  idx = si[0];
+  for (int i = 1; i < BLOCK / kWave; ++i)
+    if (better(sk[i], si[i], key, idx)) {
+      key = sk[i];
+      idx = si[i];
+    }
+  __syncthreads();
+}
+
+// ------------------------------------------------------- operator rows ----
+// Each policy sums its row over the lanes sub, sub+G, ... of a group of G
+// lanes with x(c) supplied by a functor; group_sum<G> completes the sum.
+
+// Row r of a row-major dense matrix with `cols` columns.
+template <typename V, typename AccT, bool kBf16>
+struct DenseRows {
+  using Acc = AccT;
+  const V* a;
+  int64_t cols;
+  template <int G, typename XF>
+  __device__ Acc partial(int64_t r, int sub, XF xf) const {
+    const V* row = a + r * cols;
+    Acc acc = 0;
+#pragma unroll 4
+    for (int64_t c = sub; c < cols; c += G)
+      acc = fma(static_cast<Acc>(ValTraits<V>::get(row[c])),
+                static_cast<Acc>(in_val<kBf16>(xf(c))), acc);
+    return acc;
+  }
+};
+
+// Row r of a CSR matrix (int32 row pointers and column indices).  Each lane
+// issues the index and value loads of kBatch entries, then their kBatch
+// gathers, so a row costs few dependent round trips.
+template <typename V, typename AccT, bool kBf16>
+struct CsrRows {
+  using Acc = AccT;
+  static constexpr int kBatch = 8;
+  const int* rp;
+  const int* ci;
+  const V* val;
+  template <int G, typename XF>
+  __device__ Acc partial(int64_t r, int sub, XF xf) const {
+    using X = decltype(xf(0));
+    const int beg = rp[r], end = rp[r + 1];
+    Acc acc = 0;
+    int p = beg + sub;
+    for (; p + (kBatch - 1) * G < end; p += kBatch * G) {
+      int c[kBatch];
+      V v[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        c[u] = ci[p + u * G];
+        v[u] = val[p + u * G];
+      }
+      X xv[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) xv[u] = xf(c[u]);
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u)
+        acc = fma(static_cast<Acc>(ValTraits<V>::get(v[u])),
+                  static_cast<Acc>(in_val<kBf16>(xv[u])), acc);
+    }
+    int c[kBatch];
+    V v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int q = p + u * G;
+      c[u] = q < end ? ci[q] : 0;
+      v[u] = q < end ? val[q] : V(0);
+    }
+    X xv[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) xv[u] = (p + u * G < end) ? xf(c[u]) : X(0);
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (p + u * G < end)
+        acc = fma(static_cast<Acc>(ValTraits<V>::get(v[u])),
+                  static_cast<Acc>(in_val<kBf16>(xv[u])), acc);
+    return acc;
+  }
+};
+
+// Pixel `pix` of the zero-boundary correlation with weights wt (ph x pw):
+// y(i,j) = sum_{a,b} wt(a,b) x(i + a - ph/2, j + b - pw/2).
+template <typename AccT, bool kBf16>
+struct PsfPixels {
+  using Acc = AccT;
+  const Acc* wt;
+  int rows, cols, ph, pw;
+  template <int G, typename XF>
+  __device__ Acc partial(int64_t pix, int sub, XF xf) const {
+    const int i = static_cast<int>(pix / cols);
+    const int j = static_cast<int>(pix - (int64_t)i * cols);
+    const int ch = ph / 2, cw = pw / 2;
+    Acc acc = 0;
+    for (int t = sub; t < ph * pw; t += G) {
+      const int a = t / pw, b = t - a * pw;
+      const int gi = i + a - ch, gj = j + b - cw;
+      if (gi >= 0 && gi < rows && gj >= 0 && gj < cols)
+        acc = fma(wt[t], static_cast<Acc>(in_val<kBf16>(xf((int64_t)gi * cols + gj))),
+                  acc);
+    }
+    return acc;
+  }
+};
+
+// --------------------------------------------------------------- PSF tile --
+// A 32 x 64 output tile and its halo are staged in LDS; each lane owns one
+// output column and 8 consecutive output rows, walks the PSF column by column,
+// keeps a vertical strip of 8 + ph - 1 inputs in registers and reads each
+// weight as a wave-uniform (scalar) operand.
+constexpr int kPsfTW = 64;          // tile width = lanes of a wavefront
+constexpr int kPsfR = 8;            // output rows per lane
+constexpr int kPsfWaves = 4;        // wavefronts per block
+constexpr int kPsfTH = kPsfR * kPsfWaves;  // tile height
+
+template <typename Acc, int PH>
+__host__ __device__ constexpr size_t psf_lds_bytes(int pw) {
+  return sizeof(Acc) * (kPsfTH + PH - 1) * (kPsfTW + pw - 1);
+}
+
+// acc[p] = y[i0 + r0 + p, j0 + lane] for the tile at (i0, j0), with
+// y[i,j] = sum_{a,b} Wt[a,b] * x[i + a - PH/2, j + b - pw/2]  (zero outside),
+// r0 = 8 * wavefront.  Ends with the tile still in LDS (no trailing barrier).
+template <typename T, typename Acc, int PH, bool kBf16>
+__device__ inline void psf_tile(const T* __restrict__ x, int rows, int cols,
+                                const Acc* __restrict__ Wt, int pw, int i0,
+                                int j0, Acc* tile, Acc (&acc)[kPsfR]) {
+  const int ch = PH / 2, cw = pw / 2;
+  const int TR = kPsfTH + PH - 1;
+  const int TC = kPsfTW + pw - 1;
+  for (int e = threadIdx.x; e < TR * TC; e += blockDim.x) {
+    const int tr = e / TC, tc = e - tr * TC;
+    const int gi = i0 - ch + tr, gj = j0 - cw + tc;
+    Acc v = 0;
+    if (gi >= 0 && gi < rows && gj >= 0 && gj < cols)
+      v = static_cast<Acc>(in_val<kBf16>(x[(int64_t)gi * cols + gj]));
+    tile[e] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int r0 = (threadIdx.x / kWave) * kPsfR;
+#pragma unroll
+  for (int p = 0; p < kPsfR; ++p) acc[p] = 0;
+  for (int b = 0; b < pw; ++b) {
+    Acc s[kPsfR + PH - 1];
+#pragma unroll
+    for (int q = 0; q < kPsfR + PH - 1; ++q) s[q] = tile[(r0 + q) * TC + lane + b];
+#pragma unroll
+    for (int a = 0; a < PH; ++a) {
+      const Acc wv = Wt[a * pw + b];
+#pragma unroll
+      for (int p = 0; p < kPsfR; ++p) acc[p] = fma(wv, s[p + a], acc[p]);
+    }
+  }
+}
+
+// Calls f(std::integral_constant<int, PH>) for the PSF height (odd 1..31,
+// checked when the operator is created).
+template <typename F>
+void with_ph(int ph, F&& f) {
+  switch (ph) {
+#define LSLU_PH(P) \
+  case P: f(std::integral_constant<int, P>{}); break;
+    LSLU_PH(1) LSLU_PH(3) LSLU_PH(5) LSLU_PH(7) LSLU_PH(9) LSLU_PH(11)
+    LSLU_PH(13) LSLU_PH(15) LSLU_PH(17) LSLU_PH(19) LSLU_PH(21) LSLU_PH(23)
+    LSLU_PH(25) LSLU_PH(27) LSLU_PH(29) LSLU_PH(31)
+#undef LSLU_PH
+    default: break;
+  }
+}
+
+// Calls f(V{}, Acc{}, bf16 flag) for the operator's precision mode with the
+// vector type T.
+template <typename T, typename F>
+void with_mode(int prec, F&& f) {
+  if constexpr (std::is_same_v<T, double>) {
+    if (prec == kFP64) f(double{}, double{}, std::false_type{});
+  } else {
+    if (prec == kFP32) f(float{}, double{}, std::false_type{});
+    else if (prec == kBF16) f(uint16_t{}, float{}, std::true_type{});
+  }
+}
+
+}  // namespace lslu

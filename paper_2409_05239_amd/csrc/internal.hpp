@@ -12,7 +12,10 @@ constexpr int kWave = 64;
 constexpr int kMaxIter = 256;   // largest maxiter accepted
 constexpr int kMaxGrid = 256;   // largest lambda grid accepted
 constexpr int kArgmaxBlock = 256;
-constexpr int kMaxArgmaxBlocks = 2048;
+constexpr int kMaxParts = 4096;  // pivot candidates per streaming pass
+// Pivot-entry slots hold this NaN bit pattern until written; no product of
+// finite values produces it.
+constexpr uint64_t kSlotEmpty = 0x7ff4dead0000beefull;
 
 enum Prec : int { kFP64 = 0, kFP32 = 1, kBF16 = 2 };
 enum Reg : int { kNone = 0, kFixed = 1, kWGCV = 2, kGCV = 3, kOptimal = 4 };
@@ -31,8 +34,11 @@ struct DevState {
   int k_done;       // iterates x_k that exist (x_1..x_{k_done})
   int mismatch_t;   // replay: own pivot choice differed (d side)
   int mismatch_g;   // replay: own pivot choice differed (l side)
-  int pad;
+  int ticket;       // half-iteration: pivot-entry blocks finished (reset by block 0)
   double beta;      // r_0(t(1))
+  double cur_val;   // pivot value resolved by the running half-iteration
+  int cur_pick;     // its row
+  int spin_timeouts;  // waits that hit their bound (an error; never expected)
 };
 
 // One candidate of the pivot search: |v| (key, -1 when ineligible) and row.
@@ -68,27 +74,12 @@ __host__ __device__ inline float bf16_to_f32(uint16_t h) {
 }
 
 // ------------------------------------------------------------- launchers ---
-// Basis recurrence (basis.hip).
-template <typename T>
-void launch_fill(T* p, T v, int64_t count, hipStream_t s);
-void launch_state_reset(DevState* st, hipStream_t s);
-template <typename T>
-void launch_sub(const T* a, const T* b, T* out, int64_t len, hipStream_t s);
-template <typename T>
-void launch_eliminate_argmax(const T* v0, T* out, const T* basis, int64_t ld,
-                             int nb, const double* coef,
-                             const unsigned char* mask, int64_t len,
-                             ArgPart* parts, const DevState* st, hipStream_t s);
-template <typename T>
-void launch_pivot_normalize(const T* v, T* dst, int64_t len,
-                            const ArgPart* parts, const PivotJob& job, T* Tpack,
-                            const T* basis, int64_t ld, int nb, hipStream_t s);
-template <typename T>
-void launch_gather_trisolve(const T* v0, const int* piv, int nb, const T* Tp,
-                            double* coef, const DevState* st, size_t lds_bytes,
-                            hipStream_t s);
+// A basis is stored with element (i, j) (row i of basis vector j) at
+// p[i * rs + j * cs]: column-major (rs = 1) for the PSF operator, whose kernels
+// map lanes to consecutive pixels, row-major (cs = 1) for dense and CSR, whose
+// kernels give each row to one wavefront.
 
-// Operators (operators.hip).  `stop` may be nullptr.
+// Operators (operators.hip).
 struct DeviceOp {
   int kind;         // 0 dense, 1 csr, 2 psf
   int prec;
@@ -108,8 +99,73 @@ struct DeviceOp {
   float* psf32 = nullptr;
   float* psf32_flip = nullptr;
 };
+// y = A x (transpose 0) or A^T x (transpose 1).  `stop` may be nullptr.
 void op_apply(const DeviceOp& op, int transpose, const void* x, void* y,
               const int* stop, hipStream_t s);
+
+// One half-iteration of the recurrence in one launch (recurrence.hip).
+//   block 0            resolves the pivot of the previous half from its
+//                      candidates (breakdown test, bookkeeping, triangle row)
+//                      and publishes it; then solves the triangular system for
+//                      this half's coefficients and publishes them;
+//   blocks 1..nlead-1  form the pivot entries of this half's product (one
+//                      wavefront per earlier pivot of this side);
+//   other blocks       form their rows of the product from the unnormalised
+//                      previous vector, normalise their slice of it into its
+//                      basis column once the pivot is published, and subtract
+//                      the earlier basis vectors once the coefficients are,
+//                      writing per-block pivot candidates.
+// Later blocks only ever wait for flags set by earlier ones, which never wait
+// for later ones; every wait is bounded.
+template <typename T>
+struct HalfArgs {
+  // previous half: its unnormalised vector and pivot candidates
+  const T* up;
+  int64_t lenp;
+  const ArgPart* parts_in;
+  int nparts_in;
+  PivotJob job;
+  T* dstp;                 // its basis column: element i at dstp[i * dstp_stride]
+  int64_t dstp_stride;
+  const T* basisp;         // its side's basis (for the new triangle row)
+  int64_t rsp, csp;
+  int nbp;                 // earlier vectors of that side
+  T* Trowp;                // packed triangle row destination, or nullptr
+  // this half: out = op x - basis[:, :nb] coef, x = up / pivot value
+  int64_t rows;            // 0: only the pivot of the previous half
+  const T* basis;
+  int64_t rs, cs;
+  int nb;                  // coefficients to form (earlier vectors of this side)
+  const int* piv;          // this side's pivots (rows of the pivot entries)
+  const T* Tp;             // this side's packed triangle
+  double* coef;            // coefficient destination (a column of W or H)
+  double* ybuf;            // nb slots, kSlotEmpty until written
+  const unsigned char* mask;
+  T* out;
+  ArgPart* parts_out;
+  int* flags;              // [0] pivot published (1, or 2 on breakdown), [1] coefficients
+  int nlead;               // blocks 0..nlead-1 lead; set by launch_half
+};
+// Returns the number of candidates written to parts_out.
+template <typename T>
+int launch_half(HalfArgs<T>& a, const DeviceOp& op, int transpose,
+                size_t lds_bytes, hipStream_t s);
+void recurrence_init_attributes(size_t lds_bytes);
+
+// Basis recurrence helpers (basis.hip).
+template <typename T>
+void launch_fill(T* p, T v, int64_t count, hipStream_t s);
+void launch_state_reset(DevState* st, hipStream_t s);
+template <typename T>
+void launch_sub(const T* a, const T* b, T* out, int64_t len, hipStream_t s);
+// Pivot candidates of v (no mask); returns the number of parts.
+template <typename T>
+int launch_argmax_parts(const T* v, int64_t len, ArgPart* parts,
+                        const DevState* st, hipStream_t s);
+// dst[j * len + i] = basis(i, j), j < count.
+template <typename T>
+void launch_basis_copy(const T* src, int64_t rs, int64_t cs, int64_t len,
+                       int count, T* dst, hipStream_t s);
 
 // Projected problem (projected.hip).
 struct ProjParams {
@@ -135,13 +191,13 @@ size_t projected_scratch_doubles(int K);
 
 // One-time kernel attributes (dynamic LDS limits), set at context creation so
 // that no attribute call happens while a solve is being captured.
-void basis_init_attributes(size_t lds_bytes);
 void projected_init_attributes(size_t lds_bytes);
 
 // Iterate assembly (assemble.hip).
 template <typename T>
-void launch_assemble(const T* L, int64_t ld, int64_t n, const double* Y, int K,
-                     const T* x0, T* X, const DevState* st, hipStream_t s);
+void launch_assemble(const T* L, int64_t rs, int64_t cs, int64_t n,
+                     const double* Y, int K, const T* x0, T* X,
+                     const DevState* st, hipStream_t s);
 template <typename T>
 void launch_select_x(const T* X, int64_t n, const T* x0, T* x_out,
                      const DevState* st, const int* k_sel, hipStream_t s);

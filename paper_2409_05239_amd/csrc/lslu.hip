@@ -1,14 +1,12 @@
 // C ABI (include/lslu.h) and the host-side driver of one solve.
 //
 // A solve enqueues, on the context's stream and without host synchronisation:
-//   init      r_0 = b - A x_0, pivot search over r_0, beta, d_1
-//   for k = 1..K (Algorithm 5):
-//     q0 = A^T d_k                              (operator kernel)
-//     W(1:k-1,k) from q0(g(1:k-1))              (gather + triangular solve)
-//     q = q0 - L w, zero at pivots, argmax      (streaming pass, per-block
-//                                                candidates)
-//     g(k), W(k,k), l_k = q / W(k,k), T_L row   (pivot + normalise)
-//     u0 = A l_k, H(1:k,k), u, t(k+1), H(k+1,k), d_{k+1}   (same on the d side)
+//   init      r_0 = b - A x_0, pivot candidates of r_0
+//   for k = 1..K (Algorithm 5), one launch per half-iteration:
+//     t(k), H(k,k-1) (or beta), d_k; W(1:k-1,k); q = A^T d_k - L w and its
+//       pivot candidates
+//     g(k), W(k,k), l_k; H(1:k,k); u = A l_k - D h and its candidates
+//   t(K+1), H(K+1,K), d_{K+1}
 //   projected problems for all k                (one workgroup per k)
 //   stopping rule, iterates X = x_0 + L Y, selected iterate -> x_out
 // then copies the small results to pinned host memory once and waits.
@@ -30,6 +28,8 @@ namespace {
 struct Layout {
   void *L = nullptr, *D = nullptr, *q = nullptr, *u = nullptr, *r0 = nullptr,
        *X = nullptr;
+  double* ybuf = nullptr;  // pivot entries of the products, K + 1 per launch
+  int* flags = nullptr;    // two per launch of the recurrence
   void *TL = nullptr, *TD = nullptr;  // pivot-row triangles, basis precision
   double *grid = nullptr, *proj = nullptr;
   int *rep_t = nullptr, *rep_g = nullptr, *rep_lam = nullptr;
@@ -47,9 +47,20 @@ struct Layout {
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Basis storage: element (i, j) at p[i * rs + j * cs].
+struct Strides {
+  int64_t rsL, csL, rsD, csD;
+};
+
+Strides basis_strides(bool rowmajor, int64_t m, int64_t n, int K) {
+  if (rowmajor)
+    return {(int64_t)align_up((size_t)K, 16), 1, (int64_t)align_up((size_t)K + 1, 16), 1};
+  return {1, (int64_t)align_up((size_t)n, 64), 1, (int64_t)align_up((size_t)m, 64)};
+}
+
 // Two passes: with base == nullptr only the size is computed.
 size_t carve(unsigned char* base, int64_t m, int64_t n, int K, size_t esz,
-             int64_t ldL, int64_t ldD, Layout* lay) {
+             const Strides& bs, Layout* lay) {
   size_t off = 0;
   auto take = [&](size_t bytes) -> unsigned char* {
     off = align_up(off, 256);
@@ -58,11 +69,14 @@ size_t carve(unsigned char* base, int64_t m, int64_t n, int K, size_t esz,
     return p;
   };
   Layout l;
-  l.L = take(esz * ldL * K);
-  l.D = take(esz * ldD * (K + 1));
-  l.q = take(esz * ldL);
-  l.u = take(esz * ldD);
-  l.r0 = take(esz * ldD);
+  // the last element of a basis is at (len-1)*rs + (cols-1)*cs
+  l.L = take(esz * (size_t)((n - 1) * bs.rsL + (K - 1) * bs.csL + 1));
+  l.D = take(esz * (size_t)((m - 1) * bs.rsD + K * bs.csD + 1));
+  l.q = take(esz * n);
+  l.u = take(esz * m);
+  l.r0 = take(esz * m);
+  l.ybuf = reinterpret_cast<double*>(take(sizeof(double) * (K + 1) * (2 * K + 2)));
+  l.flags = reinterpret_cast<int*>(take(sizeof(int) * 2 * (2 * K + 2)));
   l.X = take(esz * n * K);
   l.TL = take(esz * K * (K + 1) / 2);        // packed rows, strict lower
   l.TD = take(esz * (K + 1) * (K + 2) / 2);
@@ -73,7 +87,7 @@ size_t carve(unsigned char* base, int64_t m, int64_t n, int K, size_t esz,
   l.rep_lam = reinterpret_cast<int*>(take(sizeof(int) * K));
   l.mask_t = take(m);
   l.mask_g = take(n);
-  l.parts = reinterpret_cast<ArgPart*>(take(sizeof(ArgPart) * kMaxArgmaxBlocks));
+  l.parts = reinterpret_cast<ArgPart*>(take(sizeof(ArgPart) * 2 * kMaxParts));
   // result block: doubles, then ints, then the state
   off = align_up(off, 256);
   const size_t res_start = off;
@@ -112,7 +126,9 @@ struct lslu_ctx {
   unsigned char* host = nullptr;  // pinned staging for the result block
   size_t host_bytes = 0;
   Layout lay;
-  int64_t m = 0, n = 0, ldL = 0, ldD = 0;
+  int64_t m = 0, n = 0;
+  Strides bs{};
+  bool rowmajor = false;
   int K = 0;
   size_t esz = 0;
   // basis vectors formed by the last solve
@@ -194,10 +210,10 @@ void drop_graph(lslu_ctx* c) {
   c->gkey.clear();
 }
 
-lslu_status ensure_ws(lslu_ctx* c, int64_t m, int64_t n, int K, size_t esz) {
-  const int64_t ldL = (int64_t)align_up((size_t)n, 64);
-  const int64_t ldD = (int64_t)align_up((size_t)m, 64);
-  const size_t need = carve(nullptr, m, n, K, esz, ldL, ldD, nullptr);
+lslu_status ensure_ws(lslu_ctx* c, int64_t m, int64_t n, int K, size_t esz,
+                      bool rowmajor) {
+  const Strides bs = basis_strides(rowmajor, m, n, K);
+  const size_t need = carve(nullptr, m, n, K, esz, bs, nullptr);
   if (need > c->ws_bytes) {
     drop_graph(c);
     if (c->ws) (void)hipFree(c->ws);
@@ -208,7 +224,7 @@ lslu_status ensure_ws(lslu_ctx* c, int64_t m, int64_t n, int K, size_t esz) {
     c->ws = static_cast<unsigned char*>(p);
     c->ws_bytes = need;
   }
-  carve(c->ws, m, n, K, esz, ldL, ldD, &c->lay);
+  carve(c->ws, m, n, K, esz, bs, &c->lay);
   if (c->lay.res_bytes > c->host_bytes) {
     if (c->host) (void)hipHostFree(c->host);
     c->host = nullptr;
@@ -221,8 +237,8 @@ lslu_status ensure_ws(lslu_ctx* c, int64_t m, int64_t n, int K, size_t esz) {
   c->m = m;
   c->n = n;
   c->K = K;
-  c->ldL = ldL;
-  c->ldD = ldD;
+  c->bs = bs;
+  c->rowmajor = rowmajor;
   c->esz = esz;
   return LSLU_OK;
 }
@@ -234,13 +250,14 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
   const hipStream_t s = c->stream;
   const Layout& l = c->lay;
   const int K = c->K;
-  const int64_t m = c->m, n = c->n, ldL = c->ldL, ldD = c->ldD;
+  const int64_t m = c->m, n = c->n;
+  const Strides bs = c->bs;
   T* Lb = static_cast<T*>(l.L);
   T* Db = static_cast<T*>(l.D);
   T* q = static_cast<T*>(l.q);
   T* u = static_cast<T*>(l.u);
   DevState* st = l.st;
-  const int* stop = &st->stopped;
+  const size_t lds = c->lds_max;
 
   launch_state_reset(st, s);
   launch_fill<unsigned char>(l.mask_t, 0, m, s);
@@ -249,6 +266,9 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
   launch_fill<int>(l.piv_g, -1, K, s);
   launch_fill<int>(l.own_t, -1, K + 1, s);
   launch_fill<int>(l.own_g, -1, K, s);
+  launch_fill<int>(l.flags, 0, 2 * (2 * K + 2), s);
+  launch_fill<uint64_t>(reinterpret_cast<uint64_t*>(l.ybuf), kSlotEmpty,
+                        (int64_t)(K + 1) * (2 * K + 2), s);
   launch_fill<double>(l.H, 0.0, (int64_t)(K + 1) * K, s);
   launch_fill<double>(l.W, 0.0, (int64_t)K * K, s);
   launch_fill<double>(l.Y, 0.0, (int64_t)K * K, s);
@@ -256,69 +276,123 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
   T* TD = static_cast<T*>(l.TD);
   launch_fill<T>(TL, T(0), (int64_t)K * (K + 1) / 2, s);
   launch_fill<T>(TD, T(0), (int64_t)(K + 1) * (K + 2) / 2, s);
+  auto packed = [](int j) { return (int64_t)j * (j - 1) / 2; };
+  auto Hcol = [&](int k) { return l.H + (int64_t)(k - 1) * (K + 1); };  // H(:,k)
+  auto Wcol = [&](int k) { return l.W + (int64_t)(k - 1) * K; };        // W(:,k)
 
-  // r_0 = b - A x_0 (or b), its pivot, beta and d_1.
+  // r_0 = b - A x_0 (or b) and its pivot candidates.
   const T* r0 = b;
   if (x0) {
     op_apply(op, 0, x0, l.r0, nullptr, s);
     launch_sub<T>(b, static_cast<const T*>(l.r0), static_cast<T*>(l.r0), m, s);
     r0 = static_cast<const T*>(l.r0);
   }
-  PivotJob j0{};
-  j0.side = 2;
-  j0.k = 0;
-  j0.eligible = 1;
-  j0.piv_pos = 0;
-  j0.piv_val = &st->beta;
-  j0.piv_list = l.piv_t;
-  j0.own_list = l.own_t;
-  j0.mask = l.mask_t;
-  j0.replay = replay_t ? l.rep_t : nullptr;
-  j0.st = st;
-  launch_eliminate_argmax<T>(r0, u, Db, ldD, 0, nullptr, l.mask_t, m, l.parts,
-                             st, s);
-  launch_pivot_normalize<T>(u, Db, m, l.parts, j0, TD, Db, ldD, 0, s);
+  ArgPart* parts[2] = {l.parts, l.parts + kMaxParts};
+  int cur = 0;  // parts[cur] holds the candidates of the last pass
+  int nparts = launch_argmax_parts<T>(r0, m, parts[cur], st, s);
+  int launch = 0;
+
+  // The d-side search that a launch resolves: r_0 (k = 0) or the d side of
+  // iteration k, giving t(k+1).
+  auto d_job = [&](int k) {
+    PivotJob j{};
+    j.side = k == 0 ? 2 : 1;
+    j.k = k;
+    j.eligible = (k == 0 || k < m) ? 1 : 0;
+    j.piv_pos = k;
+    j.piv_val = k == 0 ? &st->beta : Hcol(k) + k;
+    j.piv_list = l.piv_t;
+    j.own_list = l.own_t;
+    j.mask = l.mask_t;
+    j.replay = replay_t ? l.rep_t : nullptr;
+    j.st = st;
+    return j;
+  };
+  auto set_prev_d = [&](HalfArgs<T>& a, int k, const T* vec) {
+    // resolves t(k+1): d_{k+1} into column k of D, row k of T_D
+    a.up = vec;
+    a.lenp = m;
+    a.parts_in = parts[cur];
+    a.nparts_in = nparts;
+    a.job = d_job(k);
+    a.dstp = Db + (int64_t)k * bs.csD;
+    a.dstp_stride = bs.rsD;
+    a.basisp = Db;
+    a.rsp = bs.rsD;
+    a.csp = bs.csD;
+    a.nbp = k;
+    a.Trowp = k > 0 ? TD + packed(k) : nullptr;
+  };
+  auto run = [&](HalfArgs<T>& a, int tr) {
+    a.ybuf = l.ybuf + (int64_t)(K + 1) * launch;
+    a.flags = l.flags + 2 * launch++;
+    a.parts_out = parts[cur ^ 1];
+    nparts = launch_half<T>(a, op, tr, lds, s);
+    cur ^= 1;
+  };
 
   for (int k = 1; k <= K; ++k) {
-    // l side: q0 = A^T d_k, W(1:k-1,k), q, g(k), W(k,k), l_k.
-    op_apply(op, 1, Db + (int64_t)(k - 1) * ldD, q, stop, s);
-    double* Wcol = l.W + (int64_t)(k - 1) * K;
-    launch_gather_trisolve<T>(q, l.piv_g, k - 1, TL, Wcol, st, c->lds_max, s);
-    PivotJob jg{};
-    jg.side = 0;
-    jg.k = k;
-    jg.eligible = (k <= n) ? 1 : 0;
-    jg.piv_pos = k - 1;
-    jg.piv_val = Wcol + (k - 1);
-    jg.piv_list = l.piv_g;
-    jg.own_list = l.own_g;
-    jg.mask = l.mask_g;
-    jg.replay = replay_g ? l.rep_g : nullptr;
-    jg.st = st;
-    launch_eliminate_argmax<T>(q, q, Lb, ldL, k - 1, Wcol, l.mask_g, n, l.parts,
-                               st, s);
-    launch_pivot_normalize<T>(q, Lb + (int64_t)(k - 1) * ldL, n, l.parts, jg,
-                              TL, Lb, ldL, k - 1, s);
-    // d side: u0 = A l_k, H(1:k,k), u, t(k+1), H(k+1,k), d_{k+1}.
-    op_apply(op, 0, Lb + (int64_t)(k - 1) * ldL, u, stop, s);
-    double* Hcol = l.H + (int64_t)(k - 1) * (K + 1);
-    launch_gather_trisolve<T>(u, l.piv_t, k, TD, Hcol, st, c->lds_max, s);
-    PivotJob jt{};
-    jt.side = 1;
-    jt.k = k;
-    jt.eligible = (k < m) ? 1 : 0;
-    jt.piv_pos = k;
-    jt.piv_val = Hcol + k;
-    jt.piv_list = l.piv_t;
-    jt.own_list = l.own_t;
-    jt.mask = l.mask_t;
-    jt.replay = replay_t ? l.rep_t : nullptr;
-    jt.st = st;
-    launch_eliminate_argmax<T>(u, u, Db, ldD, k, Hcol, l.mask_t, m, l.parts, st,
-                               s);
-    launch_pivot_normalize<T>(u, Db + (int64_t)k * ldD, m, l.parts, jt, TD, Db,
-                              ldD, k, s);
+    // t(k), d_k; then q = A^T d_k - L w with w = W(1:k-1,k).
+    HalfArgs<T> al{};
+    set_prev_d(al, k - 1, k == 1 ? r0 : u);
+    al.rows = n;
+    al.basis = Lb;
+    al.rs = bs.rsL;
+    al.cs = bs.csL;
+    al.nb = k - 1;
+    al.piv = l.piv_g;
+    al.Tp = TL;
+    al.coef = Wcol(k);
+    al.mask = l.mask_g;
+    al.out = q;
+    run(al, 1);
+    // g(k), W(k,k), l_k; then u = A l_k - D h with h = H(1:k,k).
+    HalfArgs<T> ad{};
+    ad.up = q;
+    ad.lenp = n;
+    ad.parts_in = parts[cur];
+    ad.nparts_in = nparts;
+    ad.job.side = 0;
+    ad.job.k = k;
+    ad.job.eligible = (k <= n) ? 1 : 0;
+    ad.job.piv_pos = k - 1;
+    ad.job.piv_val = Wcol(k) + (k - 1);
+    ad.job.piv_list = l.piv_g;
+    ad.job.own_list = l.own_g;
+    ad.job.mask = l.mask_g;
+    ad.job.replay = replay_g ? l.rep_g : nullptr;
+    ad.job.st = st;
+    ad.dstp = Lb + (int64_t)(k - 1) * bs.csL;
+    ad.dstp_stride = bs.rsL;
+    ad.basisp = Lb;
+    ad.rsp = bs.rsL;
+    ad.csp = bs.csL;
+    ad.nbp = k - 1;
+    ad.Trowp = TL + packed(k - 1);
+    ad.rows = m;
+    ad.basis = Db;
+    ad.rs = bs.rsD;
+    ad.cs = bs.csD;
+    ad.nb = k;
+    ad.piv = l.piv_t;
+    ad.Tp = TD;
+    ad.coef = Hcol(k);
+    ad.mask = l.mask_t;
+    ad.out = u;
+    run(ad, 0);
   }
+  // t(K+1), H(K+1,K), d_{K+1}.
+  HalfArgs<T> af{};
+  set_prev_d(af, K, u);
+  af.rows = 0;
+  af.nb = 0;
+  af.piv = l.piv_g;
+  af.Tp = TL;
+  af.coef = l.ybuf;
+  af.mask = l.mask_g;
+  af.basis = Lb;
+  af.out = q;
+  run(af, 1);
 
   ProjParams pp{};
   pp.K = K;
@@ -335,7 +409,7 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
                    l.smax, l.smin, l.proj, c->lds_max, s);
   const double tol = o->stop_tol > 0.0 ? o->stop_tol : 1e-6;
   launch_stopping(l.ghat, st, tol, o->early_stop ? 1 : 0, l.sel, s);
-  launch_assemble<T>(Lb, ldL, n, l.Y, K, x0, X, st, s);
+  launch_assemble<T>(Lb, bs.rsL, bs.csL, n, l.Y, K, x0, X, st, s);
   launch_select_x<T>(X, n, x0, x_out, st, l.sel, s);
 }
 
@@ -439,7 +513,7 @@ lslu_status lslu_create(int device, void* hip_stream, lslu_ctx** out) {
     lslu_ctx* c = new lslu_ctx();
     c->device = device;
     c->lds_max = prop.sharedMemPerBlock;
-    basis_init_attributes(c->lds_max);
+    recurrence_init_attributes(c->lds_max);
     projected_init_attributes(c->lds_max);
     if (hip_stream) {
       c->stream = static_cast<hipStream_t>(hip_stream);
@@ -664,7 +738,7 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
     LSLU_HIP(c, hipSetDevice(c->device));
     const int K = o->maxiter;
     const size_t esz = prec_size(op->d.prec);
-    lslu_status ws = ensure_ws(c, op->d.m, op->d.n, K, esz);
+    lslu_status ws = ensure_ws(c, op->d.m, op->d.n, K, esz, op->d.kind != 2);
     if (ws != LSLU_OK) return ws;
     const Layout& l = c->lay;
     const hipStream_t s = c->stream;
@@ -723,6 +797,7 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
       std::vector<double> key = {
           (double)(uintptr_t)op, (double)(uintptr_t)b, (double)(uintptr_t)x0,
           (double)(uintptr_t)x_out, (double)(uintptr_t)X, (double)(uintptr_t)c->ws,
+          (double)op->d.kind, (double)op->d.prec, (double)op->d.m, (double)op->d.n,
           (double)K, (double)o->reg, o->lambda, (double)o->n_grid,
           (double)o->grid_relative, o->omega, o->stop_tol, (double)o->early_stop,
           (double)rt, (double)rg, (double)rl};
@@ -752,6 +827,8 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
     const int* sel = reinterpret_cast<const int*>(hp(l.sel));
     c->last_nl = st->n_l;
     c->last_nd = st->n_d;
+    if (st->spin_timeouts != 0)
+      return fail(c, LSLU_EDEVICE, "a wait inside the recurrence ran out (device fault)");
     const lslu_status status = static_cast<lslu_status>(st->status);
     if (res) {
       res->status = status;
@@ -793,10 +870,16 @@ lslu_status lslu_get_basis(lslu_ctx* c, int32_t which, int32_t count, void* dst)
   if (count == 0) return LSLU_OK;
   LSLU_HIP(c, hipSetDevice(c->device));
   const int64_t len = which == 0 ? c->n : c->m;
-  const int64_t ld = which == 0 ? c->ldL : c->ldD;
+  const int64_t rs = which == 0 ? c->bs.rsL : c->bs.rsD;
+  const int64_t cs = which == 0 ? c->bs.csL : c->bs.csD;
   const void* src = which == 0 ? c->lay.L : c->lay.D;
-  LSLU_HIP(c, hipMemcpy2DAsync(dst, len * c->esz, src, ld * c->esz, len * c->esz,
-                               count, hipMemcpyDeviceToDevice, c->stream));
+  if (c->esz == sizeof(double))
+    launch_basis_copy<double>(static_cast<const double*>(src), rs, cs, len, count,
+                              static_cast<double*>(dst), c->stream);
+  else
+    launch_basis_copy<float>(static_cast<const float*>(src), rs, cs, len, count,
+                             static_cast<float*>(dst), c->stream);
+  LSLU_HIP(c, hipGetLastError());
   return LSLU_OK;
 }
 

@@ -1,109 +1,46 @@
-// Operator products A v and A^T w: the only place the method touches A
+// Operator products A v and A^T w -- the only place the method touches A
 // (Section 1: matrix-free; Algorithm 5 uses one product with A and one with
-// A^T per iteration).
+// A^T per iteration).  This file holds the standalone product (the residual
+// r_0 = b - A x_0 and the lslu_op_apply entry point); inside the iteration
+// the product is fused with the elimination that follows it
+// (recurrence.hip).
 //
-// Precision modes (template parameters V = stored operator value, T = vector
-// type, Acc = summation type):
+// Precision modes (V = stored operator value, T = vector type, Acc = sum):
 //   FP64:   V = double,   T = double, Acc = double
 //   FP32:   V = float,    T = float,  Acc = double
 //   BF16OP: V = bfloat16, T = float,  Acc = float, input entries rounded to
 //           bfloat16 before the product (bf16 x bf16 is exact in float)
 //
-// Dense and CSR products are row-parallel (one wavefront per output row, a
-// fixed lane-stride partial sum and a fixed xor-butterfly reduction), so the
-// result does not depend on the launch.  A^T is stored explicitly for both, so
-// the adjoint is also a row product with no atomics.
-//
-// The PSF product is a correlation with either the PSF (A^T) or the PSF
-// rotated by 180 degrees (A).  A 32 x 64 output tile and its halo are staged
-// in LDS; each lane owns one output column and 8 consecutive output rows, walks
-// the PSF column by column, keeps a vertical strip of 8 + ph - 1 inputs in
-// registers and reads each weight as a wave-uniform (scalar) operand.
-#include "internal.hpp"
+// Dense and CSR products are row-parallel (a group of 16 lanes per output
+// row, a fixed lane-stride partial sum and a fixed xor-butterfly reduction),
+// so the result does not depend on the launch.  A^T is stored explicitly for
+// both, so the adjoint is also a row product with no atomics.  The PSF
+// product is a correlation with either the PSF (A^T) or the PSF rotated by
+// 180 degrees (A), computed by LDS-staged tiles.
+#include "device_common.hpp"
 
 namespace lslu {
 
 namespace {
 
-struct Bf16Tag {};
+constexpr int kRowLanes = 16;
+constexpr int kRowBlock = 256;
+constexpr int kRowsPerBlock = kRowBlock / kRowLanes;
 
-template <typename V>
-struct ValTraits;
-template <>
-struct ValTraits<double> {
-  using S = double;
-  __device__ static double get(double v) { return v; }
-};
-template <>
-struct ValTraits<float> {
-  using S = float;
-  __device__ static float get(float v) { return v; }
-};
-template <>
-struct ValTraits<uint16_t> {
-  __device__ static float get(uint16_t v) { return bf16_to_f32(v); }
-};
-
-// Vector input as seen by the product.
-template <typename T, bool kBf16>
-__device__ inline auto in_val(T v) {
-  if constexpr (kBf16)
-    return bf16_to_f32(f32_to_bf16(static_cast<float>(v)));
-  else
-    return v;
-}
-
-template <typename Acc>
-__device__ inline Acc wave_sum(Acc v) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
-
-constexpr int kRowsPerBlock = 4;  // wavefronts per block, one row each
-
-template <typename V, typename T, typename Acc, bool kBf16>
-__global__ __launch_bounds__(kRowsPerBlock * kWave) void k_dense_rows(
-    const V* __restrict__ A, int64_t rows, int64_t cols, const T* __restrict__ x,
-    T* __restrict__ y, const int* stop) {
+template <class RowOp, typename T>
+__global__ __launch_bounds__(kRowBlock) void k_rows(
+    RowOp op, int64_t rows, const T* __restrict__ x, T* __restrict__ y,
+    const int* stop) {
   if (stop && *stop) return;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t r = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x / kWave;
+  const int sub = threadIdx.x % kRowLanes;
+  const int64_t r = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x / kRowLanes;
   if (r >= rows) return;
-  const V* a = A + r * cols;
-  Acc acc = 0;
-  for (int64_t c = lane; c < cols; c += kWave)
-    acc = fma(static_cast<Acc>(ValTraits<V>::get(a[c])),
-              static_cast<Acc>(in_val<T, kBf16>(x[c])), acc);
-  acc = wave_sum(acc);
-  if (lane == 0) y[r] = static_cast<T>(acc);
+  auto xf = [x](int64_t c) { return x[c]; };
+  typename RowOp::Acc acc = op.template partial<kRowLanes>(r, sub, xf);
+  acc = group_sum<kRowLanes>(acc);
+  if (sub == 0) y[r] = static_cast<T>(acc);
 }
 
-template <typename V, typename T, typename Acc, bool kBf16>
-__global__ __launch_bounds__(kRowsPerBlock * kWave) void k_csr_rows(
-    const int* __restrict__ rp, const int* __restrict__ ci,
-    const V* __restrict__ val, int64_t rows, const T* __restrict__ x,
-    T* __restrict__ y, const int* stop) {
-  if (stop && *stop) return;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t r = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x / kWave;
-  if (r >= rows) return;
-  const int beg = rp[r], end = rp[r + 1];
-  Acc acc = 0;
-  for (int p = beg + lane; p < end; p += kWave)
-    acc = fma(static_cast<Acc>(ValTraits<V>::get(val[p])),
-              static_cast<Acc>(in_val<T, kBf16>(x[ci[p]])), acc);
-  acc = wave_sum(acc);
-  if (lane == 0) y[r] = static_cast<T>(acc);
-}
-
-// ------------------------------------------------------------------ PSF ----
-constexpr int kPsfTW = 64;          // tile width = lanes of a wavefront
-constexpr int kPsfR = 8;            // output rows per lane
-constexpr int kPsfWaves = 4;        // wavefronts per block
-constexpr int kPsfTH = kPsfR * kPsfWaves;  // tile height
-
-// y[i,j] = sum_{a,b} Wt[a,b] * x[i + a - PH/2, j + b - pw/2]  (zero outside)
 template <typename T, typename Acc, int PH, bool kBf16>
 __global__ __launch_bounds__(kPsfWaves * kWave) void k_psf_corr(
     const T* __restrict__ x, T* __restrict__ y, int rows, int cols,
@@ -111,36 +48,11 @@ __global__ __launch_bounds__(kPsfWaves * kWave) void k_psf_corr(
   if (stop && *stop) return;
   extern __shared__ unsigned char smem_raw[];
   Acc* tile = reinterpret_cast<Acc*>(smem_raw);
-  const int ch = PH / 2, cw = pw / 2;
-  const int TR = kPsfTH + PH - 1;
-  const int TC = kPsfTW + pw - 1;
   const int i0 = blockIdx.y * kPsfTH, j0 = blockIdx.x * kPsfTW;
-  for (int e = threadIdx.x; e < TR * TC; e += blockDim.x) {
-    const int tr = e / TC, tc = e - tr * TC;
-    const int gi = i0 - ch + tr, gj = j0 - cw + tc;
-    Acc v = 0;
-    if (gi >= 0 && gi < rows && gj >= 0 && gj < cols)
-      v = static_cast<Acc>(in_val<T, kBf16>(x[(int64_t)gi * cols + gj]));
-    tile[e] = v;
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & (kWave - 1);
-  const int w = threadIdx.x / kWave;
-  const int r0 = w * kPsfR;  // first output row of this lane (tile-local)
   Acc acc[kPsfR];
-#pragma unroll
-  for (int p = 0; p < kPsfR; ++p) acc[p] = 0;
-  for (int b = 0; b < pw; ++b) {
-    Acc s[kPsfR + PH - 1];
-#pragma unroll
-    for (int q = 0; q < kPsfR + PH - 1; ++q) s[q] = tile[(r0 + q) * TC + lane + b];
-#pragma unroll
-    for (int a = 0; a < PH; ++a) {
-      const Acc wv = Wt[a * pw + b];
-#pragma unroll
-      for (int p = 0; p < kPsfR; ++p) acc[p] = fma(wv, s[p + a], acc[p]);
-    }
-  }
+  psf_tile<T, Acc, PH, kBf16>(x, rows, cols, Wt, pw, i0, j0, tile, acc);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int r0 = (threadIdx.x / kWave) * kPsfR;
   const int gj = j0 + lane;
   if (gj < cols) {
 #pragma unroll
@@ -151,82 +63,51 @@ __global__ __launch_bounds__(kPsfWaves * kWave) void k_psf_corr(
   }
 }
 
-template <typename T, typename Acc, bool kBf16, int PH>
-void psf_launch_ph(const T* x, T* y, int rows, int cols, const Acc* Wt, int pw,
-                   const int* stop, hipStream_t s) {
-  dim3 grid((cols + kPsfTW - 1) / kPsfTW, (rows + kPsfTH - 1) / kPsfTH);
-  const size_t lds = sizeof(Acc) * (kPsfTH + PH - 1) * (kPsfTW + pw - 1);
-  k_psf_corr<T, Acc, PH, kBf16><<<grid, kPsfWaves * kWave, lds, s>>>(
-      x, y, rows, cols, Wt, pw, stop);
+template <typename Acc>
+const Acc* psf_weights(const DeviceOp& op, int tr) {
+  if constexpr (std::is_same_v<Acc, double>)
+    return tr ? op.psf : op.psf_flip;
+  else
+    return tr ? op.psf32 : op.psf32_flip;
 }
 
-template <typename T, typename Acc, bool kBf16>
-void psf_launch(const T* x, T* y, int rows, int cols, const Acc* Wt, int ph,
-                int pw, const int* stop, hipStream_t s) {
-  switch (ph) {
-#define LSLU_PH(P) \
-  case P: psf_launch_ph<T, Acc, kBf16, P>(x, y, rows, cols, Wt, pw, stop, s); break;
-    LSLU_PH(1) LSLU_PH(3) LSLU_PH(5) LSLU_PH(7) LSLU_PH(9) LSLU_PH(11)
-    LSLU_PH(13) LSLU_PH(15) LSLU_PH(17) LSLU_PH(19) LSLU_PH(21) LSLU_PH(23)
-    LSLU_PH(25) LSLU_PH(27) LSLU_PH(29) LSLU_PH(31)
-#undef LSLU_PH
-    default: break;  // rejected at operator creation
-  }
-}
-
-inline int row_grid(int64_t rows) {
-  return static_cast<int>((rows + kRowsPerBlock - 1) / kRowsPerBlock);
-}
-
-template <typename V, typename T, typename Acc, bool kBf16>
-void dense_apply(const DeviceOp& op, int tr, const void* x, void* y,
-                 const int* stop, hipStream_t s) {
-  const int64_t rows = tr ? op.n : op.m, cols = tr ? op.m : op.n;
-  const V* A = static_cast<const V*>(tr ? op.AT : op.A);
-  k_dense_rows<V, T, Acc, kBf16><<<row_grid(rows), kRowsPerBlock * kWave, 0, s>>>(
-      A, rows, cols, static_cast<const T*>(x), static_cast<T*>(y), stop);
-}
-
-template <typename V, typename T, typename Acc, bool kBf16>
-void csr_apply(const DeviceOp& op, int tr, const void* x, void* y,
-               const int* stop, hipStream_t s) {
-  const int64_t rows = tr ? op.n : op.m;
-  k_csr_rows<V, T, Acc, kBf16><<<row_grid(rows), kRowsPerBlock * kWave, 0, s>>>(
-      tr ? op.rpT : op.rp, tr ? op.ciT : op.ci,
-      static_cast<const V*>(tr ? op.valT : op.val), rows,
-      static_cast<const T*>(x), static_cast<T*>(y), stop);
+template <typename T>
+void apply_t(const DeviceOp& op, int tr, const T* x, T* y, const int* stop,
+             hipStream_t s) {
+  with_mode<T>(op.prec, [&](auto v, auto acc, auto bf) {
+    using V = decltype(v);
+    using Acc = decltype(acc);
+    constexpr bool kB = decltype(bf)::value;
+    const int64_t rows = tr ? op.n : op.m;
+    const int grid = static_cast<int>((rows + kRowsPerBlock - 1) / kRowsPerBlock);
+    if (op.kind == 0) {
+      DenseRows<V, Acc, kB> ro{static_cast<const V*>(tr ? op.AT : op.A), tr ? op.m : op.n};
+      k_rows<<<grid, kRowBlock, 0, s>>>(ro, rows, x, y, stop);
+    } else if (op.kind == 1) {
+      CsrRows<V, Acc, kB> ro{tr ? op.rpT : op.rp, tr ? op.ciT : op.ci,
+                             static_cast<const V*>(tr ? op.valT : op.val)};
+      k_rows<<<grid, kRowBlock, 0, s>>>(ro, rows, x, y, stop);
+    } else {
+      const int R = static_cast<int>(op.rows), C = static_cast<int>(op.cols);
+      with_ph(op.ph, [&](auto phc) {
+        constexpr int PH = decltype(phc)::value;
+        dim3 g((C + kPsfTW - 1) / kPsfTW, (R + kPsfTH - 1) / kPsfTH);
+        k_psf_corr<T, Acc, PH, kB><<<g, kPsfWaves * kWave,
+                                     psf_lds_bytes<Acc, PH>(op.pw), s>>>(
+            x, y, R, C, psf_weights<Acc>(op, tr), op.pw, stop);
+      });
+    }
+  });
 }
 
 }  // namespace
 
 void op_apply(const DeviceOp& op, int tr, const void* x, void* y,
               const int* stop, hipStream_t s) {
-  if (op.kind == 0) {
-    if (op.prec == kFP64) dense_apply<double, double, double, false>(op, tr, x, y, stop, s);
-    else if (op.prec == kFP32) dense_apply<float, float, double, false>(op, tr, x, y, stop, s);
-    else dense_apply<uint16_t, float, float, true>(op, tr, x, y, stop, s);
-  } else if (op.kind == 1) {
-    if (op.prec == kFP64) csr_apply<double, double, double, false>(op, tr, x, y, stop, s);
-    else if (op.prec == kFP32) csr_apply<float, float, double, false>(op, tr, x, y, stop, s);
-    else csr_apply<uint16_t, float, float, true>(op, tr, x, y, stop, s);
-  } else {
-    const int rows = static_cast<int>(op.rows), cols = static_cast<int>(op.cols);
-    if (op.prec == kFP64)
-      psf_launch<double, double, false>(static_cast<const double*>(x),
-                                        static_cast<double*>(y), rows, cols,
-                                        tr ? op.psf : op.psf_flip, op.ph, op.pw,
-                                        stop, s);
-    else if (op.prec == kFP32)
-      psf_launch<float, double, false>(static_cast<const float*>(x),
-                                       static_cast<float*>(y), rows, cols,
-                                       tr ? op.psf : op.psf_flip, op.ph, op.pw,
-                                       stop, s);
-    else
-      psf_launch<float, float, true>(static_cast<const float*>(x),
-                                     static_cast<float*>(y), rows, cols,
-                                     tr ? op.psf32 : op.psf32_flip, op.ph, op.pw,
-                                     stop, s);
-  }
+  if (op.prec == kFP64)
+    apply_t<double>(op, tr, static_cast<const double*>(x), static_cast<double*>(y), stop, s);
+  else
+    apply_t<float>(op, tr, static_cast<const float*>(x), static_cast<float*>(y), stop, s);
 }
 
 }  // namespace lslu

@@ -1,0 +1,708 @@
+// One half-iteration of the pivoted rectangular Hessenberg process
+// (Algorithm 4; the basis part of Algorithm 5) in one launch.
+//
+// The l side at iteration k (the d side mirrors it with A, D and t): the
+// previous launch left u, the unnormalised d-side vector (zero at t(1..k-1)),
+// and its per-block pivot candidates.
+//   block 0           t(k) = the row of the largest |u| among the candidates
+//                     (smallest row among equals), the breakdown test,
+//                     H(k,k-1) (or beta at k = 1) and the new triangle row
+//                     (d_1..d_{k-1})(t(k)); publishes (t(k), H(k,k-1)).  Then
+//                     solves T_L w = (A^T d_k)(g(1..k-1)) by forward
+//                     substitution and publishes w = W(1:k-1,k).
+//   blocks 1..nlead-1 (A^T d_k)(g(j)), one wavefront per j.
+//   other blocks      their rows of q0 = A^T d_k, d_k = u / H(k,k-1) into its
+//                     basis column (IEEE division: exactly 1 at t(k)), then
+//                     q = q0 - L_{k-1} w, q = 0 at g(1..k-1), and per block the
+//                     largest remaining |q|.
+// w equals the values the sequential loop of Algorithm 5 reads at g(j): l_i is
+// 1 at g(i) and 0 at g(j), j < i.  The forward substitution gives each row j
+// its subtractions in increasing i, as that loop does; floating-point
+// contraction is disabled there so each step rounds like a multiply then a
+// subtract.
+//
+// Products read the normalised vector as they gather it: each input is u(c)
+// divided by the pivot value (IEEE division), the same value the normalised
+// basis column holds, so products and exact cancellations are those of the
+// normalised vector.  The products therefore start once the pivot is
+// published; the triangular solve of block 0 overlaps them.
+//
+// Synchronisation inside the launch: blocks only ever wait for flags set by
+// lower-numbered blocks, which never wait for higher-numbered ones; workgroups
+// are dispatched in order, so the blocks that publish are resident first.
+// Every wait is bounded: a wait that runs out counts a device error and the
+// launch finishes.  Results do not depend on timing or on the launch
+// configuration.
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "device_common.hpp"
+
+namespace lslu {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / kWave;
+constexpr int kRowLanes = 16;                          // lanes per row
+constexpr int kRowsPerBlock = kThreads / kRowLanes;    // 16
+constexpr int kCoefPerLane = kMaxIter / kRowLanes;     // 16
+constexpr int kPartsPerThread = kMaxParts / kThreads;  // 16
+constexpr int kStage = 8;
+constexpr int kNormBatch = 8;
+constexpr int kSpinLimit = 1 << 20;
+constexpr int kTriB = 32;  // rows of a diagonal block of the triangular solve
+constexpr uint64_t kSentinel = kSlotEmpty;
+constexpr size_t kTriLdsMax = 32 * 1024;
+static_assert(sizeof(ArgPart) == 16, "candidates are read as 16-byte vectors");
+
+__host__ __device__ inline int64_t packed_row(int j) { return (int64_t)j * (j - 1) / 2; }
+
+// ------------------------------------------------------------------ flags --
+// Called by thread 0 of block 0 after a block barrier: the release store makes
+// the block's earlier stores visible at device scope before the flag.  Only
+// block 0 publishes (twice per launch).  Waiting blocks read everything that
+// is produced inside the launch (the pivot, the coefficients, the pivot
+// entries) with device-coherent loads, so they never fence: a device-scope
+// fence writes back and invalidates the whole L2 of its XCD.
+__device__ inline void publish(int* flag, int v) {
+  __hip_atomic_store(flag, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline uint64_t load_u64(const double* p) {
+  return __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline int load_i(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline double load_d(const double* p) {
+  return __builtin_bit_cast(
+      double, __hip_atomic_load(reinterpret_cast<const uint64_t*>(p),
+                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// Block-wide bounded wait until *flag reaches `target` (nonzero: any nonzero
+// value).  Returns the value seen, or 0 when the bound ran out.
+__device__ inline int block_wait(const int* flag, int target, DevState* st) {
+  __shared__ int seen;
+  if (threadIdx.x == 0) {
+    int v = 0;
+    for (int it = 0; it < kSpinLimit; ++it) {
+      v = load_i(flag);
+      if (target ? v >= target : v != 0) break;
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (!(target ? v >= target : v != 0)) {
+      atomicAdd(&st->spin_timeouts, 1);
+      v = 0;
+    }
+    seen = v;
+  }
+  __syncthreads();
+  return seen;
+}
+
+// ------------------------------------------------------- triangular solve --
+// T g = g in place for the nb x nb unit lower triangular T packed by rows
+// (row j at offset j(j-1)/2 holds T(j, 0..j-1)), in 32-row blocks:
+// wavefront 0 keeps its lanes' rows of the diagonal block in registers (zero
+// above the diagonal) and runs the dependent chain with w_i broadcast by
+// readlane; the workgroup then updates the rows below.
+template <typename T>
+__device__ __attribute__((always_inline)) inline void trisolve_inplace(
+    double* g, int nb, const T* __restrict__ tp) {
+#pragma clang fp contract(off)
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  for (int b0 = 0; b0 < nb; b0 += kTriB) {
+    const int bs = min(kTriB, nb - b0);
+    if (w == 0) {
+      const int j = b0 + lane;
+      const bool act = lane < bs;
+      const T* row = tp + packed_row(act ? j : b0) + b0;  // T(j, b0 + i) = row[i]
+      T tr[kTriB];
+#pragma unroll
+      for (int i = 0; i < kTriB; ++i) tr[i] = (act && i < lane) ? row[i] : T(0);
+      double gl = act ? g[j] : 0.0;
+#pragma unroll
+      for (int i = 0; i < kTriB; ++i) {
+        const double wi = readlane_d(gl, i);
+        gl = gl - static_cast<double>(tr[i]) * wi;  // tr[i] == 0 unless i < lane
+      }
+      if (act) g[j] = gl;
+    }
+    __syncthreads();
+    for (int j = b0 + bs + tid; j < nb; j += kThreads) {
+      const T* row = tp + packed_row(j) + b0;
+      double gj = g[j];
+      int i = 0;
+      for (; i + 8 <= bs; i += 8) {
+        double tv[8], wv8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          tv[u] = static_cast<double>(row[i + u]);
+          wv8[u] = g[b0 + i + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) gj = gj - tv[u] * wv8[u];
+      }
+      for (; i < bs; ++i) gj = gj - static_cast<double>(row[i]) * g[b0 + i];
+      g[j] = gj;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ block 0 -----
+template <typename T, bool kTriLds>
+__device__ void lead(const HalfArgs<T>& a, DevState* st, unsigned char* lds) {
+  __shared__ double g[kMaxIter + 1];
+  __shared__ int all_in;
+  const int tid = threadIdx.x;
+  const int nb = a.rows > 0 ? a.nb : 0;
+  // The triangle's first pass and the candidates are loaded before either is
+  // used.
+  T tbuf[kStage];
+  const int64_t P = (kTriLds && nb > 1) ? packed_row(nb) : 0;
+#pragma unroll
+  for (int u = 0; u < kStage; ++u) {
+    const int64_t p = (int64_t)u * kThreads + tid;
+    tbuf[u] = (p < P) ? a.Tp[p] : T(0);
+  }
+  double key = -1.0;
+  int idx = INT_MAX;
+  constexpr int kHalf = kPartsPerThread / 2;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    int4 raw[kHalf];
+#pragma unroll
+    for (int u = 0; u < kHalf; ++u) {
+      const int i = tid + (h * kHalf + u) * kThreads;
+      raw[u] = (i < a.nparts_in) ? reinterpret_cast<const int4*>(a.parts_in)[i]
+                                 : make_int4(0, 0, INT_MAX, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < kHalf; ++u) {
+      const int i = tid + (h * kHalf + u) * kThreads;
+      const double k2 = (i < a.nparts_in)
+          ? __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(raw[u].y)) << 32) |
+                                           static_cast<uint32_t>(raw[u].x))
+          : -1.0;
+      if (better(k2, raw[u].z, key, idx)) {
+        key = k2;
+        idx = raw[u].z;
+      }
+    }
+  }
+  block_argmax<kThreads>(key, idx);
+  const PivotJob& job = a.job;
+  const int own = (job.eligible && key > 0.0) ? idx : -1;
+  const int pick = job.replay ? (job.eligible ? job.replay[job.piv_pos] : -1) : own;
+  const double val = (pick >= 0) ? static_cast<double>(a.up[pick]) : 0.0;
+  const bool brk = (pick < 0 || val == 0.0);
+  if (tid == 0) {
+    if (job.own_list) job.own_list[job.piv_pos] = own;
+    if (job.replay && pick != own) {
+      if (job.side == 0) st->mismatch_g += 1; else st->mismatch_t += 1;
+    }
+    if (brk) {
+      // Breakdown: no eligible nonzero entry (Algorithm 4, "else break").
+      st->stopped = 1;
+      if (job.side == 2) {
+        st->status = kZeroRHS;
+        st->k_done = 0;
+      } else if (job.side == 0) {
+        st->status = kBreakQ;  // x stays x_{k-1}
+      } else {
+        *job.piv_val = 0.0;    // H(k+1,k) = 0; x_k is still formed
+        st->status = kBreakU;
+        st->k_done = job.k;
+      }
+    } else {
+      *job.piv_val = val;
+      job.piv_list[job.piv_pos] = pick;
+      job.mask[pick] = 1;
+      st->cur_pick = pick;
+      st->cur_val = val;
+      if (job.side == 2) {
+        st->beta = val;
+        st->n_d = 1;
+      } else if (job.side == 0) {
+        st->n_l = job.k;
+      } else {
+        st->n_d = job.k + 1;
+        st->k_done = job.k;
+      }
+    }
+    publish(&a.flags[0], brk ? 2 : 1);
+  }
+  if (brk) return;
+  if (a.Trowp) {  // needed by later launches only
+    for (int j = tid; j < a.nbp; j += kThreads)
+      a.Trowp[j] = a.basisp[(int64_t)pick * a.rsp + (int64_t)j * a.csp];
+  }
+  if (a.rows == 0) return;
+  if (nb == 0) {
+    if (tid == 0) publish(&a.flags[1], 1);
+    return;
+  }
+  if constexpr (kTriLds) {
+    T* lt = reinterpret_cast<T*>(lds);
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int64_t p = (int64_t)u * kThreads + tid;
+      if (p < P) lt[p] = tbuf[u];
+    }
+    for (int64_t p0 = (int64_t)kThreads * kStage; p0 < P; p0 += (int64_t)kThreads * kStage) {
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) {
+        const int64_t p = p0 + (int64_t)u * kThreads + tid;
+        tbuf[u] = (p < P) ? a.Tp[p] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) {
+        const int64_t p = p0 + (int64_t)u * kThreads + tid;
+        if (p < P) lt[p] = tbuf[u];
+      }
+    }
+  }
+  // The pivot entries of the product, written once by blocks 1..nlead-1.
+  bool got = true;
+  for (int j = tid; j < nb; j += kThreads) {
+    uint64_t bits = kSentinel;
+    for (int it = 0; it < kSpinLimit; ++it) {
+      bits = load_u64(a.ybuf + j);
+      if (bits != kSentinel) break;
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (bits == kSentinel) got = false;
+    g[j] = __builtin_bit_cast(double, bits);
+  }
+  if (tid == 0) all_in = 1;
+  __syncthreads();
+  if (!got) all_in = 0;
+  __syncthreads();
+  if (!all_in) {
+    if (tid == 0) {
+      atomicAdd(&st->spin_timeouts, 1);
+      publish(&a.flags[1], 3);
+    }
+    return;
+  }
+  if constexpr (kTriLds)
+    trisolve_inplace<T>(g, nb, reinterpret_cast<const T*>(lds));
+  else
+    trisolve_inplace<T>(g, nb, a.Tp);
+  for (int j = tid; j < nb; j += kThreads) a.coef[j] = g[j];
+  __syncthreads();
+  if (tid == 0) publish(&a.flags[1], 1);
+}
+
+// ------------------------------------------------- pivot-entry blocks -----
+template <typename T, class RowOp>
+__device__ void pivot_entries(const HalfArgs<T>& a, const RowOp& op, DevState* st) {
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const int jr = (blockIdx.x - 1) * kWaves + w;
+  const bool act = jr < a.nb;
+  const int row = act ? a.piv[jr] : 0;
+  if (block_wait(&a.flags[0], 0, st) != 1) return;
+  const T vt = static_cast<T>(load_d(&st->cur_val));
+  if (!act) return;
+  auto xf = [&](int64_t c) -> T { return a.up[c] / vt; };
+  typename RowOp::Acc acc = op.template partial<kWave>(row, lane, xf);
+  acc = group_sum<kWave>(acc);
+  if (lane == 0) {
+    const double y = static_cast<double>(static_cast<T>(acc));
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(a.ybuf) + jr,
+                       __builtin_bit_cast(uint64_t, y), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Normalise this block's share of the previous vector into its basis column.
+template <typename T>
+__device__ inline void normalise_share(const HalfArgs<T>& a, int cb, int ncons,
+                                       int pick, T vt) {
+  const int64_t step = (int64_t)ncons * kThreads;
+  for (int64_t i0 = (int64_t)cb * kThreads + threadIdx.x; i0 < a.lenp;
+       i0 += step * kNormBatch) {
+    T vv[kNormBatch];
+#pragma unroll
+    for (int u = 0; u < kNormBatch; ++u) {
+      const int64_t i = i0 + u * step;
+      vv[u] = (i < a.lenp) ? a.up[i] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kNormBatch; ++u) {
+      const int64_t i = i0 + u * step;
+      if (i < a.lenp) a.dstp[i * a.dstp_stride] = (i == pick) ? T(1) : vv[u] / vt;
+    }
+  }
+}
+
+__device__ inline void write_part(ArgPart* parts, int b, double key, int idx) {
+  parts[b].key = key;
+  parts[b].idx = idx;
+}
+
+// Waits for the coefficients and stages them in LDS; false when the launch
+// is to end (breakdown or error).
+template <typename T>
+__device__ inline bool fetch_coef(const HalfArgs<T>& a, DevState* st, double* cf) {
+  if (a.nb == 0) return true;
+  if (block_wait(&a.flags[1], 0, st) != 1) return false;
+  for (int j = threadIdx.x; j < a.nb; j += kThreads) cf[j] = load_d(a.coef + j);
+  __syncthreads();
+  return true;
+}
+
+// --------------------------------------------------- row consumer blocks --
+// Persistent over rows r = (cb + i ncons) * 16 + group: every product first
+// (its value parked in out[r]), then one wait for the coefficients, then the
+// elimination.  A waiting block therefore never holds resources that
+// undispatched work needs.
+template <typename T, class RowOp>
+__device__ void consume_rows(const HalfArgs<T>& a, const RowOp& op, DevState* st,
+                             int cb, int ncons) {
+  using Acc = typename RowOp::Acc;
+  __shared__ double cf[kMaxIter];
+  __shared__ double sk[kRowsPerBlock];
+  __shared__ int si[kRowsPerBlock];
+  const int tid = threadIdx.x, sub = tid % kRowLanes, rl = tid / kRowLanes;
+  const int nb = a.nb;
+  const int64_t stride = (int64_t)ncons * kRowsPerBlock;
+  const int64_t r0 = (int64_t)cb * kRowsPerBlock + rl;
+  if (block_wait(&a.flags[0], 0, st) != 1) return;
+  const int pick = load_i(&st->cur_pick);
+  const T vt = static_cast<T>(load_d(&st->cur_val));
+  auto xf = [&](int64_t c) -> T { return a.up[c] / vt; };
+  for (int64_t r = r0; r < a.rows; r += stride) {
+    Acc acc = op.template partial<kRowLanes>(r, sub, xf);
+    acc = group_sum<kRowLanes>(acc);
+    if (sub == 0) a.out[r] = static_cast<T>(acc);
+  }
+  normalise_share(a, cb, ncons, pick, vt);
+  if (a.rows == 0) return;
+  if (!fetch_coef(a, st, cf)) return;
+  double key = -1.0;
+  int idx = INT_MAX;
+  for (int64_t r = r0; r < a.rows; r += stride) {
+    const bool piv = a.mask[r] != 0;
+    const T* brow = a.basis + r * a.rs;
+    T bv[kCoefPerLane];
+#pragma unroll
+    for (int u = 0; u < kCoefPerLane; ++u) {
+      const int j = sub + u * kRowLanes;
+      bv[u] = (j < nb) ? brow[(int64_t)j * a.cs] : T(0);
+    }
+    double e = 0.0;
+#pragma unroll
+    for (int u = 0; u < kCoefPerLane; ++u) {
+      const int j = sub + u * kRowLanes;
+      if (j < nb) e = fma(cf[j], static_cast<double>(bv[u]), e);
+    }
+    e = group_sum<kRowLanes>(e);
+    if (sub == 0) {
+      const double q0 = static_cast<double>(a.out[r]);
+      const T o = piv ? T(0) : static_cast<T>(q0 - e);
+      a.out[r] = o;
+      const double k2 = piv ? -1.0 : fabs(static_cast<double>(o));
+      if (better(k2, (int)r, key, idx)) {
+        key = k2;
+        idx = (int)r;
+      }
+    }
+  }
+  if (sub == 0) {
+    sk[rl] = key;
+    si[rl] = idx;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int i = 1; i < kRowsPerBlock; ++i)
+      if (better(sk[i], si[i], key, idx)) {
+        key = sk[i];
+        idx = si[i];
+      }
+    write_part(a.parts_out, cb, key, idx);
+  }
+}
+
+template <typename T, class RowOp, bool kTriLds>
+__global__ __launch_bounds__(kThreads) void k_half_rows(HalfArgs<T> a, RowOp op) {
+  extern __shared__ unsigned char lds[];
+  DevState* st = a.job.st;
+  if (st->stopped) return;
+  if (blockIdx.x == 0)
+    lead<T, kTriLds>(a, st, lds);
+  else if ((int)blockIdx.x < a.nlead)
+    pivot_entries<T, RowOp>(a, op, st);
+  else
+    consume_rows<T, RowOp>(a, op, st, blockIdx.x - a.nlead, gridDim.x - a.nlead);
+}
+
+// --------------------------------------------------- PSF consumer blocks --
+// The tile of the normalised input: each staged entry is u divided by the
+// pivot value, then (BF16 mode) rounded to bfloat16.
+template <typename T, typename Acc, int PH, bool kBf16>
+__device__ inline void psf_tile_norm(const T* __restrict__ u, T vt, int rows,
+                                     int cols, const Acc* __restrict__ Wt, int pw,
+                                     int i0, int j0, Acc* tile, Acc (&acc)[kPsfR]) {
+  const int ch = PH / 2, cw = pw / 2;
+  const int TR = kPsfTH + PH - 1, TC = kPsfTW + pw - 1;
+  for (int e = threadIdx.x; e < TR * TC; e += kThreads) {
+    const int tr = e / TC, tc = e - tr * TC;
+    const int gi = i0 - ch + tr, gj = j0 - cw + tc;
+    Acc v = 0;
+    if (gi >= 0 && gi < rows && gj >= 0 && gj < cols)
+      v = static_cast<Acc>(in_val<kBf16>(u[(int64_t)gi * cols + gj] / vt));
+    tile[e] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int r0 = (threadIdx.x / kWave) * kPsfR;
+#pragma unroll
+  for (int p = 0; p < kPsfR; ++p) acc[p] = 0;
+  for (int b = 0; b < pw; ++b) {
+    Acc s[kPsfR + PH - 1];
+#pragma unroll
+    for (int q = 0; q < kPsfR + PH - 1; ++q) s[q] = tile[(r0 + q) * TC + lane + b];
+#pragma unroll
+    for (int aa = 0; aa < PH; ++aa) {
+      const Acc wv = Wt[aa * pw + b];
+#pragma unroll
+      for (int p = 0; p < kPsfR; ++p) acc[p] = fma(wv, s[p + aa], acc[p]);
+    }
+  }
+  __syncthreads();  // the tile may be restaged next
+}
+
+// Persistent over tiles cb, cb + ncons, ...: products first (parked in out),
+// then the coefficients, then the elimination.
+template <typename T, typename Acc, int PH, bool kBf16>
+__device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
+                              int rows, int cols, int pw, DevState* st, int cb,
+                              int ncons, unsigned char* lds) {
+  __shared__ double cf[kMaxIter];
+  Acc* tile = reinterpret_cast<Acc*>(lds);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int r0 = (threadIdx.x / kWave) * kPsfR;
+  const int tiles_x = (cols + kPsfTW - 1) / kPsfTW;
+  const int ntiles = a.rows > 0 ? tiles_x * ((rows + kPsfTH - 1) / kPsfTH) : 0;
+  const int nb = a.nb;
+  if (block_wait(&a.flags[0], 0, st) != 1) return;
+  const int pick = load_i(&st->cur_pick);
+  const T vt = static_cast<T>(load_d(&st->cur_val));
+  for (int t = cb; t < ntiles; t += ncons) {
+    const int i0 = (t / tiles_x) * kPsfTH, j0 = (t % tiles_x) * kPsfTW;
+    Acc acc[kPsfR];
+    psf_tile_norm<T, Acc, PH, kBf16>(a.up, vt, rows, cols, Wt, pw, i0, j0, tile, acc);
+    const int gj = j0 + lane;
+#pragma unroll
+    for (int p = 0; p < kPsfR; ++p) {
+      const int gi = i0 + r0 + p;
+      if (gi < rows && gj < cols) a.out[(int64_t)gi * cols + gj] = static_cast<T>(acc[p]);
+    }
+  }
+  normalise_share(a, cb, ncons, pick, vt);
+  if (a.rows == 0) return;
+  if (!fetch_coef(a, st, cf)) return;
+  double best = -1.0;
+  int bidx = INT_MAX;
+  for (int t = cb; t < ntiles; t += ncons) {
+    const int i0 = (t / tiles_x) * kPsfTH, j0 = (t % tiles_x) * kPsfTW;
+    const int gj = j0 + lane;
+    int64_t pix[kPsfR];
+    bool ok[kPsfR];
+    unsigned char mk[kPsfR];
+#pragma unroll
+    for (int p = 0; p < kPsfR; ++p) {
+      const int gi = i0 + r0 + p;
+      ok[p] = gi < rows && gj < cols;
+      pix[p] = ok[p] ? (int64_t)gi * cols + gj : 0;  // in bounds either way
+      mk[p] = a.mask[pix[p]];
+    }
+    double e[kPsfR];
+#pragma unroll
+    for (int p = 0; p < kPsfR; ++p) e[p] = 0.0;
+    int j = 0;
+    for (; j + 2 <= nb; j += 2) {
+      const T* c0 = a.basis + (int64_t)j * a.cs;
+      const T* c1 = c0 + a.cs;
+      T b0[kPsfR], b1[kPsfR];
+#pragma unroll
+      for (int p = 0; p < kPsfR; ++p) {
+        b0[p] = c0[pix[p]];
+        b1[p] = c1[pix[p]];
+      }
+      const double w0 = cf[j], w1 = cf[j + 1];
+#pragma unroll
+      for (int p = 0; p < kPsfR; ++p) {
+        e[p] = fma(w0, static_cast<double>(b0[p]), e[p]);
+        e[p] = fma(w1, static_cast<double>(b1[p]), e[p]);
+      }
+    }
+    if (j < nb) {
+      const T* c0 = a.basis + (int64_t)j * a.cs;
+      const double w0 = cf[j];
+#pragma unroll
+      for (int p = 0; p < kPsfR; ++p) e[p] = fma(w0, static_cast<double>(c0[pix[p]]), e[p]);
+    }
+#pragma unroll
+    for (int p = 0; p < kPsfR; ++p) {
+      if (!ok[p]) continue;
+      const double q0 = static_cast<double>(a.out[pix[p]]);
+      const T o = mk[p] ? T(0) : static_cast<T>(q0 - e[p]);
+      a.out[pix[p]] = o;
+      const double k2 = mk[p] ? -1.0 : fabs(static_cast<double>(o));
+      if (better(k2, (int)pix[p], best, bidx)) {
+        best = k2;
+        bidx = (int)pix[p];
+      }
+    }
+  }
+  block_argmax<kThreads>(best, bidx);
+  if (threadIdx.x == 0) write_part(a.parts_out, cb, best, bidx);
+}
+
+template <typename T, typename Acc, int PH, bool kBf16, bool kTriLds>
+__global__ __launch_bounds__(kThreads) void k_half_psf(
+    HalfArgs<T> a, PsfPixels<Acc, kBf16> op, const Acc* __restrict__ Wt) {
+  extern __shared__ unsigned char lds[];
+  DevState* st = a.job.st;
+  if (st->stopped) return;
+  if (blockIdx.x == 0)
+    lead<T, kTriLds>(a, st, lds);
+  else if ((int)blockIdx.x < a.nlead)
+    pivot_entries<T, PsfPixels<Acc, kBf16>>(a, op, st);
+  else
+    consume_tiles<T, Acc, PH, kBf16>(a, Wt, op.rows, op.cols, op.pw, st,
+                                     blockIdx.x - a.nlead, gridDim.x - a.nlead, lds);
+}
+
+static_assert(kPsfWaves * kWave == kThreads, "PSF tiles use the launch's block size");
+
+// ------------------------------------------------------------- launchers --
+template <typename T>
+size_t tri_bytes(int nb) {
+  return nb > 1 ? sizeof(T) * (size_t)packed_row(nb) : 0;
+}
+
+// Blocks of `kernel` that fit on the device at once (cached per kernel, LDS
+// size and device); 0 if the runtime cannot tell.
+int resident_blocks(const void* kernel, size_t dyn_lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void*, size_t, int>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  const auto key = std::make_tuple(kernel, dyn_lds, dev);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, dyn_lds) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  cache[key] = per_cu * cus;
+  return per_cu * cus;
+}
+
+// Consumer blocks: enough for the work, at most kMaxParts, and (persistent)
+// no more than fit beside the leading blocks.
+int consumer_blocks(int64_t want, int nlead, int resident) {
+  int64_t c = std::min<int64_t>(std::max<int64_t>(want, 1), kMaxParts);
+  if (resident > nlead) c = std::min<int64_t>(c, resident - nlead);
+  return static_cast<int>(c);
+}
+
+template <typename T, class RowOp>
+int launch_rows(HalfArgs<T>& a, const RowOp& op, size_t lds_bytes, hipStream_t s) {
+  const int64_t want = a.rows > 0 ? (a.rows + kRowsPerBlock - 1) / kRowsPerBlock
+                                  : (a.lenp + kThreads * kNormBatch - 1) / (kThreads * kNormBatch);
+  const int nbk = a.rows > 0 ? a.nb : 0;
+  a.nlead = 1 + (nbk + kWaves - 1) / kWaves;
+  const size_t tb = tri_bytes<T>(nbk);
+  const bool in_lds = tb > 0 && tb <= kTriLdsMax && tb + 16 * 1024 <= lds_bytes;
+  if (in_lds) {
+    auto k = k_half_rows<T, RowOp, true>;
+    const int ncons = consumer_blocks(want, a.nlead, resident_blocks((const void*)k, tb));
+    k<<<a.nlead + ncons, kThreads, tb, s>>>(a, op);
+    return ncons;
+  }
+  auto k = k_half_rows<T, RowOp, false>;
+  const int ncons = consumer_blocks(want, a.nlead, resident_blocks((const void*)k, 0));
+  k<<<a.nlead + ncons, kThreads, 0, s>>>(a, op);
+  return ncons;
+}
+
+template <typename T, typename Acc, int PH, bool kBf16>
+int launch_tiles(HalfArgs<T>& a, const PsfPixels<Acc, kBf16>& op, const Acc* Wt,
+                 size_t lds_bytes, hipStream_t s) {
+  const int ntiles = ((op.cols + kPsfTW - 1) / kPsfTW) * ((op.rows + kPsfTH - 1) / kPsfTH);
+  const int64_t want = a.rows > 0 ? ntiles
+                                  : (a.lenp + kThreads * kNormBatch - 1) / (kThreads * kNormBatch);
+  const int nbk = a.rows > 0 ? a.nb : 0;
+  a.nlead = 1 + (nbk + kWaves - 1) / kWaves;
+  const size_t tb = tri_bytes<T>(nbk);
+  const size_t pb = psf_lds_bytes<Acc, PH>(op.pw);
+  const bool in_lds = tb > 0 && tb <= kTriLdsMax && std::max(tb, pb) + 16 * 1024 <= lds_bytes;
+  if (in_lds) {
+    auto k = k_half_psf<T, Acc, PH, kBf16, true>;
+    const size_t dyn = std::max(tb, pb);
+    const int ncons = consumer_blocks(want, a.nlead, resident_blocks((const void*)k, dyn));
+    k<<<a.nlead + ncons, kThreads, dyn, s>>>(a, op, Wt);
+    return ncons;
+  }
+  auto k = k_half_psf<T, Acc, PH, kBf16, false>;
+  const int ncons = consumer_blocks(want, a.nlead, resident_blocks((const void*)k, pb));
+  k<<<a.nlead + ncons, kThreads, pb, s>>>(a, op, Wt);
+  return ncons;
+}
+
+}  // namespace
+
+template <typename T>
+int launch_half(HalfArgs<T>& a, const DeviceOp& op, int tr, size_t lds_bytes,
+                hipStream_t s) {
+  int nparts = 0;
+  with_mode<T>(op.prec, [&](auto v, auto acc, auto bf) {
+    using V = decltype(v);
+    using Acc = decltype(acc);
+    constexpr bool kB = decltype(bf)::value;
+    if (op.kind == 0) {
+      DenseRows<V, Acc, kB> ro{static_cast<const V*>(tr ? op.AT : op.A), tr ? op.m : op.n};
+      nparts = launch_rows<T, decltype(ro)>(a, ro, lds_bytes, s);
+    } else if (op.kind == 1) {
+      CsrRows<V, Acc, kB> ro{tr ? op.rpT : op.rp, tr ? op.ciT : op.ci,
+                             static_cast<const V*>(tr ? op.valT : op.val)};
+      nparts = launch_rows<T, decltype(ro)>(a, ro, lds_bytes, s);
+    } else {
+      const Acc* wt;
+      if constexpr (std::is_same_v<Acc, double>)
+        wt = tr ? op.psf : op.psf_flip;
+      else
+        wt = tr ? op.psf32 : op.psf32_flip;
+      PsfPixels<Acc, kB> ro{wt, static_cast<int>(op.rows), static_cast<int>(op.cols),
+                            op.ph, op.pw};
+      with_ph(op.ph, [&](auto phc) {
+        constexpr int PH = decltype(phc)::value;
+        nparts = launch_tiles<T, Acc, PH, kB>(a, ro, wt, lds_bytes, s);
+      });
+    }
+  });
+  return nparts;
+}
+
+void recurrence_init_attributes(size_t lds_bytes) {
+  // Dynamic LDS stays below 64 KB (triangle up to 32 KB, PSF tile up to
+  // 46.6 KB), within the default limit.
+  (void)lds_bytes;
+}
+
+template int launch_half<double>(HalfArgs<double>&, const DeviceOp&, int, size_t, hipStream_t);
+template int launch_half<float>(HalfArgs<float>&, const DeviceOp&, int, size_t, hipStream_t);
+
+}  // namespace lslu
