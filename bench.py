@@ -12,9 +12,10 @@ bins (m = 32580, n = 16384, CSR with bilinear ray-length weights), 2% noise,
 FP64 sums, projected problem and pivot divisions).  The FP64 plain mode is
 timed on the same problem and both relative errors are reported.
 
-The JSON line also carries the roofline of the dominant kernel (timed with HIP
-events on the library's stream) and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+The JSON line also carries the roofline of the dominant kernel -- the
+half-iteration kernel of the recurrence (one launch per half-iteration), timed
+by the library with HIP events on the stream it launches on -- and the FP64
+CPU oracle timed on a bounded sample of the same workload.
 """
 
 from __future__ import annotations
@@ -35,7 +36,7 @@ PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 def _kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("operators.hip", "internal.hpp"):
+    for f in ("recurrence.hip", "device_common.hpp", "internal.hpp"):
         with open(os.path.join(ROOT, "paper_2409_05239_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -55,10 +56,30 @@ def _load_traffic(kernel, workload):
     return ent.get("bytes_per_launch")
 
 
-def csr_spmv_bytes(nnz, rows, cols, esz):
+def csr_spmv_bytes(nnz, rows, cols, vsz, esz):
     """Algorithmic bytes of one CSR product: values + column indices, row
     pointers, the input vector once and the output once."""
-    return nnz * (esz + 4) + 4 * (rows + 1) + esz * cols + esz * rows
+    return nnz * (vsz + 4) + 4 * (rows + 1) + esz * cols + esz * rows
+
+
+def recurrence_bytes(prob, K, vsz, esz):
+    """Algorithmic HBM bytes of the 2K + 1 launches of the recurrence: per
+    half-iteration the operator product (CSR: values, indices, row pointers,
+    input once, output once), the earlier basis vectors of the side once, the
+    pivot mask, and the previous vector read and written once normalised; the
+    last launch only normalises d_{K+1}."""
+    m, n = prob.m, prob.n
+    if prob.kind == "csr":
+        op = {1: csr_spmv_bytes(prob.nnz, n, m, vsz, esz),   # A^T: n rows
+              0: csr_spmv_bytes(prob.nnz, m, n, vsz, esz)}   # A:   m rows
+    else:
+        op = {1: esz * (m + n), 0: esz * (m + n)}
+    total = 0
+    for k in range(1, K + 1):
+        total += op[1] + esz * n * (k - 1) + n + 2 * esz * m   # l side
+        total += op[0] + esz * m * k + m + 2 * esz * n         # d side
+    total += 2 * esz * m
+    return total
 
 
 def run(args):
@@ -75,7 +96,9 @@ def run(args):
     grid = lambda_grid()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    ctx = capi.lslu_create(0)
+    # The library launches on this stream; every event below is recorded on it.
+    stream = torch.cuda.Stream(device=dev)
+    ctx = capi.lslu_create(0, stream=stream)
 
     def setup(p):
         dt = torch.float64 if p == "fp64" else torch.float32
@@ -83,11 +106,13 @@ def run(args):
         b = torch.tensor(prob.b, dtype=dt, device=dev)
         X = torch.zeros((K, prob.n), dtype=dt, device=dev)
         x = torch.zeros(prob.n, dtype=dt, device=dev)
+        torch.cuda.synchronize()
         return op, b, X, x
 
-    def solve(op, b, X, x):
+    def solve(op, b, X, x, timing=False):
         return capi.lslu_solve(ctx, op, b, K, reg=cfg["reg"], grid=grid,
-                               grid_relative=cfg["grid_relative"], X=X, x_out=x)
+                               grid_relative=cfg["grid_relative"], X=X, x_out=x,
+                               timing=timing)
 
     def timed(p, steps, warmup):
         op, b, X, x = setup(p)
@@ -102,7 +127,10 @@ def run(args):
         Xh = X.double().cpu().numpy()
         xt = prob.x_true
         errs = np.linalg.norm(Xh[:info["k_done"]] - xt[None, :], axis=1) / np.linalg.norm(xt)
-        return op, el, info, errs
+        # one more solve with the library's phase events (eager launches)
+        _, _, tinfo = solve(op, b, X, x, timing=True)
+        torch.cuda.synchronize()
+        return op, el, info, errs, tinfo["timing"]
 
     print(f"[bench] workload={args.workload} m={prob.m} n={prob.n} nnz={prob.nnz} "
           f"K={K} prec={prec}", flush=True)
@@ -114,45 +142,37 @@ def run(args):
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    op, el, info, errs = timed(prec, args.steps, args.warmup)
+    op, el, info, errs, tm = timed(prec, args.steps, args.warmup)
     ms = el / args.steps * 1e3
     print(f"[bench] {prec}: {ms:.3f} ms/step", flush=True)
     fp64 = None
     if prec != "fp64" and not args.no_fp64:
-        op64, el64, info64, errs64 = timed("fp64", args.steps, args.warmup)
+        op64, el64, info64, errs64, _ = timed("fp64", args.steps, args.warmup)
         fp64 = dict(iters_per_s=K * args.steps / el64, ms_per_step=el64 / args.steps * 1e3,
                     rel_err_final=float(errs64[-1]), rel_err_min=float(errs64.min()),
                     k_min=int(errs64.argmin()) + 1)
         capi.lslu_op_destroy(op64)
         print(f"[bench] fp64: {fp64['ms_per_step']:.3f} ms/step", flush=True)
 
-    # Dominant kernel: the operator product, timed with HIP events on the
-    # library's stream (torch's current stream) through lslu_op_apply.
-    dt = torch.float64 if prec == "fp64" else torch.float32
-    xin = torch.rand(prob.m, dtype=dt, device=dev)
-    yout = torch.empty(prob.n, dtype=dt, device=dev)
-    reps = 200
-    for _ in range(10):
-        capi.lslu_op_apply(ctx, op, 1, xin, yout)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        capi.lslu_op_apply(ctx, op, 1, xin, yout)
-    e1.record()
-    torch.cuda.synchronize()
-    t_launch = e0.elapsed_time(e1) / reps * 1e-3
+    # Dominant kernel: the half-iteration kernel of the recurrence.  Its
+    # average launch duration is the recurrence's device time (HIP events the
+    # library records on its stream around the 2K + 1 launches) per launch.
     esz = 8 if prec == "fp64" else 4
-    if prob.kind == "csr":
-        kname = "k_csr_rows"
-        nbytes = csr_spmv_bytes(prob.nnz, prob.n, prob.m, esz if prec != "bf16op" else 2)
-    else:
-        kname = "operator"
-        nbytes = esz * (prob.m + prob.n)
+    vsz = {"fp64": 8, "fp32": 4, "bf16op": 2}[prec]
+    n_launch = tm["n_recurrence_launches"]
+    t_launch = tm["t_recurrence_ms"] * 1e-3 / n_launch
+    nbytes = recurrence_bytes(prob, K, vsz, esz) / n_launch
+    kname = "k_half_rows" if prob.kind in ("csr", "dense") else "k_half_psf"
     achieved = nbytes / t_launch / 1e9
-    roof = dict(bound="hbm", kernel=f"{kname} (A^T product)", achieved=round(achieved, 1),
+    roof = dict(bound="hbm", kernel=f"{kname} (one half-iteration: product, "
+                "elimination, pivot)", achieved=round(achieved, 1),
                 peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
                 traffic=_load_traffic(kname, args.workload),
-                us_per_launch=round(t_launch * 1e6, 3), bytes_per_launch=int(nbytes))
+                us_per_launch=round(t_launch * 1e6, 3), bytes_per_launch=int(nbytes),
+                launches_per_step=n_launch,
+                phase_ms=dict(recurrence=round(tm["t_recurrence_ms"], 4),
+                              projected=round(tm["t_projected_ms"], 4),
+                              assemble=round(tm["t_assemble_ms"], 4)))
 
     cpu = None
     if not args.no_cpu_baseline:

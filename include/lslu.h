@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LSLU_ABI_VERSION 2
+#define LSLU_ABI_VERSION 3
 
 typedef enum lslu_status {
   LSLU_OK = 0,
@@ -173,7 +173,12 @@ typedef struct lslu_opts {
 typedef enum lslu_flag {
   /* Enqueue every kernel directly instead of replaying the context's cached
    * HIP graph of the solve.  Results are identical either way. */
-  LSLU_FLAG_EAGER = 1
+  LSLU_FLAG_EAGER = 1,
+  /* Enqueue directly (as LSLU_FLAG_EAGER) and record HIP events on the
+   * context's stream around the recurrence, the projected problems and the
+   * assembly; the elapsed times are returned in lslu_result.  Events between
+   * launches add a little time of their own. */
+  LSLU_FLAG_TIMING = 2
 } lslu_flag;
 
 typedef struct lslu_result {
@@ -197,6 +202,13 @@ typedef struct lslu_result {
   double* sep_lambda; /* maxiter: (G_2 - G_1)/G_1 over the grid */
   double* sigma_max;  /* maxiter: largest singular value of H_{k+1,k} */
   double* sigma_min;  /* maxiter: smallest singular value of H_{k+1,k} */
+  /* With LSLU_FLAG_TIMING (else 0): device time of the basis recurrence
+   * (n_recurrence_launches launches, one per half-iteration plus the last
+   * pivot), of the projected problems and of the assembly of the iterates. */
+  double t_recurrence_ms;
+  int32_t n_recurrence_launches;
+  double t_projected_ms;
+  double t_assemble_ms;
 } lslu_result;
 
 /* Run Hybrid LSLU (LSLU with LSLU_REG_NONE) for opts->maxiter iterations.

@@ -66,6 +66,7 @@ class lslu_opts(ctypes.Structure):
 
 
 LSLU_FLAG_EAGER = 1
+LSLU_FLAG_TIMING = 2
 
 
 class lslu_result(ctypes.Structure):
@@ -91,6 +92,10 @@ class lslu_result(ctypes.Structure):
         ("sep_lambda", POINTER(c_double)),
         ("sigma_max", POINTER(c_double)),
         ("sigma_min", POINTER(c_double)),
+        ("t_recurrence_ms", c_double),
+        ("n_recurrence_launches", c_int32),
+        ("t_projected_ms", c_double),
+        ("t_assemble_ms", c_double),
     ]
 
 
@@ -256,7 +261,7 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
                grid_relative=False, omega=0.0, x0=None, x_true=None,
                stop_tol=0.0, early_stop=False, X=None, x_out=None,
                replay_piv_t=None, replay_piv_g=None, replay_lambda_idx=None,
-               eager=False):
+               eager=False, timing=False):
     """Run the solver.  ``b``, ``x0``, ``X``, ``x_out`` are torch device
     tensors in the working precision (``x_out`` is allocated when None).
     Returns ``(status, x_out, info)`` where ``info`` holds the host-side
@@ -282,7 +287,7 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
     o.stop_tol = float(stop_tol)
     o.early_stop = 1 if early_stop else 0
     o.X_dev = _dptr(X)
-    o.flags = LSLU_FLAG_EAGER if eager else 0
+    o.flags = (LSLU_FLAG_EAGER if eager else 0) | (LSLU_FLAG_TIMING if timing else 0)
     for name, arr in (("replay_piv_t", replay_piv_t), ("replay_piv_g", replay_piv_g),
                       ("replay_lambda_idx", replay_lambda_idx)):
         if arr is not None:
@@ -311,6 +316,11 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
                 lambda_k=host["lambda_k"], lambda_idx=host["lambda_idx"],
                 ghat=host["ghat"], sep_lambda=host["sep_lambda"],
                 sigma_max=host["sigma_max"], sigma_min=host["sigma_min"])
+    if timing:
+        info["timing"] = dict(t_recurrence_ms=r.t_recurrence_ms,
+                              n_recurrence_launches=r.n_recurrence_launches,
+                              t_projected_ms=r.t_projected_ms,
+                              t_assemble_ms=r.t_assemble_ms)
     return st, x_out, info
 
 

@@ -243,10 +243,20 @@ lslu_status ensure_ws(lslu_ctx* c, int64_t m, int64_t n, int K, size_t esz,
   return LSLU_OK;
 }
 
+// Events of a timed (LSLU_FLAG_TIMING) solve, recorded on the solve's stream.
+struct PhaseEvents {
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  int launches = 0;
+  bool on = false;
+  void mark(int i, hipStream_t s) {
+    if (on) (void)hipEventRecord(ev[i], s);
+  }
+};
+
 template <typename T>
 void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
                    const lslu_opts* o, T* x_out, T* X, bool replay_t,
-                   bool replay_g, bool replay_lam) {
+                   bool replay_g, bool replay_lam, PhaseEvents* pe) {
   const hipStream_t s = c->stream;
   const Layout& l = c->lay;
   const int K = c->K;
@@ -291,6 +301,7 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
   int cur = 0;  // parts[cur] holds the candidates of the last pass
   int nparts = launch_argmax_parts<T>(r0, m, parts[cur], st, s);
   int launch = 0;
+  pe->mark(0, s);
 
   // The d-side search that a launch resolves: r_0 (k = 0) or the d side of
   // iteration k, giving t(k+1).
@@ -393,6 +404,8 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
   af.basis = Lb;
   af.out = q;
   run(af, 1);
+  pe->launches = launch;
+  pe->mark(1, s);
 
   ProjParams pp{};
   pp.K = K;
@@ -407,10 +420,12 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
   pp.replay_lambda = replay_lam ? l.rep_lam : nullptr;
   launch_projected(l.H, st, 0.0, pp, l.Y, l.lam, l.lam_idx, l.ghat, l.sep,
                    l.smax, l.smin, l.proj, c->lds_max, s);
+  pe->mark(2, s);
   const double tol = o->stop_tol > 0.0 ? o->stop_tol : 1e-6;
   launch_stopping(l.ghat, st, tol, o->early_stop ? 1 : 0, l.sel, s);
   launch_assemble<T>(Lb, bs.rsL, bs.csL, n, l.Y, K, x0, X, st, s);
   launch_select_x<T>(X, n, x0, x_out, st, l.sel, s);
+  pe->mark(3, s);
 }
 
 lslu_status validate_opts(lslu_ctx* c, const lslu_op* op, const lslu_opts* o) {
@@ -778,19 +793,31 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
       }
     }
     void* X = o->X_dev ? o->X_dev : l.X;
+    PhaseEvents pe;
     auto enqueue = [&]() {
       if (esz == sizeof(double))
         enqueue_solve<double>(c, op->d, static_cast<const double*>(b),
                               static_cast<const double*>(x0), o,
                               static_cast<double*>(x_out), static_cast<double*>(X),
-                              rt, rg, rl);
+                              rt, rg, rl, &pe);
       else
         enqueue_solve<float>(c, op->d, static_cast<const float*>(b),
                              static_cast<const float*>(x0), o,
                              static_cast<float*>(x_out), static_cast<float*>(X),
-                             rt, rg, rl);
+                             rt, rg, rl, &pe);
     };
-    if (o->flags & LSLU_FLAG_EAGER) {
+    struct EventsGuard {
+      PhaseEvents& p;
+      ~EventsGuard() {
+        for (auto& e : p.ev)
+          if (e) (void)hipEventDestroy(e);
+      }
+    } guard{pe};
+    if (o->flags & LSLU_FLAG_TIMING) {
+      for (auto& e : pe.ev) LSLU_HIP(c, hipEventCreate(&e));
+      pe.on = true;
+      enqueue();
+    } else if (o->flags & LSLU_FLAG_EAGER) {
       enqueue();
     } else {
       // Everything the captured kernels bake in: pointers, sizes, options.
@@ -829,6 +856,12 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
     c->last_nd = st->n_d;
     if (st->spin_timeouts != 0)
       return fail(c, LSLU_EDEVICE, "a wait inside the recurrence ran out (device fault)");
+    float t_rec = 0.f, t_proj = 0.f, t_asm = 0.f;
+    if (pe.on) {
+      LSLU_HIP(c, hipEventElapsedTime(&t_rec, pe.ev[0], pe.ev[1]));
+      LSLU_HIP(c, hipEventElapsedTime(&t_proj, pe.ev[1], pe.ev[2]));
+      LSLU_HIP(c, hipEventElapsedTime(&t_asm, pe.ev[2], pe.ev[3]));
+    }
     const lslu_status status = static_cast<lslu_status>(st->status);
     if (res) {
       res->status = status;
@@ -852,6 +885,10 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
       copy_out(res->sep_lambda, reinterpret_cast<const double*>(hp(l.sep)), K);
       copy_out(res->sigma_max, reinterpret_cast<const double*>(hp(l.smax)), K);
       copy_out(res->sigma_min, reinterpret_cast<const double*>(hp(l.smin)), K);
+      res->t_recurrence_ms = t_rec;
+      res->n_recurrence_launches = pe.on ? pe.launches : 0;
+      res->t_projected_ms = t_proj;
+      res->t_assemble_ms = t_asm;
     }
     return status;
   } catch (const std::bad_alloc&) {
