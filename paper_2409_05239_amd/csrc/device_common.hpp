@@ -37,13 +37,79 @@ __device__ inline auto in_val(T v) {
     return v;
 }
 
+// ------------------------------------------------------------ normaliser --
+// x / v with the value of IEEE division, for many x and one v.  FP32: the
+// product x * RN(1/v) formed in FP64 has relative error at most 2^-52, while
+// a quotient of two 24-bit numbers lies at least 2^-49 (relative) from every
+// FP32 rounding midpoint and is never exactly on one; rounding the FP64
+// product to FP32 therefore gives RN(x/v) exactly, with one multiply instead
+// of a division sequence.  FP64: IEEE division.
+template <typename T>
+struct Normaliser;
+template <>
+struct Normaliser<float> {
+  float v;
+  double r;
+  __device__ explicit Normaliser(float pivot) : v(pivot), r(1.0 / static_cast<double>(pivot)) {}
+  __device__ float operator()(float x) const {
+    return static_cast<float>(static_cast<double>(x) * r);
+  }
+};
+template <>
+struct Normaliser<double> {
+  double v;
+  __device__ explicit Normaliser(double pivot) : v(pivot) {}
+  __device__ double operator()(double x) const { return x / v; }
+};
+
 // ------------------------------------------------------------ reductions --
-// Sum over the G lanes of an aligned lane group, fixed xor butterfly: the
-// result does not depend on timing.
+// Lane exchanges through DPP (data-parallel primitives: VALU moves, no LDS
+// round trip).  `dpp<CTRL>(v)` returns v of the lane that CTRL names.
+template <int CTRL>
+__device__ inline float dpp(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<uint32_t>(u)), CTRL,
+                                             0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<uint32_t>(u >> 32)),
+                                             CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
+                                        static_cast<uint32_t>(lo));
+}
+
+template <typename Acc>
+__device__ inline Acc readlane_any(Acc v, int lane);
+template <>
+__device__ inline float readlane_any(float v, int lane) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
+// Sum over the G lanes of an aligned lane group (G = 4, 8, 16, 32, 64), every
+// lane of the group gets the same sum.  Within 16 lanes: pairs (quad_perm
+// [1,0,3,2]), quads ([2,3,0,1]), half rows (row_half_mirror), rows
+// (row_mirror); each step adds two equal-ranked partial sums, so all lanes
+// hold bitwise the same value and the order never depends on timing.  Rows of
+// 16 are then added through readlane in a fixed order.
 template <int G, typename Acc>
 __device__ inline Acc group_sum(Acc v) {
-#pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  static_assert(G == 4 || G == 8 || G == 16 || G == 32 || G == 64, "group size");
+  v += dpp<0xB1>(v);
+  v += dpp<0x4E>(v);
+  if constexpr (G >= 8) v += dpp<0x141>(v);
+  if constexpr (G >= 16) v += dpp<0x140>(v);
+  if constexpr (G >= 32) {
+    const Acc r0 = readlane_any(v, 0), r1 = readlane_any(v, 16);
+    const Acc r2 = readlane_any(v, 32), r3 = readlane_any(v, 48);
+    if constexpr (G == 64) {
+      v = (r0 + r1) + (r2 + r3);
+    } else {
+      v = ((threadIdx.x & (kWave - 1)) < 32) ? r0 + r1 : r2 + r3;
+    }
+  }
   return v;
 }
 
@@ -55,6 +121,8 @@ __device__ inline double readlane_d(double v, int lane) {
       __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(u >> 32)), lane));
   return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
 }
+template <>
+__device__ inline double readlane_any(double v, int lane) { return readlane_d(v, lane); }
 
 // Total order of every pivot search: larger |v| first, then the smaller row
 // (ties go to the smallest index).  Ineligible rows carry key -1.

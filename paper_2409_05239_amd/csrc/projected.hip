@@ -22,10 +22,11 @@
 // In exact arithmetic these equal the SVD expressions of Section 3.2.1
 // (eq. gcv2, the SVD form of weighted GCV, eq. stop2 and the filtered SVD
 // solution for y).
+#include <algorithm>
 #include <cfloat>
 #include <climits>
 
-#include "internal.hpp"
+#include "device_common.hpp"
 
 namespace lslu {
 
@@ -34,7 +35,7 @@ namespace {
 constexpr int kPT = 256;            // threads per projected problem
 constexpr int kSectRounds1 = 8;     // multisection rounds for sigma_1
 constexpr int kSectRoundsMin = 8;   // multisection rounds for sigma_min
-constexpr size_t kStaticLds = 24 * 1024;  // bound on the static LDS below
+size_t g_static_lds = 32 * 1024;  // static LDS of k_projected, read at init
 
 // Working matrix A ((k+1) x k, leading dimension k+1).
 __host__ __device__ inline size_t proj_a_doubles(int k) { return (size_t)(k + 1) * k; }
@@ -43,11 +44,7 @@ __host__ __device__ inline size_t proj_scratch_per_k(int K) {
   return proj_a_doubles(K) + (size_t)3 * K * kMaxGrid;
 }
 
-__device__ inline double wave_sum_d(double v) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
+__device__ inline double wave_sum_d(double v) { return group_sum<kWave>(v); }
 
 // sum_i u[i] * x[i*stride], i < len, with four independent partial sums so the
 // loads of consecutive terms overlap.
@@ -151,9 +148,12 @@ __device__ inline double elden_backward(const double* d, const double* e,
   return mis;
 }
 
+// Dynamic LDS: [A when a_in_lds][per-grid-value Elden scratch when l_in_lds],
+// sized for the largest k of the launch (k_last).
+template <bool a_in_lds, bool l_in_lds>
 __global__ __launch_bounds__(kPT) void k_projected(
     const double* __restrict__ H, const DevState* __restrict__ st,
-    ProjParams p, int k_first, int a_in_lds, double* __restrict__ Y,
+    ProjParams p, int k_first, int k_last, double* __restrict__ Y,
     double* __restrict__ lam_out, int* __restrict__ lam_idx_out,
     double* __restrict__ ghat_out, double* __restrict__ sep_out,
     double* __restrict__ smax_out, double* __restrict__ smin_out,
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kPT) void k_projected(
   __shared__ double g[kMaxIter + 1], vb[kMaxIter + 1], taur[kMaxIter];
   __shared__ double d[kMaxIter], e[kMaxIter], ta[kMaxIter], tb[kMaxIter];
   __shared__ double zy[kMaxIter], gv[kMaxGrid];
-  __shared__ int s_cnt[kPT];
+  __shared__ int s_first;
   __shared__ double s_tau, s_lo, s_hi, s_sig1, s_lam, s_sep;
   __shared__ int s_lidx;
 
@@ -173,8 +173,13 @@ __global__ __launch_bounds__(kPT) void k_projected(
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const int lda = k + 1;
   double* blk = scratch + (size_t)(k - 1) * proj_scratch_per_k(K);
-  double* A = a_in_lds ? lds_a : blk;
-  double* lamscr = blk + proj_a_doubles(K);  // 3*K doubles per grid value
+  double* A;
+  if constexpr (a_in_lds) A = lds_a; else A = blk;
+  double* lamscr;  // 3*K doubles per grid value
+  if constexpr (l_in_lds)
+    lamscr = lds_a + (a_in_lds ? proj_a_doubles(k_last) : 0);
+  else
+    lamscr = blk + proj_a_doubles(K);
 
   // 1. Load H (column-major, leading dimension K+1) into A; g = beta e_1.
   for (int idx = tid; idx < (k + 1) * k; idx += kPT) {
@@ -299,11 +304,15 @@ __global__ __launch_bounds__(kPT) void k_projected(
     for (int rd = 0; rd < rounds; ++rd) {
       const double lo = s_lo, hi = s_hi;
       const double step = (hi - lo) / (double)(kPT + 1);
-      s_cnt[tid] = sturm_count(ta, tb, k, lo + step * (tid + 1), pivmin);
+      const int cnt = sturm_count(ta, tb, k, lo + step * (tid + 1), pivmin);
+      if (tid == 0) s_first = kPT;
+      __syncthreads();
+      // the first point whose count reaches the target brackets it (the last
+      // interval when none does); a minimum, so the choice is deterministic
+      if (cnt >= target) atomicMin(&s_first, tid);
       __syncthreads();
       if (tid == 0) {
-        int t = 0;
-        while (t < kPT && s_cnt[t] < target) ++t;
+        const int t = s_first;
         s_lo = (t == 0) ? lo : lo + step * t;
         s_hi = (t == kPT) ? hi : lo + step * (t + 1);
       }
@@ -408,31 +417,55 @@ __global__ __launch_bounds__(kPT) void k_projected(
 size_t projected_scratch_doubles(int K) { return proj_scratch_per_k(K) * (size_t)K; }
 
 void projected_init_attributes(size_t lds_bytes) {
-  if (lds_bytes <= kStaticLds) return;
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_projected),
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            static_cast<int>(lds_bytes - kStaticLds));
+  hipFuncAttributes fa{};
+  size_t st = 0;
+  const void* kp[] = {reinterpret_cast<const void*>(k_projected<true, true>),
+                      reinterpret_cast<const void*>(k_projected<true, false>),
+                      reinterpret_cast<const void*>(k_projected<false, true>),
+                      reinterpret_cast<const void*>(k_projected<false, false>)};
+  for (const void* k : kp)
+    if (hipFuncGetAttributes(&fa, k) == hipSuccess) st = std::max(st, fa.sharedSizeBytes);
+  if (st > 0) g_static_lds = st;
+  if (lds_bytes <= g_static_lds) return;
+  const int dyn = static_cast<int>(lds_bytes - g_static_lds);
+  const void* ks[] = {reinterpret_cast<const void*>(k_projected<true, true>),
+                      reinterpret_cast<const void*>(k_projected<true, false>),
+                      reinterpret_cast<const void*>(k_projected<false, true>),
+                      reinterpret_cast<const void*>(k_projected<false, false>)};
+  for (const void* k : ks)
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
 }
 
 void launch_projected(const double* H, const DevState* st, double,
                       const ProjParams& p, double* Y, double* lam, int* lam_idx,
                       double* ghat, double* sep, double* smax, double* smin,
                       double* scratch, size_t lds_bytes, hipStream_t s) {
-  // Problems whose working matrix fits in LDS keep it there; the others use
-  // their slice of global scratch.
-  int k_lds = 0;
-  while (k_lds < p.K &&
-         proj_a_doubles(k_lds + 1) * sizeof(double) + kStaticLds <= lds_bytes)
-    ++k_lds;
-  if (k_lds > 0) {
-    const size_t dyn = proj_a_doubles(k_lds) * sizeof(double);
-    k_projected<<<k_lds, kPT, dyn, s>>>(H, st, p, 1, 1, Y, lam, lam_idx, ghat,
-                                        sep, smax, smin, scratch);
-  }
-  if (k_lds < p.K) {
-    k_projected<<<p.K - k_lds, kPT, 0, s>>>(H, st, p, k_lds + 1, 0, Y, lam,
-                                            lam_idx, ghat, sep, smax, smin,
-                                            scratch);
+  // Each problem keeps its working matrix and its per-grid-value Elden
+  // scratch (3 K doubles per grid value, indexed with stride K) in LDS when
+  // they fit, else in its slice of global scratch.  Consecutive k with the
+  // same placement share one launch sized for the largest of them.
+  const size_t room = lds_bytes > g_static_lds ? lds_bytes - g_static_lds : 0;
+  const int G = (p.reg == kWGCV || p.reg == kGCV) ? std::max(p.n_grid, 1) : 1;
+  const size_t lam_bytes = sizeof(double) * 3 * (size_t)p.K * G;
+  auto place = [&](int k) {
+    const size_t a = proj_a_doubles(k) * sizeof(double);
+    if (a + lam_bytes <= room) return 3;  // both
+    if (a <= room) return 1;              // the matrix (the bidiagonalisation)
+    if (lam_bytes <= room) return 2;      // grid scratch only
+    return 0;
+  };
+  int k0 = 1;
+  while (k0 <= p.K) {
+    const int pl = place(k0);
+    int k1 = k0;
+    while (k1 + 1 <= p.K && place(k1 + 1) == pl) ++k1;
+    const int a_l = (pl & 1) ? 1 : 0, l_l = (pl & 2) ? 1 : 0;
+    const size_t dyn = (a_l ? proj_a_doubles(k1) * sizeof(double) : 0) + (l_l ? lam_bytes : 0);
+    auto kern = a_l ? (l_l ? k_projected<true, true> : k_projected<true, false>)
+                    : (l_l ? k_projected<false, true> : k_projected<false, false>);
+    kern<<<k1 - k0 + 1, kPT, dyn, s>>>(H, st, p, k0, k1, Y, lam, lam_idx, ghat, sep,
+                                       smax, smin, scratch);
+    k0 = k1 + 1;
   }
 }
 

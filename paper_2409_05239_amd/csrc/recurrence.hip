@@ -22,9 +22,9 @@
 // subtract.
 //
 // Products read the normalised vector as they gather it: each input is u(c)
-// divided by the pivot value (IEEE division), the same value the normalised
-// basis column holds, so products and exact cancellations are those of the
-// normalised vector.  The products therefore start once the pivot is
+// divided by the pivot value with the value of IEEE division (Normaliser), the
+// same value the normalised basis column holds, so products and exact
+// cancellations are those of the normalised vector.  The products therefore start once the pivot is
 // published; the triangular solve of block 0 overlaps them.
 //
 // Synchronisation inside the launch: blocks only ever wait for flags set by
@@ -309,9 +309,9 @@ __device__ void pivot_entries(const HalfArgs<T>& a, const RowOp& op, DevState* s
   const bool act = jr < a.nb;
   const int row = act ? a.piv[jr] : 0;
   if (block_wait(&a.flags[0], 0, st) != 1) return;
-  const T vt = static_cast<T>(load_d(&st->cur_val));
+  const Normaliser<T> nz(static_cast<T>(load_d(&st->cur_val)));
   if (!act) return;
-  auto xf = [&](int64_t c) -> T { return a.up[c] / vt; };
+  auto xf = [&](int64_t c) -> T { return nz(a.up[c]); };
   typename RowOp::Acc acc = op.template partial<kWave>(row, lane, xf);
   acc = group_sum<kWave>(acc);
   if (lane == 0) {
@@ -325,7 +325,7 @@ __device__ void pivot_entries(const HalfArgs<T>& a, const RowOp& op, DevState* s
 // Normalise this block's share of the previous vector into its basis column.
 template <typename T>
 __device__ inline void normalise_share(const HalfArgs<T>& a, int cb, int ncons,
-                                       int pick, T vt) {
+                                       int pick, const Normaliser<T>& nz) {
   const int64_t step = (int64_t)ncons * kThreads;
   for (int64_t i0 = (int64_t)cb * kThreads + threadIdx.x; i0 < a.lenp;
        i0 += step * kNormBatch) {
@@ -338,7 +338,7 @@ __device__ inline void normalise_share(const HalfArgs<T>& a, int cb, int ncons,
 #pragma unroll
     for (int u = 0; u < kNormBatch; ++u) {
       const int64_t i = i0 + u * step;
-      if (i < a.lenp) a.dstp[i * a.dstp_stride] = (i == pick) ? T(1) : vv[u] / vt;
+      if (i < a.lenp) a.dstp[i * a.dstp_stride] = (i == pick) ? T(1) : nz(vv[u]);
     }
   }
 }
@@ -377,14 +377,14 @@ __device__ void consume_rows(const HalfArgs<T>& a, const RowOp& op, DevState* st
   const int64_t r0 = (int64_t)cb * kRowsPerBlock + rl;
   if (block_wait(&a.flags[0], 0, st) != 1) return;
   const int pick = load_i(&st->cur_pick);
-  const T vt = static_cast<T>(load_d(&st->cur_val));
-  auto xf = [&](int64_t c) -> T { return a.up[c] / vt; };
+  const Normaliser<T> nz(static_cast<T>(load_d(&st->cur_val)));
+  auto xf = [&](int64_t c) -> T { return nz(a.up[c]); };
   for (int64_t r = r0; r < a.rows; r += stride) {
     Acc acc = op.template partial<kRowLanes>(r, sub, xf);
     acc = group_sum<kRowLanes>(acc);
     if (sub == 0) a.out[r] = static_cast<T>(acc);
   }
-  normalise_share(a, cb, ncons, pick, vt);
+  normalise_share(a, cb, ncons, pick, nz);
   if (a.rows == 0) return;
   if (!fetch_coef(a, st, cf)) return;
   double key = -1.0;
@@ -448,7 +448,7 @@ __global__ __launch_bounds__(kThreads) void k_half_rows(HalfArgs<T> a, RowOp op)
 // The tile of the normalised input: each staged entry is u divided by the
 // pivot value, then (BF16 mode) rounded to bfloat16.
 template <typename T, typename Acc, int PH, bool kBf16>
-__device__ inline void psf_tile_norm(const T* __restrict__ u, T vt, int rows,
+__device__ inline void psf_tile_norm(const T* __restrict__ u, const Normaliser<T>& nz, int rows,
                                      int cols, const Acc* __restrict__ Wt, int pw,
                                      int i0, int j0, Acc* tile, Acc (&acc)[kPsfR]) {
   const int ch = PH / 2, cw = pw / 2;
@@ -458,7 +458,7 @@ __device__ inline void psf_tile_norm(const T* __restrict__ u, T vt, int rows,
     const int gi = i0 - ch + tr, gj = j0 - cw + tc;
     Acc v = 0;
     if (gi >= 0 && gi < rows && gj >= 0 && gj < cols)
-      v = static_cast<Acc>(in_val<kBf16>(u[(int64_t)gi * cols + gj] / vt));
+      v = static_cast<Acc>(in_val<kBf16>(nz(u[(int64_t)gi * cols + gj])));
     tile[e] = v;
   }
   __syncthreads();
@@ -495,11 +495,11 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
   const int nb = a.nb;
   if (block_wait(&a.flags[0], 0, st) != 1) return;
   const int pick = load_i(&st->cur_pick);
-  const T vt = static_cast<T>(load_d(&st->cur_val));
+  const Normaliser<T> nz(static_cast<T>(load_d(&st->cur_val)));
   for (int t = cb; t < ntiles; t += ncons) {
     const int i0 = (t / tiles_x) * kPsfTH, j0 = (t % tiles_x) * kPsfTW;
     Acc acc[kPsfR];
-    psf_tile_norm<T, Acc, PH, kBf16>(a.up, vt, rows, cols, Wt, pw, i0, j0, tile, acc);
+    psf_tile_norm<T, Acc, PH, kBf16>(a.up, nz, rows, cols, Wt, pw, i0, j0, tile, acc);
     const int gj = j0 + lane;
 #pragma unroll
     for (int p = 0; p < kPsfR; ++p) {
@@ -507,7 +507,7 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
       if (gi < rows && gj < cols) a.out[(int64_t)gi * cols + gj] = static_cast<T>(acc[p]);
     }
   }
-  normalise_share(a, cb, ncons, pick, vt);
+  normalise_share(a, cb, ncons, pick, nz);
   if (a.rows == 0) return;
   if (!fetch_coef(a, st, cf)) return;
   double best = -1.0;
