@@ -63,7 +63,11 @@ typedef enum lslu_reg {
   LSLU_REG_FIXED = 1,   /* lambda_k = opts.lambda */
   LSLU_REG_WGCV = 2,    /* weighted GCV on the grid (Section 3.2.1) */
   LSLU_REG_GCV = 3,     /* GCV on the grid (eq. gcv2) */
-  LSLU_REG_OPTIMAL = 4  /* argmin ||x_k(lambda) - x_true|| on the grid (eq. lambda) */
+  LSLU_REG_OPTIMAL = 4  /* argmin ||x_k(lambda) - x_true|| on the grid (eq. lambda;
+                           a diagnostic for simulated data): needs x_true_dev and
+                           a grid; priced from the FP64 Gram matrix of
+                           [L_K, x_true - x_0], the one place the library forms
+                           inner products of basis vectors */
 } lslu_reg;
 
 typedef struct lslu_ctx lslu_ctx;
@@ -154,7 +158,8 @@ typedef struct lslu_opts {
   int32_t grid_relative;      /* nonzero: grid values are multiplied by the
                                  largest singular value of H_{k+1,k} */
   double omega;               /* WGCV weight; <= 0 selects (k+1)/m */
-  const void* x_true_dev;     /* OPTIMAL: device, wp, n entries */
+  const void* x_true_dev;     /* OPTIMAL (required, else LSLU_EINVAL): device,
+                                 wp, n entries; borrowed for the call */
   double stop_tol;            /* tolerance of the stopping rule (eq. tol);
                                  <= 0 selects 1e-6 */
   int32_t early_stop;         /* nonzero: x_out is x_{k_stop} */

@@ -178,9 +178,7 @@ struct ProjParams {
   double omega;    // <= 0: (k+1)/m
   const double* grid;         // device
   const int* replay_lambda;   // device or nullptr
-  const double* gram;         // OPTIMAL: K x K Gram matrix of L
-  const double* gvec;         // OPTIMAL: L^T (x_true - x0)
-  const double* e0;           // OPTIMAL: ||x_true - x0||^2
+  const double* gram;  // OPTIMAL: (K+1) x (K+1) Gram matrix of [L, x_true - x_0]
 };
 void launch_projected(const double* H, const DevState* st, double beta_unused,
                       const ProjParams& p, double* Y, double* lam,
@@ -192,6 +190,16 @@ size_t projected_scratch_doubles(int K);
 // One-time kernel attributes (dynamic LDS limits), set at context creation so
 // that no attribute call happens while a solve is being captured.
 void projected_init_attributes(size_t lds_bytes);
+
+// Gram matrix of [L_K, x_true - x_0] for the optimal rule (gram.hip):
+// G ((K+1) x (K+1), FP64) from the first n_l columns of L (the others count
+// as zero); scratch holds gram_scratch_doubles(K) doubles.
+constexpr int kGramChunks = 32;
+size_t gram_scratch_doubles(int K);
+template <typename T>
+void launch_gram(const T* L, int64_t rs, int64_t cs, int64_t n, int K,
+                 const T* x_true, const T* x0, const DevState* st,
+                 double* scratch, double* G, hipStream_t s);
 
 // Iterate assembly (assemble.hip).
 template <typename T>

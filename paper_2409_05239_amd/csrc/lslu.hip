@@ -32,6 +32,7 @@ struct Layout {
   int* flags = nullptr;    // two per launch of the recurrence
   void *TL = nullptr, *TD = nullptr;  // pivot-row triangles, basis precision
   double *grid = nullptr, *proj = nullptr;
+  double *gram = nullptr, *gram_part = nullptr;  // optimal rule only
   int *rep_t = nullptr, *rep_g = nullptr, *rep_lam = nullptr;
   unsigned char *mask_t = nullptr, *mask_g = nullptr;
   ArgPart* parts = nullptr;
@@ -82,6 +83,8 @@ size_t carve(unsigned char* base, int64_t m, int64_t n, int K, size_t esz,
   l.TD = take(esz * (K + 1) * (K + 2) / 2);
   l.grid = reinterpret_cast<double*>(take(sizeof(double) * kMaxGrid));
   l.proj = reinterpret_cast<double*>(take(sizeof(double) * projected_scratch_doubles(K)));
+  l.gram = reinterpret_cast<double*>(take(sizeof(double) * (K + 1) * (K + 1)));
+  l.gram_part = reinterpret_cast<double*>(take(sizeof(double) * gram_scratch_doubles(K)));
   l.rep_t = reinterpret_cast<int*>(take(sizeof(int) * (K + 1)));
   l.rep_g = reinterpret_cast<int*>(take(sizeof(int) * K));
   l.rep_lam = reinterpret_cast<int*>(take(sizeof(int) * K));
@@ -418,6 +421,11 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
   pp.omega = o->omega;
   pp.grid = l.grid;
   pp.replay_lambda = replay_lam ? l.rep_lam : nullptr;
+  if (o->reg == LSLU_REG_OPTIMAL) {
+    launch_gram<T>(Lb, bs.rsL, bs.csL, n, K, static_cast<const T*>(o->x_true_dev), x0, st,
+                   l.gram_part, l.gram, s);
+    pp.gram = l.gram;
+  }
   launch_projected(l.H, st, 0.0, pp, l.Y, l.lam, l.lam_idx, l.ghat, l.sep,
                    l.smax, l.smin, l.proj, c->lds_max, s);
   pe->mark(2, s);
@@ -436,11 +444,11 @@ lslu_status validate_opts(lslu_ctx* c, const lslu_op* op, const lslu_opts* o) {
     return fail(c, LSLU_EINVAL, "maxiter must not exceed min(m, n) + 1");
   if (o->reg < LSLU_REG_NONE || o->reg > LSLU_REG_OPTIMAL)
     return fail(c, LSLU_EINVAL, "unknown regularisation rule");
-  if (o->reg == LSLU_REG_OPTIMAL)
-    return fail(c, LSLU_EUNSUPPORTED, "LSLU_REG_OPTIMAL is not implemented");
+  if (o->reg == LSLU_REG_OPTIMAL && !o->x_true_dev)
+    return fail(c, LSLU_EINVAL, "LSLU_REG_OPTIMAL needs x_true_dev");
   if (o->reg == LSLU_REG_FIXED && !(std::isfinite(o->lambda) && o->lambda >= 0.0))
     return fail(c, LSLU_EINVAL, "lambda must be finite and >= 0");
-  if (o->reg == LSLU_REG_WGCV || o->reg == LSLU_REG_GCV) {
+  if (o->reg == LSLU_REG_WGCV || o->reg == LSLU_REG_GCV || o->reg == LSLU_REG_OPTIMAL) {
     if (!o->lambda_grid || o->n_grid < 1 || o->n_grid > kMaxGrid)
       return fail(c, LSLU_EINVAL, "a lambda grid of 1..256 values is required");
     for (int i = 0; i < o->n_grid; ++i) {
@@ -763,7 +771,7 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
     // synchronise with the host).
     {
       std::vector<double> grid;
-      if (o->reg == LSLU_REG_WGCV || o->reg == LSLU_REG_GCV)
+      if (o->reg == LSLU_REG_WGCV || o->reg == LSLU_REG_GCV || o->reg == LSLU_REG_OPTIMAL)
         grid.assign(o->lambda_grid, o->lambda_grid + o->n_grid);
       // the cached copy is tied to the device buffer, which moves with the
       // workspace layout
@@ -827,7 +835,7 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
           (double)op->d.kind, (double)op->d.prec, (double)op->d.m, (double)op->d.n,
           (double)K, (double)o->reg, o->lambda, (double)o->n_grid,
           (double)o->grid_relative, o->omega, o->stop_tol, (double)o->early_stop,
-          (double)rt, (double)rg, (double)rl};
+          (double)rt, (double)rg, (double)rl, (double)(uintptr_t)o->x_true_dev};
       if (!c->gexec || key != c->gkey) {
         drop_graph(c);
         LSLU_HIP(c, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));

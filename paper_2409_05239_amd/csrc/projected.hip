@@ -148,6 +148,28 @@ __device__ inline double elden_backward(const double* d, const double* e,
   return mis;
 }
 
+// y = Q z in place, by one wavefront: the right reflectors j = k-3..0 with
+// vectors [1 at j+1; A(j, j+2:k-1)] and factors taur[j].
+__device__ inline void apply_q(const double* A, int lda, const double* taur, int k,
+                               double* z, int lane) {
+  for (int j = k - 3; j >= 0; --j) {
+    const double tau = taur[j];
+    if (tau == 0.0) continue;
+    double w = 0.0;
+    for (int c = j + 1 + lane; c < k; c += kWave) {
+      const double u = (c == j + 1) ? 1.0 : A[(size_t)c * lda + j];
+      w = fma(u, z[c], w);
+    }
+    w = wave_sum_d(w) * tau;
+    for (int c = j + 1 + lane; c < k; c += kWave) {
+      const double u = (c == j + 1) ? 1.0 : A[(size_t)c * lda + j];
+      z[c] = fma(-w, u, z[c]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // Dynamic LDS: [A when a_in_lds][per-grid-value Elden scratch when l_in_lds],
 // sized for the largest k of the launch (k_last).
 template <bool a_in_lds, bool l_in_lds>
@@ -365,6 +387,52 @@ __global__ __launch_bounds__(kPT) void k_projected(
       s_lidx = use;
       s_sep = sep;
     }
+  } else if (reg == kOptimal) {
+    // z_lam for every grid value (one thread each, z over q in its slot),
+    // then y_lam = Q z_lam and ||x_0 + L_k y_lam - x_true|| from the Gram
+    // matrix of [L, x_true - x_0] (one wavefront per grid value).
+    for (int gi = tid; gi < p.n_grid; gi += kPT) {
+      const double lam = p.grid_relative ? p.grid[gi] * sig1 : p.grid[gi];
+      double* rho = lamscr + (size_t)gi * 3 * K;
+      double* ff = rho + K;
+      double* qq = ff + K;
+      elden_forward(d, e, g, k, lam, rho, ff, qq);
+      elden_backward(d, e, g, k, rho, ff, qq, qq);
+    }
+    __syncthreads();
+    const int ldg = K + 1;
+    const double e0 = p.gram[(size_t)K * ldg + K];
+    for (int gi = wv; gi < p.n_grid; gi += kPT / kWave) {
+      double* y = lamscr + (size_t)gi * 3 * K + 2 * K;
+      apply_q(A, lda, taur, k, y, lane);
+      // y^T G y - 2 y^T h, h = G(0:k-1, K)
+      double part = 0.0;
+      for (int i = lane; i < k; i += kWave) {
+        const double* Gi = p.gram + (size_t)i * ldg;
+        double t = 0.0;
+        for (int j = 0; j < k; ++j) t = fma(Gi[j], y[j], t);
+        part = fma(y[i], t - 2.0 * Gi[K], part);
+      }
+      part = wave_sum_d(part);
+      if (lane == 0) gv[gi] = sqrt(fmax(part + e0, 0.0));
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int bi = 0;
+      for (int gi = 1; gi < p.n_grid; ++gi)
+        if (gv[gi] < gv[bi]) bi = gi;
+      double g2 = INFINITY;
+      for (int gi = 0; gi < p.n_grid; ++gi)
+        if (gi != bi && gv[gi] < g2) g2 = gv[gi];
+      double sep = INFINITY;
+      if (p.n_grid > 1)
+        sep = gv[bi] > 0.0 ? (g2 - gv[bi]) / gv[bi] : (g2 > 0.0 ? INFINITY : 0.0);
+      int use = bi;
+      if (p.replay_lambda && p.replay_lambda[k - 1] >= 0) use = p.replay_lambda[k - 1];
+      s_lam = p.grid_relative ? p.grid[use] * sig1 : p.grid[use];
+      s_lidx = use;
+      s_sep = sep;
+    }
   } else if (tid == 0) {
     s_lam = (reg == kFixed) ? p.lambda : 0.0;
     s_lidx = -1;
@@ -388,25 +456,7 @@ __global__ __launch_bounds__(kPT) void k_projected(
     sep_out[k - 1] = s_sep;
   }
   __syncthreads();
-  if (wv == 0) {
-    for (int j = k - 3; j >= 0; --j) {
-      const double tau = taur[j];
-      if (tau == 0.0) continue;
-      // reflector vector u = [1 at j+1; A(j, j+2:k-1)]
-      double w = 0.0;
-      for (int c = j + 1 + lane; c < k; c += kWave) {
-        const double u = (c == j + 1) ? 1.0 : A[(size_t)c * lda + j];
-        w = fma(u, zy[c], w);
-      }
-      w = wave_sum_d(w) * tau;
-      for (int c = j + 1 + lane; c < k; c += kWave) {
-        const double u = (c == j + 1) ? 1.0 : A[(size_t)c * lda + j];
-        zy[c] = fma(-w, u, zy[c]);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-    }
-  }
+  if (wv == 0) apply_q(A, lda, taur, k, zy, lane);
   __syncthreads();
   for (int r = tid; r < K; r += kPT)
     Y[(size_t)(k - 1) * K + r] = (r < k) ? zy[r] : 0.0;
@@ -445,7 +495,8 @@ void launch_projected(const double* H, const DevState* st, double,
   // they fit, else in its slice of global scratch.  Consecutive k with the
   // same placement share one launch sized for the largest of them.
   const size_t room = lds_bytes > g_static_lds ? lds_bytes - g_static_lds : 0;
-  const int G = (p.reg == kWGCV || p.reg == kGCV) ? std::max(p.n_grid, 1) : 1;
+  const int G = (p.reg == kWGCV || p.reg == kGCV || p.reg == kOptimal)
+                    ? std::max(p.n_grid, 1) : 1;
   const size_t lam_bytes = sizeof(double) * 3 * (size_t)p.K * G;
   auto place = [&](int k) {
     const size_t a = proj_a_doubles(k) * sizeof(double);

@@ -17,7 +17,7 @@ def torch_dtype(prec):
 def gpu_solve(capi, ctx, prob, prec="fp64", K=10, reg="none", lam=0.0,
               grid=None, grid_relative=False, replay=None, x0=None,
               early_stop=False, stop_tol=0.0, bases=True, op=None, eager=False,
-              b=None):
+              b=None, x_true=None):
     """Solve on the GPU; returns the info dict with x, X (n x K), L, D."""
     import torch
     dt = torch_dtype(prec)
@@ -31,13 +31,14 @@ def gpu_solve(capi, ctx, prob, prec="fp64", K=10, reg="none", lam=0.0,
             b = torch.tensor(prob.b, dtype=dt, device="cuda")
         X = torch.zeros((K, prob.n), dtype=dt, device="cuda")
         x0t = None if x0 is None else torch.tensor(x0, dtype=dt, device="cuda")
+        xtt = None if x_true is None else torch.tensor(x_true, dtype=dt, device="cuda")
         kw = {}
         if replay is not None:
             kw.update(replay)
         st, x, info = capi.lslu_solve(ctx, op, b, K, reg=reg, lam=lam, grid=grid,
                                       grid_relative=grid_relative, X=X, x0=x0t,
                                       early_stop=early_stop, stop_tol=stop_tol,
-                                      eager=eager, **kw)
+                                      eager=eager, x_true=xtt, **kw)
         torch.cuda.synchronize()
         info["x"] = x.double().cpu().numpy()
         info["X"] = X.double().cpu().numpy().T.copy()

@@ -41,24 +41,41 @@ def _perturbed(prob, eps, seed):
     return dataclasses.replace(prob, **kw)
 
 
-def forward_sensitivity(prob, R, reg, K, eps=1e-9, seeds=(1, 2)):
-    """s_k, k = 1..K: the largest over ``seeds`` of
-    ||x_k(perturbed) - x_k|| / (||x_k|| eps), with the perturbed run's
-    pivots required to equal the unperturbed ones (eps is far below every
-    pivot separation the tests rely on, so the response is linear)."""
-    s = np.zeros(K)
+def perturbed_runs(prob, R, reg, K, eps=1e-9, seeds=(1, 2)):
+    """Oracle runs on copies of the problem with A's stored values and b
+    perturbed by a relative eps; their pivots are required to equal R's (eps
+    is far below every pivot separation the tests rely on, so the response is
+    linear)."""
+    runs = []
     for seed in seeds:
         P = _perturbed(prob, eps, seed)
         Rp = hybrid_lslu(make_operator(P), P.b, K, reg)
         if Rp.piv_g[:K] != R.piv_g[:K] or Rp.piv_t[:K + 1] != R.piv_t[:K + 1]:
             raise AssertionError("perturbation changed the pivots; lower eps")
-        for k in range(1, min(K, R.k_done, Rp.k_done) + 1):
+        runs.append(Rp)
+    return runs
+
+
+def sensitivity_at(runs, lambdas, X_ref, K, eps=1e-9):
+    """s_k, k = 1..K: the largest over the perturbed runs of
+    ||x_k(perturbed) - x_k|| / (||x_k|| eps), each perturbed x_k re-solved at
+    the given lambda_k (the bases do not depend on lambda, so any lambda
+    sequence can be priced from the same runs)."""
+    s = np.zeros(K)
+    for Rp in runs:
+        for k in range(1, min(K, Rp.k_done, X_ref.shape[1]) + 1):
             sv, c, V = projected_svd(Rp.H[:k + 1, :k])
-            y = tikhonov_coeffs(Rp.beta, sv, c, V, R.lambdas[k - 1])
+            y = tikhonov_coeffs(Rp.beta, sv, c, V, lambdas[k - 1])
             xk = Rp.L[:, :k] @ y
-            ref = R.X[:, k - 1]
+            ref = X_ref[:, k - 1]
             s[k - 1] = max(s[k - 1], np.linalg.norm(xk - ref) / (np.linalg.norm(ref) * eps))
     return s
+
+
+def forward_sensitivity(prob, R, reg, K, eps=1e-9, seeds=(1, 2)):
+    """s_k of the iterates R.X at R's own lambda_k (see sensitivity_at)."""
+    runs = perturbed_runs(prob, R, reg, K, eps, seeds)
+    return sensitivity_at(runs, R.lambdas, R.X, min(K, R.k_done), eps)
 
 
 def step_tolerances(s, u, stated):

@@ -25,7 +25,7 @@ from gpu_helpers import (TAU, check_basis_invariants, check_relations,
 from oracle import RegParam, make_operator
 from oracle.hessenberg import hybrid_lslu
 from oracle.projected import projected_svd, select_lambda, tikhonov_coeffs
-from sensitivity import forward_sensitivity, step_tolerances
+from sensitivity import perturbed_runs, sensitivity_at, step_tolerances
 from workloads import config_problem, lambda_grid
 
 pytestmark = pytest.mark.gpu
@@ -43,8 +43,9 @@ def tomo():
     prob = config_problem("tomo128")
     reg = RegParam("wgcv", grid=lambda_grid(), grid_relative=True)
     R = hybrid_lslu(make_operator(prob), prob.b, 100, reg)
-    sens = forward_sensitivity(prob, R, reg, 100)
-    return prob, R, sens
+    runs = perturbed_runs(prob, R, reg, 100)
+    sens = sensitivity_at(runs, R.lambdas, R.X, min(100, R.k_done))
+    return prob, R, sens, runs
 
 
 def test_tomo128_fp32_replay_full(lib, ctx, tomo):
@@ -56,7 +57,7 @@ def test_tomo128_fp32_replay_full(lib, ctx, tomo):
     problem's forward sensitivity allows it and to 10 k u s_k beyond (see
     ``sensitivity.py``): the LU-type bases of this problem turn a relative
     perturbation of 1e-9 into ~1e-6 by k = 16 and ~3e-5 by k = 79."""
-    prob, R, sens = tomo
+    prob, R, sens, _ = tomo
     K = min(100, R.k_done)
     G = gpu_solve(lib, ctx, prob, "fp32", K, "wgcv", grid=lambda_grid(),
                   grid_relative=True, replay=replay_from(R, K))
@@ -87,7 +88,7 @@ def test_tomo128_fp32_replay_full(lib, ctx, tomo):
 
 
 def test_tomo128_fp64_free_full(lib, ctx, tomo):
-    prob, R, sens = tomo
+    prob, R, sens, _ = tomo
     G = gpu_solve(lib, ctx, prob, "fp64", 100, "wgcv", grid=lambda_grid(),
                   grid_relative=True, bases=False)
     k_piv = pivot_prefix(R, TAU["fp64"], min(R.k_done, G["k_done"]))
@@ -113,6 +114,45 @@ def test_tomo128_fp64_free_full(lib, ctx, tomo):
         assert e <= tol[k - 1], (k, e, tol[k - 1])
     print(f"[tomo128 fp64 free] x_k compared at {same} of {k_piv} steps; stated "
           f"1e-10 applies for k <= {k_stated}; max err/tol {worst:.2f}")
+    assert same >= k_piv // 2
+
+
+def test_tomo128_fp64_optimal_full(lib, ctx, tomo):
+    """The optimal rule (eq. lambda) at full size.  The bases do not depend on
+    lambda, so the oracle's wGCV run supplies L_k, H and beta; its optimal
+    lambda_k and x_k follow from them with the oracle's own rule."""
+    prob, R, _, runs = tomo
+    grid = lambda_grid()
+    G = gpu_solve(lib, ctx, prob, "fp64", 100, "optimal", grid=grid,
+                  grid_relative=True, bases=False, x_true=prob.x_true)
+    k_piv = pivot_prefix(R, TAU["fp64"], min(R.k_done, G["k_done"]))
+    assert k_piv >= 90
+    assert list(G["piv_g"][:k_piv]) == R.piv_g[:k_piv]
+    assert list(G["piv_t"][:k_piv]) == R.piv_t[:k_piv]
+    reg = RegParam("optimal", grid=grid, grid_relative=True, x_true=prob.x_true)
+    x0 = np.zeros(prob.n)
+    lams, idxs, seps = [], [], []
+    Xo = np.zeros((prob.n, k_piv))
+    for k in range(1, k_piv + 1):
+        s, c, V = projected_svd(R.H[:k + 1, :k])
+        lam, idx, sep, _ = select_lambda(reg, k, prob.m, R.beta, s, c, V, R.L[:, :k], x0)
+        lams.append(lam)
+        idxs.append(idx)
+        seps.append(sep)
+        Xo[:, k - 1] = R.L[:, :k] @ tikhonov_coeffs(R.beta, s, c, V, lam)
+    # the sensitivity of these iterates, at the optimal lambda sequence
+    tol = step_tolerances(sensitivity_at(runs, lams, Xo, k_piv), 2.0 ** -53, 1e-10)
+    same, worst = 0, 0.0
+    for k in range(1, k_piv + 1):
+        if G["lambda_idx"][k - 1] != idxs[k - 1]:
+            assert seps[k - 1] <= TAU["fp64"], (k, idxs[k - 1], G["lambda_idx"][k - 1])
+            continue
+        same += 1
+        e = rel(G["X"][:, k - 1], Xo[:, k - 1])
+        worst = max(worst, e / tol[k - 1])
+        assert e <= tol[k - 1], (k, e, tol[k - 1])
+    print(f"[tomo128 fp64 optimal] lambda and x_k compared at {same} of {k_piv} "
+          f"steps; max err/tol {worst:.2f}")
     assert same >= k_piv // 2
 
 

@@ -40,11 +40,12 @@ def _compare(lib, ctx, prob, prec, K, kind, relative, lam=0.05, replay=True,
              check_free=True, kappa_cap=None):
     """Run oracle + GPU (free and replay) and check the parity bar."""
     op = make_operator(prob)
-    R = hybrid_lslu(op, prob.b, K, _reg(kind, relative, lam))
-    grid = lambda_grid() if kind in ("wgcv", "gcv") else None
+    xt = prob.x_true if kind == "optimal" else None
+    R = hybrid_lslu(op, prob.b, K, _reg(kind, relative, lam, x_true=xt))
+    grid = lambda_grid() if kind in ("wgcv", "gcv", "optimal") else None
     tol = TOL[prec]
     if check_free:
-        G = gpu_solve(lib, ctx, prob, prec, K, kind, lam, grid, relative)
+        G = gpu_solve(lib, ctx, prob, prec, K, kind, lam, grid, relative, x_true=xt)
         check_basis_invariants(G, prob.m, prob.n)
         k_piv = pivot_prefix(R, TAU[prec], min(R.k_done, G["k_done"]))
         assert list(G["piv_g"][:k_piv]) == R.piv_g[:k_piv]
@@ -58,7 +59,7 @@ def _compare(lib, ctx, prob, prec, K, kind, relative, lam=0.05, replay=True,
     if replay:
         Kr = min(K, R.k_done)
         G = gpu_solve(lib, ctx, prob, prec, Kr, kind, lam, grid, relative,
-                      replay=replay_from(R, Kr))
+                      replay=replay_from(R, Kr), x_true=xt)
         check_basis_invariants(G, prob.m, prob.n, bound=1.0 + 10 * TAU[prec])
         assert G["k_done"] == Kr
         worst = []
@@ -141,7 +142,7 @@ def test_operator_products(lib, ctx, which, prec):
 
 # ------------------------------------------------------------ solve parity
 
-@pytest.mark.parametrize("kind", ["none", "wgcv", "gcv", "fixed"])
+@pytest.mark.parametrize("kind", ["none", "wgcv", "gcv", "fixed", "optimal"])
 def test_dense_blur_fp64(lib, ctx, kind):
     prob = config_problem("dense256")
     _compare(lib, ctx, prob, "fp64", 50, kind, relative=False, kappa_cap=1e5)
@@ -161,6 +162,34 @@ def test_tomography_small(lib, ctx, prec):
     prob = config_problem("tomo32")
     _compare(lib, ctx, prob, prec, 30, "wgcv", relative=True,
              check_free=(prec == "fp64"))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tomography_small_optimal(lib, ctx, prec):
+    prob = config_problem("tomo32")
+    _compare(lib, ctx, prob, prec, 30, "optimal", relative=True,
+             check_free=(prec == "fp64"))
+
+
+@pytest.mark.parametrize("prec,slack", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_optimal_error_not_above_wgcv(lib, ctx, prec, slack):
+    """The basis does not depend on lambda, so at every k the optimal grid
+    value (eq. lambda) gives an error to x_true no larger than the weighted
+    GCV choice on the same grid."""
+    prob = config_problem("tomo32")
+    grid = lambda_grid()
+    W = gpu_solve(lib, ctx, prob, prec, 30, "wgcv", grid=grid, grid_relative=True,
+                  bases=False)
+    O = gpu_solve(lib, ctx, prob, prec, 30, "optimal", grid=grid, grid_relative=True,
+                  bases=False, x_true=prob.x_true)
+    assert O["k_done"] == W["k_done"]
+    assert np.array_equal(O["piv_t"], W["piv_t"]) and np.array_equal(O["piv_g"], W["piv_g"])
+    nx = np.linalg.norm(prob.x_true)
+    for k in range(1, O["k_done"] + 1):
+        eo = np.linalg.norm(O["X"][:, k - 1] - prob.x_true) / nx
+        ew = np.linalg.norm(W["X"][:, k - 1] - prob.x_true) / nx
+        assert eo <= ew * (1 + slack) + slack, (k, eo, ew)
+    assert 0 <= O["lambda_idx"][:O["k_done"]].min() and O["lambda_idx"][:O["k_done"]].max() < len(grid)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -272,6 +301,7 @@ def test_invalid_options_are_rejected(lib, ctx):
     try:
         for kw in (dict(maxiter=0), dict(maxiter=20),
                    dict(maxiter=3, reg="wgcv"),
+                   dict(maxiter=3, reg="optimal", grid=[0.1, 1.0]),
                    dict(maxiter=3, reg="wgcv", grid=[1.0, 0.5]),
                    dict(maxiter=3, reg="fixed", lam=-1.0)):
             K = kw.pop("maxiter")
