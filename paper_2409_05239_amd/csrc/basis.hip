@@ -32,17 +32,18 @@ __global__ void k_sub(const T* __restrict__ a, const T* __restrict__ b,
 constexpr int kArgBlock = 256;
 constexpr int kMaxArgBlocks = 1024;
 
-// Per-block largest |v| (smallest index among equals).
+// Per-block entry of largest |v| (smallest index among equals), as the
+// signed value and its index.
 template <typename T>
 __global__ __launch_bounds__(kArgBlock) void k_argmax_parts(
     const T* __restrict__ v, int64_t len, ArgPart* __restrict__ parts,
     const DevState* st) {
   if (st->stopped) return;
-  double best = -1.0;
+  double best = 0.0;
   int bidx = INT_MAX;
   for (int64_t i = blockIdx.x * (int64_t)kArgBlock + threadIdx.x; i < len;
        i += (int64_t)gridDim.x * kArgBlock) {
-    const double key = fabs(static_cast<double>(v[i]));
+    const double key = static_cast<double>(v[i]);
     if (better(key, (int)i, best, bidx)) {
       best = key;
       bidx = (int)i;

@@ -124,10 +124,13 @@ __device__ inline double readlane_d(double v, int lane) {
 template <>
 __device__ inline double readlane_any(double v, int lane) { return readlane_d(v, lane); }
 
-// Total order of every pivot search: larger |v| first, then the smaller row
-// (ties go to the smallest index).  Ineligible rows carry key -1.
+// Total order of every pivot search over signed keys: larger |v| first, then
+// the smaller row (ties go to the smallest index).  Ineligible rows carry key
+// 0, so they never win over a nonzero entry and a search whose winner has key
+// 0 has found no pivot.
 __device__ inline bool better(double ka, int ia, double kb, int ib) {
-  return ka > kb || (ka == kb && ia < ib);
+  const double a = fabs(ka), b = fabs(kb);
+  return a > b || (a == b && ia < ib);
 }
 
 __device__ inline void wave_argmax(double& key, int& idx) {
@@ -165,6 +168,19 @@ __device__ inline void block_argmax(double& key, int& idx) {
 }
 
 // ------------------------------------------------------- operator rows ----
+// Operands of the first NP terms of a lane's share of one row: the operator
+// values and the entries of the not yet normalised input that they multiply.
+// Loading them needs no pivot, so a launch issues these loads before the
+// pivot is known; finish() normalises the staged inputs (x / pivot value,
+// the values the normalised vector holds) and adds the terms in the order
+// partial() would.
+template <typename V, typename T, int NP>
+struct RowStage {
+  V v[NP];
+  T x[NP];
+  int64_t row, next, end;
+};
+
 // Each policy sums its row over the lanes sub, sub+G, ... of a group of G
 // lanes with x(c) supplied by a functor; group_sum<G> completes the sum.
 
@@ -172,17 +188,46 @@ __device__ inline void block_argmax(double& key, int& idx) {
 template <typename V, typename AccT, bool kBf16>
 struct DenseRows {
   using Acc = AccT;
+  using Val = V;
   const V* a;
   int64_t cols;
   template <int G, typename XF>
-  __device__ Acc partial(int64_t r, int sub, XF xf) const {
+  __device__ Acc rest(int64_t r, int64_t c0, XF xf, Acc acc) const {
     const V* row = a + r * cols;
-    Acc acc = 0;
 #pragma unroll 4
-    for (int64_t c = sub; c < cols; c += G)
+    for (int64_t c = c0; c < cols; c += G)
       acc = fma(static_cast<Acc>(ValTraits<V>::get(row[c])),
                 static_cast<Acc>(in_val<kBf16>(xf(c))), acc);
     return acc;
+  }
+  template <int G, typename XF>
+  __device__ Acc partial(int64_t r, int sub, XF xf) const {
+    return rest<G>(r, sub, xf, Acc(0));
+  }
+  // The first NP terms of the lane: columns sub, sub+G, ...
+  template <int G, int NP, typename T>
+  __device__ void stage(int64_t r, int sub, const T* __restrict__ u,
+                        RowStage<V, T, NP>& s) const {
+    const V* row = a + r * cols;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const int64_t c = sub + (int64_t)k * G;
+      s.v[k] = c < cols ? row[c] : V(0);
+      s.x[k] = c < cols ? u[c] : T(0);
+    }
+    s.row = r;
+    s.next = sub + (int64_t)NP * G;
+    s.end = cols;
+  }
+  template <int G, int NP, typename T, typename NZ, typename XF>
+  __device__ Acc finish(const RowStage<V, T, NP>& s, const NZ& nz, XF xf) const {
+    Acc acc = 0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+      if (s.next - (int64_t)(NP - k) * G < s.end)
+        acc = fma(static_cast<Acc>(ValTraits<V>::get(s.v[k])),
+                  static_cast<Acc>(in_val<kBf16>(nz(s.x[k]))), acc);
+    return rest<G>(s.row, s.next, xf, acc);
   }
 };
 
@@ -192,16 +237,15 @@ struct DenseRows {
 template <typename V, typename AccT, bool kBf16>
 struct CsrRows {
   using Acc = AccT;
+  using Val = V;
   static constexpr int kBatch = 8;
   const int* rp;
   const int* ci;
   const V* val;
+  // Entries p, p+G, ... below end, added to acc in that order.
   template <int G, typename XF>
-  __device__ Acc partial(int64_t r, int sub, XF xf) const {
+  __device__ Acc rest(int p, int end, XF xf, Acc acc) const {
     using X = decltype(xf(0));
-    const int beg = rp[r], end = rp[r + 1];
-    Acc acc = 0;
-    int p = beg + sub;
     for (; p + (kBatch - 1) * G < end; p += kBatch * G) {
       int c[kBatch];
       V v[kBatch];
@@ -236,6 +280,40 @@ struct CsrRows {
                   static_cast<Acc>(in_val<kBf16>(xv[u])), acc);
     return acc;
   }
+  template <int G, typename XF>
+  __device__ Acc partial(int64_t r, int sub, XF xf) const {
+    return rest<G>(rp[r] + sub, rp[r + 1], xf, Acc(0));
+  }
+  // The first NP entries of the lane (positions beg+sub, beg+sub+G, ...):
+  // values and the raw input entries they multiply.
+  template <int G, int NP, typename T>
+  __device__ void stage(int64_t r, int sub, const T* __restrict__ u,
+                        RowStage<V, T, NP>& s) const {
+    const int end = rp[r + 1];
+    const int p = rp[r] + sub;
+    int c[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const int q = p + k * G;
+      c[k] = q < end ? ci[q] : 0;
+      s.v[k] = q < end ? val[q] : V(0);
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) s.x[k] = (p + k * G < end) ? u[c[k]] : T(0);
+    s.row = r;
+    s.next = p + NP * G;
+    s.end = end;
+  }
+  template <int G, int NP, typename T, typename NZ, typename XF>
+  __device__ Acc finish(const RowStage<V, T, NP>& s, const NZ& nz, XF xf) const {
+    Acc acc = 0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+      if (s.next - (NP - k) * G < s.end)
+        acc = fma(static_cast<Acc>(ValTraits<V>::get(s.v[k])),
+                  static_cast<Acc>(in_val<kBf16>(nz(s.x[k]))), acc);
+    return rest<G>(static_cast<int>(s.next), static_cast<int>(s.end), xf, acc);
+  }
 };
 
 // Pixel `pix` of the zero-boundary correlation with weights wt (ph x pw):
@@ -243,6 +321,7 @@ struct CsrRows {
 template <typename AccT, bool kBf16>
 struct PsfPixels {
   using Acc = AccT;
+  using Val = AccT;
   const Acc* wt;
   int rows, cols, ph, pw;
   template <int G, typename XF>
@@ -259,6 +338,16 @@ struct PsfPixels {
                   acc);
     }
     return acc;
+  }
+  // Nothing is staged: the terms need the pivot value only through x.
+  template <int G, int NP, typename T>
+  __device__ void stage(int64_t pix, int sub, const T* __restrict__, RowStage<Acc, T, NP>& s) const {
+    s.row = pix;
+    s.next = sub;
+  }
+  template <int G, int NP, typename T, typename NZ, typename XF>
+  __device__ Acc finish(const RowStage<Acc, T, NP>& s, const NZ&, XF xf) const {
+    return partial<G>(s.row, static_cast<int>(s.next), xf);
   }
 };
 

@@ -36,12 +36,12 @@ struct DevState {
   int mismatch_g;   // replay: own pivot choice differed (l side)
   int ticket;       // half-iteration: pivot-entry blocks finished (reset by block 0)
   double beta;      // r_0(t(1))
-  double cur_val;   // pivot value resolved by the running half-iteration
-  int cur_pick;     // its row
   int spin_timeouts;  // waits that hit their bound (an error; never expected)
 };
 
-// One candidate of the pivot search: |v| (key, -1 when ineligible) and row.
+// One candidate of the pivot search: the signed value v at row idx (key; 0
+// for a row that may not be a pivot).  Candidates are ordered by |key|, then
+// by the smaller row, so the winner's key is the pivot value itself.
 struct ArgPart {
   double key;
   int idx;
@@ -115,8 +115,18 @@ void op_apply(const DeviceOp& op, int transpose, const void* x, void* y,
 //                      basis column once the pivot is published, and subtract
 //                      the earlier basis vectors once the coefficients are,
 //                      writing per-block pivot candidates.
-// Later blocks only ever wait for flags set by earlier ones, which never wait
-// for later ones; every wait is bounded.
+// Later blocks only ever wait for values written by earlier ones, which never
+// wait for later ones; every wait is bounded.  Everything published inside a
+// launch goes through slots that hold kSlotEmpty until written once, so a
+// waiter reads the value itself and no flag orders other memory.
+//
+// Slots of one launch (slots_per_launch(K) doubles):
+//   [0, K+1)       pivot entries of the product      (blocks 1.. -> block 0)
+//   [K+1, 2K+2)    coefficients                      (block 0 -> consumers)
+//   2K+2, 2K+3     pivot value; row | state << 32    (block 0 -> all), state
+//                  1 = pivot found, 2 = breakdown (the launch ends)
+__host__ __device__ inline int64_t slots_per_launch(int K) { return 2 * (int64_t)K + 4; }
+
 template <typename T>
 struct HalfArgs {
   // previous half: its unnormalised vector and pivot candidates
@@ -139,11 +149,13 @@ struct HalfArgs {
   const int* piv;          // this side's pivots (rows of the pivot entries)
   const T* Tp;             // this side's packed triangle
   double* coef;            // coefficient destination (a column of W or H)
-  double* ybuf;            // nb slots, kSlotEmpty until written
+  double* entries;         // this launch's slots (layout above)
+  double* cslot;
+  uint64_t* pslot;
+  int* fail;               // set by block 0 when it cannot publish coefficients
   const unsigned char* mask;
   T* out;
   ArgPart* parts_out;
-  int* flags;              // [0] pivot published (1, or 2 on breakdown), [1] coefficients
   int nlead;               // blocks 0..nlead-1 lead; set by launch_half
 };
 // Returns the number of candidates written to parts_out.

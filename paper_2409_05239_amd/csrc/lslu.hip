@@ -28,8 +28,8 @@ namespace {
 struct Layout {
   void *L = nullptr, *D = nullptr, *q = nullptr, *u = nullptr, *r0 = nullptr,
        *X = nullptr;
-  double* ybuf = nullptr;  // pivot entries of the products, K + 1 per launch
-  int* flags = nullptr;    // two per launch of the recurrence
+  double* ybuf = nullptr;  // slots of the recurrence, slots_per_launch(K) per launch
+  int* flags = nullptr;    // one failure flag per launch of the recurrence
   void *TL = nullptr, *TD = nullptr;  // pivot-row triangles, basis precision
   double *grid = nullptr, *proj = nullptr;
   double *gram = nullptr, *gram_part = nullptr;  // optimal rule only
@@ -76,8 +76,8 @@ size_t carve(unsigned char* base, int64_t m, int64_t n, int K, size_t esz,
   l.q = take(esz * n);
   l.u = take(esz * m);
   l.r0 = take(esz * m);
-  l.ybuf = reinterpret_cast<double*>(take(sizeof(double) * (K + 1) * (2 * K + 2)));
-  l.flags = reinterpret_cast<int*>(take(sizeof(int) * 2 * (2 * K + 2)));
+  l.ybuf = reinterpret_cast<double*>(take(sizeof(double) * slots_per_launch(K) * (2 * K + 2)));
+  l.flags = reinterpret_cast<int*>(take(sizeof(int) * (2 * K + 2)));
   l.X = take(esz * n * K);
   l.TL = take(esz * K * (K + 1) / 2);        // packed rows, strict lower
   l.TD = take(esz * (K + 1) * (K + 2) / 2);
@@ -279,9 +279,9 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
   launch_fill<int>(l.piv_g, -1, K, s);
   launch_fill<int>(l.own_t, -1, K + 1, s);
   launch_fill<int>(l.own_g, -1, K, s);
-  launch_fill<int>(l.flags, 0, 2 * (2 * K + 2), s);
+  launch_fill<int>(l.flags, 0, 2 * K + 2, s);
   launch_fill<uint64_t>(reinterpret_cast<uint64_t*>(l.ybuf), kSlotEmpty,
-                        (int64_t)(K + 1) * (2 * K + 2), s);
+                        slots_per_launch(K) * (2 * K + 2), s);
   launch_fill<double>(l.H, 0.0, (int64_t)(K + 1) * K, s);
   launch_fill<double>(l.W, 0.0, (int64_t)K * K, s);
   launch_fill<double>(l.Y, 0.0, (int64_t)K * K, s);
@@ -338,8 +338,10 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
     a.Trowp = k > 0 ? TD + packed(k) : nullptr;
   };
   auto run = [&](HalfArgs<T>& a, int tr) {
-    a.ybuf = l.ybuf + (int64_t)(K + 1) * launch;
-    a.flags = l.flags + 2 * launch++;
+    a.entries = l.ybuf + slots_per_launch(K) * launch;
+    a.cslot = a.entries + (K + 1);
+    a.pslot = reinterpret_cast<uint64_t*>(a.entries + 2 * (K + 1));
+    a.fail = l.flags + launch++;
     a.parts_out = parts[cur ^ 1];
     nparts = launch_half<T>(a, op, tr, lds, s);
     cur ^= 1;

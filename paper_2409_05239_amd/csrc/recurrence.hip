@@ -27,12 +27,17 @@
 // cancellations are those of the normalised vector.  The products therefore start once the pivot is
 // published; the triangular solve of block 0 overlaps them.
 //
-// Synchronisation inside the launch: blocks only ever wait for flags set by
-// lower-numbered blocks, which never wait for higher-numbered ones; workgroups
-// are dispatched in order, so the blocks that publish are resident first.
-// Every wait is bounded: a wait that runs out counts a device error and the
-// launch finishes.  Results do not depend on timing or on the launch
-// configuration.
+// Synchronisation inside the launch: blocks only ever wait for values written
+// by lower-numbered blocks, which never wait for higher-numbered ones;
+// workgroups are dispatched in order, so the blocks that publish are resident
+// first.  Everything published inside a launch (the pivot, its value, the
+// pivot entries, the coefficients) goes through slots that hold a sentinel
+// until written once; a waiter polls the slot itself, so no flag has to order
+// other memory and nobody fences.  Every load a product needs that does not
+// depend on the pivot (indices, values and the gathered entries of the
+// unnormalised vector) is issued before the wait.  Every wait is bounded: a
+// wait that runs out counts a device error and the launch finishes.  Results
+// do not depend on timing or on the launch configuration.
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -50,6 +55,8 @@ constexpr int kRowsPerBlock = kThreads / kRowLanes;    // 16
 constexpr int kCoefPerLane = kMaxIter / kRowLanes;     // 16
 constexpr int kPartsPerThread = kMaxParts / kThreads;  // 16
 constexpr int kStage = 8;
+constexpr int kEntryStage = 8;   // staged terms per lane of a pivot-entry row
+constexpr int kRowStage = 8;     // staged terms per lane of a consumer's first row
 constexpr int kNormBatch = 8;
 constexpr int kSpinLimit = 1 << 20;
 constexpr int kTriB = 32;  // rows of a diagonal block of the triangular solve
@@ -59,51 +66,56 @@ static_assert(sizeof(ArgPart) == 16, "candidates are read as 16-byte vectors");
 
 __host__ __device__ inline int64_t packed_row(int j) { return (int64_t)j * (j - 1) / 2; }
 
-// ------------------------------------------------------------------ flags --
-// Called by thread 0 of block 0 after a block barrier: the release store makes
-// the block's earlier stores visible at device scope before the flag.  Only
-// block 0 publishes (twice per launch).  Waiting blocks read everything that
-// is produced inside the launch (the pivot, the coefficients, the pivot
-// entries) with device-coherent loads, so they never fence: a device-scope
-// fence writes back and invalidates the whole L2 of its XCD.
-__device__ inline void publish(int* flag, int v) {
-  __hip_atomic_store(flag, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+// ------------------------------------------------------------------ slots --
+// Slots are written once per launch with device-coherent stores and polled
+// with device-coherent loads (they bypass the non-coherent caches, so no
+// fence is needed on either side: a device-scope fence writes back and
+// invalidates the whole L2 of the XCD).
+__device__ inline void store_u64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline uint64_t load_u64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ inline uint64_t load_u64(const double* p) {
-  return __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+  return load_u64(reinterpret_cast<const uint64_t*>(p));
 }
 
 __device__ inline int load_i(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ inline double load_d(const double* p) {
-  return __builtin_bit_cast(
-      double, __hip_atomic_load(reinterpret_cast<const uint64_t*>(p),
-                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-}
+__device__ inline uint64_t dbits(double v) { return __builtin_bit_cast(uint64_t, v); }
 
-// Block-wide bounded wait until *flag reaches `target` (nonzero: any nonzero
-// value).  Returns the value seen, or 0 when the bound ran out.
-__device__ inline int block_wait(const int* flag, int target, DevState* st) {
-  __shared__ int seen;
+// Block-wide bounded wait for the pivot of the previous half.  Returns true
+// with its row and value when one was found, false on breakdown or when the
+// bound ran out (counted as a device error).
+template <typename T>
+__device__ inline bool wait_pivot(const HalfArgs<T>& a, DevState* st, int& pick,
+                                  double& val) {
+  __shared__ uint64_t sv, sp;
   if (threadIdx.x == 0) {
-    int v = 0;
+    uint64_t v = kSentinel, p = kSentinel;
     for (int it = 0; it < kSpinLimit; ++it) {
-      v = load_i(flag);
-      if (target ? v >= target : v != 0) break;
+      v = load_u64(a.pslot);
+      p = load_u64(a.pslot + 1);
+      if (v != kSentinel && p != kSentinel) break;
       __builtin_amdgcn_s_sleep(1);
     }
-    if (!(target ? v >= target : v != 0)) {
+    if (v == kSentinel || p == kSentinel) {
       atomicAdd(&st->spin_timeouts, 1);
-      v = 0;
+      p = 0;  // state 0: stop
     }
-    seen = v;
+    sv = v;
+    sp = p;
   }
   __syncthreads();
-  return seen;
+  const uint64_t p = sp;
+  pick = static_cast<int>(static_cast<uint32_t>(p));
+  val = __builtin_bit_cast(double, sv);
+  return (p >> 32) == 1;
 }
 
 // ------------------------------------------------------- triangular solve --
@@ -172,7 +184,7 @@ __device__ void lead(const HalfArgs<T>& a, DevState* st, unsigned char* lds) {
     const int64_t p = (int64_t)u * kThreads + tid;
     tbuf[u] = (p < P) ? a.Tp[p] : T(0);
   }
-  double key = -1.0;
+  double key = 0.0;
   int idx = INT_MAX;
   constexpr int kHalf = kPartsPerThread / 2;
 #pragma unroll
@@ -186,11 +198,9 @@ __device__ void lead(const HalfArgs<T>& a, DevState* st, unsigned char* lds) {
     }
 #pragma unroll
     for (int u = 0; u < kHalf; ++u) {
-      const int i = tid + (h * kHalf + u) * kThreads;
-      const double k2 = (i < a.nparts_in)
-          ? __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(raw[u].y)) << 32) |
-                                           static_cast<uint32_t>(raw[u].x))
-          : -1.0;
+      const double k2 = __builtin_bit_cast(
+          double, (static_cast<uint64_t>(static_cast<uint32_t>(raw[u].y)) << 32) |
+                      static_cast<uint32_t>(raw[u].x));
       if (better(k2, raw[u].z, key, idx)) {
         key = k2;
         idx = raw[u].z;
@@ -199,11 +209,15 @@ __device__ void lead(const HalfArgs<T>& a, DevState* st, unsigned char* lds) {
   }
   block_argmax<kThreads>(key, idx);
   const PivotJob& job = a.job;
-  const int own = (job.eligible && key > 0.0) ? idx : -1;
+  const int own = (job.eligible && fabs(key) > 0.0) ? idx : -1;
   const int pick = job.replay ? (job.eligible ? job.replay[job.piv_pos] : -1) : own;
-  const double val = (pick >= 0) ? static_cast<double>(a.up[pick]) : 0.0;
+  // The winning candidate carries the pivot value; a replayed pivot is read.
+  const double val = pick < 0 ? 0.0
+                     : (job.replay ? static_cast<double>(a.up[pick]) : key);
   const bool brk = (pick < 0 || val == 0.0);
   if (tid == 0) {
+    store_u64(a.pslot, dbits(brk ? 0.0 : val));
+    store_u64(a.pslot + 1, static_cast<uint32_t>(pick) | (static_cast<uint64_t>(brk ? 2 : 1) << 32));
     if (job.own_list) job.own_list[job.piv_pos] = own;
     if (job.replay && pick != own) {
       if (job.side == 0) st->mismatch_g += 1; else st->mismatch_t += 1;
@@ -225,8 +239,6 @@ __device__ void lead(const HalfArgs<T>& a, DevState* st, unsigned char* lds) {
       *job.piv_val = val;
       job.piv_list[job.piv_pos] = pick;
       job.mask[pick] = 1;
-      st->cur_pick = pick;
-      st->cur_val = val;
       if (job.side == 2) {
         st->beta = val;
         st->n_d = 1;
@@ -237,18 +249,13 @@ __device__ void lead(const HalfArgs<T>& a, DevState* st, unsigned char* lds) {
         st->k_done = job.k;
       }
     }
-    publish(&a.flags[0], brk ? 2 : 1);
   }
   if (brk) return;
   if (a.Trowp) {  // needed by later launches only
     for (int j = tid; j < a.nbp; j += kThreads)
       a.Trowp[j] = a.basisp[(int64_t)pick * a.rsp + (int64_t)j * a.csp];
   }
-  if (a.rows == 0) return;
-  if (nb == 0) {
-    if (tid == 0) publish(&a.flags[1], 1);
-    return;
-  }
+  if (nb == 0) return;
   if constexpr (kTriLds) {
     T* lt = reinterpret_cast<T*>(lds);
 #pragma unroll
@@ -274,7 +281,7 @@ __device__ void lead(const HalfArgs<T>& a, DevState* st, unsigned char* lds) {
   for (int j = tid; j < nb; j += kThreads) {
     uint64_t bits = kSentinel;
     for (int it = 0; it < kSpinLimit; ++it) {
-      bits = load_u64(a.ybuf + j);
+      bits = load_u64(a.entries + j);
       if (bits != kSentinel) break;
       __builtin_amdgcn_s_sleep(1);
     }
@@ -288,7 +295,7 @@ __device__ void lead(const HalfArgs<T>& a, DevState* st, unsigned char* lds) {
   if (!all_in) {
     if (tid == 0) {
       atomicAdd(&st->spin_timeouts, 1);
-      publish(&a.flags[1], 3);
+      __hip_atomic_store(a.fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     return;
   }
@@ -296,9 +303,10 @@ __device__ void lead(const HalfArgs<T>& a, DevState* st, unsigned char* lds) {
     trisolve_inplace<T>(g, nb, reinterpret_cast<const T*>(lds));
   else
     trisolve_inplace<T>(g, nb, a.Tp);
-  for (int j = tid; j < nb; j += kThreads) a.coef[j] = g[j];
-  __syncthreads();
-  if (tid == 0) publish(&a.flags[1], 1);
+  for (int j = tid; j < nb; j += kThreads) {
+    store_u64(reinterpret_cast<uint64_t*>(a.cslot) + j, dbits(g[j]));
+    a.coef[j] = g[j];
+  }
 }
 
 // ------------------------------------------------- pivot-entry blocks -----
@@ -307,19 +315,19 @@ __device__ void pivot_entries(const HalfArgs<T>& a, const RowOp& op, DevState* s
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
   const int jr = (blockIdx.x - 1) * kWaves + w;
   const bool act = jr < a.nb;
-  const int row = act ? a.piv[jr] : 0;
-  if (block_wait(&a.flags[0], 0, st) != 1) return;
-  const Normaliser<T> nz(static_cast<T>(load_d(&st->cur_val)));
+  RowStage<typename RowOp::Val, T, kEntryStage> sg;
+  if (act) op.template stage<kWave, kEntryStage>(a.piv[jr], lane, a.up, sg);
+  int pick;
+  double val;
+  if (!wait_pivot(a, st, pick, val)) return;
   if (!act) return;
+  const Normaliser<T> nz(static_cast<T>(val));
   auto xf = [&](int64_t c) -> T { return nz(a.up[c]); };
-  typename RowOp::Acc acc = op.template partial<kWave>(row, lane, xf);
+  typename RowOp::Acc acc = op.template finish<kWave, kEntryStage>(sg, nz, xf);
   acc = group_sum<kWave>(acc);
-  if (lane == 0) {
-    const double y = static_cast<double>(static_cast<T>(acc));
-    __hip_atomic_store(reinterpret_cast<uint64_t*>(a.ybuf) + jr,
-                       __builtin_bit_cast(uint64_t, y), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (lane == 0)
+    store_u64(reinterpret_cast<uint64_t*>(a.entries) + jr,
+              dbits(static_cast<double>(static_cast<T>(acc))));
 }
 
 // Normalise this block's share of the previous vector into its basis column.
@@ -348,20 +356,57 @@ __device__ inline void write_part(ArgPart* parts, int b, double key, int idx) {
   parts[b].idx = idx;
 }
 
-// Waits for the coefficients and stages them in LDS; false when the launch
-// is to end (breakdown or error).
+// Waits for the coefficients and stages them in LDS (wavefront 0 polls all
+// nb slots at once); false when the launch is to end (block 0 could not form
+// them, or the bound ran out).
 template <typename T>
 __device__ inline bool fetch_coef(const HalfArgs<T>& a, DevState* st, double* cf) {
-  if (a.nb == 0) return true;
-  if (block_wait(&a.flags[1], 0, st) != 1) return false;
-  for (int j = threadIdx.x; j < a.nb; j += kThreads) cf[j] = load_d(a.coef + j);
+  __shared__ int ok_s;
+  const int nb = a.nb;
+  if (nb == 0) return true;
+  if (threadIdx.x < kWave) {
+    constexpr int kPer = kMaxIter / kWave;
+    const int lane = threadIdx.x;
+    const uint64_t* cs = reinterpret_cast<const uint64_t*>(a.cslot);
+    uint64_t bits[kPer];
+    bool ok = false, failed = false;
+    for (int it = 0; it < kSpinLimit; ++it) {
+      bool miss = false;
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int j = lane + u * kWave;
+        bits[u] = j < nb ? load_u64(cs + j) : 0;
+        miss = miss || (j < nb && bits[u] == kSentinel);
+      }
+      if (__ballot(miss) == 0) {
+        ok = true;
+        break;
+      }
+      if (load_i(a.fail) != 0) {
+        failed = true;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int j = lane + u * kWave;
+      if (j < nb) cf[j] = __builtin_bit_cast(double, bits[u]);
+    }
+    if (lane == 0) {
+      ok_s = ok ? 1 : 0;
+      if (!ok && !failed) atomicAdd(&st->spin_timeouts, 1);
+    }
+  }
   __syncthreads();
-  return true;
+  return ok_s != 0;
 }
 
 // --------------------------------------------------- row consumer blocks --
-// Persistent over rows r = (cb + i ncons) * 16 + group: every product first
-// (its value parked in out[r]), then one wait for the coefficients, then the
+// Persistent over rows r = (cb + i ncons) * 16 + group: the loads of the
+// first row's first terms before the pivot is known, then every product (the
+// first kept in a register, the others parked in out[r]), the elimination
+// inputs of the first row, one wait for the coefficients, then the
 // elimination.  A waiting block therefore never holds resources that
 // undispatched work needs.
 template <typename T, class RowOp>
@@ -375,28 +420,55 @@ __device__ void consume_rows(const HalfArgs<T>& a, const RowOp& op, DevState* st
   const int nb = a.nb;
   const int64_t stride = (int64_t)ncons * kRowsPerBlock;
   const int64_t r0 = (int64_t)cb * kRowsPerBlock + rl;
-  if (block_wait(&a.flags[0], 0, st) != 1) return;
-  const int pick = load_i(&st->cur_pick);
-  const Normaliser<T> nz(static_cast<T>(load_d(&st->cur_val)));
+  const bool has0 = r0 < a.rows;
+  RowStage<typename RowOp::Val, T, kRowStage> sg;
+  if (has0) op.template stage<kRowLanes, kRowStage>(r0, sub, a.up, sg);
+  int pick;
+  double val;
+  if (!wait_pivot(a, st, pick, val)) return;
+  const Normaliser<T> nz(static_cast<T>(val));
   auto xf = [&](int64_t c) -> T { return nz(a.up[c]); };
-  for (int64_t r = r0; r < a.rows; r += stride) {
+  T q_first = T(0);
+  if (has0) {
+    Acc acc = op.template finish<kRowLanes, kRowStage>(sg, nz, xf);
+    q_first = static_cast<T>(group_sum<kRowLanes>(acc));
+  }
+  for (int64_t r = r0 + stride; r < a.rows; r += stride) {
     Acc acc = op.template partial<kRowLanes>(r, sub, xf);
     acc = group_sum<kRowLanes>(acc);
     if (sub == 0) a.out[r] = static_cast<T>(acc);
   }
   normalise_share(a, cb, ncons, pick, nz);
   if (a.rows == 0) return;
-  if (!fetch_coef(a, st, cf)) return;
-  double key = -1.0;
-  int idx = INT_MAX;
-  for (int64_t r = r0; r < a.rows; r += stride) {
-    const bool piv = a.mask[r] != 0;
-    const T* brow = a.basis + r * a.rs;
-    T bv[kCoefPerLane];
+  // Elimination inputs of the first row, loaded before the coefficients.
+  T bv0[kCoefPerLane];
+  bool piv0 = true;
+  if (has0) {
+    piv0 = a.mask[r0] != 0;
+    const T* brow = a.basis + r0 * a.rs;
 #pragma unroll
     for (int u = 0; u < kCoefPerLane; ++u) {
       const int j = sub + u * kRowLanes;
-      bv[u] = (j < nb) ? brow[(int64_t)j * a.cs] : T(0);
+      bv0[u] = (j < nb) ? brow[(int64_t)j * a.cs] : T(0);
+    }
+  }
+  if (!fetch_coef(a, st, cf)) return;
+  double key = 0.0;
+  int idx = INT_MAX;
+  for (int64_t r = r0; r < a.rows; r += stride) {
+    const bool first = r == r0;
+    const bool piv = first ? piv0 : a.mask[r] != 0;
+    T bv[kCoefPerLane];
+    if (first) {
+#pragma unroll
+      for (int u = 0; u < kCoefPerLane; ++u) bv[u] = bv0[u];
+    } else {
+      const T* brow = a.basis + r * a.rs;
+#pragma unroll
+      for (int u = 0; u < kCoefPerLane; ++u) {
+        const int j = sub + u * kRowLanes;
+        bv[u] = (j < nb) ? brow[(int64_t)j * a.cs] : T(0);
+      }
     }
     double e = 0.0;
 #pragma unroll
@@ -406,10 +478,10 @@ __device__ void consume_rows(const HalfArgs<T>& a, const RowOp& op, DevState* st
     }
     e = group_sum<kRowLanes>(e);
     if (sub == 0) {
-      const double q0 = static_cast<double>(a.out[r]);
+      const double q0 = static_cast<double>(first ? q_first : a.out[r]);
       const T o = piv ? T(0) : static_cast<T>(q0 - e);
       a.out[r] = o;
-      const double k2 = piv ? -1.0 : fabs(static_cast<double>(o));
+      const double k2 = piv ? 0.0 : static_cast<double>(o);
       if (better(k2, (int)r, key, idx)) {
         key = k2;
         idx = (int)r;
@@ -493,9 +565,10 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
   const int tiles_x = (cols + kPsfTW - 1) / kPsfTW;
   const int ntiles = a.rows > 0 ? tiles_x * ((rows + kPsfTH - 1) / kPsfTH) : 0;
   const int nb = a.nb;
-  if (block_wait(&a.flags[0], 0, st) != 1) return;
-  const int pick = load_i(&st->cur_pick);
-  const Normaliser<T> nz(static_cast<T>(load_d(&st->cur_val)));
+  int pick;
+  double val;
+  if (!wait_pivot(a, st, pick, val)) return;
+  const Normaliser<T> nz(static_cast<T>(val));
   for (int t = cb; t < ntiles; t += ncons) {
     const int i0 = (t / tiles_x) * kPsfTH, j0 = (t % tiles_x) * kPsfTW;
     Acc acc[kPsfR];
@@ -510,7 +583,7 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
   normalise_share(a, cb, ncons, pick, nz);
   if (a.rows == 0) return;
   if (!fetch_coef(a, st, cf)) return;
-  double best = -1.0;
+  double best = 0.0;
   int bidx = INT_MAX;
   for (int t = cb; t < ntiles; t += ncons) {
     const int i0 = (t / tiles_x) * kPsfTH, j0 = (t % tiles_x) * kPsfTW;
@@ -557,7 +630,7 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
       const double q0 = static_cast<double>(a.out[pix[p]]);
       const T o = mk[p] ? T(0) : static_cast<T>(q0 - e[p]);
       a.out[pix[p]] = o;
-      const double k2 = mk[p] ? -1.0 : fabs(static_cast<double>(o));
+      const double k2 = mk[p] ? 0.0 : static_cast<double>(o);
       if (better(k2, (int)pix[p], best, bidx)) {
         best = k2;
         bidx = (int)pix[p];
