@@ -1,8 +1,11 @@
 // Iterates x_k = x_0 + L_k y_k (Algorithm 5, last step of the loop), for all
 // k = 1..k_done at once: X = x_0 1^T + L Y with Y upper triangular (column k-1
-// of Y holds y_k).  Each thread owns one row of L and a block of kChunk
-// consecutive iterates; y entries are wave-uniform.  Sums run over j in
-// increasing order in FP64.
+// of Y holds y_k).  A register-tiled product: a block owns 64 rows of L and
+// 64 iterates; chunks of 16 columns of L (staged with loads along the
+// basis's contiguous direction) and the matching 16 x 64 block of Y go
+// through LDS; each thread accumulates a 4 x 4 tile.  Every x_k(r) sums its
+// terms over j in increasing order in FP64, so the result does not depend on
+// the tiling.  Columns of L beyond k_done are never read.
 //
 // Also here: the stopping rule (eq. tol) evaluated on the device, and the copy
 // of the selected iterate into the caller's output vector.
@@ -12,7 +15,9 @@ namespace lslu {
 
 namespace {
 
-constexpr int kChunk = 32;
+constexpr int kAR = 64;   // rows of L per block
+constexpr int kAC = 64;   // iterates per block
+constexpr int kAJ = 16;   // columns of L per chunk
 constexpr int kAsmBlock = 256;
 
 template <typename T>
@@ -20,28 +25,69 @@ __global__ __launch_bounds__(kAsmBlock) void k_assemble(
     const T* __restrict__ L, int64_t rs, int64_t cs, int64_t n, const double* __restrict__ Y,
     int K, const T* __restrict__ x0, T* __restrict__ X,
     const DevState* __restrict__ st) {
+  __shared__ double sl[kAJ][kAR + 1];
+  __shared__ double sy[kAJ][kAC + 1];
   const int kd = st->k_done;
-  const int k0 = blockIdx.y * kChunk;  // iterates k0+1 .. k0+kChunk
+  const int k0 = blockIdx.y * kAC;  // iterates k0+1 .. k0+kAC
   if (k0 >= kd) return;
-  const int64_t r = (int64_t)blockIdx.x * kAsmBlock + threadIdx.x;
-  if (r >= n) return;
-  const int kc = min(kChunk, kd - k0);
-  double acc[kChunk];
+  const int64_t r0 = (int64_t)blockIdx.x * kAR;
+  const int tid = threadIdx.x;
+  const int tr = (tid % (kAR / 4)) * 4;  // 4 consecutive rows
+  const int tc = (tid / (kAR / 4)) * 4;  // 4 consecutive iterates
+  double acc[4][4];
 #pragma unroll
-  for (int c = 0; c < kChunk; ++c) acc[c] = 0.0;
-  const int jmax = k0 + kc;  // y_{k0+kc} has k0+kc entries
-  for (int j = 0; j < jmax; ++j) {
-    const double l = static_cast<double>(L[r * rs + (int64_t)j * cs]);
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int c = 0; c < kChunk; ++c) {
-      // y_{k0+c+1} has entries j = 0 .. k0+c
-      if (c < kc && j <= k0 + c) acc[c] = fma(l, Y[(int64_t)(k0 + c) * K + j], acc[c]);
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  // y_k has entries j < k, so this block needs j < min(k0 + kAC, k_done)
+  const int jmax = min(k0 + kAC, kd);
+  for (int j0 = 0; j0 < jmax; j0 += kAJ) {
+    for (int e = tid; e < kAJ * kAR; e += kAsmBlock) {
+      int jj, rr;
+      if (rs == 1) {  // columns contiguous: consecutive threads along rows
+        rr = e % kAR;
+        jj = e / kAR;
+      } else {        // rows contiguous: consecutive threads along columns
+        jj = e % kAJ;
+        rr = e / kAJ;
+      }
+      const int64_t r = r0 + rr;
+      const int j = j0 + jj;
+      sl[jj][rr] = (r < n && j < jmax) ? static_cast<double>(L[r * rs + (int64_t)j * cs]) : 0.0;
+    }
+    for (int e = tid; e < kAJ * kAC; e += kAsmBlock) {
+      const int jj = e % kAJ, cc = e / kAJ;  // column k0+cc of Y is y_{k0+cc+1}
+      const int j = j0 + jj, k = k0 + cc;
+      sy[jj][cc] = (j < jmax && k < kd) ? Y[(int64_t)k * K + j] : 0.0;
+    }
+    __syncthreads();
+    const int jn = min(kAJ, jmax - j0);
+    for (int jj = 0; jj < jn; ++jj) {
+      double lv[4], yv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) lv[a] = sl[jj][tr + a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) yv[b] = sy[jj][tc + b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fma(lv[a], yv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int k = k0 + tc + b;
+    if (k >= kd) continue;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int64_t r = r0 + tr + a;
+      if (r < n) {
+        const double xb = x0 ? static_cast<double>(x0[r]) : 0.0;
+        X[(int64_t)k * n + r] = static_cast<T>(xb + acc[a][b]);
+      }
     }
   }
-  const double xb = x0 ? static_cast<double>(x0[r]) : 0.0;
-#pragma unroll
-  for (int c = 0; c < kChunk; ++c)
-    if (c < kc) X[(int64_t)(k0 + c) * n + r] = static_cast<T>(xb + acc[c]);
 }
 
 // k_sel: iterate to return (0 = x_0).
@@ -78,8 +124,7 @@ template <typename T>
 void launch_assemble(const T* L, int64_t rs, int64_t cs, int64_t n,
                      const double* Y, int K, const T* x0, T* X,
                      const DevState* st, hipStream_t s) {
-  dim3 grid((unsigned)((n + kAsmBlock - 1) / kAsmBlock),
-            (unsigned)((K + kChunk - 1) / kChunk));
+  dim3 grid((unsigned)((n + kAR - 1) / kAR), (unsigned)((K + kAC - 1) / kAC));
   k_assemble<T><<<grid, kAsmBlock, 0, s>>>(L, rs, cs, n, Y, K, x0, X, st);
 }
 

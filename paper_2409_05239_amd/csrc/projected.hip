@@ -33,6 +33,7 @@ namespace lslu {
 namespace {
 
 constexpr int kPT = 256;            // threads per projected problem
+constexpr int kBL = 8;              // lanes per column (row) of a reflector update
 constexpr int kSectRounds1 = 8;     // multisection rounds for sigma_1
 constexpr int kSectRoundsMin = 8;   // multisection rounds for sigma_min
 size_t g_static_lds = 32 * 1024;  // static LDS of k_projected, read at init
@@ -45,24 +46,6 @@ __host__ __device__ inline size_t proj_scratch_per_k(int K) {
 }
 
 __device__ inline double wave_sum_d(double v) { return group_sum<kWave>(v); }
-
-// sum_i u[i] * x[i*stride], i < len, with four independent partial sums so the
-// loads of consecutive terms overlap.
-__device__ inline double dot_unrolled(const double* u, const double* x, int len,
-                                      int stride) {
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int i = 0;
-  for (; i + 4 <= len; i += 4) {
-    const double x0 = x[(size_t)i * stride], x1 = x[(size_t)(i + 1) * stride];
-    const double x2 = x[(size_t)(i + 2) * stride], x3 = x[(size_t)(i + 3) * stride];
-    s0 = fma(u[i], x0, s0);
-    s1 = fma(u[i + 1], x1, s1);
-    s2 = fma(u[i + 2], x2, s2);
-    s3 = fma(u[i + 3], x3, s3);
-  }
-  for (; i < len; ++i) s0 = fma(u[i], x[(size_t)i * stride], s0);
-  return (s0 + s1) + (s2 + s3);
-}
 
 // Number of eigenvalues of the tridiagonal T = B^T B (diagonal a,
 // off-diagonal b) below x, from the signs of its LDL^T pivots.
@@ -238,14 +221,18 @@ __global__ __launch_bounds__(kPT) void k_projected(
     }
     __syncthreads();
     {
+      // kBL lanes per column: each sums its rows j + li, j + li + kBL, ...,
+      // the group adds the partial sums (fixed DPP order), then updates them.
       const double tau = s_tau;
       const int ncol = k - 1 - j;  // columns j+1..k-1, then g
       if (tau != 0.0) {
-        for (int t = tid; t <= ncol; t += kPT) {
+        const int li = tid % kBL;
+        for (int t = tid / kBL; t <= ncol; t += kPT / kBL) {
           double* col = (t < ncol) ? A + (size_t)(j + 1 + t) * lda : g;
-          const double w = tau * dot_unrolled(vb, col + j, k + 1 - j, 1);
-#pragma unroll 8
-          for (int r = j; r <= k; ++r) col[r] = fma(-w, vb[r - j], col[r]);
+          double d = 0.0;
+          for (int r = j + li; r <= k; r += kBL) d = fma(vb[r - j], col[r], d);
+          const double w = tau * group_sum<kBL>(d);
+          for (int r = j + li; r <= k; r += kBL) col[r] = fma(-w, vb[r - j], col[r]);
         }
       }
     }
@@ -282,13 +269,16 @@ __global__ __launch_bounds__(kPT) void k_projected(
     {
       const double tau = s_tau;
       const int nrow = k - j;  // rows j+1..k
+      const int nc = k - 1 - j;
       if (tau != 0.0) {
-        for (int t = tid; t < nrow; t += kPT) {
+        const int li = tid % kBL;
+        for (int t = tid / kBL; t < nrow; t += kPT / kBL) {
           const int r = j + 1 + t;
           double* row = A + (size_t)(j + 1) * lda + r;  // A(r, j+1), stride lda
-          const double w = tau * dot_unrolled(vb, row, k - 1 - j, lda);
-#pragma unroll 8
-          for (int c = 0; c < k - 1 - j; ++c)
+          double d = 0.0;
+          for (int c = li; c < nc; c += kBL) d = fma(vb[c], row[(size_t)c * lda], d);
+          const double w = tau * group_sum<kBL>(d);
+          for (int c = li; c < nc; c += kBL)
             row[(size_t)c * lda] = fma(-w, vb[c], row[(size_t)c * lda]);
         }
       }

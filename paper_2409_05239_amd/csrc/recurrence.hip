@@ -50,9 +50,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
-constexpr int kRowLanes = 16;                          // lanes per row
-constexpr int kRowsPerBlock = kThreads / kRowLanes;    // 16
-constexpr int kCoefPerLane = kMaxIter / kRowLanes;     // 16
+constexpr int kCoefPerLane = 16;  // coefficients per lane of the elimination
 constexpr int kPartsPerThread = kMaxParts / kThreads;  // 16
 constexpr int kStage = 8;
 constexpr int kEntryStage = 8;   // staged terms per lane of a pivot-entry row
@@ -166,6 +164,62 @@ __device__ __attribute__((always_inline)) inline void trisolve_inplace(
     }
     __syncthreads();
   }
+}
+
+// T g = g in place for 2 <= nb <= 64 S by one wavefront, the unit lower
+// triangular T packed by rows in LDS: row j lives in lane j % 64, slot
+// j / 64; step i broadcasts w_i = g_i by readlane and every later row
+// subtracts T(j,i) w_i, so each row sees the sequential order.  The entries
+// of the next 8 steps are loaded ahead (indices clamped into the triangle;
+// rows not updated by a step keep their value), so no step waits on LDS.
+template <typename T, int S>
+__device__ __attribute__((always_inline)) inline void trisolve_wave(double* g, int nb,
+                                                                    const T* __restrict__ tp) {
+#pragma clang fp contract(off)
+  const int lane = threadIdx.x & (kWave - 1);
+  if (threadIdx.x < kWave) {
+    const int64_t P = packed_row(nb);
+    double gr[S];
+    int64_t base[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int j = lane + kWave * s;
+      gr[s] = j < nb ? g[j] : 0.0;
+      base[s] = j < nb ? packed_row(j) : 0;
+    }
+#pragma unroll
+    for (int s0 = 0; s0 < S; ++s0) {
+      const int ib = kWave * s0, ie = min(nb, kWave * (s0 + 1));
+      for (int i0 = ib; i0 < ie; i0 += 8) {
+        T t[S][8];
+#pragma unroll
+        for (int s = s0; s < S; ++s)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int64_t q = base[s] + i0 + u;
+            t[s][u] = tp[q < P ? q : P - 1];
+          }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = i0 + u;
+          if (i >= ie) break;
+          const double wi = readlane_d(gr[s0], i - ib);
+#pragma unroll
+          for (int s = s0; s < S; ++s) {
+            const int j = lane + kWave * s;
+            const double nv = gr[s] - static_cast<double>(t[s][u]) * wi;
+            gr[s] = (j > i && j < nb) ? nv : gr[s];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int j = lane + kWave * s;
+      if (j < nb) g[j] = gr[s];
+    }
+  }
+  __syncthreads();
 }
 
 // ------------------------------------------------------------ block 0 -----
@@ -299,10 +353,17 @@ __device__ void lead(const HalfArgs<T>& a, DevState* st, unsigned char* lds) {
     }
     return;
   }
-  if constexpr (kTriLds)
-    trisolve_inplace<T>(g, nb, reinterpret_cast<const T*>(lds));
-  else
+  if constexpr (kTriLds) {
+    const T* lt = reinterpret_cast<const T*>(lds);
+    if (nb >= 2 && nb <= kWave)
+      trisolve_wave<T, 1>(g, nb, lt);
+    else if (nb > kWave && nb <= 2 * kWave)
+      trisolve_wave<T, 2>(g, nb, lt);
+    else
+      trisolve_inplace<T>(g, nb, lt);
+  } else {
     trisolve_inplace<T>(g, nb, a.Tp);
+  }
   for (int j = tid; j < nb; j += kThreads) {
     store_u64(reinterpret_cast<uint64_t*>(a.cslot) + j, dbits(g[j]));
     a.coef[j] = g[j];
@@ -403,26 +464,39 @@ __device__ inline bool fetch_coef(const HalfArgs<T>& a, DevState* st, double* cf
 }
 
 // --------------------------------------------------- row consumer blocks --
-// Persistent over rows r = (cb + i ncons) * 16 + group: the loads of the
-// first row's first terms before the pivot is known, then every product (the
-// first kept in a register, the others parked in out[r]), the elimination
-// inputs of the first row, one wait for the coefficients, then the
-// elimination.  A waiting block therefore never holds resources that
-// undispatched work needs.
-template <typename T, class RowOp>
+// G lanes per row, 256 / G rows per block.  Persistent over rows
+// r = (cb + i ncons) * (256 / G) + group: the loads of the first row's first
+// terms before the pivot is known, then every product (the first kept in a
+// register, the others parked in out[r]), the elimination inputs of the first
+// row, one wait for the coefficients, then the elimination.  A waiting block
+// therefore never holds resources that undispatched work needs.
+template <int G, typename T>
+__device__ inline void load_basis_row(const HalfArgs<T>& a, int64_t r, int sub,
+                                      T (&bv)[kCoefPerLane]) {
+  const T* brow = a.basis + r * a.rs;
+#pragma unroll
+  for (int u = 0; u < kCoefPerLane; ++u) {
+    const int j = sub + u * G;
+    bv[u] = (j < a.nb) ? brow[(int64_t)j * a.cs] : T(0);
+  }
+}
+
+template <int G, typename T, class RowOp>
 __device__ void consume_rows(const HalfArgs<T>& a, const RowOp& op, DevState* st,
                              int cb, int ncons) {
   using Acc = typename RowOp::Acc;
+  constexpr int kRows = kThreads / G;  // rows per block and pass
+  static_assert(G * kCoefPerLane >= kMaxIter, "one pass over the coefficients");
   __shared__ double cf[kMaxIter];
-  __shared__ double sk[kRowsPerBlock];
-  __shared__ int si[kRowsPerBlock];
-  const int tid = threadIdx.x, sub = tid % kRowLanes, rl = tid / kRowLanes;
+  __shared__ double sk[kRows];
+  __shared__ int si[kRows];
+  const int tid = threadIdx.x, sub = tid % G, rl = tid / G;
   const int nb = a.nb;
-  const int64_t stride = (int64_t)ncons * kRowsPerBlock;
-  const int64_t r0 = (int64_t)cb * kRowsPerBlock + rl;
+  const int64_t stride = (int64_t)ncons * kRows;
+  const int64_t r0 = (int64_t)cb * kRows + rl;
   const bool has0 = r0 < a.rows;
   RowStage<typename RowOp::Val, T, kRowStage> sg;
-  if (has0) op.template stage<kRowLanes, kRowStage>(r0, sub, a.up, sg);
+  if (has0) op.template stage<G, kRowStage>(r0, sub, a.up, sg);
   int pick;
   double val;
   if (!wait_pivot(a, st, pick, val)) return;
@@ -430,12 +504,12 @@ __device__ void consume_rows(const HalfArgs<T>& a, const RowOp& op, DevState* st
   auto xf = [&](int64_t c) -> T { return nz(a.up[c]); };
   T q_first = T(0);
   if (has0) {
-    Acc acc = op.template finish<kRowLanes, kRowStage>(sg, nz, xf);
-    q_first = static_cast<T>(group_sum<kRowLanes>(acc));
+    Acc acc = op.template finish<G, kRowStage>(sg, nz, xf);
+    q_first = static_cast<T>(group_sum<G>(acc));
   }
   for (int64_t r = r0 + stride; r < a.rows; r += stride) {
-    Acc acc = op.template partial<kRowLanes>(r, sub, xf);
-    acc = group_sum<kRowLanes>(acc);
+    Acc acc = op.template partial<G>(r, sub, xf);
+    acc = group_sum<G>(acc);
     if (sub == 0) a.out[r] = static_cast<T>(acc);
   }
   normalise_share(a, cb, ncons, pick, nz);
@@ -445,12 +519,7 @@ __device__ void consume_rows(const HalfArgs<T>& a, const RowOp& op, DevState* st
   bool piv0 = true;
   if (has0) {
     piv0 = a.mask[r0] != 0;
-    const T* brow = a.basis + r0 * a.rs;
-#pragma unroll
-    for (int u = 0; u < kCoefPerLane; ++u) {
-      const int j = sub + u * kRowLanes;
-      bv0[u] = (j < nb) ? brow[(int64_t)j * a.cs] : T(0);
-    }
+    load_basis_row<G>(a, r0, sub, bv0);
   }
   if (!fetch_coef(a, st, cf)) return;
   double key = 0.0;
@@ -463,20 +532,15 @@ __device__ void consume_rows(const HalfArgs<T>& a, const RowOp& op, DevState* st
 #pragma unroll
       for (int u = 0; u < kCoefPerLane; ++u) bv[u] = bv0[u];
     } else {
-      const T* brow = a.basis + r * a.rs;
-#pragma unroll
-      for (int u = 0; u < kCoefPerLane; ++u) {
-        const int j = sub + u * kRowLanes;
-        bv[u] = (j < nb) ? brow[(int64_t)j * a.cs] : T(0);
-      }
+      load_basis_row<G>(a, r, sub, bv);
     }
     double e = 0.0;
 #pragma unroll
     for (int u = 0; u < kCoefPerLane; ++u) {
-      const int j = sub + u * kRowLanes;
+      const int j = sub + u * G;
       if (j < nb) e = fma(cf[j], static_cast<double>(bv[u]), e);
     }
-    e = group_sum<kRowLanes>(e);
+    e = group_sum<G>(e);
     if (sub == 0) {
       const double q0 = static_cast<double>(first ? q_first : a.out[r]);
       const T o = piv ? T(0) : static_cast<T>(q0 - e);
@@ -494,7 +558,7 @@ __device__ void consume_rows(const HalfArgs<T>& a, const RowOp& op, DevState* st
   }
   __syncthreads();
   if (tid == 0) {
-    for (int i = 1; i < kRowsPerBlock; ++i)
+    for (int i = 1; i < kRows; ++i)
       if (better(sk[i], si[i], key, idx)) {
         key = sk[i];
         idx = si[i];
@@ -503,7 +567,7 @@ __device__ void consume_rows(const HalfArgs<T>& a, const RowOp& op, DevState* st
   }
 }
 
-template <typename T, class RowOp, bool kTriLds>
+template <typename T, class RowOp, bool kTriLds, int G>
 __global__ __launch_bounds__(kThreads) void k_half_rows(HalfArgs<T> a, RowOp op) {
   extern __shared__ unsigned char lds[];
   DevState* st = a.job.st;
@@ -513,7 +577,7 @@ __global__ __launch_bounds__(kThreads) void k_half_rows(HalfArgs<T> a, RowOp op)
   else if ((int)blockIdx.x < a.nlead)
     pivot_entries<T, RowOp>(a, op, st);
   else
-    consume_rows<T, RowOp>(a, op, st, blockIdx.x - a.nlead, gridDim.x - a.nlead);
+    consume_rows<G, T, RowOp>(a, op, st, blockIdx.x - a.nlead, gridDim.x - a.nlead);
 }
 
 // --------------------------------------------------- PSF consumer blocks --
@@ -691,24 +755,28 @@ int consumer_blocks(int64_t want, int nlead, int resident) {
   return static_cast<int>(c);
 }
 
+template <typename T, class RowOp, int G>
+int launch_rows_g(HalfArgs<T>& a, const RowOp& op, size_t tb, bool in_lds, hipStream_t s) {
+  constexpr int kRows = kThreads / G;
+  const int64_t want = a.rows > 0 ? (a.rows + kRows - 1) / kRows
+                                  : (a.lenp + kThreads * kNormBatch - 1) / (kThreads * kNormBatch);
+  auto k = in_lds ? k_half_rows<T, RowOp, true, G> : k_half_rows<T, RowOp, false, G>;
+  const size_t dyn = in_lds ? tb : 0;
+  const int ncons = consumer_blocks(want, a.nlead, resident_blocks((const void*)k, dyn));
+  k<<<a.nlead + ncons, kThreads, dyn, s>>>(a, op);
+  return ncons;
+}
+
+// 16 lanes per row.  (8 lanes per row, which makes the d side of the
+// tomography one pass over the rows, measured slower: the longer per-lane
+// chains of dependent loads cost more than the second pass.)
 template <typename T, class RowOp>
 int launch_rows(HalfArgs<T>& a, const RowOp& op, size_t lds_bytes, hipStream_t s) {
-  const int64_t want = a.rows > 0 ? (a.rows + kRowsPerBlock - 1) / kRowsPerBlock
-                                  : (a.lenp + kThreads * kNormBatch - 1) / (kThreads * kNormBatch);
   const int nbk = a.rows > 0 ? a.nb : 0;
   a.nlead = 1 + (nbk + kWaves - 1) / kWaves;
   const size_t tb = tri_bytes<T>(nbk);
   const bool in_lds = tb > 0 && tb <= kTriLdsMax && tb + 16 * 1024 <= lds_bytes;
-  if (in_lds) {
-    auto k = k_half_rows<T, RowOp, true>;
-    const int ncons = consumer_blocks(want, a.nlead, resident_blocks((const void*)k, tb));
-    k<<<a.nlead + ncons, kThreads, tb, s>>>(a, op);
-    return ncons;
-  }
-  auto k = k_half_rows<T, RowOp, false>;
-  const int ncons = consumer_blocks(want, a.nlead, resident_blocks((const void*)k, 0));
-  k<<<a.nlead + ncons, kThreads, 0, s>>>(a, op);
-  return ncons;
+  return launch_rows_g<T, RowOp, 16>(a, op, tb, in_lds, s);
 }
 
 template <typename T, typename Acc, int PH, bool kBf16>
