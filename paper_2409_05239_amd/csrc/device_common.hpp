@@ -178,7 +178,9 @@ template <typename V, typename T, int NP>
 struct RowStage {
   V v[NP];
   T x[NP];
-  int64_t row, next, end;
+  int64_t row;   // the row (dense, PSF) or its first entry position (CSR)
+  int64_t next;  // where the terms after the staged ones start
+  int64_t end;
 };
 
 // Each policy sums its row over the lanes sub, sub+G, ... of a group of G
@@ -231,88 +233,151 @@ struct DenseRows {
   }
 };
 
-// Row r of a CSR matrix (int32 row pointers and column indices).  Each lane
-// issues the index and value loads of kBatch entries, then their kBatch
-// gathers, so a row costs few dependent round trips.
+// Four consecutive operator values from a position that is a multiple of 4
+// (16-byte loads for float, two for double, one 8-byte load for bfloat16).
+template <typename V>
+struct Quad;
+template <>
+struct Quad<float> {
+  __device__ static void load(const float* p, float (&v)[4]) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  }
+};
+template <>
+struct Quad<double> {
+  __device__ static void load(const double* p, double (&v)[4]) {
+    const double2 a = reinterpret_cast<const double2*>(p)[0];
+    const double2 b = reinterpret_cast<const double2*>(p)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+  }
+};
+template <>
+struct Quad<uint16_t> {
+  __device__ static void load(const uint16_t* p, uint16_t (&v)[4]) {
+    const uint2 q = *reinterpret_cast<const uint2*>(p);
+    v[0] = static_cast<uint16_t>(q.x & 0xffffu); v[1] = static_cast<uint16_t>(q.x >> 16);
+    v[2] = static_cast<uint16_t>(q.y & 0xffffu); v[3] = static_cast<uint16_t>(q.y >> 16);
+  }
+};
+
+// Row r of a CSR matrix (int32 row pointers and column indices; index and
+// value arrays 16-byte aligned and readable 3 entries past nnz).  The row is
+// read in aligned chunks of 4 entries: lane `sub` of a group of G takes the
+// chunks that start at (beg & ~3) + 4 sub + 4 G i, with one vector load for
+// the indices and one for the values per chunk, then the gathers of its
+// entries inside [beg, end), kChunks chunks per batch so a row costs few
+// dependent round trips.  Each lane adds its entries in chunk order.
 template <typename V, typename AccT, bool kBf16>
 struct CsrRows {
   using Acc = AccT;
   using Val = V;
-  static constexpr int kBatch = 8;
+  static constexpr int kChunks = 2;
   const int* rp;
   const int* ci;
   const V* val;
-  // Entries p, p+G, ... below end, added to acc in that order.
+  // Chunks q, q + 4G, ... below end (entries outside [beg, end) skipped).
   template <int G, typename XF>
-  __device__ Acc rest(int p, int end, XF xf, Acc acc) const {
+  __device__ Acc rest(int q, int beg, int end, XF xf, Acc acc) const {
     using X = decltype(xf(0));
-    for (; p + (kBatch - 1) * G < end; p += kBatch * G) {
-      int c[kBatch];
-      V v[kBatch];
+    for (; q < end; q += kChunks * 4 * G) {
+      int c[kChunks][4];
+      V v[kChunks][4];
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        c[u] = ci[p + u * G];
-        v[u] = val[p + u * G];
+      for (int h = 0; h < kChunks; ++h) {
+        const int qh = q + h * 4 * G;
+        if (qh < end) {
+          const int4 c4 = *reinterpret_cast<const int4*>(ci + qh);
+          c[h][0] = c4.x; c[h][1] = c4.y; c[h][2] = c4.z; c[h][3] = c4.w;
+          Quad<V>::load(val + qh, v[h]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            c[h][e] = 0;
+            v[h][e] = V(0);
+          }
+        }
       }
-      X xv[kBatch];
+      X x[kChunks][4];
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u) xv[u] = xf(c[u]);
+      for (int h = 0; h < kChunks; ++h)
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u)
-        acc = fma(static_cast<Acc>(ValTraits<V>::get(v[u])),
-                  static_cast<Acc>(in_val<kBf16>(xv[u])), acc);
+        for (int e = 0; e < 4; ++e) {
+          const int pos = q + h * 4 * G + e;
+          x[h][e] = (pos >= beg && pos < end) ? xf(c[h][e]) : X(0);
+        }
+#pragma unroll
+      for (int h = 0; h < kChunks; ++h)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int pos = q + h * 4 * G + e;
+          if (pos >= beg && pos < end)
+            acc = fma(static_cast<Acc>(ValTraits<V>::get(v[h][e])),
+                      static_cast<Acc>(in_val<kBf16>(x[h][e])), acc);
+        }
     }
-    int c[kBatch];
-    V v[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int q = p + u * G;
-      c[u] = q < end ? ci[q] : 0;
-      v[u] = q < end ? val[q] : V(0);
-    }
-    X xv[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) xv[u] = (p + u * G < end) ? xf(c[u]) : X(0);
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u)
-      if (p + u * G < end)
-        acc = fma(static_cast<Acc>(ValTraits<V>::get(v[u])),
-                  static_cast<Acc>(in_val<kBf16>(xv[u])), acc);
     return acc;
   }
   template <int G, typename XF>
   __device__ Acc partial(int64_t r, int sub, XF xf) const {
-    return rest<G>(rp[r] + sub, rp[r + 1], xf, Acc(0));
+    const int beg = rp[r], end = rp[r + 1];
+    return rest<G>((beg & ~3) + 4 * sub, beg, end, xf, Acc(0));
   }
-  // The first NP entries of the lane (positions beg+sub, beg+sub+G, ...):
-  // values and the raw input entries they multiply.
+  // The lane's first NP entries (NP / 4 chunks): values and the raw input
+  // entries they multiply.
   template <int G, int NP, typename T>
   __device__ void stage(int64_t r, int sub, const T* __restrict__ u,
                         RowStage<V, T, NP>& s) const {
-    const int end = rp[r + 1];
-    const int p = rp[r] + sub;
+    static_assert(NP % 4 == 0, "whole chunks");
+    constexpr int NC = NP / 4;
+    const int beg = rp[r], end = rp[r + 1];
+    const int q = (beg & ~3) + 4 * sub;
     int c[NP];
 #pragma unroll
-    for (int k = 0; k < NP; ++k) {
-      const int q = p + k * G;
-      c[k] = q < end ? ci[q] : 0;
-      s.v[k] = q < end ? val[q] : V(0);
+    for (int h = 0; h < NC; ++h) {
+      const int qh = q + h * 4 * G;
+      V vv[4];
+      if (qh < end) {
+        const int4 c4 = *reinterpret_cast<const int4*>(ci + qh);
+        c[4 * h] = c4.x; c[4 * h + 1] = c4.y; c[4 * h + 2] = c4.z; c[4 * h + 3] = c4.w;
+        Quad<V>::load(val + qh, vv);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          c[4 * h + e] = 0;
+          vv[e] = V(0);
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) s.v[4 * h + e] = vv[e];
     }
 #pragma unroll
-    for (int k = 0; k < NP; ++k) s.x[k] = (p + k * G < end) ? u[c[k]] : T(0);
-    s.row = r;
-    s.next = p + NP * G;
+    for (int h = 0; h < NC; ++h)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int pos = q + h * 4 * G + e;
+        s.x[4 * h + e] = (pos >= beg && pos < end) ? u[c[4 * h + e]] : T(0);
+      }
+    s.row = beg;
+    s.next = q;
     s.end = end;
   }
   template <int G, int NP, typename T, typename NZ, typename XF>
   __device__ Acc finish(const RowStage<V, T, NP>& s, const NZ& nz, XF xf) const {
+    constexpr int NC = NP / 4;
+    const int beg = static_cast<int>(s.row), end = static_cast<int>(s.end);
+    const int q = static_cast<int>(s.next);
     Acc acc = 0;
 #pragma unroll
-    for (int k = 0; k < NP; ++k)
-      if (s.next - (NP - k) * G < s.end)
-        acc = fma(static_cast<Acc>(ValTraits<V>::get(s.v[k])),
-                  static_cast<Acc>(in_val<kBf16>(nz(s.x[k]))), acc);
-    return rest<G>(static_cast<int>(s.next), static_cast<int>(s.end), xf, acc);
+    for (int h = 0; h < NC; ++h)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int pos = q + h * 4 * G + e;
+        if (pos >= beg && pos < end)
+          acc = fma(static_cast<Acc>(ValTraits<V>::get(s.v[4 * h + e])),
+                    static_cast<Acc>(in_val<kBf16>(nz(s.x[4 * h + e]))), acc);
+      }
+    return rest<G>(q + NC * 4 * G, beg, end, xf, acc);
   }
 };
 

@@ -39,6 +39,9 @@ struct DevState {
   int spin_timeouts;  // waits that hit their bound (an error; never expected)
 };
 
+// Zero entries past nnz in the device CSR index and value arrays.
+constexpr int64_t kCsrPad = 4;
+
 // One candidate of the pivot search: the signed value v at row idx (key; 0
 // for a row that may not be a pivot).  Candidates are ordered by |key|, then
 // by the smaller row, so the winner's key is the pivot value itself.

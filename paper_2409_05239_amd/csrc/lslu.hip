@@ -652,13 +652,21 @@ lslu_status lslu_op_csr(lslu_ctx* c, int64_t m, int64_t n, int64_t nnz,
     op->d.m = m;
     op->d.n = n;
     op->d.nnz = nnz;
-    auto va = convert_values(data, nnz, prec);
-    auto vt = convert_values(valT.data(), nnz, prec);
+    // Index and value arrays carry kCsrPad zero entries past nnz: the
+    // products read rows in aligned chunks of 4 entries.
+    std::vector<int> cpad(indices, indices + nnz);
+    cpad.resize(nnz + kCsrPad, 0);
+    ciT.resize(nnz + kCsrPad, 0);
+    std::vector<double> dpad(data, data + nnz);
+    dpad.resize(nnz + kCsrPad, 0.0);
+    valT.resize(nnz + kCsrPad, 0.0);
+    auto va = convert_values(dpad.data(), nnz + kCsrPad, prec);
+    auto vt = convert_values(valT.data(), nnz + kCsrPad, prec);
     lslu_status st = upload(c, reinterpret_cast<void**>(&op->d.rp), rp.data(), sizeof(int) * (m + 1));
-    if (st == LSLU_OK) st = upload(c, reinterpret_cast<void**>(&op->d.ci), indices, sizeof(int) * nnz);
+    if (st == LSLU_OK) st = upload(c, reinterpret_cast<void**>(&op->d.ci), cpad.data(), sizeof(int) * cpad.size());
     if (st == LSLU_OK) st = upload(c, &op->d.val, va.data(), va.size());
     if (st == LSLU_OK) st = upload(c, reinterpret_cast<void**>(&op->d.rpT), rpT.data(), sizeof(int) * (n + 1));
-    if (st == LSLU_OK) st = upload(c, reinterpret_cast<void**>(&op->d.ciT), ciT.data(), sizeof(int) * nnz);
+    if (st == LSLU_OK) st = upload(c, reinterpret_cast<void**>(&op->d.ciT), ciT.data(), sizeof(int) * ciT.size());
     if (st == LSLU_OK) st = upload(c, &op->d.valT, vt.data(), vt.size());
     if (st != LSLU_OK) {
       free_op(op->d);
