@@ -56,6 +56,7 @@ constexpr int kStage = 8;
 constexpr int kEntryStage = 8;   // staged terms per lane of a pivot-entry row
 constexpr int kRowStage = 8;     // staged terms per lane of a consumer's first row
 constexpr int kNormBatch = 8;
+constexpr int kNormStage = 2;  // entries of the normalisation share loaded before the pivot
 constexpr int kSpinLimit = 1 << 20;
 constexpr int kTriB = 32;  // rows of a diagonal block of the triangular solve
 constexpr uint64_t kSentinel = kSlotEmpty;
@@ -391,22 +392,47 @@ __device__ void pivot_entries(const HalfArgs<T>& a, const RowOp& op, DevState* s
               dbits(static_cast<double>(static_cast<T>(acc))));
 }
 
-// Normalise this block's share of the previous vector into its basis column.
+// Normalise this block's share of the previous vector into its basis column:
+// entries i = cb * 256 + tid + u * ncons * 256.  The first kNormStage of a
+// thread's entries are loaded before the pivot is known (stage), the rest
+// after it.
+template <typename T>
+struct NormStage {
+  T v[kNormStage];
+};
+
+template <typename T>
+__device__ inline void normalise_stage(const HalfArgs<T>& a, int cb, int ncons, NormStage<T>& s) {
+  const int64_t step = (int64_t)ncons * kThreads;
+  const int64_t i0 = (int64_t)cb * kThreads + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kNormStage; ++u) {
+    const int64_t i = i0 + u * step;
+    s.v[u] = (i < a.lenp) ? a.up[i] : T(0);
+  }
+}
+
 template <typename T>
 __device__ inline void normalise_share(const HalfArgs<T>& a, int cb, int ncons,
-                                       int pick, const Normaliser<T>& nz) {
+                                       int pick, const Normaliser<T>& nz,
+                                       const NormStage<T>& s) {
   const int64_t step = (int64_t)ncons * kThreads;
-  for (int64_t i0 = (int64_t)cb * kThreads + threadIdx.x; i0 < a.lenp;
-       i0 += step * kNormBatch) {
-    T vv[kNormBatch];
+  const int64_t i0 = (int64_t)cb * kThreads + threadIdx.x;
 #pragma unroll
-    for (int u = 0; u < kNormBatch; ++u) {
-      const int64_t i = i0 + u * step;
+  for (int u = 0; u < kNormStage; ++u) {
+    const int64_t i = i0 + u * step;
+    if (i < a.lenp) a.dstp[i * a.dstp_stride] = (i == pick) ? T(1) : nz(s.v[u]);
+  }
+  for (int64_t j0 = i0 + kNormStage * step; j0 < a.lenp; j0 += step * kNormStage) {
+    T vv[kNormStage];
+#pragma unroll
+    for (int u = 0; u < kNormStage; ++u) {
+      const int64_t i = j0 + u * step;
       vv[u] = (i < a.lenp) ? a.up[i] : T(0);
     }
 #pragma unroll
-    for (int u = 0; u < kNormBatch; ++u) {
-      const int64_t i = i0 + u * step;
+    for (int u = 0; u < kNormStage; ++u) {
+      const int64_t i = j0 + u * step;
       if (i < a.lenp) a.dstp[i * a.dstp_stride] = (i == pick) ? T(1) : nz(vv[u]);
     }
   }
@@ -497,10 +523,13 @@ __device__ void consume_rows(const HalfArgs<T>& a, const RowOp& op, DevState* st
   const bool has0 = r0 < a.rows;
   RowStage<typename RowOp::Val, T, kRowStage> sg;
   if (has0) op.template stage<G, kRowStage>(r0, sub, a.up, sg);
+  NormStage<T> ns;
+  normalise_stage(a, cb, ncons, ns);
   int pick;
   double val;
   if (!wait_pivot(a, st, pick, val)) return;
   const Normaliser<T> nz(static_cast<T>(val));
+  normalise_share(a, cb, ncons, pick, nz, ns);
   auto xf = [&](int64_t c) -> T { return nz(a.up[c]); };
   T q_first = T(0);
   if (has0) {
@@ -512,7 +541,6 @@ __device__ void consume_rows(const HalfArgs<T>& a, const RowOp& op, DevState* st
     acc = group_sum<G>(acc);
     if (sub == 0) a.out[r] = static_cast<T>(acc);
   }
-  normalise_share(a, cb, ncons, pick, nz);
   if (a.rows == 0) return;
   // Elimination inputs of the first row, loaded before the coefficients.
   T bv0[kCoefPerLane];
@@ -567,8 +595,14 @@ __device__ void consume_rows(const HalfArgs<T>& a, const RowOp& op, DevState* st
   }
 }
 
+// Occupancy floor: 5 wavefronts per SIMD for FP32 vectors (1280 resident
+// blocks, so the 1024 row groups of a 16384-row side run in one pass), 4 for
+// FP64.
+template <typename T>
+constexpr int half_min_waves() { return sizeof(T) == 4 ? 5 : 4; }
+
 template <typename T, class RowOp, bool kTriLds, int G>
-__global__ __launch_bounds__(kThreads) void k_half_rows(HalfArgs<T> a, RowOp op) {
+__global__ __launch_bounds__(kThreads, half_min_waves<T>()) void k_half_rows(HalfArgs<T> a, RowOp op) {
   extern __shared__ unsigned char lds[];
   DevState* st = a.job.st;
   if (st->stopped) return;
@@ -629,10 +663,13 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
   const int tiles_x = (cols + kPsfTW - 1) / kPsfTW;
   const int ntiles = a.rows > 0 ? tiles_x * ((rows + kPsfTH - 1) / kPsfTH) : 0;
   const int nb = a.nb;
+  NormStage<T> ns;
+  normalise_stage(a, cb, ncons, ns);
   int pick;
   double val;
   if (!wait_pivot(a, st, pick, val)) return;
   const Normaliser<T> nz(static_cast<T>(val));
+  normalise_share(a, cb, ncons, pick, nz, ns);
   for (int t = cb; t < ntiles; t += ncons) {
     const int i0 = (t / tiles_x) * kPsfTH, j0 = (t % tiles_x) * kPsfTW;
     Acc acc[kPsfR];
@@ -644,7 +681,6 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
       if (gi < rows && gj < cols) a.out[(int64_t)gi * cols + gj] = static_cast<T>(acc[p]);
     }
   }
-  normalise_share(a, cb, ncons, pick, nz);
   if (a.rows == 0) return;
   if (!fetch_coef(a, st, cf)) return;
   double best = 0.0;
