@@ -30,6 +30,14 @@ Readings where the paper is silent, ambiguous or inconsistent:
 * R7 (beta): the signed entry ``r_0(i)``.
 * R8 (regularisation term): the penalty is on ``y``, i.e. on
   ``L_k^+ (x - x_0)``; this matches eq. TP when ``x_0 = 0``.
+* R19 (sampled pivots, the variant proposed in Section 2.2 and shown in
+  Fig. 1): the paper does not say how the sample is drawn.  Each search gets
+  a list of distinct random rows of its vector (an input, from
+  ``workloads.pivot_sample_lists``); the sample is the first s rows of that
+  list that are not earlier pivots (so s non-pivot rows, without
+  replacement), the pivot is the sampled row of largest magnitude (ties:
+  smallest row), and a sample whose largest magnitude is 0 falls back to the
+  full search, so breakdown is still decided exactly (R3).
 * R13 (stopping): ``k_stop`` is the first ``k`` with
   ``|Ghat(k+1) - Ghat(k)| / Ghat(1) < tol``; it is reported and only ends the
   loop when ``early_stop`` is set (then the result is ``x_{k_stop}``).
@@ -100,11 +108,37 @@ def pivot_search(v: np.ndarray, perm: np.ndarray, start: int):
     return pos, float(amax), sep
 
 
+def pivot_search_sampled(v: np.ndarray, perm: np.ndarray, start: int,
+                         cand_rows: np.ndarray, s: int):
+    """The sampled pivot of Section 2.2 (reading R19): among the first s rows
+    of ``cand_rows`` that are not earlier pivots (``perm[:start]``), the row
+    of largest |v| (ties: smallest row).  Falls back to ``pivot_search`` when
+    that largest magnitude is 0.  Same return values as ``pivot_search``."""
+    used = np.zeros(v.shape[0], dtype=bool)
+    used[perm[:start]] = True
+    sel = [int(r) for r in cand_rows if r >= 0 and not used[r]][:s]
+    a = np.abs(v[sel]) if sel else np.zeros(0)
+    if a.shape[0] == 0 or a.max() == 0.0:
+        return pivot_search(v, perm, start)
+    amax = a.max()
+    row = min(r for r, ar in zip(sel, a) if ar == amax)
+    pos = int(np.nonzero(perm == row)[0][0])
+    if a.shape[0] == 1:
+        sep = 1.0
+    else:
+        a2 = np.partition(a, a.shape[0] - 2)[a.shape[0] - 2]
+        sep = float((amax - a2) / amax)
+    return pos, float(amax), sep
+
+
 def hybrid_lslu(op, b, maxiter: int, reg: Optional[RegParam] = None,
                 x0: Optional[np.ndarray] = None, stop_tol: float = 1e-6,
-                early_stop: bool = False) -> Result:
+                early_stop: bool = False, pivot_sample=None) -> Result:
     """Hybrid LSLU (Algorithm 5); ``reg=None`` or ``RegParam('none')`` gives
-    LSLU (lambda = 0)."""
+    LSLU (lambda = 0).  ``pivot_sample = (lists, s)`` selects the sampled
+    pivots of Section 2.2 (reading R19): ``lists[i]`` holds the candidate
+    rows of search i (0: r_0; 2k-1: q of iteration k; 2k: u of iteration
+    k)."""
     reg = reg if reg is not None else RegParam("none")
     m, n = op.shape
     K = int(maxiter)
@@ -137,9 +171,15 @@ def hybrid_lslu(op, b, maxiter: int, reg: Optional[RegParam] = None,
             ghat=np.array(ghat), sep_t=sep_t, sep_g=sep_g,
             sep_lambda=np.array(sep_lam), k_stop=k_stop)
 
+    def search(v, perm, start, i):
+        if pivot_sample is None:
+            return pivot_search(v, perm, start)
+        lists, s = pivot_sample
+        return pivot_search_sampled(v, perm, start, lists[i], s)
+
     # r_0 = b - A x_0; the pivot of r_0; beta; d_1.
     r0 = b - op.matvec(x0v) if x0 is not None else b.copy()
-    pos, amax, sep = pivot_search(r0, t, 0)
+    pos, amax, sep = search(r0, t, 0, 0)
     beta = 0.0
     if amax == 0.0:
         return finish(Status.ZERO_RHS, x0v.copy(), 0)
@@ -159,7 +199,7 @@ def hybrid_lslu(op, b, maxiter: int, reg: Optional[RegParam] = None,
             q = q - W[j - 1, k - 1] * Lb[j - 1]
         # Pivot for l_k (guard k <= n, reading R1; exact zero test, R3).
         if k <= n:
-            pos, amax, sep = pivot_search(q, g, k - 1)
+            pos, amax, sep = search(q, g, k - 1, 2 * k - 1)
         else:
             amax = 0.0
         if amax == 0.0:
@@ -177,7 +217,7 @@ def hybrid_lslu(op, b, maxiter: int, reg: Optional[RegParam] = None,
             u = u - H[j - 1, k - 1] * Db[j - 1]
         last = False
         if k < m:
-            pos, amax, sep = pivot_search(u, t, k)
+            pos, amax, sep = search(u, t, k, 2 * k)
         else:
             amax = 0.0
         if amax == 0.0:

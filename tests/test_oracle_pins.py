@@ -504,3 +504,71 @@ def test_pivot_search_separation_and_stop_rule():
     re = hybrid_lslu(op, prob.b, 20, reg, stop_tol=1e-2, early_stop=True)
     assert re.k_stop == r.k_stop
     assert np.array_equal(re.x, r.X[:, r.k_stop - 1])
+
+
+# ---------------------------------------------------------------------------
+# Sampled pivots (the variant of Section 2.2 / Fig. 1, reading R19)
+# ---------------------------------------------------------------------------
+
+def _sampled_winner(vec, rows, earlier, s):
+    """Brute force: the largest |vec| among the first s listed rows that are
+    not earlier pivots, ties to the smallest row; None if that is 0."""
+    sample = [int(r) for r in rows if r >= 0 and int(r) not in earlier][:s]
+    if not sample or max(abs(vec[r]) for r in sample) == 0.0:
+        return None
+    return max(sample, key=lambda r: (abs(vec[r]), -r))
+
+
+@pytest.mark.parametrize("seed,s", [(1, 3), (2, 5), (3, 12)])
+def test_sampled_pivot_rule_by_brute_force(seed, s):
+    from workloads import pivot_sample_lists
+    prob = random_dense(40, 28, seed=seed, nu=0.05)
+    op = make_operator(prob)
+    K = 10
+    lists = pivot_sample_lists(prob.m, prob.n, K, s, seed=seed)
+    r = hybrid_lslu(op, prob.b, K, pivot_sample=(lists, s))
+    # every search's winner, re-derived from the result's own vectors: q_k is
+    # a multiple of l_k, u_k of d_{k+1}, r_0 of d_1 (pivot entries exactly 1)
+    assert r.piv_t[0] == _sampled_winner(r.D[:, 0], lists[0], set(), s)
+    for k in range(1, r.k_done + 1):
+        wg = _sampled_winner(r.L[:, k - 1], lists[2 * k - 1], set(r.piv_g[:k - 1]), s)
+        assert wg is not None and r.piv_g[k - 1] == wg
+        if k < len(r.piv_t):
+            wt = _sampled_winner(r.D[:, k], lists[2 * k], set(r.piv_t[:k]), s)
+            assert wt is not None and r.piv_t[k] == wt
+    # any pivot choice keeps the Hessenberg relations of Section 2.2
+    k = r.k_done
+    A = prob.A
+    assert np.allclose(A @ r.L[:, :k], r.D[:, :k + 1] @ r.H[:k + 1, :k], atol=1e-10)
+    assert np.allclose(A.T @ r.D[:, :k], r.L[:, :k] @ r.W[:k, :k], atol=1e-10)
+
+
+def test_sampled_pivots_with_every_row_listed_equal_full_pivoting():
+    prob = random_dense(36, 25, seed=4, nu=0.05)
+    op = make_operator(prob)
+    K = 12
+    rng = np.random.default_rng(7)
+    L = K + max(prob.m, prob.n)
+    lists = np.full((2 * K + 1, L), -1, dtype=np.int32)
+    for i in range(2 * K + 1):
+        length = prob.m if i % 2 == 0 else prob.n
+        lists[i, :length] = rng.permutation(length)
+    reg = RegParam("wgcv", grid=lambda_grid(), grid_relative=True)
+    full = hybrid_lslu(op, prob.b, K, reg)
+    samp = hybrid_lslu(op, prob.b, K, reg, pivot_sample=(lists, L))
+    assert samp.piv_t == full.piv_t and samp.piv_g == full.piv_g
+    assert np.array_equal(samp.X, full.X)
+
+
+def test_sampled_pivot_falls_back_to_full_search_on_a_zero_sample():
+    prob = random_dense(30, 20, seed=5, nu=0.05)
+    op = make_operator(prob)
+    K, s = 4, 3
+    lists = np.full((2 * K + 1, s + K), -1, dtype=np.int32)
+    for i in range(2 * K + 1):
+        lists[i, :s + K] = np.arange(s + K)
+    b = prob.b.copy()
+    b[:s + K] = 0.0  # every listed row of r_0 is zero
+    r = hybrid_lslu(op, b, K, pivot_sample=(lists, s))
+    full_t1 = int(np.argmax(np.abs(b)))
+    assert r.piv_t[0] == full_t1 and abs(r.beta) == np.abs(b).max()

@@ -20,4 +20,5 @@ from .problems import (  # noqa: F401
     config_problem,
     CONFIGS,
     lambda_grid,
+    pivot_sample_lists,
 )

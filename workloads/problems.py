@@ -327,3 +327,25 @@ def lambda_grid(n_grid: int = 20, lo: float = 1e-4, hi: float = 1.0):
 
 def config_problem(name: str) -> Problem:
     return CONFIGS[name]["make"]()
+
+
+def pivot_sample_lists(m: int, n: int, K: int, s: int, seed: int = 0) -> np.ndarray:
+    """Random candidate rows for the sampled pivot searches of a solve with at
+    most K iterations (the variant of Section 2.2 that takes the largest entry
+    of a small random sample instead of the infinity norm).
+
+    Search i = 0, 1, ..., 2K resolves, in order: the pivot of r_0 (length m),
+    then for k = 1..K the pivot of q (length n) and of u (length m).  Row i of
+    the result is a uniformly random sequence of distinct rows of that vector
+    (a prefix of a random permutation, drawn from ``default_rng([seed, i])``),
+    s + K long, padded with -1 when the vector is shorter.  Taking the first s
+    entries that are not earlier pivots gives a sample of s non-pivot rows
+    drawn without replacement."""
+    L = s + K
+    out = np.full((2 * K + 1, L), -1, dtype=np.int32)
+    for i in range(2 * K + 1):
+        length = m if i % 2 == 0 else n
+        rng = np.random.default_rng([seed, i])
+        take = min(length, L)
+        out[i, :take] = rng.choice(length, size=take, replace=False)
+    return out
