@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LSLU_ABI_VERSION 3
+#define LSLU_ABI_VERSION 4
 
 typedef enum lslu_status {
   LSLU_OK = 0,
@@ -172,6 +172,17 @@ typedef struct lslu_opts {
   const int32_t* replay_piv_g;
   const int32_t* replay_lambda_idx;
   int32_t flags;              /* bitwise OR of lslu_flag values; 0 = default */
+  /* Sampled pivots (the variant of Section 2.2 that takes the largest entry
+   * of a small random sample instead of the infinity norm).  NULL = full
+   * searches.  Host array of (2*maxiter + 1) rows of sample_len int32:
+   * row 0 lists candidate rows of r_0 (< m), row 2k-1 of q at iteration k
+   * (< n), row 2k of u at iteration k (< m); -1 entries are skipped.  A
+   * search takes the first sample_s listed rows that are not earlier pivots
+   * and picks the one of largest magnitude (ties: smallest row); if their
+   * largest magnitude is 0 it falls back to the full search.  Copied. */
+  const int32_t* sample_rows;
+  int32_t sample_s;           /* >= 1 */
+  int32_t sample_len;         /* 1..512 */
 } lslu_opts;
 
 /* lslu_opts.flags */

@@ -62,6 +62,9 @@ class lslu_opts(ctypes.Structure):
         ("replay_piv_g", POINTER(c_int32)),
         ("replay_lambda_idx", POINTER(c_int32)),
         ("flags", c_int32),
+        ("sample_rows", POINTER(c_int32)),
+        ("sample_s", c_int32),
+        ("sample_len", c_int32),
     ]
 
 
@@ -261,9 +264,11 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
                grid_relative=False, omega=0.0, x0=None, x_true=None,
                stop_tol=0.0, early_stop=False, X=None, x_out=None,
                replay_piv_t=None, replay_piv_g=None, replay_lambda_idx=None,
-               eager=False, timing=False):
+               eager=False, timing=False, pivot_sample=None):
     """Run the solver.  ``b``, ``x0``, ``X``, ``x_out`` are torch device
     tensors in the working precision (``x_out`` is allocated when None).
+    ``pivot_sample = (rows, s)`` selects sampled pivots: ``rows`` is the
+    (2 maxiter + 1) x L int32 array of candidate rows per search.
     Returns ``(status, x_out, info)`` where ``info`` holds the host-side
     results as NumPy arrays."""
     import torch
@@ -294,6 +299,14 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
             a, pa = _np(arr, np.int32)
             keep.append(a)
             setattr(o, name, pa)
+    if pivot_sample is not None:
+        rows, ssz = pivot_sample
+        rows = np.ascontiguousarray(rows, dtype=np.int32)
+        a, pa = _np(rows.reshape(-1), np.int32)
+        keep.append(a)
+        o.sample_rows = pa
+        o.sample_s = int(ssz)
+        o.sample_len = int(rows.shape[1])
     r = lslu_result()
     host = dict(
         piv_t=np.full(K + 1, -1, np.int32), piv_g=np.full(K, -1, np.int32),

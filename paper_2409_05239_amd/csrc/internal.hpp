@@ -62,8 +62,12 @@ struct PivotJob {
   int* own_list;         // own choices (device)
   unsigned char* mask;   // "is a pivot" flag per row
   const int* replay;     // replay pivot list (device) or nullptr
+  const int* sample;     // candidate rows of a sampled search (device) or nullptr
+  int sample_s, sample_len;
   DevState* st;
 };
+// Longest candidate list of a sampled pivot search.
+constexpr int kMaxSampleLen = 512;
 
 // ---------------------------------------------------------------- bf16 ----
 __host__ __device__ inline uint16_t f32_to_bf16(float f) {

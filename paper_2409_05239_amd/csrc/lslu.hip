@@ -34,6 +34,7 @@ struct Layout {
   double *grid = nullptr, *proj = nullptr;
   double *gram = nullptr, *gram_part = nullptr;  // optimal rule only
   int *rep_t = nullptr, *rep_g = nullptr, *rep_lam = nullptr;
+  int* samp = nullptr;  // sampled-pivot candidate rows, (2K+1) x kMaxSampleLen
   unsigned char *mask_t = nullptr, *mask_g = nullptr;
   ArgPart* parts = nullptr;
   // result block (copied to the host in one transfer)
@@ -88,6 +89,7 @@ size_t carve(unsigned char* base, int64_t m, int64_t n, int K, size_t esz,
   l.rep_t = reinterpret_cast<int*>(take(sizeof(int) * (K + 1)));
   l.rep_g = reinterpret_cast<int*>(take(sizeof(int) * K));
   l.rep_lam = reinterpret_cast<int*>(take(sizeof(int) * K));
+  l.samp = reinterpret_cast<int*>(take(sizeof(int) * (2 * K + 1) * kMaxSampleLen));
   l.mask_t = take(m);
   l.mask_g = take(n);
   l.parts = reinterpret_cast<ArgPart*>(take(sizeof(ArgPart) * 2 * kMaxParts));
@@ -143,6 +145,7 @@ struct lslu_ctx {
   // last uploaded lambda grid and replay arrays (skipped when unchanged)
   std::vector<double> up_grid;
   std::vector<int> up_rep;
+  std::vector<int> up_samp;
 };
 
 struct lslu_op {
@@ -337,7 +340,12 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
     a.nbp = k;
     a.Trowp = k > 0 ? TD + packed(k) : nullptr;
   };
+  const bool sampled = o->sample_rows != nullptr;
   auto run = [&](HalfArgs<T>& a, int tr) {
+    // launch i resolves pivot search i (r_0, then q and u of each iteration)
+    a.job.sample = sampled ? l.samp + (int64_t)launch * kMaxSampleLen : nullptr;
+    a.job.sample_s = sampled ? o->sample_s : 0;
+    a.job.sample_len = sampled ? o->sample_len : 0;
     a.entries = l.ybuf + slots_per_launch(K) * launch;
     a.cslot = a.entries + (K + 1);
     a.pslot = reinterpret_cast<uint64_t*>(a.entries + 2 * (K + 1));
@@ -474,6 +482,18 @@ lslu_status validate_opts(lslu_ctx* c, const lslu_op* op, const lslu_opts* o) {
     return LSLU_OK;
   };
   const int K = o->maxiter;
+  if (o->sample_rows) {
+    if (o->sample_s < 1 || o->sample_len < 1 || o->sample_len > kMaxSampleLen)
+      return fail(c, LSLU_EINVAL, "sample_s must be >= 1 and sample_len in [1, 512]");
+    for (int i = 0; i < 2 * K + 1; ++i) {
+      const int64_t len = (i % 2 == 0) ? m : n;
+      for (int e = 0; e < o->sample_len; ++e) {
+        const int32_t r = o->sample_rows[(int64_t)i * o->sample_len + e];
+        if (r < -1 || r >= len)
+          return fail(c, LSLU_EINVAL, "sample_rows: row out of range");
+      }
+    }
+  }
   if (o->replay_piv_t) {
     lslu_status st = check_piv(o->replay_piv_t, (int)std::min<int64_t>(K + 1, m), m,
                                "replay_piv_t");
@@ -809,6 +829,23 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
         LSLU_HIP(c, hipStreamSynchronize(s));
         c->up_rep = rep;
       }
+      if (o->sample_rows) {
+        // rows of kMaxSampleLen on the device; the key also ties the cached
+        // copy to the buffer's address
+        std::vector<int> sm((size_t)(2 * K + 1) * kMaxSampleLen + 2, -1);
+        for (int i = 0; i < 2 * K + 1; ++i)
+          std::memcpy(sm.data() + (size_t)i * kMaxSampleLen,
+                      o->sample_rows + (int64_t)i * o->sample_len, sizeof(int) * o->sample_len);
+        const uintptr_t sp = reinterpret_cast<uintptr_t>(l.samp);
+        sm[sm.size() - 2] = static_cast<int>(sp & 0x7fffffff);
+        sm[sm.size() - 1] = static_cast<int>((sp >> 31) & 0x7fffffff);
+        if (sm != c->up_samp) {
+          LSLU_HIP(c, hipMemcpyAsync(l.samp, sm.data(), sizeof(int) * (sm.size() - 2),
+                                     hipMemcpyHostToDevice, s));
+          LSLU_HIP(c, hipStreamSynchronize(s));
+          c->up_samp = sm;
+        }
+      }
     }
     void* X = o->X_dev ? o->X_dev : l.X;
     PhaseEvents pe;
@@ -845,7 +882,8 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
           (double)op->d.kind, (double)op->d.prec, (double)op->d.m, (double)op->d.n,
           (double)K, (double)o->reg, o->lambda, (double)o->n_grid,
           (double)o->grid_relative, o->omega, o->stop_tol, (double)o->early_stop,
-          (double)rt, (double)rg, (double)rl, (double)(uintptr_t)o->x_true_dev};
+          (double)rt, (double)rg, (double)rl, (double)(uintptr_t)o->x_true_dev,
+          (double)(o->sample_rows != nullptr), (double)o->sample_s};
       if (!c->gexec || key != c->gkey) {
         drop_graph(c);
         LSLU_HIP(c, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));

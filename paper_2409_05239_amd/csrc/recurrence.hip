@@ -223,6 +223,48 @@ __device__ __attribute__((always_inline)) inline void trisolve_wave(double* g, i
   __syncthreads();
 }
 
+// Sampled pivot search (the variant of Section 2.2): among the first
+// sample_s listed rows that are not earlier pivots, the entry of largest
+// magnitude (ties: smallest row), as a signed key; 0 when all are 0.  The
+// rank of a listed row among the eligible ones comes from a block-wide
+// ballot prefix count in list order.
+template <typename T>
+__device__ inline void sampled_search(const HalfArgs<T>& a, double& key, int& idx) {
+  __shared__ int wcount[kWaves];
+  const PivotJob& job = a.job;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  key = 0.0;
+  idx = INT_MAX;
+  int base = 0;
+  for (int c0 = 0; c0 < job.sample_len; c0 += kThreads) {
+    const int li = c0 + tid;
+    const int row = li < job.sample_len ? job.sample[li] : -1;
+    bool elig = false;
+    double v = 0.0;
+    if (row >= 0) {
+      elig = job.mask[row] == 0;
+      v = static_cast<double>(a.up[row]);
+    }
+    const uint64_t bal = __ballot(elig);
+    const int below = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wcount[w] = __popcll(bal);
+    __syncthreads();
+    int before = base, total = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) {
+      if (i < w) before += wcount[i];
+      total += wcount[i];
+    }
+    __syncthreads();
+    if (elig && before + below < job.sample_s && better(v, row, key, idx)) {
+      key = v;
+      idx = row;
+    }
+    base += total;
+  }
+  block_argmax<kThreads>(key, idx);
+}
+
 // ------------------------------------------------------------ block 0 -----
 template <typename T, bool kTriLds>
 __device__ void lead(const HalfArgs<T>& a, DevState* st, unsigned char* lds) {
@@ -264,6 +306,15 @@ __device__ void lead(const HalfArgs<T>& a, DevState* st, unsigned char* lds) {
   }
   block_argmax<kThreads>(key, idx);
   const PivotJob& job = a.job;
+  if (job.sample) {  // a sample whose entries are all 0 keeps the full search
+    double skey;
+    int sidx;
+    sampled_search(a, skey, sidx);
+    if (fabs(skey) > 0.0) {
+      key = skey;
+      idx = sidx;
+    }
+  }
   const int own = (job.eligible && fabs(key) > 0.0) ? idx : -1;
   const int pick = job.replay ? (job.eligible ? job.replay[job.piv_pos] : -1) : own;
   // The winning candidate carries the pivot value; a replayed pivot is read.

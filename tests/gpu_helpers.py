@@ -17,7 +17,7 @@ def torch_dtype(prec):
 def gpu_solve(capi, ctx, prob, prec="fp64", K=10, reg="none", lam=0.0,
               grid=None, grid_relative=False, replay=None, x0=None,
               early_stop=False, stop_tol=0.0, bases=True, op=None, eager=False,
-              b=None, x_true=None):
+              b=None, x_true=None, pivot_sample=None):
     """Solve on the GPU; returns the info dict with x, X (n x K), L, D."""
     import torch
     dt = torch_dtype(prec)
@@ -38,7 +38,8 @@ def gpu_solve(capi, ctx, prob, prec="fp64", K=10, reg="none", lam=0.0,
         st, x, info = capi.lslu_solve(ctx, op, b, K, reg=reg, lam=lam, grid=grid,
                                       grid_relative=grid_relative, X=X, x0=x0t,
                                       early_stop=early_stop, stop_tol=stop_tol,
-                                      eager=eager, x_true=xtt, **kw)
+                                      eager=eager, x_true=xtt,
+                                      pivot_sample=pivot_sample, **kw)
         torch.cuda.synchronize()
         info["x"] = x.double().cpu().numpy()
         info["X"] = X.double().cpu().numpy().T.copy()

@@ -37,16 +37,21 @@ def _reg(kind, relative, lam=0.05, x_true=None):
 
 
 def _compare(lib, ctx, prob, prec, K, kind, relative, lam=0.05, replay=True,
-             check_free=True, kappa_cap=None):
+             check_free=True, kappa_cap=None, pivot_sample=None):
     """Run oracle + GPU (free and replay) and check the parity bar."""
     op = make_operator(prob)
     xt = prob.x_true if kind == "optimal" else None
-    R = hybrid_lslu(op, prob.b, K, _reg(kind, relative, lam, x_true=xt))
+    R = hybrid_lslu(op, prob.b, K, _reg(kind, relative, lam, x_true=xt),
+                    pivot_sample=pivot_sample)
     grid = lambda_grid() if kind in ("wgcv", "gcv", "optimal") else None
     tol = TOL[prec]
     if check_free:
-        G = gpu_solve(lib, ctx, prob, prec, K, kind, lam, grid, relative, x_true=xt)
-        check_basis_invariants(G, prob.m, prob.n)
+        G = gpu_solve(lib, ctx, prob, prec, K, kind, lam, grid, relative, x_true=xt,
+                      pivot_sample=pivot_sample)
+        # a sampled pivot is the largest entry of its sample only, so the
+        # entries of the bases are not bounded by 1 then
+        check_basis_invariants(G, prob.m, prob.n,
+                               bound=1.0 if pivot_sample is None else np.inf)
         k_piv = pivot_prefix(R, TAU[prec], min(R.k_done, G["k_done"]))
         assert list(G["piv_g"][:k_piv]) == R.piv_g[:k_piv]
         assert list(G["piv_t"][:k_piv]) == R.piv_t[:k_piv]
@@ -58,9 +63,14 @@ def _compare(lib, ctx, prob, prec, K, kind, relative, lam=0.05, replay=True,
                 assert rel(G["X"][:, k - 1], R.X[:, k - 1]) <= tol, k
     if replay:
         Kr = min(K, R.k_done)
+        ps = None
+        if pivot_sample is not None:  # the lists of a Kr-iteration solve
+            rows, ssz = pivot_sample
+            ps = (rows[:2 * Kr + 1], ssz)
         G = gpu_solve(lib, ctx, prob, prec, Kr, kind, lam, grid, relative,
-                      replay=replay_from(R, Kr), x_true=xt)
-        check_basis_invariants(G, prob.m, prob.n, bound=1.0 + 10 * TAU[prec])
+                      replay=replay_from(R, Kr), x_true=xt, pivot_sample=ps)
+        check_basis_invariants(G, prob.m, prob.n,
+                               bound=1.0 + 10 * TAU[prec] if pivot_sample is None else np.inf)
         assert G["k_done"] == Kr
         worst = []
         for k in range(1, Kr + 1):
@@ -192,6 +202,44 @@ def test_optimal_error_not_above_wgcv(lib, ctx, prec, slack):
     assert 0 <= O["lambda_idx"][:O["k_done"]].min() and O["lambda_idx"][:O["k_done"]].max() < len(grid)
 
 
+# ------------------------------------------------ sampled pivots (Sec. 2.2)
+
+@pytest.mark.parametrize("name,prec,K,s", [("tomo32", "fp64", 30, 25), ("tomo32", "fp32", 30, 50),
+                                           ("dense256", "fp64", 40, 25), ("deblur96", "fp64", 30, 100)])
+def test_sampled_pivots(lib, ctx, name, prec, K, s):
+    """The sampled-pivot variant against the oracle on the same candidate
+    lists: pivots, x_k, H and W as for full pivoting (free and replay)."""
+    from workloads import pivot_sample_lists
+    prob = config_problem(name)
+    rows = pivot_sample_lists(prob.m, prob.n, K, s, seed=11)
+    relative = name != "dense256"
+    R, G = _compare(lib, ctx, prob, prec, K, "wgcv", relative,
+                    check_free=(prec == "fp64"), kappa_cap=1e5 if name == "dense256" else None,
+                    pivot_sample=(rows, s))
+    # the sample really decides: some pivots differ from full pivoting
+    full = hybrid_lslu(make_operator(prob), prob.b, K, _reg("wgcv", relative))
+    assert R.piv_t != full.piv_t[:len(R.piv_t)] or R.piv_g != full.piv_g[:len(R.piv_g)]
+
+
+def test_sampled_pivots_listing_every_row_equal_full_pivoting(lib, ctx):
+    """With every row listed and a sample as long as the list, the sampled
+    search is the full search: bit-identical to the library's full run."""
+    rng = np.random.default_rng(3)
+    small = random_dense(60, 45, seed=9, nu=0.05)
+    K = 20
+    rows = np.full((2 * K + 1, 64), -1, dtype=np.int32)
+    for i in range(2 * K + 1):
+        length = small.m if i % 2 == 0 else small.n
+        rows[i, :length] = rng.permutation(length)
+    grid = lambda_grid()
+    full = gpu_solve(lib, ctx, small, "fp64", K, "wgcv", grid=grid, grid_relative=True,
+                     bases=False)
+    samp = gpu_solve(lib, ctx, small, "fp64", K, "wgcv", grid=grid, grid_relative=True,
+                     bases=False, pivot_sample=(rows, 64))
+    assert np.array_equal(full["piv_t"], samp["piv_t"]) and np.array_equal(full["piv_g"], samp["piv_g"])
+    assert np.array_equal(full["X"], samp["X"])
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_deblur_small(lib, ctx, prec):
     prob = config_problem("deblur96")
@@ -303,7 +351,9 @@ def test_invalid_options_are_rejected(lib, ctx):
                    dict(maxiter=3, reg="wgcv"),
                    dict(maxiter=3, reg="optimal", grid=[0.1, 1.0]),
                    dict(maxiter=3, reg="wgcv", grid=[1.0, 0.5]),
-                   dict(maxiter=3, reg="fixed", lam=-1.0)):
+                   dict(maxiter=3, reg="fixed", lam=-1.0),
+                   dict(maxiter=2, pivot_sample=(np.zeros((5, 4), np.int32), 0)),
+                   dict(maxiter=2, pivot_sample=(np.full((5, 4), 10, np.int32), 2))):
             K = kw.pop("maxiter")
             with pytest.raises(lib.LsluError) as ei:
                 lib.lslu_solve(ctx, op, b, K, **kw)
