@@ -109,10 +109,16 @@ def run(args):
         torch.cuda.synchronize()
         return op, b, X, x
 
+    sample = None
+    if args.pivot_sample > 0:  # the sampled-pivot variant (Section 2.2)
+        from workloads import pivot_sample_lists
+        sample = (pivot_sample_lists(prob.m, prob.n, K, args.pivot_sample, seed=0),
+                  args.pivot_sample)
+
     def solve(op, b, X, x, timing=False):
         return capi.lslu_solve(ctx, op, b, K, reg=cfg["reg"], grid=grid,
                                grid_relative=cfg["grid_relative"], X=X, x_out=x,
-                               timing=timing)
+                               timing=timing, pivot_sample=sample)
 
     def timed(p, steps, warmup):
         op, b, X, x = setup(p)
@@ -195,7 +201,8 @@ def run(args):
         "data": "synthetic",
         "config": {"workload": args.workload, "m": prob.m, "n": prob.n,
                    "nnz": prob.nnz, "iters": K, "precision": prec,
-                   "reg": cfg["reg"], "grid_relative": cfg["grid_relative"]},
+                   "reg": cfg["reg"], "grid_relative": cfg["grid_relative"],
+                   "pivot_sample": args.pivot_sample or None},
         "rel_err_final": float(errs[-1]),
         "rel_err_min": float(errs.min()),
         "k_min": int(errs.argmin()) + 1,
@@ -242,6 +249,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--pivot-sample", type=int, default=0,
+                    help="sampled pivots: sample size per search (0: full searches)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (counter scaling)")
     args = ap.parse_args()
