@@ -164,7 +164,7 @@ def run(args):
     # average launch duration is the recurrence's device time (HIP events the
     # library records on its stream around the 2K + 1 launches) per launch.
     esz = 8 if prec == "fp64" else 4
-    vsz = {"fp64": 8, "fp32": 4, "bf16op": 2}[prec]
+    vsz = {"fp64": 8, "fp32": 4, "bf16op": 2, "fp16op": 2}[prec]
     n_launch = tm["n_recurrence_launches"]
     t_launch = tm["t_recurrence_ms"] * 1e-3 / n_launch
     nbytes = recurrence_bytes(prob, K, vsz, esz) / n_launch
@@ -197,7 +197,7 @@ def run(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16op": "bf16-op/f32"}[prec],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16op": "bf16-op/f32", "fp16op": "f16-op/f32"}[prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "m": prob.m, "n": prob.n,
                    "nnz": prob.nnz, "iters": K, "precision": prec,

@@ -21,7 +21,7 @@
  *   given to lslu_solve/lslu_op_apply are only borrowed for the duration of the
  *   call.  No caller pointer is kept after a call returns.
  * - "Working precision" (wp) is the vector type of an operator: double for
- *   LSLU_FP64, float for LSLU_FP32 and LSLU_BF16OP.  Device vectors passed to
+ *   LSLU_FP64, float for LSLU_FP32, LSLU_BF16OP and LSLU_FP16OP.  Device vectors passed to
  *   the library are contiguous arrays of that type.
  * - All work of one context is enqueued on that context's HIP stream (the one
  *   given to lslu_create, or one it made).  Calls on one context must not
@@ -54,8 +54,10 @@ typedef enum lslu_status {
 typedef enum lslu_precision {
   LSLU_FP64 = 0,  /* operator, bases and vectors in double */
   LSLU_FP32 = 1,  /* operator, bases and vectors in float; sums in double */
-  LSLU_BF16OP = 2 /* operator values and its input in bfloat16, products summed
-                     in float; bases and vectors in float */
+  LSLU_BF16OP = 2, /* operator values and its input in bfloat16, products summed
+                      in float; bases and vectors in float */
+  LSLU_FP16OP = 3  /* operator values and its input in IEEE binary16, products
+                      summed in float; bases and vectors in float */
 } lslu_precision;
 
 typedef enum lslu_reg {

@@ -26,13 +26,23 @@ template <>
 struct ValTraits<uint16_t> {
   __device__ static float get(uint16_t v) { return bf16_to_f32(v); }
 };
+template <>
+struct ValTraits<Half> {
+  __device__ static float get(Half v) {
+    return static_cast<float>(__builtin_bit_cast(_Float16, v.bits));
+  }
+};
 
-// Vector entry as seen by a product: in the BF16 operator mode the input is
-// rounded to bfloat16 (bf16 x bf16 products are exact in float).
-template <bool kBf16, typename T>
+// Input rounding of the operator modes (kIn: kInNone, kInBf16, kInFp16):
+// in the 16-bit operator modes a product's input entries are rounded to the
+// operator's format, so every term is a product of two 16-bit numbers, exact
+// in float.
+template <int kIn, typename T>
 __device__ inline auto in_val(T v) {
-  if constexpr (kBf16)
+  if constexpr (kIn == kInBf16)
     return bf16_to_f32(f32_to_bf16(static_cast<float>(v)));
+  else if constexpr (kIn == kInFp16)
+    return static_cast<float>(static_cast<_Float16>(static_cast<float>(v)));
   else
     return v;
 }
@@ -187,7 +197,7 @@ struct RowStage {
 // lanes with x(c) supplied by a functor; group_sum<G> completes the sum.
 
 // Row r of a row-major dense matrix with `cols` columns.
-template <typename V, typename AccT, bool kBf16>
+template <typename V, typename AccT, int kIn>
 struct DenseRows {
   using Acc = AccT;
   using Val = V;
@@ -199,7 +209,7 @@ struct DenseRows {
 #pragma unroll 4
     for (int64_t c = c0; c < cols; c += G)
       acc = fma(static_cast<Acc>(ValTraits<V>::get(row[c])),
-                static_cast<Acc>(in_val<kBf16>(xf(c))), acc);
+                static_cast<Acc>(in_val<kIn>(xf(c))), acc);
     return acc;
   }
   template <int G, typename XF>
@@ -228,7 +238,7 @@ struct DenseRows {
     for (int k = 0; k < NP; ++k)
       if (s.next - (int64_t)(NP - k) * G < s.end)
         acc = fma(static_cast<Acc>(ValTraits<V>::get(s.v[k])),
-                  static_cast<Acc>(in_val<kBf16>(nz(s.x[k]))), acc);
+                  static_cast<Acc>(in_val<kIn>(nz(s.x[k]))), acc);
     return rest<G>(s.row, s.next, xf, acc);
   }
 };
@@ -261,6 +271,15 @@ struct Quad<uint16_t> {
   }
 };
 
+template <>
+struct Quad<Half> {
+  __device__ static void load(const Half* p, Half (&v)[4]) {
+    const uint2 q = *reinterpret_cast<const uint2*>(p);
+    v[0].bits = static_cast<uint16_t>(q.x & 0xffffu); v[1].bits = static_cast<uint16_t>(q.x >> 16);
+    v[2].bits = static_cast<uint16_t>(q.y & 0xffffu); v[3].bits = static_cast<uint16_t>(q.y >> 16);
+  }
+};
+
 // Row r of a CSR matrix (int32 row pointers and column indices; index and
 // value arrays 16-byte aligned and readable 3 entries past nnz).  The row is
 // read in aligned chunks of 4 entries: lane `sub` of a group of G takes the
@@ -268,7 +287,7 @@ struct Quad<uint16_t> {
 // the indices and one for the values per chunk, then the gathers of its
 // entries inside [beg, end), kChunks chunks per batch so a row costs few
 // dependent round trips.  Each lane adds its entries in chunk order.
-template <typename V, typename AccT, bool kBf16>
+template <typename V, typename AccT, int kIn>
 struct CsrRows {
   using Acc = AccT;
   using Val = V;
@@ -313,7 +332,7 @@ struct CsrRows {
           const int pos = q + h * 4 * G + e;
           if (pos >= beg && pos < end)
             acc = fma(static_cast<Acc>(ValTraits<V>::get(v[h][e])),
-                      static_cast<Acc>(in_val<kBf16>(x[h][e])), acc);
+                      static_cast<Acc>(in_val<kIn>(x[h][e])), acc);
         }
     }
     return acc;
@@ -375,7 +394,7 @@ struct CsrRows {
         const int pos = q + h * 4 * G + e;
         if (pos >= beg && pos < end)
           acc = fma(static_cast<Acc>(ValTraits<V>::get(s.v[4 * h + e])),
-                    static_cast<Acc>(in_val<kBf16>(nz(s.x[4 * h + e]))), acc);
+                    static_cast<Acc>(in_val<kIn>(nz(s.x[4 * h + e]))), acc);
       }
     return rest<G>(q + NC * 4 * G, beg, end, xf, acc);
   }
@@ -383,7 +402,7 @@ struct CsrRows {
 
 // Pixel `pix` of the zero-boundary correlation with weights wt (ph x pw):
 // y(i,j) = sum_{a,b} wt(a,b) x(i + a - ph/2, j + b - pw/2).
-template <typename AccT, bool kBf16>
+template <typename AccT, int kIn>
 struct PsfPixels {
   using Acc = AccT;
   using Val = AccT;
@@ -399,7 +418,7 @@ struct PsfPixels {
       const int a = t / pw, b = t - a * pw;
       const int gi = i + a - ch, gj = j + b - cw;
       if (gi >= 0 && gi < rows && gj >= 0 && gj < cols)
-        acc = fma(wt[t], static_cast<Acc>(in_val<kBf16>(xf((int64_t)gi * cols + gj))),
+        acc = fma(wt[t], static_cast<Acc>(in_val<kIn>(xf((int64_t)gi * cols + gj))),
                   acc);
     }
     return acc;
@@ -434,7 +453,7 @@ __host__ __device__ constexpr size_t psf_lds_bytes(int pw) {
 // acc[p] = y[i0 + r0 + p, j0 + lane] for the tile at (i0, j0), with
 // y[i,j] = sum_{a,b} Wt[a,b] * x[i + a - PH/2, j + b - pw/2]  (zero outside),
 // r0 = 8 * wavefront.  Ends with the tile still in LDS (no trailing barrier).
-template <typename T, typename Acc, int PH, bool kBf16>
+template <typename T, typename Acc, int PH, int kIn>
 __device__ inline void psf_tile(const T* __restrict__ x, int rows, int cols,
                                 const Acc* __restrict__ Wt, int pw, int i0,
                                 int j0, Acc* tile, Acc (&acc)[kPsfR]) {
@@ -446,7 +465,7 @@ __device__ inline void psf_tile(const T* __restrict__ x, int rows, int cols,
     const int gi = i0 - ch + tr, gj = j0 - cw + tc;
     Acc v = 0;
     if (gi >= 0 && gi < rows && gj >= 0 && gj < cols)
-      v = static_cast<Acc>(in_val<kBf16>(x[(int64_t)gi * cols + gj]));
+      v = static_cast<Acc>(in_val<kIn>(x[(int64_t)gi * cols + gj]));
     tile[e] = v;
   }
   __syncthreads();
@@ -487,10 +506,11 @@ void with_ph(int ph, F&& f) {
 template <typename T, typename F>
 void with_mode(int prec, F&& f) {
   if constexpr (std::is_same_v<T, double>) {
-    if (prec == kFP64) f(double{}, double{}, std::false_type{});
+    if (prec == kFP64) f(double{}, double{}, std::integral_constant<int, kInNone>{});
   } else {
-    if (prec == kFP32) f(float{}, double{}, std::false_type{});
-    else if (prec == kBF16) f(uint16_t{}, float{}, std::true_type{});
+    if (prec == kFP32) f(float{}, double{}, std::integral_constant<int, kInNone>{});
+    else if (prec == kBF16) f(uint16_t{}, float{}, std::integral_constant<int, kInBf16>{});
+    else if (prec == kFP16) f(Half{}, float{}, std::integral_constant<int, kInFp16>{});
   }
 }
 

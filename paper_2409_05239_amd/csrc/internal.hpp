@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <string>
 
@@ -17,7 +18,14 @@ constexpr int kMaxParts = 4096;  // pivot candidates per streaming pass
 // finite values produces it.
 constexpr uint64_t kSlotEmpty = 0x7ff4dead0000beefull;
 
-enum Prec : int { kFP64 = 0, kFP32 = 1, kBF16 = 2 };
+enum Prec : int { kFP64 = 0, kFP32 = 1, kBF16 = 2, kFP16 = 3 };
+// Input rounding of a product (the 16-bit operator modes).
+enum InMode : int { kInNone = 0, kInBf16 = 1, kInFp16 = 2 };
+// An IEEE binary16 operator value (its bits).
+struct Half {
+  uint16_t bits;
+  __host__ __device__ constexpr Half(int z = 0) : bits(static_cast<uint16_t>(z)) {}
+};
 enum Reg : int { kNone = 0, kFixed = 1, kWGCV = 2, kGCV = 3, kOptimal = 4 };
 enum Status : int {
   kOK = 0, kBreakQ = 1, kBreakU = 2, kZeroRHS = 3,
@@ -78,6 +86,39 @@ __host__ __device__ inline uint16_t f32_to_bf16(float f) {
 }
 __host__ __device__ inline float bf16_to_f32(uint16_t h) {
   return __builtin_bit_cast(float, static_cast<uint32_t>(h) << 16);
+}
+
+// ---------------------------------------------------------------- fp16 ----
+// IEEE binary16 (1 sign, 5 exponent bits with bias 15, 10 fraction bits) on
+// the host: a double rounded once to nearest, ties to even (overflow to
+// infinity, gradual underflow to the subnormals 2^-24 * m), and back.
+inline uint16_t f64_to_f16(double d) {
+  if (std::isnan(d)) return 0x7e00;
+  const uint16_t sign = std::signbit(d) ? 0x8000 : 0;
+  const double a = std::fabs(d);
+  if (a >= 65520.0) return sign | 0x7c00;        // at or beyond the rounding
+                                                   // boundary of 65504
+  if (a < 0x1p-14) {                               // subnormal (or zero)
+    const double m = std::nearbyint(a * 0x1p24);   // exact scaling, RNE
+    return sign | static_cast<uint16_t>(m);        // m == 1024: smallest normal
+  }
+  int e2 = 0;
+  (void)std::frexp(a, &e2);                        // a = f 2^e2, f in [0.5, 1)
+  int e = e2 - 1;                                  // a in [2^e, 2^(e+1))
+  double m = std::nearbyint((std::ldexp(a, -e) - 1.0) * 1024.0);
+  if (m == 1024.0) {
+    m = 0.0;
+    ++e;
+  }
+  if (e > 15) return sign | 0x7c00;
+  return sign | static_cast<uint16_t>((e + 15) << 10) | static_cast<uint16_t>(m);
+}
+inline float f16_to_f32(uint16_t h) {
+  const int e = (h >> 10) & 0x1f, m = h & 0x3ff;
+  const float sign = (h & 0x8000) ? -1.0f : 1.0f;
+  if (e == 0) return sign * std::ldexp(static_cast<float>(m), -24);
+  if (e == 31) return m ? NAN : sign * INFINITY;
+  return sign * std::ldexp(1.0f + static_cast<float>(m) / 1024.0f, e - 15);
 }
 
 // ------------------------------------------------------------- launchers ---

@@ -186,10 +186,14 @@ std::vector<unsigned char> convert_values(const double* v, int64_t count, int pr
     out.resize(sizeof(float) * count);
     float* o = reinterpret_cast<float*>(out.data());
     for (int64_t i = 0; i < count; ++i) o[i] = static_cast<float>(v[i]);
-  } else {
+  } else if (prec == kBF16) {
     out.resize(sizeof(uint16_t) * count);
     uint16_t* o = reinterpret_cast<uint16_t*>(out.data());
     for (int64_t i = 0; i < count; ++i) o[i] = f32_to_bf16(static_cast<float>(v[i]));
+  } else {  // binary16, rounded once from the given double
+    out.resize(sizeof(uint16_t) * count);
+    uint16_t* o = reinterpret_cast<uint16_t*>(out.data());
+    for (int64_t i = 0; i < count; ++i) o[i] = f64_to_f16(v[i]);
   }
   return out;
 }
@@ -596,7 +600,7 @@ lslu_status lslu_op_dense(lslu_ctx* c, int64_t m, int64_t n, const double* A,
   if (!out || !A) return fail(c, LSLU_EINVAL, "NULL argument");
   *out = nullptr;
   if (m < 1 || n < 1) return fail(c, LSLU_EINVAL, "m and n must be >= 1");
-  if (prec < LSLU_FP64 || prec > LSLU_BF16OP) return fail(c, LSLU_EINVAL, "bad precision");
+  if (prec < LSLU_FP64 || prec > LSLU_FP16OP) return fail(c, LSLU_EINVAL, "bad precision");
   if (m > INT32_MAX || n > INT32_MAX) return fail(c, LSLU_EINVAL, "size too large");
   try {
     if (!finite_all(A, m * n)) return fail(c, LSLU_ENONFINITE, "A has NaN/Inf");
@@ -636,7 +640,7 @@ lslu_status lslu_op_csr(lslu_ctx* c, int64_t m, int64_t n, int64_t nnz,
   if (m < 1 || n < 1 || nnz < 0) return fail(c, LSLU_EINVAL, "bad shape");
   if (m > INT32_MAX - 1 || n > INT32_MAX - 1 || nnz > INT32_MAX - 1)
     return fail(c, LSLU_EINVAL, "sizes must be < 2^31");
-  if (prec < LSLU_FP64 || prec > LSLU_BF16OP) return fail(c, LSLU_EINVAL, "bad precision");
+  if (prec < LSLU_FP64 || prec > LSLU_FP16OP) return fail(c, LSLU_EINVAL, "bad precision");
   try {
     if (indptr[0] != 0 || indptr[m] != nnz)
       return fail(c, LSLU_EINVAL, "indptr[0] must be 0 and indptr[m] must be nnz");
@@ -710,7 +714,7 @@ lslu_status lslu_op_psf(lslu_ctx* c, int64_t rows, int64_t cols, int32_t ph,
     return fail(c, LSLU_EINVAL, "bad image shape");
   if (ph < 1 || pw < 1 || ph % 2 == 0 || pw % 2 == 0 || ph > 31 || pw > 31)
     return fail(c, LSLU_EINVAL, "PSF sizes must be odd and <= 31");
-  if (prec < LSLU_FP64 || prec > LSLU_BF16OP) return fail(c, LSLU_EINVAL, "bad precision");
+  if (prec < LSLU_FP64 || prec > LSLU_FP16OP) return fail(c, LSLU_EINVAL, "bad precision");
   if (!finite_all(psf, (int64_t)ph * pw)) return fail(c, LSLU_ENONFINITE, "PSF has NaN/Inf");
   try {
     LSLU_HIP(c, hipSetDevice(c->device));
@@ -718,10 +722,16 @@ lslu_status lslu_op_psf(lslu_ctx* c, int64_t rows, int64_t cols, int32_t ph,
     std::vector<double> p(psf, psf + np), pf(np);
     for (int a = 0; a < ph; ++a)
       for (int b = 0; b < pw; ++b) pf[a * pw + b] = psf[(ph - 1 - a) * pw + (pw - 1 - b)];
+    // float copies of the weights in the 16-bit operator formats
     std::vector<float> p32(np), pf32(np);
     for (int i = 0; i < np; ++i) {
-      p32[i] = bf16_to_f32(f32_to_bf16(static_cast<float>(p[i])));
-      pf32[i] = bf16_to_f32(f32_to_bf16(static_cast<float>(pf[i])));
+      if (prec == kFP16) {
+        p32[i] = f16_to_f32(f64_to_f16(p[i]));
+        pf32[i] = f16_to_f32(f64_to_f16(pf[i]));
+      } else {
+        p32[i] = bf16_to_f32(f32_to_bf16(static_cast<float>(p[i])));
+        pf32[i] = bf16_to_f32(f32_to_bf16(static_cast<float>(pf[i])));
+      }
     }
     lslu_op* op = new lslu_op();
     op->ctx = c;

@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kRowBlock) void k_rows(
   if (sub == 0) y[r] = static_cast<T>(acc);
 }
 
-template <typename T, typename Acc, int PH, bool kBf16>
+template <typename T, typename Acc, int PH, int kIn>
 __global__ __launch_bounds__(kPsfWaves * kWave) void k_psf_corr(
     const T* __restrict__ x, T* __restrict__ y, int rows, int cols,
     const Acc* __restrict__ Wt, int pw, const int* stop) {
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kPsfWaves * kWave) void k_psf_corr(
   Acc* tile = reinterpret_cast<Acc*>(smem_raw);
   const int i0 = blockIdx.y * kPsfTH, j0 = blockIdx.x * kPsfTW;
   Acc acc[kPsfR];
-  psf_tile<T, Acc, PH, kBf16>(x, rows, cols, Wt, pw, i0, j0, tile, acc);
+  psf_tile<T, Acc, PH, kIn>(x, rows, cols, Wt, pw, i0, j0, tile, acc);
   const int lane = threadIdx.x & (kWave - 1);
   const int r0 = (threadIdx.x / kWave) * kPsfR;
   const int gj = j0 + lane;
@@ -77,7 +77,7 @@ void apply_t(const DeviceOp& op, int tr, const T* x, T* y, const int* stop,
   with_mode<T>(op.prec, [&](auto v, auto acc, auto bf) {
     using V = decltype(v);
     using Acc = decltype(acc);
-    constexpr bool kB = decltype(bf)::value;
+    constexpr int kB = decltype(bf)::value;
     const int64_t rows = tr ? op.n : op.m;
     const int grid = static_cast<int>((rows + kRowsPerBlock - 1) / kRowsPerBlock);
     if (op.kind == 0) {

@@ -668,7 +668,7 @@ __global__ __launch_bounds__(kThreads, half_min_waves<T>()) void k_half_rows(Hal
 // --------------------------------------------------- PSF consumer blocks --
 // The tile of the normalised input: each staged entry is u divided by the
 // pivot value, then (BF16 mode) rounded to bfloat16.
-template <typename T, typename Acc, int PH, bool kBf16>
+template <typename T, typename Acc, int PH, int kIn>
 __device__ inline void psf_tile_norm(const T* __restrict__ u, const Normaliser<T>& nz, int rows,
                                      int cols, const Acc* __restrict__ Wt, int pw,
                                      int i0, int j0, Acc* tile, Acc (&acc)[kPsfR]) {
@@ -679,7 +679,7 @@ __device__ inline void psf_tile_norm(const T* __restrict__ u, const Normaliser<T
     const int gi = i0 - ch + tr, gj = j0 - cw + tc;
     Acc v = 0;
     if (gi >= 0 && gi < rows && gj >= 0 && gj < cols)
-      v = static_cast<Acc>(in_val<kBf16>(nz(u[(int64_t)gi * cols + gj])));
+      v = static_cast<Acc>(in_val<kIn>(nz(u[(int64_t)gi * cols + gj])));
     tile[e] = v;
   }
   __syncthreads();
@@ -703,7 +703,7 @@ __device__ inline void psf_tile_norm(const T* __restrict__ u, const Normaliser<T
 
 // Persistent over tiles cb, cb + ncons, ...: products first (parked in out),
 // then the coefficients, then the elimination.
-template <typename T, typename Acc, int PH, bool kBf16>
+template <typename T, typename Acc, int PH, int kIn>
 __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
                               int rows, int cols, int pw, DevState* st, int cb,
                               int ncons, unsigned char* lds) {
@@ -724,7 +724,7 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
   for (int t = cb; t < ntiles; t += ncons) {
     const int i0 = (t / tiles_x) * kPsfTH, j0 = (t % tiles_x) * kPsfTW;
     Acc acc[kPsfR];
-    psf_tile_norm<T, Acc, PH, kBf16>(a.up, nz, rows, cols, Wt, pw, i0, j0, tile, acc);
+    psf_tile_norm<T, Acc, PH, kIn>(a.up, nz, rows, cols, Wt, pw, i0, j0, tile, acc);
     const int gj = j0 + lane;
 #pragma unroll
     for (int p = 0; p < kPsfR; ++p) {
@@ -792,18 +792,18 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
   if (threadIdx.x == 0) write_part(a.parts_out, cb, best, bidx);
 }
 
-template <typename T, typename Acc, int PH, bool kBf16, bool kTriLds>
+template <typename T, typename Acc, int PH, int kIn, bool kTriLds>
 __global__ __launch_bounds__(kThreads) void k_half_psf(
-    HalfArgs<T> a, PsfPixels<Acc, kBf16> op, const Acc* __restrict__ Wt) {
+    HalfArgs<T> a, PsfPixels<Acc, kIn> op, const Acc* __restrict__ Wt) {
   extern __shared__ unsigned char lds[];
   DevState* st = a.job.st;
   if (st->stopped) return;
   if (blockIdx.x == 0)
     lead<T, kTriLds>(a, st, lds);
   else if ((int)blockIdx.x < a.nlead)
-    pivot_entries<T, PsfPixels<Acc, kBf16>>(a, op, st);
+    pivot_entries<T, PsfPixels<Acc, kIn>>(a, op, st);
   else
-    consume_tiles<T, Acc, PH, kBf16>(a, Wt, op.rows, op.cols, op.pw, st,
+    consume_tiles<T, Acc, PH, kIn>(a, Wt, op.rows, op.cols, op.pw, st,
                                      blockIdx.x - a.nlead, gridDim.x - a.nlead, lds);
 }
 
@@ -866,8 +866,8 @@ int launch_rows(HalfArgs<T>& a, const RowOp& op, size_t lds_bytes, hipStream_t s
   return launch_rows_g<T, RowOp, 16>(a, op, tb, in_lds, s);
 }
 
-template <typename T, typename Acc, int PH, bool kBf16>
-int launch_tiles(HalfArgs<T>& a, const PsfPixels<Acc, kBf16>& op, const Acc* Wt,
+template <typename T, typename Acc, int PH, int kIn>
+int launch_tiles(HalfArgs<T>& a, const PsfPixels<Acc, kIn>& op, const Acc* Wt,
                  size_t lds_bytes, hipStream_t s) {
   const int ntiles = ((op.cols + kPsfTW - 1) / kPsfTW) * ((op.rows + kPsfTH - 1) / kPsfTH);
   const int64_t want = a.rows > 0 ? ntiles
@@ -878,13 +878,13 @@ int launch_tiles(HalfArgs<T>& a, const PsfPixels<Acc, kBf16>& op, const Acc* Wt,
   const size_t pb = psf_lds_bytes<Acc, PH>(op.pw);
   const bool in_lds = tb > 0 && tb <= kTriLdsMax && std::max(tb, pb) + 16 * 1024 <= lds_bytes;
   if (in_lds) {
-    auto k = k_half_psf<T, Acc, PH, kBf16, true>;
+    auto k = k_half_psf<T, Acc, PH, kIn, true>;
     const size_t dyn = std::max(tb, pb);
     const int ncons = consumer_blocks(want, a.nlead, resident_blocks((const void*)k, dyn));
     k<<<a.nlead + ncons, kThreads, dyn, s>>>(a, op, Wt);
     return ncons;
   }
-  auto k = k_half_psf<T, Acc, PH, kBf16, false>;
+  auto k = k_half_psf<T, Acc, PH, kIn, false>;
   const int ncons = consumer_blocks(want, a.nlead, resident_blocks((const void*)k, pb));
   k<<<a.nlead + ncons, kThreads, pb, s>>>(a, op, Wt);
   return ncons;
@@ -899,7 +899,7 @@ int launch_half(HalfArgs<T>& a, const DeviceOp& op, int tr, size_t lds_bytes,
   with_mode<T>(op.prec, [&](auto v, auto acc, auto bf) {
     using V = decltype(v);
     using Acc = decltype(acc);
-    constexpr bool kB = decltype(bf)::value;
+    constexpr int kB = decltype(bf)::value;
     if (op.kind == 0) {
       DenseRows<V, Acc, kB> ro{static_cast<const V*>(tr ? op.AT : op.A), tr ? op.m : op.n};
       nparts = launch_rows<T, decltype(ro)>(a, ro, lds_bytes, s);

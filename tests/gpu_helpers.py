@@ -5,7 +5,7 @@ from __future__ import annotations
 
 import numpy as np
 
-TAU = {"fp64": 1e-9, "fp32": 1e-3, "bf16op": 1e-2}
+TAU = {"fp64": 1e-9, "fp32": 1e-3, "bf16op": 1e-2, "fp16op": 1e-2}
 TOL = {"fp64": 1e-10, "fp32": 1e-4}
 
 

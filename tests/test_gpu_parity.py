@@ -100,12 +100,12 @@ def _compare(lib, ctx, prob, prec, K, kind, relative, lam=0.05, replay=True,
 # --------------------------------------------------------------- operators
 
 def _bound(Aabs_x, prec, nterms):
-    u = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "bf16op": 2.0 ** -8}[prec]
-    acc = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -53, "bf16op": 2.0 ** -24}[prec]
+    u = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "bf16op": 2.0 ** -8, "fp16op": 2.0 ** -11}[prec]
+    acc = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -53, "bf16op": 2.0 ** -24, "fp16op": 2.0 ** -24}[prec]
     return (4 * u + nterms * acc) * Aabs_x + 1e-300
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16op"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16op", "fp16op"])
 @pytest.mark.parametrize("which", ["dense", "csr", "psf31", "psf_nonsym"])
 def test_operator_products(lib, ctx, which, prec):
     import torch
@@ -247,17 +247,24 @@ def test_deblur_small(lib, ctx, prec):
              check_free=(prec == "fp64"))
 
 
-def test_deblur_small_bf16op_error(lib, ctx):
-    prob = config_problem("deblur96")
+@pytest.mark.parametrize("prec", ["bf16op", "fp16op"])
+@pytest.mark.parametrize("name", ["deblur96", "tomo32"])
+def test_16bit_operator_error(lib, ctx, prec, name):
+    """The 16-bit operator modes (values and product inputs rounded to
+    bfloat16 / binary16, sums and bases in float): exact pivot structure,
+    and the error to x_true, stated against the FP64 oracle's."""
+    prob = config_problem(name)
     op = make_operator(prob)
-    R = hybrid_lslu(op, prob.b, 40, _reg("wgcv", True))
-    G = gpu_solve(lib, ctx, prob, "bf16op", 40, "wgcv", grid=lambda_grid(),
+    K = 40 if name == "deblur96" else 30
+    R = hybrid_lslu(op, prob.b, K, _reg("wgcv", True))
+    G = gpu_solve(lib, ctx, prob, prec, K, "wgcv", grid=lambda_grid(),
                   grid_relative=True)
     check_basis_invariants(G, prob.m, prob.n)
-    e_bf = rel(G["x"], prob.x_true)
-    e_64 = rel(R.x, prob.x_true)
-    print(f"[deblur96 bf16op] rel err vs x_true {e_bf:.4f} (fp64 oracle {e_64:.4f})")
-    assert e_bf < 2 * e_64
+    e_lo = np.array([rel(G["X"][:, k], prob.x_true) for k in range(G["k_done"])])
+    e_64 = np.array([rel(R.X[:, k], prob.x_true) for k in range(R.k_done)])
+    print(f"[{name} {prec}] rel err vs x_true: min {e_lo.min():.4f} at k={int(e_lo.argmin()) + 1}, "
+          f"final {e_lo[-1]:.4f} (fp64 oracle: min {e_64.min():.4f}, final {e_64[-1]:.4f})")
+    assert e_lo.min() < 1.5 * e_64.min()
 
 
 # -------------------------------------------------------------- edge cases
