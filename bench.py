@@ -255,8 +255,9 @@ def main():
                     help="run one 256 MiB device copy first (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the "
-              "multi-GPU path is not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the "
+              "library has no multi-GPU path (how it would shard is described "
+              "with the design)", file=sys.stderr)
         sys.exit(2)
     run(args)
 
