@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LSLU_ABI_VERSION 4
+#define LSLU_ABI_VERSION 5
 
 typedef enum lslu_status {
   LSLU_OK = 0,
@@ -196,7 +196,15 @@ typedef enum lslu_flag {
    * context's stream around the recurrence, the projected problems and the
    * assembly; the elapsed times are returned in lslu_result.  Events between
    * launches add a little time of their own. */
-  LSLU_FLAG_TIMING = 2
+  LSLU_FLAG_TIMING = 2,
+  /* Enqueue the whole solve, including the copy of the small results to
+   * pinned host memory, on the context's stream and return LSLU_OK without
+   * waiting; lslu_wait completes it.  Until then the caller keeps every array
+   * the call was given (device vectors and the lslu_result arrays), and the
+   * context accepts no other solve.  Solves on several contexts (one stream
+   * each) run concurrently: many small problems share the GPU.  Not with
+   * LSLU_FLAG_TIMING. */
+  LSLU_FLAG_ASYNC = 4
 } lslu_flag;
 
 typedef struct lslu_result {
@@ -244,6 +252,11 @@ typedef struct lslu_result {
 lslu_status lslu_solve(lslu_ctx* ctx, const lslu_op* op, const void* b_dev,
                        const void* x0_dev, const lslu_opts* opts,
                        void* x_out_dev, lslu_result* res);
+
+/* Completes the pending LSLU_FLAG_ASYNC solve of the context: waits for its
+ * stream, fills the lslu_result given to lslu_solve and returns the solve's
+ * status (as lslu_solve would have).  LSLU_OK when nothing is pending. */
+lslu_status lslu_wait(lslu_ctx* ctx);
 
 /* Copy basis vectors of the last solve on ctx into a device buffer (wp,
  * column-major, leading dimension = vector length): which = 0 copies the

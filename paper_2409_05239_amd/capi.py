@@ -42,7 +42,7 @@ EXPORTS = (
     "lslu_create", "lslu_destroy", "lslu_last_error", "lslu_status_name",
     "lslu_abi_version", "lslu_op_dense", "lslu_op_csr", "lslu_op_psf",
     "lslu_op_apply", "lslu_op_info", "lslu_op_destroy", "lslu_solve",
-    "lslu_get_basis",
+    "lslu_wait", "lslu_get_basis",
 )
 
 
@@ -71,6 +71,7 @@ class lslu_opts(ctypes.Structure):
 
 LSLU_FLAG_EAGER = 1
 LSLU_FLAG_TIMING = 2
+LSLU_FLAG_ASYNC = 4
 
 
 class lslu_result(ctypes.Structure):
@@ -138,6 +139,7 @@ def _load():
         "lslu_solve": (c_int, [vp, vp, vp, vp, POINTER(lslu_opts), vp,
                                POINTER(lslu_result)]),
         "lslu_get_basis": (c_int, [vp, c_int32, c_int32, vp]),
+        "lslu_wait": (c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -265,11 +267,13 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
                grid_relative=False, omega=0.0, x0=None, x_true=None,
                stop_tol=0.0, early_stop=False, X=None, x_out=None,
                replay_piv_t=None, replay_piv_g=None, replay_lambda_idx=None,
-               eager=False, timing=False, pivot_sample=None):
+               eager=False, timing=False, pivot_sample=None, asynchronous=False):
     """Run the solver.  ``b``, ``x0``, ``X``, ``x_out`` are torch device
     tensors in the working precision (``x_out`` is allocated when None).
     ``pivot_sample = (rows, s)`` selects sampled pivots: ``rows`` is the
     (2 maxiter + 1) x L int32 array of candidate rows per search.
+    ``asynchronous=True`` enqueues the solve and returns a ``Pending``;
+    ``lslu_wait(ctx, pending)`` completes it and returns the same triple.
     Returns ``(status, x_out, info)`` where ``info`` holds the host-side
     results as NumPy arrays."""
     import torch
@@ -293,7 +297,8 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
     o.stop_tol = float(stop_tol)
     o.early_stop = 1 if early_stop else 0
     o.X_dev = _dptr(X)
-    o.flags = (LSLU_FLAG_EAGER if eager else 0) | (LSLU_FLAG_TIMING if timing else 0)
+    o.flags = ((LSLU_FLAG_EAGER if eager else 0) | (LSLU_FLAG_TIMING if timing else 0)
+               | (LSLU_FLAG_ASYNC if asynchronous else 0))
     for name, arr in (("replay_piv_t", replay_piv_t), ("replay_piv_g", replay_piv_g),
                       ("replay_lambda_idx", replay_lambda_idx)):
         if arr is not None:
@@ -320,6 +325,27 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
         setattr(r, name, arr.ctypes.data_as(POINTER(ct)))
     st = _check(ctx, lib.lslu_solve(ctx, op, _dptr(b), _dptr(x0), ctypes.byref(o),
                                     _dptr(x_out), ctypes.byref(r)))
+    if asynchronous:
+        # everything the library may still write or read stays referenced
+        return Pending(r, host, keep, x_out, (b, x0, X, x_true), timing)
+    return st, x_out, _info(st, r, host, timing)
+
+
+class Pending:
+    """An enqueued asynchronous solve (see ``lslu_solve``)."""
+
+    def __init__(self, r, host, keep, x_out, refs, timing):
+        self.r, self.host, self.keep, self.x_out, self.refs = r, host, keep, x_out, refs
+        self.timing = timing
+
+
+def lslu_wait(ctx, pending):
+    """Completes the context's pending solve; returns ``(status, x_out, info)``."""
+    st = _check(ctx, lib.lslu_wait(ctx))
+    return st, pending.x_out, _info(st, pending.r, pending.host, pending.timing)
+
+
+def _info(st, r, host, timing):
     info = dict(status=st, k_done=r.k_done, k_stop=r.k_stop, n_l=r.n_l, n_d=r.n_d,
                 beta=r.beta, piv_t_mismatch=r.piv_t_mismatch,
                 piv_g_mismatch=r.piv_g_mismatch)
@@ -335,7 +361,7 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
                               n_recurrence_launches=r.n_recurrence_launches,
                               t_projected_ms=r.t_projected_ms,
                               t_assemble_ms=r.t_assemble_ms)
-    return st, x_out, info
+    return info
 
 
 def lslu_get_basis(ctx, which, count, dst):

@@ -139,13 +139,22 @@ struct lslu_ctx {
   // basis vectors formed by the last solve
   int last_nl = 0, last_nd = 0;
   // captured solve (replayed while the key matches)
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  std::vector<double> gkey;
+  // captured solves, replayed while the key (pointers, sizes, options)
+  // matches; the least recently captured is dropped beyond kGraphCache
+  struct Captured {
+    std::vector<double> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<Captured> graphs;
   // last uploaded lambda grid and replay arrays (skipped when unchanged)
   std::vector<double> up_grid;
   std::vector<int> up_rep;
   std::vector<int> up_samp;
+  // an LSLU_FLAG_ASYNC solve whose results lslu_wait has not collected yet
+  bool pending = false;
+  int pend_K = 0;
+  lslu_result* pend_res = nullptr;
 };
 
 struct lslu_op {
@@ -212,12 +221,18 @@ void free_op(DeviceOp& d) {
   d = DeviceOp{};
 }
 
+constexpr size_t kGraphCache = 64;
+
+void destroy_captured(lslu_ctx::Captured& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g.exec = nullptr;
+  g.graph = nullptr;
+}
+
 void drop_graph(lslu_ctx* c) {
-  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-  if (c->graph) (void)hipGraphDestroy(c->graph);
-  c->gexec = nullptr;
-  c->graph = nullptr;
-  c->gkey.clear();
+  for (auto& g : c->graphs) destroy_captured(g);
+  c->graphs.clear();
 }
 
 lslu_status ensure_ws(lslu_ctx* c, int64_t m, int64_t n, int K, size_t esz,
@@ -789,12 +804,72 @@ lslu_status lslu_op_destroy(lslu_op* op) {
   return LSLU_OK;
 }
 
+// Waits for the solve's stream and unpacks the result block copied to
+// pinned host memory (same layout as on the device) into res.
+static lslu_status complete_solve(lslu_ctx* c, int K, lslu_result* res,
+                                  const PhaseEvents* pe_in) {
+  const hipStream_t s = c->stream;
+  const Layout& l = c->lay;
+  LSLU_HIP(c, hipStreamSynchronize(s));
+  PhaseEvents none;
+  const PhaseEvents& pe = pe_in ? *pe_in : none;
+    // Unpack the result block (same layout as on the device).
+    auto hp = [&](const void* dev) {
+      return c->host + (static_cast<const unsigned char*>(dev) - l.res);
+    };
+    const DevState* st = reinterpret_cast<const DevState*>(hp(l.st));
+    const int* sel = reinterpret_cast<const int*>(hp(l.sel));
+    c->last_nl = st->n_l;
+    c->last_nd = st->n_d;
+    if (st->spin_timeouts != 0)
+      return fail(c, LSLU_EDEVICE, "a wait inside the recurrence ran out (device fault)");
+    float t_rec = 0.f, t_proj = 0.f, t_asm = 0.f;
+    if (pe.on) {
+      LSLU_HIP(c, hipEventElapsedTime(&t_rec, pe.ev[0], pe.ev[1]));
+      LSLU_HIP(c, hipEventElapsedTime(&t_proj, pe.ev[1], pe.ev[2]));
+      LSLU_HIP(c, hipEventElapsedTime(&t_asm, pe.ev[2], pe.ev[3]));
+    }
+    const lslu_status status = static_cast<lslu_status>(st->status);
+    if (res) {
+      res->status = status;
+      res->k_done = st->k_done;
+      res->k_stop = sel[0];
+      res->n_l = st->n_l;
+      res->n_d = st->n_d;
+      res->beta = st->beta;
+      res->piv_t_mismatch = st->mismatch_t;
+      res->piv_g_mismatch = st->mismatch_g;
+      copy_out(res->piv_t, reinterpret_cast<const int32_t*>(hp(l.piv_t)), K + 1);
+      copy_out(res->piv_g, reinterpret_cast<const int32_t*>(hp(l.piv_g)), K);
+      copy_out(res->own_piv_t, reinterpret_cast<const int32_t*>(hp(l.own_t)), K + 1);
+      copy_out(res->own_piv_g, reinterpret_cast<const int32_t*>(hp(l.own_g)), K);
+      copy_out(res->H, reinterpret_cast<const double*>(hp(l.H)), (size_t)(K + 1) * K);
+      copy_out(res->W, reinterpret_cast<const double*>(hp(l.W)), (size_t)K * K);
+      copy_out(res->Y, reinterpret_cast<const double*>(hp(l.Y)), (size_t)K * K);
+      copy_out(res->lambda_k, reinterpret_cast<const double*>(hp(l.lam)), K);
+      copy_out(res->lambda_idx, reinterpret_cast<const int32_t*>(hp(l.lam_idx)), K);
+      copy_out(res->ghat, reinterpret_cast<const double*>(hp(l.ghat)), K);
+      copy_out(res->sep_lambda, reinterpret_cast<const double*>(hp(l.sep)), K);
+      copy_out(res->sigma_max, reinterpret_cast<const double*>(hp(l.smax)), K);
+      copy_out(res->sigma_min, reinterpret_cast<const double*>(hp(l.smin)), K);
+      res->t_recurrence_ms = t_rec;
+      res->n_recurrence_launches = pe.on ? pe.launches : 0;
+      res->t_projected_ms = t_proj;
+      res->t_assemble_ms = t_asm;
+    }
+    return status;
+}
+
 lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
                        const void* x0, const lslu_opts* o, void* x_out,
                        lslu_result* res) {
   if (!c) return LSLU_EINVAL;
   if (!op || !b || !o || !x_out) return fail(c, LSLU_EINVAL, "NULL argument");
   if (op->ctx != c) return fail(c, LSLU_EINVAL, "operator belongs to another context");
+  if (c->pending)
+    return fail(c, LSLU_EINVAL, "an asynchronous solve is pending on this context (lslu_wait)");
+  if ((o->flags & LSLU_FLAG_ASYNC) && (o->flags & LSLU_FLAG_TIMING))
+    return fail(c, LSLU_EINVAL, "LSLU_FLAG_TIMING needs a synchronous solve");
   try {
     lslu_status vs = validate_opts(c, op, o);
     if (vs != LSLU_OK) return vs;
@@ -893,72 +968,57 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
           (double)K, (double)o->reg, o->lambda, (double)o->n_grid,
           (double)o->grid_relative, o->omega, o->stop_tol, (double)o->early_stop,
           (double)rt, (double)rg, (double)rl, (double)(uintptr_t)o->x_true_dev,
-          (double)(o->sample_rows != nullptr), (double)o->sample_s};
-      if (!c->gexec || key != c->gkey) {
-        drop_graph(c);
+          (double)(o->sample_rows != nullptr), (double)o->sample_s, (double)o->sample_len};
+      hipGraphExec_t exec = nullptr;
+      for (auto& g : c->graphs)
+        if (g.key == key) exec = g.exec;
+      if (!exec) {
+        if (c->graphs.size() >= kGraphCache) {
+          destroy_captured(c->graphs.front());
+          c->graphs.erase(c->graphs.begin());
+        }
         LSLU_HIP(c, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
         enqueue();
-        hipGraph_t g = nullptr;
-        const hipError_t ce = hipStreamEndCapture(s, &g);
-        if (ce != hipSuccess || !g)
+        lslu_ctx::Captured cap;
+        cap.key = key;
+        const hipError_t ce = hipStreamEndCapture(s, &cap.graph);
+        if (ce != hipSuccess || !cap.graph)
           return fail(c, LSLU_EDEVICE, std::string("graph capture failed: ") +
                                            hipGetErrorString(ce));
-        c->graph = g;
-        LSLU_HIP(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
-        c->gkey = key;
+        const hipError_t ie = hipGraphInstantiate(&cap.exec, cap.graph, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+          destroy_captured(cap);
+          return fail(c, LSLU_EDEVICE, std::string("graph instantiation failed: ") +
+                                           hipGetErrorString(ie));
+        }
+        exec = cap.exec;
+        c->graphs.push_back(std::move(cap));
       }
-      LSLU_HIP(c, hipGraphLaunch(c->gexec, s));
+      LSLU_HIP(c, hipGraphLaunch(exec, s));
     }
     LSLU_HIP(c, hipGetLastError());
     LSLU_HIP(c, hipMemcpyAsync(c->host, l.res, l.res_bytes, hipMemcpyDeviceToHost, s));
-    LSLU_HIP(c, hipStreamSynchronize(s));
-    // Unpack the result block (same layout as on the device).
-    auto hp = [&](const void* dev) {
-      return c->host + (static_cast<const unsigned char*>(dev) - l.res);
-    };
-    const DevState* st = reinterpret_cast<const DevState*>(hp(l.st));
-    const int* sel = reinterpret_cast<const int*>(hp(l.sel));
-    c->last_nl = st->n_l;
-    c->last_nd = st->n_d;
-    if (st->spin_timeouts != 0)
-      return fail(c, LSLU_EDEVICE, "a wait inside the recurrence ran out (device fault)");
-    float t_rec = 0.f, t_proj = 0.f, t_asm = 0.f;
-    if (pe.on) {
-      LSLU_HIP(c, hipEventElapsedTime(&t_rec, pe.ev[0], pe.ev[1]));
-      LSLU_HIP(c, hipEventElapsedTime(&t_proj, pe.ev[1], pe.ev[2]));
-      LSLU_HIP(c, hipEventElapsedTime(&t_asm, pe.ev[2], pe.ev[3]));
+    if (o->flags & LSLU_FLAG_ASYNC) {
+      c->pending = true;
+      c->pend_K = K;
+      c->pend_res = res;
+      return LSLU_OK;
     }
-    const lslu_status status = static_cast<lslu_status>(st->status);
-    if (res) {
-      res->status = status;
-      res->k_done = st->k_done;
-      res->k_stop = sel[0];
-      res->n_l = st->n_l;
-      res->n_d = st->n_d;
-      res->beta = st->beta;
-      res->piv_t_mismatch = st->mismatch_t;
-      res->piv_g_mismatch = st->mismatch_g;
-      copy_out(res->piv_t, reinterpret_cast<const int32_t*>(hp(l.piv_t)), K + 1);
-      copy_out(res->piv_g, reinterpret_cast<const int32_t*>(hp(l.piv_g)), K);
-      copy_out(res->own_piv_t, reinterpret_cast<const int32_t*>(hp(l.own_t)), K + 1);
-      copy_out(res->own_piv_g, reinterpret_cast<const int32_t*>(hp(l.own_g)), K);
-      copy_out(res->H, reinterpret_cast<const double*>(hp(l.H)), (size_t)(K + 1) * K);
-      copy_out(res->W, reinterpret_cast<const double*>(hp(l.W)), (size_t)K * K);
-      copy_out(res->Y, reinterpret_cast<const double*>(hp(l.Y)), (size_t)K * K);
-      copy_out(res->lambda_k, reinterpret_cast<const double*>(hp(l.lam)), K);
-      copy_out(res->lambda_idx, reinterpret_cast<const int32_t*>(hp(l.lam_idx)), K);
-      copy_out(res->ghat, reinterpret_cast<const double*>(hp(l.ghat)), K);
-      copy_out(res->sep_lambda, reinterpret_cast<const double*>(hp(l.sep)), K);
-      copy_out(res->sigma_max, reinterpret_cast<const double*>(hp(l.smax)), K);
-      copy_out(res->sigma_min, reinterpret_cast<const double*>(hp(l.smin)), K);
-      res->t_recurrence_ms = t_rec;
-      res->n_recurrence_launches = pe.on ? pe.launches : 0;
-      res->t_projected_ms = t_proj;
-      res->t_assemble_ms = t_asm;
-    }
-    return status;
+    return complete_solve(c, K, res, &pe);
   } catch (const std::bad_alloc&) {
     return fail(c, LSLU_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(c, LSLU_EDEVICE, "unexpected exception");
+  }
+}
+
+lslu_status lslu_wait(lslu_ctx* c) {
+  if (!c) return LSLU_EINVAL;
+  if (!c->pending) return LSLU_OK;
+  try {
+    LSLU_HIP(c, hipSetDevice(c->device));
+    c->pending = false;
+    return complete_solve(c, c->pend_K, c->pend_res, nullptr);
   } catch (...) {
     return fail(c, LSLU_EDEVICE, "unexpected exception");
   }
@@ -967,6 +1027,8 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
 lslu_status lslu_get_basis(lslu_ctx* c, int32_t which, int32_t count, void* dst) {
   if (!c) return LSLU_EINVAL;
   if (!dst) return fail(c, LSLU_EINVAL, "NULL argument");
+  if (c->pending)
+    return fail(c, LSLU_EINVAL, "an asynchronous solve is pending on this context (lslu_wait)");
   const int have = which == 0 ? c->last_nl : c->last_nd;
   if (which < 0 || which > 1 || count < 0 || count > have)
     return fail(c, LSLU_EINVAL, "count exceeds the basis of the last solve");

@@ -21,4 +21,5 @@ from .problems import (  # noqa: F401
     CONFIGS,
     lambda_grid,
     pivot_sample_lists,
+    batch_problems,
 )

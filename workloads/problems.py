@@ -349,3 +349,23 @@ def pivot_sample_lists(m: int, n: int, K: int, s: int, seed: int = 0) -> np.ndar
         take = min(length, L)
         out[i, :take] = rng.choice(length, size=take, replace=False)
     return out
+
+
+def batch_problems(count: int, seed: int = 0) -> list:
+    """A set of uneven problems for batched solves: alternately a parallel-beam
+    tomography problem with side s ~ U{32..96} (s angles, s + 1 bins) and a
+    deblurring problem with side ~ U{64..256} and a Gaussian PSF with
+    sigma ~ U(1.5, 4) and half-width ceil(3 sigma).  Each problem has its own
+    seed."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        if i % 2 == 0:
+            side = int(rng.integers(32, 97))
+            out.append(tomography(side, side, side + 1, 0.02, seed=seed * 100003 + i))
+        else:
+            side = int(rng.integers(64, 257))
+            sigma = float(rng.uniform(1.5, 4.0))
+            out.append(psf_deblur(side, int(math.ceil(3 * sigma)), sigma, 0.01,
+                                  seed=seed * 100003 + i))
+    return out
