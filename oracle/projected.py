@@ -100,6 +100,28 @@ def tikhonov_coeffs(beta, s, c, V, lam):
     return beta * (V @ coef)
 
 
+def tikhonov_coeffs_dlambda(beta, s, c, V, lam):
+    """d y / d lambda of ``tikhonov_coeffs``:
+    ``-2 lambda beta sum_i sigma_i c_i / (sigma_i^2 + lambda^2)^2 v_i``, i.e.
+    ``-2 lambda (H^T H + lambda^2 I)^-1 y`` for the projected problem
+    (eq. TSP) written through the SVD of H (Section 3.2.1)."""
+    k = s.shape[0]
+    den = s * s + lam * lam
+    coef = np.zeros(k)
+    nz = den > 0
+    coef[nz] = -2.0 * lam * s[nz] * c[:k][nz] / (den[nz] * den[nz])
+    return beta * (V @ coef)
+
+
+def dloss_dlambda(beta, s, c, V, lam, Lk, x0, x_true):
+    """Derivative in lambda of the loss ``||x_0 + L_k y_lambda - x_true||^2``
+    (the quantity minimised over lambda in eq. lambda):
+    ``2 (x_k - x_true)^T L_k dy/dlambda``."""
+    y = tikhonov_coeffs(beta, s, c, V, lam)
+    r = x0 + Lk @ y - x_true
+    return float(2.0 * r @ (Lk @ tikhonov_coeffs_dlambda(beta, s, c, V, lam)))
+
+
 def _residual_part(s, c, lam):
     k = s.shape[0]
     f = _filter(s, lam)

@@ -572,3 +572,34 @@ def test_sampled_pivot_falls_back_to_full_search_on_a_zero_sample():
     r = hybrid_lslu(op, b, K, pivot_sample=(lists, s))
     full_t1 = int(np.argmax(np.abs(b)))
     assert r.piv_t[0] == full_t1 and abs(r.beta) == np.abs(b).max()
+
+
+# ---------------------------------------------------------------------------
+# d loss / d lambda of the projected Tikhonov solve (eq. TSP, eq. lambda)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("lam", [1e-3, 0.02, 0.3])
+def test_dloss_dlambda_against_central_differences(lam):
+    from oracle.projected import dloss_dlambda, tikhonov_coeffs_dlambda
+    prob = config_problem("dense256")
+    op = make_operator(prob)
+    r = hybrid_lslu(op, prob.b, 15)
+    x0 = np.zeros(prob.n)
+    for k in (3, 8, 15):
+        s, c, V = projected_svd(r.H[:k + 1, :k])
+        Lk = r.L[:, :k]
+
+        def loss(l):
+            y = tikhonov_coeffs(r.beta, s, c, V, l)
+            return float(np.sum((x0 + Lk @ y - prob.x_true) ** 2))
+
+        h = lam * 1e-4
+        fd = (loss(lam + h) - loss(lam - h)) / (2 * h)
+        g = dloss_dlambda(r.beta, s, c, V, lam, Lk, x0, prob.x_true)
+        assert abs(g - fd) <= 1e-6 * max(1.0, abs(fd)), (k, g, fd)
+        # dy/dlambda also from the normal equations, without the SVD
+        Hk = r.H[:k + 1, :k]
+        y = tikhonov_coeffs(r.beta, s, c, V, lam)
+        dy = -2 * lam * np.linalg.solve(Hk.T @ Hk + lam * lam * np.eye(k), y)
+        assert np.allclose(tikhonov_coeffs_dlambda(r.beta, s, c, V, lam), dy,
+                           rtol=1e-7, atol=1e-9 * np.abs(dy).max())
