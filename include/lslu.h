@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LSLU_ABI_VERSION 5
+#define LSLU_ABI_VERSION 6
 
 typedef enum lslu_status {
   LSLU_OK = 0,
@@ -160,8 +160,9 @@ typedef struct lslu_opts {
   int32_t grid_relative;      /* nonzero: grid values are multiplied by the
                                  largest singular value of H_{k+1,k} */
   double omega;               /* WGCV weight; <= 0 selects (k+1)/m */
-  const void* x_true_dev;     /* OPTIMAL (required, else LSLU_EINVAL): device,
-                                 wp, n entries; borrowed for the call */
+  const void* x_true_dev;     /* OPTIMAL and LSLU_FLAG_GRAD_LAMBDA (required,
+                                 else LSLU_EINVAL): device, wp, n entries;
+                                 borrowed for the call */
   double stop_tol;            /* tolerance of the stopping rule (eq. tol);
                                  <= 0 selects 1e-6 */
   int32_t early_stop;         /* nonzero: x_out is x_{k_stop} */
@@ -204,7 +205,17 @@ typedef enum lslu_flag {
    * context accepts no other solve.  Solves on several contexts (one stream
    * each) run concurrently: many small problems share the GPU.  Not with
    * LSLU_FLAG_TIMING. */
-  LSLU_FLAG_ASYNC = 4
+  LSLU_FLAG_ASYNC = 4,
+  /* Also return, for every k, the derivative in lambda of the squared error
+   * ||x_k(lambda) - x_true||^2 of the regularised projected solution of
+   * iteration k (Section 3.2.1, eq. TSP), taken at the lambda_k the rule
+   * chose: the gradient of the optimal-parameter loss (eq. lambda) that a
+   * learned or tuned parameter rule descends.  Needs x_true_dev (borrowed as
+   * for LSLU_REG_OPTIMAL) and lslu_result.dloss_dlambda; works with every
+   * rule.  0 where lambda_k = 0 (the derivative of the projected solution
+   * vanishes there).  FP64 throughout, from the Gram matrix of
+   * [L_k, x_true - x_0]. */
+  LSLU_FLAG_GRAD_LAMBDA = 8
 } lslu_flag;
 
 typedef struct lslu_result {
@@ -235,6 +246,9 @@ typedef struct lslu_result {
   int32_t n_recurrence_launches;
   double t_projected_ms;
   double t_assemble_ms;
+  /* maxiter: with LSLU_FLAG_GRAD_LAMBDA, d/dlambda ||x_k(lambda) - x_true||^2
+   * at lambda = lambda_k (NULL: not copied) */
+  double* dloss_dlambda;
 } lslu_result;
 
 /* Run Hybrid LSLU (LSLU with LSLU_REG_NONE) for opts->maxiter iterations.

@@ -72,6 +72,7 @@ class lslu_opts(ctypes.Structure):
 LSLU_FLAG_EAGER = 1
 LSLU_FLAG_TIMING = 2
 LSLU_FLAG_ASYNC = 4
+LSLU_FLAG_GRAD_LAMBDA = 8
 
 
 class lslu_result(ctypes.Structure):
@@ -101,6 +102,7 @@ class lslu_result(ctypes.Structure):
         ("n_recurrence_launches", c_int32),
         ("t_projected_ms", c_double),
         ("t_assemble_ms", c_double),
+        ("dloss_dlambda", POINTER(c_double)),
     ]
 
 
@@ -267,13 +269,15 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
                grid_relative=False, omega=0.0, x0=None, x_true=None,
                stop_tol=0.0, early_stop=False, X=None, x_out=None,
                replay_piv_t=None, replay_piv_g=None, replay_lambda_idx=None,
-               eager=False, timing=False, pivot_sample=None, asynchronous=False):
+               eager=False, timing=False, pivot_sample=None, asynchronous=False,
+               grad_lambda=False):
     """Run the solver.  ``b``, ``x0``, ``X``, ``x_out`` are torch device
     tensors in the working precision (``x_out`` is allocated when None).
     ``pivot_sample = (rows, s)`` selects sampled pivots: ``rows`` is the
     (2 maxiter + 1) x L int32 array of candidate rows per search.
     ``asynchronous=True`` enqueues the solve and returns a ``Pending``;
     ``lslu_wait(ctx, pending)`` completes it and returns the same triple.
+    ``grad_lambda=True`` (needs ``x_true``) adds ``info["dloss_dlambda"]``.
     Returns ``(status, x_out, info)`` where ``info`` holds the host-side
     results as NumPy arrays."""
     import torch
@@ -298,7 +302,8 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
     o.early_stop = 1 if early_stop else 0
     o.X_dev = _dptr(X)
     o.flags = ((LSLU_FLAG_EAGER if eager else 0) | (LSLU_FLAG_TIMING if timing else 0)
-               | (LSLU_FLAG_ASYNC if asynchronous else 0))
+               | (LSLU_FLAG_ASYNC if asynchronous else 0)
+               | (LSLU_FLAG_GRAD_LAMBDA if grad_lambda else 0))
     for name, arr in (("replay_piv_t", replay_piv_t), ("replay_piv_g", replay_piv_g),
                       ("replay_lambda_idx", replay_lambda_idx)):
         if arr is not None:
@@ -320,6 +325,8 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
         H=np.zeros((K, K + 1)), W=np.zeros((K, K)), Y=np.zeros((K, K)),
         lambda_k=np.zeros(K), lambda_idx=np.zeros(K, np.int32), ghat=np.zeros(K),
         sep_lambda=np.zeros(K), sigma_max=np.zeros(K), sigma_min=np.zeros(K))
+    if grad_lambda:
+        host["dloss_dlambda"] = np.zeros(K)
     for name, arr in host.items():
         ct = c_int32 if arr.dtype == np.int32 else c_double
         setattr(r, name, arr.ctypes.data_as(POINTER(ct)))
@@ -356,6 +363,8 @@ def _info(st, r, host, timing):
                 lambda_k=host["lambda_k"], lambda_idx=host["lambda_idx"],
                 ghat=host["ghat"], sep_lambda=host["sep_lambda"],
                 sigma_max=host["sigma_max"], sigma_min=host["sigma_min"])
+    if "dloss_dlambda" in host:
+        info["dloss_dlambda"] = host["dloss_dlambda"]
     if timing:
         info["timing"] = dict(t_recurrence_ms=r.t_recurrence_ms,
                               n_recurrence_launches=r.n_recurrence_launches,

@@ -238,7 +238,8 @@ struct ProjParams {
   double omega;    // <= 0: (k+1)/m
   const double* grid;         // device
   const int* replay_lambda;   // device or nullptr
-  const double* gram;  // OPTIMAL: (K+1) x (K+1) Gram matrix of [L, x_true - x_0]
+  const double* gram;  // OPTIMAL, gradient: (K+1) x (K+1) Gram matrix of [L, x_true - x_0]
+  double* dldl;        // nullptr, or K entries: d/dlambda ||x_k(lambda) - x_true||^2 at lambda_k
 };
 void launch_projected(const double* H, const DevState* st, double beta_unused,
                       const ProjParams& p, double* Y, double* lam,

@@ -41,7 +41,8 @@ struct Layout {
   unsigned char* res = nullptr;
   size_t res_bytes = 0;
   double *H = nullptr, *W = nullptr, *Y = nullptr, *lam = nullptr,
-         *ghat = nullptr, *sep = nullptr, *smax = nullptr, *smin = nullptr;
+         *ghat = nullptr, *sep = nullptr, *smax = nullptr, *smin = nullptr,
+         *dldl = nullptr;
   int *piv_t = nullptr, *piv_g = nullptr, *own_t = nullptr, *own_g = nullptr,
       *lam_idx = nullptr, *sel = nullptr;
   DevState* st = nullptr;
@@ -104,6 +105,7 @@ size_t carve(unsigned char* base, int64_t m, int64_t n, int K, size_t esz,
   l.sep = reinterpret_cast<double*>(take(sizeof(double) * K));
   l.smax = reinterpret_cast<double*>(take(sizeof(double) * K));
   l.smin = reinterpret_cast<double*>(take(sizeof(double) * K));
+  l.dldl = reinterpret_cast<double*>(take(sizeof(double) * K));
   l.piv_t = reinterpret_cast<int*>(take(sizeof(int) * (K + 1)));
   l.piv_g = reinterpret_cast<int*>(take(sizeof(int) * K));
   l.own_t = reinterpret_cast<int*>(take(sizeof(int) * (K + 1)));
@@ -450,11 +452,13 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
   pp.omega = o->omega;
   pp.grid = l.grid;
   pp.replay_lambda = replay_lam ? l.rep_lam : nullptr;
-  if (o->reg == LSLU_REG_OPTIMAL) {
+  const bool grad = (o->flags & LSLU_FLAG_GRAD_LAMBDA) != 0;
+  if (o->reg == LSLU_REG_OPTIMAL || grad) {
     launch_gram<T>(Lb, bs.rsL, bs.csL, n, K, static_cast<const T*>(o->x_true_dev), x0, st,
                    l.gram_part, l.gram, s);
     pp.gram = l.gram;
   }
+  pp.dldl = grad ? l.dldl : nullptr;
   launch_projected(l.H, st, 0.0, pp, l.Y, l.lam, l.lam_idx, l.ghat, l.sep,
                    l.smax, l.smin, l.proj, c->lds_max, s);
   pe->mark(2, s);
@@ -475,6 +479,8 @@ lslu_status validate_opts(lslu_ctx* c, const lslu_op* op, const lslu_opts* o) {
     return fail(c, LSLU_EINVAL, "unknown regularisation rule");
   if (o->reg == LSLU_REG_OPTIMAL && !o->x_true_dev)
     return fail(c, LSLU_EINVAL, "LSLU_REG_OPTIMAL needs x_true_dev");
+  if ((o->flags & LSLU_FLAG_GRAD_LAMBDA) && !o->x_true_dev)
+    return fail(c, LSLU_EINVAL, "LSLU_FLAG_GRAD_LAMBDA needs x_true_dev");
   if (o->reg == LSLU_REG_FIXED && !(std::isfinite(o->lambda) && o->lambda >= 0.0))
     return fail(c, LSLU_EINVAL, "lambda must be finite and >= 0");
   if (o->reg == LSLU_REG_WGCV || o->reg == LSLU_REG_GCV || o->reg == LSLU_REG_OPTIMAL) {
@@ -852,6 +858,7 @@ static lslu_status complete_solve(lslu_ctx* c, int K, lslu_result* res,
       copy_out(res->sep_lambda, reinterpret_cast<const double*>(hp(l.sep)), K);
       copy_out(res->sigma_max, reinterpret_cast<const double*>(hp(l.smax)), K);
       copy_out(res->sigma_min, reinterpret_cast<const double*>(hp(l.smin)), K);
+      copy_out(res->dloss_dlambda, reinterpret_cast<const double*>(hp(l.dldl)), K);
       res->t_recurrence_ms = t_rec;
       res->n_recurrence_launches = pe.on ? pe.launches : 0;
       res->t_projected_ms = t_proj;
@@ -968,7 +975,8 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
           (double)K, (double)o->reg, o->lambda, (double)o->n_grid,
           (double)o->grid_relative, o->omega, o->stop_tol, (double)o->early_stop,
           (double)rt, (double)rg, (double)rl, (double)(uintptr_t)o->x_true_dev,
-          (double)(o->sample_rows != nullptr), (double)o->sample_s, (double)o->sample_len};
+          (double)(o->sample_rows != nullptr), (double)o->sample_s, (double)o->sample_len,
+          (double)(o->flags & LSLU_FLAG_GRAD_LAMBDA)};
       hipGraphExec_t exec = nullptr;
       for (auto& g : c->graphs)
         if (g.key == key) exec = g.exec;

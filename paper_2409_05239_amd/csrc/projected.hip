@@ -444,12 +444,52 @@ __global__ __launch_bounds__(kPT) void k_projected(
     lam_out[k - 1] = lam;
     lam_idx_out[k - 1] = s_lidx;
     sep_out[k - 1] = s_sep;
+    if (p.dldl) {
+      // dy/dlambda = -2 lambda (H^T H + lambda^2 I)^-1 y = -2 lambda Q w with
+      // R^T R w = z: B^T B + lambda^2 I = R^T R for Elden's factor R (upper
+      // bidiagonal: diagonal rho, superdiagonal ff); w overwrites qq.
+      double* w = qq;
+      if (lam == 0.0) {
+        for (int i = 0; i < k; ++i) w[i] = 0.0;
+      } else {
+        for (int i = 0; i < k; ++i)  // R^T t = z
+          w[i] = (zy[i] - (i > 0 ? ff[i - 1] * w[i - 1] : 0.0)) / rho[i];
+        for (int i = k - 1; i >= 0; --i)  // R w = t
+          w[i] = (w[i] - (i + 1 < k ? ff[i] * w[i + 1] : 0.0)) / rho[i];
+        for (int i = 0; i < k; ++i) w[i] *= -2.0 * lam;
+      }
+    }
   }
   __syncthreads();
-  if (wv == 0) apply_q(A, lda, taur, k, zy, lane);
+  double* dy = lamscr + 2 * K;  // -2 lambda Q w, when asked for
+  if (wv == 0) {
+    apply_q(A, lda, taur, k, zy, lane);
+    if (p.dldl) apply_q(A, lda, taur, k, dy, lane);
+  }
   __syncthreads();
   for (int r = tid; r < K; r += kPT)
     Y[(size_t)(k - 1) * K + r] = (r < k) ? zy[r] : 0.0;
+  if (p.dldl) {
+    // d/dlambda ||x_0 + L_k y - x_true||^2 = 2 (y^T G dy - h^T dy), G and h
+    // the leading blocks of the Gram matrix of [L, x_true - x_0]
+    const int ldg = K + 1;
+    double part = 0.0;
+    for (int i = tid; i < k; i += kPT) {
+      const double* Gi = p.gram + (size_t)i * ldg;
+      double t = 0.0;
+      for (int j = 0; j < k; ++j) t = fma(Gi[j], dy[j], t);
+      part = fma(zy[i], t, part);
+      part = fma(-Gi[K], dy[i], part);
+    }
+    part = wave_sum_d(part);
+    if (lane == 0) gv[wv] = part;
+    __syncthreads();
+    if (tid == 0) {
+      double tot = 0.0;
+      for (int i = 0; i < kPT / kWave; ++i) tot += gv[i];
+      p.dldl[k - 1] = 2.0 * tot;
+    }
+  }
 }
 
 }  // namespace

@@ -17,7 +17,7 @@ def torch_dtype(prec):
 def gpu_solve(capi, ctx, prob, prec="fp64", K=10, reg="none", lam=0.0,
               grid=None, grid_relative=False, replay=None, x0=None,
               early_stop=False, stop_tol=0.0, bases=True, op=None, eager=False,
-              b=None, x_true=None, pivot_sample=None):
+              b=None, x_true=None, pivot_sample=None, grad_lambda=False):
     """Solve on the GPU; returns the info dict with x, X (n x K), L, D."""
     import torch
     dt = torch_dtype(prec)
@@ -39,7 +39,8 @@ def gpu_solve(capi, ctx, prob, prec="fp64", K=10, reg="none", lam=0.0,
                                       grid_relative=grid_relative, X=X, x0=x0t,
                                       early_stop=early_stop, stop_tol=stop_tol,
                                       eager=eager, x_true=xtt,
-                                      pivot_sample=pivot_sample, **kw)
+                                      pivot_sample=pivot_sample,
+                                      grad_lambda=grad_lambda, **kw)
         torch.cuda.synchronize()
         info["x"] = x.double().cpu().numpy()
         info["X"] = X.double().cpu().numpy().T.copy()
