@@ -116,7 +116,7 @@ def run(args):
                   args.pivot_sample)
 
     def solve(op, b, X, x, timing=False):
-        return capi.lslu_solve(ctx, op, b, K, reg=cfg["reg"], grid=grid,
+        return capi.lslu_solve(ctx, op, b, K, reg=cfg["reg"], lam=cfg.get("lam", 0.0), grid=grid,
                                grid_relative=cfg["grid_relative"], X=X, x_out=x,
                                timing=timing, pivot_sample=sample)
 
@@ -238,6 +238,137 @@ def cpu_baseline(prob, cfg, grid, iters):
                       f"median of 3 runs of {el:.2f} s (FP64 NumPy/SciPy, one thread)"}
 
 
+def vjp_bytes(m, n, K, esz):
+    """Algorithmic HBM bytes of one reverse pass (lslu_vjp at k = K) with
+    every basis vector formed: each array the pass needs is read (or written)
+    once per kernel that needs it.  Per iteration kk (K down to 1):
+    d-side: dots of dbar_{kk+1} (+ the l-side product) with d_1..d_{kk+1},
+    the update that writes the product input and updates dbar_1..dbar_kk
+    (read and write), and the product with A^T; l-side: the same with n, kk
+    columns, kk-1 updated columns and the product with A.  Start: the dots
+    and update of d_1.  Set-up: clearing Dbar, Lbar = xbar y^T and
+    ybar = L^T xbar."""
+    tot = (K + 1) * m + (K + 1) * n + (K + 1) * n
+    for kk in range(K, 0, -1):
+        v2 = 1 if kk < K else 0
+        tot += (kk + 1) * m + (1 + v2) * m               # d-side dots
+        tot += (1 + v2) * m + m + 2 * kk * m             # d-side update
+        tot += m + n                                     # A^T product
+        tot += kk * n + 2 * n                            # l-side dots
+        tot += 2 * n + n + 2 * (kk - 1) * n              # l-side update
+        tot += n + m                                     # A product
+    tot += m + 2 * m + 2 * m + m                         # start
+    return tot * esz
+
+
+def run_vjp(args):
+    """Forward solve + reverse pass (lslu_vjp) of the differentiable workload:
+    512 x 512 deblurring, 15 x 15 PSF, 40 iterations, fixed lambda = 0.01,
+    loss ||x_K - x_true||^2.  value = iterations per second of forward plus
+    reverse; the forward and reverse times are also reported apart."""
+    import numpy as np
+    import torch
+
+    from paper_2409_05239_amd import capi
+    from workloads import CONFIGS
+
+    cfg = CONFIGS["deblur512"]
+    prob = cfg["make"]()
+    K, lam = cfg["iters"], cfg["lam"]
+    prec = args.precision or cfg["precision"]
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(device=dev)
+    ctx = capi.lslu_create(0, stream=stream)
+    op = capi.make_operator(ctx, prob, capi.PRECISIONS[prec])
+    with torch.cuda.stream(stream):
+        b = torch.tensor(prob.b, dtype=dt, device=dev)
+        xt = torch.tensor(prob.x_true, dtype=dt, device=dev)
+        x = torch.zeros(prob.n, dtype=dt, device=dev)
+        xbar = torch.zeros(prob.n, dtype=dt, device=dev)
+        bbar = torch.zeros(prob.m, dtype=dt, device=dev)
+    torch.cuda.synchronize()
+
+    def forward():
+        st, _, info = capi.lslu_solve(ctx, op, b, K, reg="fixed", lam=lam, x_out=x)
+        with torch.cuda.stream(stream):
+            torch.sub(x, xt, out=xbar)
+            xbar.mul_(2.0)
+        return info
+
+    def reverse(k):
+        return capi.lslu_vjp(ctx, op, k, xbar, bbar)
+
+    for _ in range(args.warmup):
+        info = forward()
+        reverse(info["k_done"])
+    torch.cuda.synchronize()
+    t_f = t_r = 0.0
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        info = forward()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, lam_bar = reverse(info["k_done"])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        t_f += t1 - t0
+        t_r += t2 - t1
+    t_f /= args.steps
+    t_r /= args.steps
+    k = info["k_done"]
+    esz = 8 if prec == "fp64" else 4
+    rb = vjp_bytes(prob.m, prob.n, k, esz)
+    loss = float(((x - xt) ** 2).sum())
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import make_operator
+        from oracle.gradient import vjp_directional
+        oop = make_operator(prob)
+        pt = list(info["piv_t"][:k + 1])
+        pg = list(info["piv_g"][:k])
+        xb = xbar.double().cpu().numpy()
+        v = np.random.default_rng(0).standard_normal(prob.m)
+        c0 = time.perf_counter()
+        vjp_directional(oop, prob.b, k, lam, pt, pg, xb, v)
+        el = time.perf_counter() - c0
+        cpu = {"value": round(1.0 / el, 4), "unit": "directional derivatives/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"one complex-step directional derivative of the same loss "
+                         f"({el:.1f} s, FP64 NumPy/SciPy); the whole gradient needs "
+                         f"m = {prob.m} of them"}
+    capi.lslu_op_destroy(op)
+    capi.lslu_destroy(ctx)
+    out = {
+        "metric": "Differentiable Hybrid LSLU: forward + reverse iterations/s",
+        "value": round(k / (t_f + t_r), 1),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round((t_f + t_r) * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "deblur512: 512x512 image, 15x15 Gaussian PSF (sigma 2), "
+                               "40 iterations, fixed lambda 0.01, loss ||x_K - x_true||^2",
+                   "precision": prec},
+        "forward_ms": round(t_f * 1e3, 4),
+        "reverse_ms": round(t_r * 1e3, 4),
+        "reverse_roofline": {"bound": "hbm", "achieved": round(rb / t_r / 1e9, 1),
+                             "peak": 8000.0, "unit": "GB/s",
+                             "frac": round(rb / t_r / 1e9 / 8000.0, 4),
+                             "bytes": rb, "traffic": None},
+        "loss": loss,
+        "lambda_bar": lam_bar,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_batch(args):
     """Many uneven problems (workloads.batch_problems: tomography and deblurring
     of different sizes), BF16 operator with FP32 bases, 60 iterations each:
@@ -355,6 +486,9 @@ def main():
                     help="batched mode: contexts (streams) solving concurrently")
     ap.add_argument("--pivot-sample", type=int, default=0,
                     help="sampled pivots: sample size per search (0: full searches)")
+    ap.add_argument("--vjp", action="store_true",
+                    help="time forward + reverse pass of the differentiable "
+                         "deblurring workload (512x512, 15x15 PSF, 40 iterations)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (counter scaling)")
     args = ap.parse_args()
@@ -363,7 +497,9 @@ def main():
               "library has no multi-GPU path (how it would shard is described "
               "with the design)", file=sys.stderr)
         sys.exit(2)
-    if args.batch > 0:
+    if args.vjp:
+        run_vjp(args)
+    elif args.batch > 0:
         run_batch(args)
     else:
         run(args)

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LSLU_ABI_VERSION 6
+#define LSLU_ABI_VERSION 7
 
 typedef enum lslu_status {
   LSLU_OK = 0,
@@ -271,6 +271,26 @@ lslu_status lslu_solve(lslu_ctx* ctx, const lslu_op* op, const void* b_dev,
  * stream, fills the lslu_result given to lslu_solve and returns the solve's
  * status (as lslu_solve would have).  LSLU_OK when nothing is pending. */
 lslu_status lslu_wait(lslu_ctx* ctx);
+
+/* Reverse pass (vector-Jacobian product) of the context's last completed
+ * solve, which must have used `op`:
+ *     bbar_dev   <- (d x_k / d b)^T xbar      (m entries, wp, device, written)
+ *     *lambda_bar = xbar^T (d x_k / d lambda)  (host, NULL: not returned)
+ * for 1 <= k <= k_done, with the pivots t(.), g(.) of that solve, x_0 and
+ * lambda_k held fixed (Algorithm 5 with fixed pivots is a smooth map of b;
+ * the projected problem is the Tikhonov problem of eq. TSP, Section 3.2.1).
+ * With the loss ||x_k - x_true||^2, xbar = 2 (x_k - x_true) gives its
+ * gradient in b and lambda.  xbar_dev: n entries, wp, device, borrowed.  The
+ * pass reads the bases and small arrays the solve left on the device (no
+ * recomputation), so no other solve may run on the context in between; it
+ * allocates its scratch (about (m + n) (K + 3) wp values plus
+ * O(K^2) doubles) on the first call and keeps it with the context.  Returns
+ * after the device work finished.
+ * Errors: LSLU_EINVAL (no such solve, k out of range, a pending solve, or
+ * H_k^T H_k + lambda_k^2 I singular: lambda_k = 0 with a rank-deficient
+ * H_k), LSLU_ENOMEM, LSLU_EDEVICE. */
+lslu_status lslu_vjp(lslu_ctx* ctx, const lslu_op* op, int32_t k,
+                     const void* xbar_dev, void* bbar_dev, double* lambda_bar);
 
 /* Copy basis vectors of the last solve on ctx into a device buffer (wp,
  * column-major, leading dimension = vector length): which = 0 copies the

@@ -42,7 +42,7 @@ EXPORTS = (
     "lslu_create", "lslu_destroy", "lslu_last_error", "lslu_status_name",
     "lslu_abi_version", "lslu_op_dense", "lslu_op_csr", "lslu_op_psf",
     "lslu_op_apply", "lslu_op_info", "lslu_op_destroy", "lslu_solve",
-    "lslu_wait", "lslu_get_basis",
+    "lslu_wait", "lslu_get_basis", "lslu_vjp",
 )
 
 
@@ -142,6 +142,7 @@ def _load():
                                POINTER(lslu_result)]),
         "lslu_get_basis": (c_int, [vp, c_int32, c_int32, vp]),
         "lslu_wait": (c_int, [vp]),
+        "lslu_vjp": (c_int, [vp, vp, c_int32, vp, vp, POINTER(c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -330,6 +331,7 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
     for name, arr in host.items():
         ct = c_int32 if arr.dtype == np.int32 else c_double
         setattr(r, name, arr.ctypes.data_as(POINTER(ct)))
+    _SERIAL[ctx.value] = _SERIAL.get(ctx.value, 0) + 1  # any solve replaces the last
     st = _check(ctx, lib.lslu_solve(ctx, op, _dptr(b), _dptr(x0), ctypes.byref(o),
                                     _dptr(x_out), ctypes.byref(r)))
     if asynchronous:
@@ -371,6 +373,29 @@ def _info(st, r, host, timing):
                               t_projected_ms=r.t_projected_ms,
                               t_assemble_ms=r.t_assemble_ms)
     return info
+
+
+_SERIAL = {}
+
+
+def solve_serial(ctx):
+    """Number of solves started on ``ctx`` through this binding (lslu_vjp
+    differentiates the last one)."""
+    return _SERIAL.get(ctx.value, 0)
+
+
+def lslu_vjp(ctx, op, k, xbar, bbar=None):
+    """Reverse pass of the context's last completed solve (which used ``op``):
+    returns ``(bbar, lambda_bar)`` with ``bbar = (d x_k/d b)^T xbar`` (a device
+    tensor of m entries, allocated when None) and ``lambda_bar = xbar^T
+    d x_k/d lambda``, pivots, x_0 and lambda_k held fixed."""
+    import torch
+    m, n, prec = lslu_op_info(op)
+    if bbar is None:
+        bbar = torch.empty(m, dtype=_torch_dtype(prec), device=xbar.device)
+    lb = c_double(0.0)
+    _check(ctx, lib.lslu_vjp(ctx, op, int(k), _dptr(xbar), _dptr(bbar), ctypes.byref(lb)))
+    return bbar, lb.value
 
 
 def lslu_get_basis(ctx, which, count, dst):

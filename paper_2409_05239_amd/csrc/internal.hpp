@@ -273,4 +273,34 @@ void launch_select_x(const T* X, int64_t n, const T* x0, T* x_out,
 void launch_stopping(const double* ghat, const DevState* st, double tol,
                      int early, int* out, hipStream_t s);
 
+// Reverse pass of a finished solve (adjoint.hip): bbar = (d x_k/d b)^T xbar
+// and lambda_bar = xbar^T d x_k/d lambda with the pivots held fixed.  The
+// forward arrays are those of the solve (device, as it left them); the
+// adjoint arrays are scratch in the working precision (column-major, leading
+// dimensions ldl >= n and ldd >= m) and FP64.
+struct VjpArgs {
+  const DeviceOp* op;
+  int64_t m, n;
+  int K, k, n_d;
+  const void *L, *D;  // bases l_1..l_{n_l}, d_1..d_{n_d}
+  int64_t rsL, csL, rsD, csD;
+  const double *H, *W, *Y, *lam;  // (K+1) x K, K x K, K x K, K
+  const int *piv_t, *piv_g;
+  const DevState* st;
+  const void* xbar;  // n entries
+  void* bbar;        // m entries (out)
+  void *Lbar, *Dbar;  // n x K (ldl), m x (K+1) (ldd)
+  int64_t ldl, ldd;
+  void *um, *un, *pm, *pn;  // m, n, m, n entries
+  double* part;   // adjoint_part_doubles(K)
+  double* M;      // K x K
+  double* Hbar;   // (K+1) x K, leading dimension K+1
+  double* corr;   // K+2
+  double* scal;   // 4: betabar, lambda_bar, 1/pivot
+  int* fail;      // 1 when H^T H + lambda^2 I is not positive definite
+};
+size_t adjoint_part_doubles(int K);
+template <typename T>
+int run_vjp(const VjpArgs& a, hipStream_t s);
+
 }  // namespace lslu

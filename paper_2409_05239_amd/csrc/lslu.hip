@@ -140,6 +140,14 @@ struct lslu_ctx {
   size_t esz = 0;
   // basis vectors formed by the last solve
   int last_nl = 0, last_nd = 0;
+  // the last completed solve (what lslu_vjp differentiates)
+  const lslu_op* last_op = nullptr;
+  int last_kdone = 0;
+  bool last_ok = false;
+  // reverse-pass scratch (grown on demand) and a pinned word block
+  unsigned char* adj = nullptr;
+  size_t adj_bytes = 0;
+  double* adj_host = nullptr;
   // captured solve (replayed while the key matches)
   // captured solves, replayed while the key (pointers, sizes, options)
   // matches; the least recently captured is dropped beyond kGraphCache
@@ -609,7 +617,9 @@ lslu_status lslu_destroy(lslu_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   drop_graph(c);
   if (c->ws) (void)hipFree(c->ws);
+  if (c->adj) (void)hipFree(c->adj);
   if (c->host) (void)hipHostFree(c->host);
+  if (c->adj_host) (void)hipHostFree(c->adj_host);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return LSLU_OK;
@@ -804,6 +814,10 @@ lslu_status lslu_op_destroy(lslu_op* op) {
   if (op->ctx) {
     (void)hipSetDevice(op->ctx->device);
     if (op->ctx->stream) (void)hipStreamSynchronize(op->ctx->stream);
+    if (op->ctx->last_op == op) {
+      op->ctx->last_op = nullptr;
+      op->ctx->last_ok = false;
+    }
   }
   free_op(op->d);
   delete op;
@@ -829,6 +843,8 @@ static lslu_status complete_solve(lslu_ctx* c, int K, lslu_result* res,
     c->last_nd = st->n_d;
     if (st->spin_timeouts != 0)
       return fail(c, LSLU_EDEVICE, "a wait inside the recurrence ran out (device fault)");
+    c->last_kdone = st->k_done;
+    c->last_ok = st->status >= 0;
     float t_rec = 0.f, t_proj = 0.f, t_asm = 0.f;
     if (pe.on) {
       LSLU_HIP(c, hipEventElapsedTime(&t_rec, pe.ev[0], pe.ev[1]));
@@ -880,6 +896,8 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
   try {
     lslu_status vs = validate_opts(c, op, o);
     if (vs != LSLU_OK) return vs;
+    c->last_ok = false;
+    c->last_op = op;
     LSLU_HIP(c, hipSetDevice(c->device));
     const int K = o->maxiter;
     const size_t esz = prec_size(op->d.prec);
@@ -1027,6 +1045,104 @@ lslu_status lslu_wait(lslu_ctx* c) {
     LSLU_HIP(c, hipSetDevice(c->device));
     c->pending = false;
     return complete_solve(c, c->pend_K, c->pend_res, nullptr);
+  } catch (...) {
+    return fail(c, LSLU_EDEVICE, "unexpected exception");
+  }
+}
+
+lslu_status lslu_vjp(lslu_ctx* c, const lslu_op* op, int32_t k, const void* xbar,
+                     void* bbar, double* lambda_bar) {
+  if (!c) return LSLU_EINVAL;
+  if (!op || !xbar || !bbar) return fail(c, LSLU_EINVAL, "NULL argument");
+  if (op->ctx != c) return fail(c, LSLU_EINVAL, "operator belongs to another context");
+  if (c->pending)
+    return fail(c, LSLU_EINVAL, "an asynchronous solve is pending on this context (lslu_wait)");
+  if (!c->last_ok || c->last_op != op)
+    return fail(c, LSLU_EINVAL, "no completed solve with this operator on the context");
+  if (k < 1 || k > c->last_kdone)
+    return fail(c, LSLU_EINVAL, "k must be in [1, k_done] of the last solve");
+  try {
+    LSLU_HIP(c, hipSetDevice(c->device));
+    const int K = c->K;
+    const int64_t m = c->m, n = c->n;
+    const size_t esz = c->esz;
+    const int64_t ldl = (int64_t)align_up((size_t)n, 64), ldd = (int64_t)align_up((size_t)m, 64);
+    // scratch: two passes, sizes then pointers
+    VjpArgs a{};
+    auto carve_adj = [&](unsigned char* base) {
+      size_t off = 0;
+      auto take = [&](size_t bytes) -> unsigned char* {
+        off = align_up(off, 256);
+        unsigned char* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+      };
+      a.Lbar = take(esz * ldl * K);
+      a.Dbar = take(esz * ldd * (K + 1));
+      a.um = take(esz * m);
+      a.un = take(esz * n);
+      a.pm = take(esz * m);
+      a.pn = take(esz * n);
+      a.part = reinterpret_cast<double*>(take(sizeof(double) * adjoint_part_doubles(K)));
+      a.M = reinterpret_cast<double*>(take(sizeof(double) * K * K));
+      a.Hbar = reinterpret_cast<double*>(take(sizeof(double) * (K + 1) * K));
+      a.corr = reinterpret_cast<double*>(take(sizeof(double) * (K + 2)));
+      a.scal = reinterpret_cast<double*>(take(sizeof(double) * 4));
+      a.fail = reinterpret_cast<int*>(take(sizeof(int)));
+      return align_up(off, 256);
+    };
+    const size_t need = carve_adj(nullptr);
+    if (need > c->adj_bytes) {
+      if (c->adj) LSLU_HIP(c, hipFree(c->adj));
+      c->adj = nullptr;
+      c->adj_bytes = 0;
+      LSLU_HIP(c, hipMalloc(&c->adj, need));
+      c->adj_bytes = need;
+    }
+    if (!c->adj_host) LSLU_HIP(c, hipHostMalloc(&c->adj_host, 64));
+    carve_adj(c->adj);
+    const Layout& l = c->lay;
+    a.op = &op->d;
+    a.m = m;
+    a.n = n;
+    a.K = K;
+    a.k = k;
+    a.n_d = c->last_nd;
+    a.L = l.L;
+    a.D = l.D;
+    a.rsL = c->bs.rsL;
+    a.csL = c->bs.csL;
+    a.rsD = c->bs.rsD;
+    a.csD = c->bs.csD;
+    a.H = l.H;
+    a.W = l.W;
+    a.Y = l.Y;
+    a.lam = l.lam;
+    a.piv_t = l.piv_t;
+    a.piv_g = l.piv_g;
+    a.st = l.st;
+    a.xbar = xbar;
+    a.bbar = bbar;
+    a.ldl = ldl;
+    a.ldd = ldd;
+    const hipStream_t s = c->stream;
+    if (esz == sizeof(double))
+      run_vjp<double>(a, s);
+    else
+      run_vjp<float>(a, s);
+    LSLU_HIP(c, hipGetLastError());
+    LSLU_HIP(c, hipMemcpyAsync(c->adj_host, a.scal, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+    LSLU_HIP(c, hipMemcpyAsync(c->adj_host + 2, a.fail, sizeof(int), hipMemcpyDeviceToHost, s));
+    LSLU_HIP(c, hipStreamSynchronize(s));
+    int bad = 0;
+    std::memcpy(&bad, c->adj_host + 2, sizeof(int));
+    if (bad)
+      return fail(c, LSLU_EINVAL,
+                  "H_k^T H_k + lambda_k^2 I is singular: the derivative is not defined");
+    if (lambda_bar) *lambda_bar = c->adj_host[1];
+    return LSLU_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(c, LSLU_ENOMEM, "host allocation failed");
   } catch (...) {
     return fail(c, LSLU_EDEVICE, "unexpected exception");
   }

@@ -1,0 +1,257 @@
+"""The reverse pass (lslu_vjp) and its autograd binding against the oracle's
+complex-step derivatives (oracle/gradient.py), taken with the GPU solve's own
+pivots: bbar = (d x_k/d b)^T xbar and lambda_bar = xbar^T d x_k/d lambda.
+
+Element by element at sizes where the oracle forms the whole gradient (one
+complex step per entry of b), by random directions at larger sizes, and at
+the deblurring size of the differentiable workload (512 x 512 image, 15 x 15
+PSF, 40 iterations, FP32, fixed lambda = 0.01) by directions and by central
+differences of the library's own FP64 iterates.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import make_operator
+from oracle.gradient import vjp_directional, vjp_full, vjp_lambda
+from workloads import config_problem, psf_deblur, random_dense, tomography
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    c = lib.lslu_create(0)
+    yield c
+    lib.lslu_destroy(c)
+
+
+def _dt(prec):
+    import torch
+    return torch.float64 if prec == "fp64" else torch.float32
+
+
+def _solve(lib, ctx, op, prob, prec, K, reg="fixed", lam=0.05):
+    import torch
+    b = torch.tensor(prob.b, dtype=_dt(prec), device="cuda")
+    X = torch.zeros((K, prob.n), dtype=_dt(prec), device="cuda")
+    st, x, info = lib.lslu_solve(ctx, op, b, K, reg=reg, lam=lam, X=X)
+    torch.cuda.synchronize()
+    info["X"] = X.double().cpu().numpy().T.copy()
+    return info
+
+
+def _pivots(info):
+    return (list(info["piv_t"][:info["k_done"] + 1]), list(info["piv_g"][:info["k_done"]]))
+
+
+def _vjp(lib, ctx, op, k, xbar, prec):
+    import torch
+    xb = torch.tensor(xbar, dtype=_dt(prec), device="cuda")
+    bbar, lb = lib.lslu_vjp(ctx, op, k, xb)
+    torch.cuda.synchronize()
+    return bbar.double().cpu().numpy(), lb
+
+
+def _small():
+    return [random_dense(40, 30, seed=3, nu=0.01), random_dense(25, 35, seed=4, nu=0.01),
+            tomography(16, 12, 23, 0.02, seed=5), psf_deblur(12, 3, 1.5, 0.01, seed=6)]
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_vjp_elementwise_fp64(lib, ctx, idx):
+    prob = _small()[idx]
+    K, lam = 10, 0.05
+    op = lib.make_operator(ctx, prob, lib.PRECISIONS["fp64"])
+    try:
+        print(f"[vjp] {prob.name} fp64 K={K}", flush=True)
+        info = _solve(lib, ctx, op, prob, "fp64", K, lam=lam)
+        pt, pg = _pivots(info)
+        oop = make_operator(prob)
+        rng = np.random.default_rng(idx)
+        for k in sorted({1, 4, info["k_done"]}):
+            xbar = rng.standard_normal(prob.n)
+            g, lb = _vjp(lib, ctx, op, k, xbar, "fp64")
+            ref = vjp_full(oop, prob.b, k, lam, pt, pg, xbar)
+            err = np.abs(g - ref).max() / np.abs(ref).max()
+            assert err <= 1e-9, (k, err)
+            lref = vjp_lambda(oop, prob.b, k, lam, pt, pg, xbar)
+            assert abs(lb - lref) <= 1e-9 * max(abs(lref), 1e-300), (k, lb, lref)
+    finally:
+        lib.lslu_op_destroy(op)
+
+
+@pytest.mark.parametrize("seed", [5, 7])
+def test_vjp_full_dimension_is_inverse_transpose(lib, ctx, seed):
+    """Square nonsingular A, lambda = 0, k = n: x_n = A^{-1} b, so the reverse
+    pass must give A^{-T} xbar (the d-side ends without a new vector)."""
+    prob = random_dense(12, 12, seed=seed)
+    op = lib.make_operator(ctx, prob, lib.PRECISIONS["fp64"])
+    try:
+        info = _solve(lib, ctx, op, prob, "fp64", 12, reg="none")
+        assert info["k_done"] == 12 and info["n_d"] == 12
+        xbar = np.random.default_rng(seed).standard_normal(12)
+        g, lb = _vjp(lib, ctx, op, 12, xbar, "fp64")
+        ex = np.linalg.solve(prob.A.T, xbar)
+        kappa = np.linalg.cond(prob.A)
+        assert np.abs(g - ex).max() <= 1e3 * kappa * kappa * 2.0 ** -53 * np.abs(ex).max()
+        assert lb == 0.0
+    finally:
+        lib.lslu_op_destroy(op)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_vjp_directions_tomography(lib, ctx, prec, tol):
+    prob = config_problem("tomo32")
+    K, lam = 30, 0.5
+    op = lib.make_operator(ctx, prob, lib.PRECISIONS[prec])
+    try:
+        print(f"[vjp] {prob.name} {prec} K={K}", flush=True)
+        info = _solve(lib, ctx, op, prob, prec, K, lam=lam)
+        pt, pg = _pivots(info)
+        k = info["k_done"]
+        oop = make_operator(prob)
+        xbar = 2.0 * (info["X"][:, k - 1] - prob.x_true)
+        g, lb = _vjp(lib, ctx, op, k, xbar, prec)
+        rng = np.random.default_rng(11)
+        worst = 0.0
+        for _ in range(3):
+            v = rng.standard_normal(prob.m)
+            ref = vjp_directional(oop, prob.b, k, lam, pt, pg, xbar, v)
+            e = abs(v @ g - ref) / (np.linalg.norm(v) * np.linalg.norm(g))
+            worst = max(worst, e)
+            assert e <= tol, (e, v @ g, ref)
+        lref = vjp_lambda(oop, prob.b, k, lam, pt, pg, xbar)
+        assert abs(lb - lref) <= tol * abs(lref), (lb, lref)
+        print(f"[vjp] {prob.name} {prec}: worst direction error {worst:.2e}")
+    finally:
+        lib.lslu_op_destroy(op)
+
+
+def _deblur512():
+    # the differentiable workload: 512 x 512 image, 15 x 15 Gaussian PSF
+    # (sigma 2), 1% noise
+    return config_problem("deblur512")
+
+
+def test_vjp_deblur512_central_differences_fp64(lib, ctx):
+    """Full size: the directional derivative against central differences of
+    the library's own FP64 iterates (the base solve's pivots replayed)."""
+    import torch
+    prob = _deblur512()
+    K, lam = 40, 0.01
+    op = lib.make_operator(ctx, prob, lib.PRECISIONS["fp64"])
+    try:
+        print("[vjp] deblur512 fp64 central differences", flush=True)
+        base = _solve(lib, ctx, op, prob, "fp64", K, lam=lam)
+        k = base["k_done"]
+        xbar = 2.0 * (base["X"][:, k - 1] - prob.x_true)
+        g, _ = _vjp(lib, ctx, op, k, xbar, "fp64")
+        rng = np.random.default_rng(5)
+        v = rng.standard_normal(prob.m)
+        h = 1e-6 * np.linalg.norm(prob.b) / np.linalg.norm(v)
+        xs = []
+        for sgn in (1.0, -1.0):
+            b = torch.tensor(prob.b + sgn * h * v, dtype=torch.float64, device="cuda")
+            # the base solve's pivots, replayed: the fixed-pivot map
+            st, x, info = lib.lslu_solve(ctx, op, b, K, reg="fixed", lam=lam,
+                                         replay_piv_t=base["piv_t"],
+                                         replay_piv_g=base["piv_g"])
+            xs.append(x.double().cpu().numpy())
+        fd = xbar @ (xs[0] - xs[1]) / (2 * h)
+        assert abs(v @ g - fd) <= 1e-5 * np.linalg.norm(v) * np.linalg.norm(g), (v @ g, fd)
+    finally:
+        lib.lslu_op_destroy(op)
+
+
+def test_vjp_deblur512_fp32_against_oracle(lib, ctx):
+    """Full size, FP32 (the workload's precision): one random direction and
+    lambda against the FP64 complex-step oracle with the GPU's pivots."""
+    prob = _deblur512()
+    K, lam = 40, 0.01
+    op = lib.make_operator(ctx, prob, lib.PRECISIONS["fp32"])
+    try:
+        print("[vjp] deblur512 fp32 vs oracle", flush=True)
+        info = _solve(lib, ctx, op, prob, "fp32", K, lam=lam)
+        pt, pg = _pivots(info)
+        k = info["k_done"]
+        assert k == K
+        xbar = 2.0 * (info["X"][:, k - 1] - prob.x_true)
+        g, lb = _vjp(lib, ctx, op, k, xbar, "fp32")
+        v = np.random.default_rng(9).standard_normal(prob.m)
+        oop = make_operator(prob)
+        ref = vjp_directional(oop, prob.b, k, lam, pt, pg, xbar, v)
+        e = abs(v @ g - ref) / (np.linalg.norm(v) * np.linalg.norm(g))
+        print(f"[vjp] deblur512 fp32 direction error {e:.2e} ({v @ g:.6e} vs {ref:.6e})")
+        assert e <= 1e-4
+        lref = vjp_lambda(oop, prob.b, k, lam, pt, pg, xbar)
+        assert abs(lb - lref) <= 1e-4 * abs(lref), (lb, lref)
+    finally:
+        lib.lslu_op_destroy(op)
+
+
+def test_autograd_matches_vjp_and_grad_lambda(lib, ctx):
+    import torch
+    from paper_2409_05239_amd.autograd import hybrid_lslu
+    prob = config_problem("tomo32")
+    K, lam = 20, 0.5
+    op = lib.make_operator(ctx, prob, lib.PRECISIONS["fp64"])
+    try:
+        b = torch.tensor(prob.b, dtype=torch.float64, device="cuda", requires_grad=True)
+        lt = torch.tensor(lam, dtype=torch.float64, requires_grad=True)
+        xt = torch.tensor(prob.x_true, dtype=torch.float64, device="cuda")
+        x = hybrid_lslu(ctx, op, b, lt, K)
+        loss = ((x - xt) ** 2).sum()
+        loss.backward()
+        gb = b.grad.double().cpu().numpy()
+        # the same through the C ABI directly
+        xbar = (2.0 * (x.detach() - xt)).contiguous()
+        g2, lb2 = lib.lslu_vjp(ctx, op, K, xbar)
+        assert torch.equal(b.grad, g2)
+        assert lt.grad.item() == lb2
+        # lambda gradient against the projected kernel's own derivative
+        # (LSLU_FLAG_GRAD_LAMBDA) and the oracle's pivots-fixed reference
+        st, x3, info = lib.lslu_solve(ctx, op, b.detach(), K, reg="fixed", lam=lam,
+                                      x_true=xt, grad_lambda=True)
+        d = info["dloss_dlambda"][K - 1]
+        assert abs(lt.grad.item() - d) <= 1e-9 * abs(d), (lt.grad.item(), d)
+        pt, pg = _pivots(info)
+        ref = vjp_directional(make_operator(prob), prob.b, K, lam, pt, pg,
+                              xbar.cpu().numpy(), gb / np.linalg.norm(gb))
+        assert abs(np.linalg.norm(gb) - ref) <= 1e-9 * abs(ref)
+        # a later solve on the context invalidates the forward state
+        x4 = hybrid_lslu(ctx, op, b, lt, K)
+        lib.lslu_solve(ctx, op, b.detach(), K, reg="fixed", lam=lam)
+        with pytest.raises(RuntimeError):
+            ((x4 - xt) ** 2).sum().backward()
+    finally:
+        lib.lslu_op_destroy(op)
+
+
+def test_vjp_is_deterministic_and_checks_its_arguments(lib, ctx):
+    import torch
+    prob = psf_deblur(24, 3, 1.5, 0.01, seed=8)
+    op = lib.make_operator(ctx, prob, lib.PRECISIONS["fp32"])
+    op2 = lib.make_operator(ctx, prob, lib.PRECISIONS["fp32"])
+    try:
+        info = _solve(lib, ctx, op, prob, "fp32", 15)
+        xb = torch.randn(prob.n, dtype=torch.float32, device="cuda")
+        g1, l1 = lib.lslu_vjp(ctx, op, 15, xb)
+        g2, l2 = lib.lslu_vjp(ctx, op, 15, xb)
+        assert torch.equal(g1, g2) and l1 == l2
+        for bad in (0, info["k_done"] + 1):
+            with pytest.raises(lib.LsluError) as ei:
+                lib.lslu_vjp(ctx, op, bad, xb)
+            assert ei.value.status == lib.LSLU_EINVAL
+        with pytest.raises(lib.LsluError):
+            lib.lslu_vjp(ctx, op2, 5, xb)  # not the operator of the last solve
+    finally:
+        lib.lslu_op_destroy(op)
+        lib.lslu_op_destroy(op2)
+    # the solve's operator is gone: nothing to differentiate
+    op3 = lib.make_operator(ctx, prob, lib.PRECISIONS["fp32"])
+    try:
+        with pytest.raises(lib.LsluError):
+            lib.lslu_vjp(ctx, op3, 5, xb)
+    finally:
+        lib.lslu_op_destroy(op3)

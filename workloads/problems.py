@@ -311,6 +311,11 @@ CONFIGS = {
     "deblur1024": dict(make=lambda: psf_deblur(1024, 15, 2.5, 0.01, 1002),
                        iters=150, precision="fp64", reg="wgcv",
                        grid_relative=True),
+    # The differentiable workload: d ||x_k - x_true||^2 / d (b, lambda) with a
+    # fixed lambda (15 x 15 Gaussian PSF, sigma 2).
+    "deblur512": dict(make=lambda: psf_deblur(512, 7, 2.0, 0.01, 1005),
+                      iters=40, precision="fp32", reg="fixed", lam=0.01,
+                      grid_relative=False),
     # Reduced-size siblings used by the parity tests (same recipes).
     "tomo32": dict(make=lambda: tomography(32, 36, 45, 0.02, 1101),
                    iters=30, precision="fp64", reg="wgcv",
