@@ -25,9 +25,10 @@
 // and x_k = x_0 + L_k y gives Lbar = xbar y^T, ybar = L_k^T xbar.
 //
 // The basis stays resident in HBM from the forward solve (it is needed for
-// x_k anyway), so nothing is recomputed.  Dot products are summed in FP64 by
-// fixed row chunks and reduced in a fixed order: the result does not depend
-// on the launch.
+// x_k anyway), and so do the entries of the basis at the pivot rows (the
+// packed triangles the recurrence keeps), so nothing is recomputed.  Dot
+// products are summed in FP64 by fixed row chunks and reduced in a fixed
+// order: the result does not depend on the launch.
 #include "device_common.hpp"
 
 namespace lslu {
@@ -35,45 +36,54 @@ namespace lslu {
 namespace {
 
 constexpr int kAT = 256;          // threads per block
-constexpr int kDotMaxChunks = 256;
+constexpr int kDotCols = 8;       // basis columns per block of the dot products
+constexpr int kDotRowsPerThread = 8;
+constexpr int64_t kDotChunk = (int64_t)kDotRowsPerThread * kAT;  // rows per block
+constexpr int kTriCap = 8256;     // triangle entries staged in LDS (p <= 128)
 
-int dot_chunks(int64_t len) {
-  const int64_t c = (len + 1023) / 1024;
-  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(kDotMaxChunks, c)));
-}
+__host__ __device__ inline int64_t tri_row(int i) { return (int64_t)i * (i - 1) / 2; }
 
-// part[c * ncol + j] = sum over the rows of chunk c of (v1 + v2)(r) * B(r, j).
+int dot_chunks(int64_t len) { return static_cast<int>((len + kDotChunk - 1) / kDotChunk); }
+
+// part[c * ncol + j] = sum over the rows of chunk c (blockIdx.x, kDotChunk
+// rows) of (v1 + v2)(r) * B(r, j), for the kDotCols columns j of blockIdx.y:
+// each thread reads the vector once for all of them, its rows' loads issued
+// together.
 template <typename T>
 __global__ __launch_bounds__(kAT) void k_dots(const T* __restrict__ B, int64_t rs,
                                              int64_t cs, int64_t len, int ncol,
                                              const T* __restrict__ v1,
-                                             const T* __restrict__ v2, int64_t chunk,
+                                             const T* __restrict__ v2,
                                              double* __restrict__ part) {
-  const int64_t r0 = (int64_t)blockIdx.x * chunk;
-  const int64_t r1 = (r0 + chunk < len) ? r0 + chunk : len;
-  double* out = part + (size_t)blockIdx.x * ncol;
-  auto vec = [&](int64_t r) {
+  __shared__ double red[kAT / kWave][kDotCols];
+  const int c0 = blockIdx.y * kDotCols;
+  const int nc = (ncol - c0 < kDotCols) ? ncol - c0 : kDotCols;
+  const int64_t r0 = (int64_t)blockIdx.x * kDotChunk;
+  double acc[kDotCols];
+#pragma unroll
+  for (int c = 0; c < kDotCols; ++c) acc[c] = 0.0;
+#pragma unroll
+  for (int u = 0; u < kDotRowsPerThread; ++u) {
+    const int64_t r = r0 + threadIdx.x + (int64_t)u * kAT;
+    if (r >= len) break;
     double v = static_cast<double>(v1[r]);
     if (v2) v += static_cast<double>(v2[r]);
-    return v;
-  };
-  if (cs == 1) {
-    // rows contiguous: one thread per column, rows in order
-    for (int j = threadIdx.x; j < ncol; j += kAT) {
-      double acc = 0.0;
-      for (int64_t r = r0; r < r1; ++r) acc = fma(vec(r), static_cast<double>(B[r * rs + j]), acc);
-      out[j] = acc;
-    }
-  } else {
-    // columns contiguous: one wavefront per column, lanes along the rows
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    for (int j = w; j < ncol; j += kAT / kWave) {
-      double acc = 0.0;
-      for (int64_t r = r0 + lane; r < r1; r += kWave)
-        acc = fma(vec(r), static_cast<double>(B[r * rs + (int64_t)j * cs]), acc);
-      acc = group_sum<kWave>(acc);
-      if (lane == 0) out[j] = acc;
-    }
+    const T* row = B + r * rs + (int64_t)c0 * cs;
+#pragma unroll
+    for (int c = 0; c < kDotCols; ++c)
+      if (c < nc) acc[c] = fma(v, static_cast<double>(row[(int64_t)c * cs]), acc[c]);
+  }
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+  for (int c = 0; c < kDotCols; ++c) {
+    const double t = group_sum<kWave>(acc[c]);
+    if (lane == 0) red[w][c] = t;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nc) {
+    double t = 0.0;
+    for (int i = 0; i < kAT / kWave; ++i) t += red[i][threadIdx.x];
+    part[(size_t)blockIdx.x * ncol + c0 + threadIdx.x] = t;
   }
 }
 
@@ -176,76 +186,104 @@ struct SideArgs {
   const double* pivval;    // pivot entry of b_{p+1}
   const double* pivbar;    // its direct adjoint, or nullptr
   const double* cbar;      // direct adjoints of c_1..c_p, or nullptr
-  const int* piv;          // pivot rows piv_1..piv_{p+1}
-  const void* B;           // basis b_1..b_{p+1}, working precision
-  int64_t rs, cs;
+  const void* Tp;          // packed rows: row i holds b_j(piv_i), j < i (wp)
   double* alpha;           // out: 1 / pivval (0 without b_{p+1})
   double* corr;            // out: corr_1..corr_{p+1}
 };
 
-// The coefficient adjoints of one half-iteration (one block): the triangular
-// recurrence for corr_j, column by column (the entries b_j(piv_i), i > j, of
-// one pivot row are read together).
+// The coefficient adjoints of one half-iteration.  All threads reduce the
+// partial dot products (a fixed split of the chunks, added in a fixed
+// order) and stage the triangle; then one wavefront runs the triangular
+// recurrence for corr_j, one pivot row per step: lane l holds j = l, l + 64,
+// ..., and corr_i, final once the rows below i are folded in, is broadcast
+// from its lane by readlane.
 template <typename T>
 __global__ __launch_bounds__(kAT) void k_adj_side(SideArgs a) {
-  __shared__ double sc[kMaxIter + 2];
-  __shared__ double s_alpha;
+  __shared__ double tri[kTriCap];
+  __shared__ double red[4][kMaxIter + 2];
   const int tid = threadIdx.x, p = a.p;
   const int ncol = a.has_next ? p + 1 : 0;
-  const T* B = static_cast<const T*>(a.B);
-  if (tid == 0) {
-    double s = 0.0;
-    if (a.has_next) {
-      for (int c = 0; c < a.nchunks; ++c) s += a.part[(size_t)c * ncol + p];
-      const double piv = *a.pivval;
-      s_alpha = 1.0 / piv;
-      sc[p] = (a.pivbar ? *a.pivbar : 0.0) - s / piv;
-    } else {
-      s_alpha = 0.0;
-      sc[p] = 0.0;
+  const T* Tp = static_cast<const T*>(a.Tp);
+  const int64_t ntri = tri_row(p + 1);  // rows 0..p
+  const bool in_lds = ntri <= kTriCap;
+  if (in_lds)
+    for (int64_t e = tid; e < ntri; e += kAT) tri[e] = static_cast<double>(Tp[e]);
+  const int nsplit = ncol <= 64 ? 4 : (ncol <= 128 ? 2 : 1);
+  if (ncol > 0) {
+    const int span = kAT / nsplit, part_i = tid / span;
+    for (int j = tid % span; j < ncol; j += span) {
+      double t = 0.0;
+      for (int c = part_i; c < a.nchunks; c += nsplit) t += a.part[(size_t)c * ncol + j];
+      red[part_i][j] = t;
     }
   }
   __syncthreads();
-  const double alpha = s_alpha;
-  // acc_j for j = tid, tid + kAT (p <= kMaxIter = 2 kAT at most)
-  double acc[2] = {0.0, 0.0};
-  for (int q = 0; q < 2; ++q) {
-    const int j = tid + q * kAT;
-    if (j >= p) continue;
-    double d = 0.0;
-    if (a.has_next)
-      for (int c = 0; c < a.nchunks; ++c) d += a.part[(size_t)c * ncol + j];
-    acc[q] = (a.cbar ? a.cbar[j] : 0.0) - d * alpha;
+  if (tid >= kWave) return;
+  const int lane = tid;
+  auto dot = [&](int j) {
+    double t = 0.0;
+    for (int i = 0; i < nsplit; ++i) t += red[i][j];
+    return t;
+  };
+  double alpha = 0.0, cp = 0.0;
+  if (a.has_next) {
+    alpha = 1.0 / *a.pivval;
+    cp = (a.pivbar ? *a.pivbar : 0.0) - dot(p) * alpha;
+  }
+  constexpr int kQ = kMaxIter / kWave;
+  double acc[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int j = lane + q * kWave;
+    acc[q] = 0.0;
+    if (j < p) acc[q] = (a.cbar ? a.cbar[j] : 0.0) - (a.has_next ? dot(j) * alpha : 0.0);
   }
   for (int i = p; i >= 1; --i) {
-    // corr_i (index i) is final: fold it into every j < i
-    const double ci = sc[i];
-    if (i < p || a.has_next) {
-      const int64_t row = a.piv[i];
-      for (int q = 0; q < 2; ++q) {
-        const int j = tid + q * kAT;
-        if (j < i && ci != 0.0)
-          acc[q] = fma(-ci, static_cast<double>(B[row * a.rs + (int64_t)j * a.cs]), acc[q]);
+    double ci = cp;
+    if (i < p) {
+      double src = acc[0];
+#pragma unroll
+      for (int q = 1; q < kQ; ++q)
+        if (q == (i >> 6)) src = acc[q];
+      ci = readlane_d(src, i & (kWave - 1));
+    }
+    if ((i < p || a.has_next) && ci != 0.0) {
+      const int64_t row = tri_row(i);
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        const int j = lane + q * kWave;
+        if (j < i) {
+          const double t = in_lds ? tri[row + j] : static_cast<double>(Tp[row + j]);
+          acc[q] = fma(-ci, t, acc[q]);
+        }
       }
     }
-    if (tid == ((i - 1) & (kAT - 1))) sc[i - 1] = acc[(i - 1) / kAT];
-    __syncthreads();
   }
-  if (tid == 0) *a.alpha = alpha;
-  for (int i = tid; i <= p; i += kAT) a.corr[i] = sc[i];
+  if (lane == 0) {
+    *a.alpha = alpha;
+    a.corr[p] = cp;
+  }
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int j = lane + q * kWave;
+    if (j < p) a.corr[j] = acc[q];
+  }
 }
 
-// vt = alpha (v1 + v2) into out; Bbar(:, j) -= c_j vt for j < p.
+// Streaming part of one half-iteration, with the pivot-row terms folded in:
+//     out(r)     = vt(r) + corr_i                 (r = piv_i, i <= top)
+//     Bbar(r, j) -= c_j (vt(r) + [j < i] corr_i)  (j < p)
+// with vt = alpha (v1 + v2) and inv[r] the pivot position of row r (-1 if
+// none; positions above top carry no term in this half-iteration).
 template <typename T>
-__global__ __launch_bounds__(kAT) void k_adj_update(int64_t len, int p,
-                                                   const double* __restrict__ alpha_p,
-                                                   const T* __restrict__ v1,
-                                                   const T* __restrict__ v2,
-                                                   const double* __restrict__ coef,
-                                                   T* __restrict__ Bbar, int64_t ldb,
-                                                   T* __restrict__ out) {
-  __shared__ double sc[kMaxIter];
+__global__ __launch_bounds__(kAT) void k_adj_update(
+    int64_t len, int p, int top, const double* __restrict__ alpha_p,
+    const T* __restrict__ v1, const T* __restrict__ v2, const double* __restrict__ coef,
+    const double* __restrict__ corr, const int* __restrict__ inv, T* __restrict__ Bbar,
+    int64_t ldb, T* __restrict__ out) {
+  __shared__ double sc[kMaxIter], scr[kMaxIter + 2];
   for (int j = threadIdx.x; j < p; j += kAT) sc[j] = coef[j];
+  for (int j = threadIdx.x; j <= top; j += kAT) scr[j] = corr[j];
   __syncthreads();
   const double alpha = *alpha_p;
   for (int64_t r = (int64_t)blockIdx.x * kAT + threadIdx.x; r < len;
@@ -254,34 +292,21 @@ __global__ __launch_bounds__(kAT) void k_adj_update(int64_t len, int p,
     if (v1) v = static_cast<double>(v1[r]);
     if (v2) v += static_cast<double>(v2[r]);
     const double vt = alpha * v;
-    out[r] = static_cast<T>(vt);
+    const int pi = inv[r];
+    const double cr = (pi >= 0 && pi <= top) ? scr[pi] : 0.0;
+    out[r] = static_cast<T>(vt + cr);
     for (int j = 0; j < p; ++j) {
       T* e = Bbar + (int64_t)j * ldb + r;
-      *e = static_cast<T>(fma(-sc[j], vt, static_cast<double>(*e)));
+      const double u = (j < pi) ? vt + cr : vt;
+      *e = static_cast<T>(fma(-sc[j], u, static_cast<double>(*e)));
     }
   }
 }
 
-// The pivot-row terms: out(piv_i) += corr_i and Bbar(piv_i, j) -= c_j corr_i
-// for j < i (distinct entries, no conflicts).
-template <typename T>
-__global__ __launch_bounds__(kAT) void k_adj_points(int p, int has_next,
-                                                   const double* __restrict__ corr,
-                                                   const int* __restrict__ piv,
-                                                   const double* __restrict__ coef,
-                                                   T* __restrict__ Bbar, int64_t ldb,
-                                                   T* __restrict__ out) {
-  const int top = has_next ? p : p - 1;  // largest i with a pivot row
-  for (int i = threadIdx.x; i <= top; i += kAT) {
-    const int64_t row = piv[i];
-    out[row] = static_cast<T>(static_cast<double>(out[row]) + corr[i]);
-  }
-  for (int idx = threadIdx.x; idx < (top + 1) * p; idx += kAT) {
-    const int i = idx / p, j = idx - i * p;
-    if (j >= i) continue;
-    T* e = Bbar + (int64_t)j * ldb + piv[i];
-    *e = static_cast<T>(fma(-coef[j], corr[i], static_cast<double>(*e)));
-  }
+// inv[piv[i]] = i for the count pivots of a side (inv cleared to -1 first).
+__global__ void k_inv(const int* __restrict__ piv, int count, int* __restrict__ inv) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+    inv[piv[i]] = i;
 }
 
 // Lbar(:, j) = xbar y_j for j < k.
@@ -296,13 +321,16 @@ __global__ __launch_bounds__(kAT) void k_adj_init_l(int64_t n, int k, const T* _
   }
 }
 
+
 int stream_grid(int64_t len) {
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((len + kAT - 1) / kAT, 4096)));
 }
 
 }  // namespace
 
-size_t adjoint_part_doubles(int K) { return (size_t)kDotMaxChunks * (K + 2); }
+size_t adjoint_part_doubles(int K, int64_t maxlen) {
+  return (size_t)dot_chunks(maxlen) * (K + 2);
+}
 
 template <typename T>
 int run_vjp(const VjpArgs& v, hipStream_t s) {
@@ -319,12 +347,16 @@ int run_vjp(const VjpArgs& v, hipStream_t s) {
   auto dots = [&](const T* B, int64_t rs, int64_t cs, int64_t len, int ncol, const T* v1,
                   const T* v2) {
     const int ch = dot_chunks(len);
-    const int64_t chunk = (len + ch - 1) / ch;
-    k_dots<T><<<ch, kAT, 0, s>>>(B, rs, cs, len, ncol, v1, v2, chunk, v.part);
+    dim3 grid(ch, (ncol + kDotCols - 1) / kDotCols);
+    k_dots<T><<<grid, kAT, 0, s>>>(B, rs, cs, len, ncol, v1, v2, v.part);
     return ch;
   };
 
   launch_fill<T>(Dbar, T(0), v.ldd * (int64_t)(K + 1), s);
+  launch_fill<int>(v.inv_t, -1, v.m, s);
+  launch_fill<int>(v.inv_g, -1, v.n, s);
+  k_inv<<<1, kAT, 0, s>>>(v.piv_t, v.n_d, v.inv_t);
+  k_inv<<<1, kAT, 0, s>>>(v.piv_g, v.n_l, v.inv_g);
   k_adj_init_l<T><<<stream_grid(v.n), kAT, 0, s>>>(v.n, k, static_cast<const T*>(v.xbar),
                                                    v.Y + (size_t)(k - 1) * K, Lbar, v.ldl);
   int nch = dots(L, v.rsL, v.csL, v.n, k, static_cast<const T*>(v.xbar), nullptr);
@@ -343,17 +375,14 @@ int run_vjp(const VjpArgs& v, hipStream_t s) {
       a.pivval = v.H + (size_t)(kk - 1) * ldh + kk;
       a.pivbar = v.Hbar + (size_t)(kk - 1) * ldh + kk;
       a.cbar = v.Hbar + (size_t)(kk - 1) * ldh;
-      a.piv = v.piv_t;
-      a.B = D;
-      a.rs = v.rsD;
-      a.cs = v.csD;
+      a.Tp = v.TD;
       a.alpha = v.scal + 2;
       a.corr = v.corr;
       k_adj_side<T><<<1, kAT, 0, s>>>(a);
       const double* coef = v.H + (size_t)(kk - 1) * ldh;
-      k_adj_update<T><<<stream_grid(v.m), kAT, 0, s>>>(v.m, kk, v.scal + 2, v1, pm_in, coef,
-                                                       Dbar, v.ldd, um);
-      k_adj_points<T><<<1, kAT, 0, s>>>(kk, a.has_next, v.corr, v.piv_t, coef, Dbar, v.ldd, um);
+      k_adj_update<T><<<stream_grid(v.m), kAT, 0, s>>>(v.m, kk, a.has_next ? kk : kk - 1,
+                                                       v.scal + 2, v1, pm_in, coef, v.corr,
+                                                       v.inv_t, Dbar, v.ldd, um);
       op_apply(*v.op, 1, um, pn, nullptr, s);
     }
     // l-side of iteration kk: b = l, p = kk - 1, c = W(1:kk-1, kk), pivot W(kk, kk)
@@ -367,17 +396,13 @@ int run_vjp(const VjpArgs& v, hipStream_t s) {
       a.pivval = v.W + (size_t)(kk - 1) * K + (kk - 1);
       a.pivbar = nullptr;
       a.cbar = nullptr;
-      a.piv = v.piv_g;
-      a.B = L;
-      a.rs = v.rsL;
-      a.cs = v.csL;
+      a.Tp = v.TL;
       a.alpha = v.scal + 2;
       a.corr = v.corr;
       k_adj_side<T><<<1, kAT, 0, s>>>(a);
       const double* coef = v.W + (size_t)(kk - 1) * K;
-      k_adj_update<T><<<stream_grid(v.n), kAT, 0, s>>>(v.n, kk - 1, v.scal + 2, v1, pn, coef,
-                                                       Lbar, v.ldl, un);
-      k_adj_points<T><<<1, kAT, 0, s>>>(kk - 1, 1, v.corr, v.piv_g, coef, Lbar, v.ldl, un);
+      k_adj_update<T><<<stream_grid(v.n), kAT, 0, s>>>(v.n, kk - 1, kk - 1, v.scal + 2, v1, pn,
+                                                       coef, v.corr, v.inv_g, Lbar, v.ldl, un);
       op_apply(*v.op, 0, un, pm, nullptr, s);
       pm_in = pm;
     }
@@ -393,17 +418,13 @@ int run_vjp(const VjpArgs& v, hipStream_t s) {
     a.pivval = &v.st->beta;
     a.pivbar = v.scal;  // betabar
     a.cbar = nullptr;
-    a.piv = v.piv_t;
-    a.B = D;
-    a.rs = v.rsD;
-    a.cs = v.csD;
+    a.Tp = v.TD;
     a.alpha = v.scal + 2;
     a.corr = v.corr;
     k_adj_side<T><<<1, kAT, 0, s>>>(a);
-    T* bbar = static_cast<T*>(v.bbar);
-    k_adj_update<T><<<stream_grid(v.m), kAT, 0, s>>>(v.m, 0, v.scal + 2, v1, pm_in, nullptr,
-                                                     Dbar, v.ldd, bbar);
-    k_adj_points<T><<<1, kAT, 0, s>>>(0, 1, v.corr, v.piv_t, nullptr, Dbar, v.ldd, bbar);
+    k_adj_update<T><<<stream_grid(v.m), kAT, 0, s>>>(v.m, 0, 0, v.scal + 2, v1, pm_in, nullptr,
+                                                     v.corr, v.inv_t, Dbar, v.ldd,
+                                                     static_cast<T*>(v.bbar));
   }
   return 0;
 }

@@ -281,9 +281,10 @@ void launch_stopping(const double* ghat, const DevState* st, double tol,
 struct VjpArgs {
   const DeviceOp* op;
   int64_t m, n;
-  int K, k, n_d;
+  int K, k, n_l, n_d;
   const void *L, *D;  // bases l_1..l_{n_l}, d_1..d_{n_d}
   int64_t rsL, csL, rsD, csD;
+  const void *TL, *TD;  // packed pivot-row triangles of the solve (wp)
   const double *H, *W, *Y, *lam;  // (K+1) x K, K x K, K x K, K
   const int *piv_t, *piv_g;
   const DevState* st;
@@ -292,14 +293,15 @@ struct VjpArgs {
   void *Lbar, *Dbar;  // n x K (ldl), m x (K+1) (ldd)
   int64_t ldl, ldd;
   void *um, *un, *pm, *pn;  // m, n, m, n entries
-  double* part;   // adjoint_part_doubles(K)
+  double* part;   // adjoint_part_doubles(K, max(m, n))
   double* M;      // K x K
   double* Hbar;   // (K+1) x K, leading dimension K+1
   double* corr;   // K+2
   double* scal;   // 4: betabar, lambda_bar, 1/pivot
+  int *inv_t, *inv_g;  // m and n: pivot position of each row, or -1
   int* fail;      // 1 when H^T H + lambda^2 I is not positive definite
 };
-size_t adjoint_part_doubles(int K);
+size_t adjoint_part_doubles(int K, int64_t maxlen);
 template <typename T>
 int run_vjp(const VjpArgs& a, hipStream_t s);
 

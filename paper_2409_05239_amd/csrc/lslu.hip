@@ -12,6 +12,7 @@
 // then copies the small results to pinned host memory once and waits.
 // Breakdowns are detected on the device; later kernels then do nothing.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -170,7 +171,15 @@ struct lslu_ctx {
 struct lslu_op {
   lslu_ctx* ctx = nullptr;
   DeviceOp d;
+  // unique for the life of the process: captured solves are keyed by it, so
+  // an operator allocated where a destroyed one lived never matches a graph
+  // that baked in the destroyed operator's device arrays
+  uint64_t serial = 0;
 };
+
+namespace {
+std::atomic<uint64_t> g_op_serial{0};
+}  // namespace
 
 namespace {
 
@@ -243,6 +252,19 @@ void destroy_captured(lslu_ctx::Captured& g) {
 void drop_graph(lslu_ctx* c) {
   for (auto& g : c->graphs) destroy_captured(g);
   c->graphs.clear();
+}
+
+// Releases the captured solves of one operator (key entry 0 is its serial).
+void drop_op_graphs(lslu_ctx* c, uint64_t serial) {
+  auto& gs = c->graphs;
+  for (auto it = gs.begin(); it != gs.end();) {
+    if (!it->key.empty() && it->key[0] == static_cast<double>(serial)) {
+      destroy_captured(*it);
+      it = gs.erase(it);
+    } else {
+      ++it;
+    }
+  }
 }
 
 lslu_status ensure_ws(lslu_ctx* c, int64_t m, int64_t n, int K, size_t esz,
@@ -640,6 +662,7 @@ lslu_status lslu_op_dense(lslu_ctx* c, int64_t m, int64_t n, const double* A,
     for (int64_t i = 0; i < m; ++i)
       for (int64_t j = 0; j < n; ++j) AT[j * m + i] = A[i * n + j];
     lslu_op* op = new lslu_op();
+    op->serial = ++g_op_serial;
     op->ctx = c;
     op->d.kind = 0;
     op->d.prec = prec;
@@ -701,6 +724,7 @@ lslu_status lslu_op_csr(lslu_ctx* c, int64_t m, int64_t n, int64_t nnz,
         valT[dst] = data[p];
       }
     lslu_op* op = new lslu_op();
+    op->serial = ++g_op_serial;
     op->ctx = c;
     op->d.kind = 1;
     op->d.prec = prec;
@@ -765,6 +789,7 @@ lslu_status lslu_op_psf(lslu_ctx* c, int64_t rows, int64_t cols, int32_t ph,
       }
     }
     lslu_op* op = new lslu_op();
+    op->serial = ++g_op_serial;
     op->ctx = c;
     op->d.kind = 2;
     op->d.prec = prec;
@@ -818,6 +843,7 @@ lslu_status lslu_op_destroy(lslu_op* op) {
       op->ctx->last_op = nullptr;
       op->ctx->last_ok = false;
     }
+    drop_op_graphs(op->ctx, op->serial);
   }
   free_op(op->d);
   delete op;
@@ -987,7 +1013,7 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
     } else {
       // Everything the captured kernels bake in: pointers, sizes, options.
       std::vector<double> key = {
-          (double)(uintptr_t)op, (double)(uintptr_t)b, (double)(uintptr_t)x0,
+          (double)op->serial, (double)(uintptr_t)b, (double)(uintptr_t)x0,
           (double)(uintptr_t)x_out, (double)(uintptr_t)X, (double)(uintptr_t)c->ws,
           (double)op->d.kind, (double)op->d.prec, (double)op->d.m, (double)op->d.n,
           (double)K, (double)o->reg, o->lambda, (double)o->n_grid,
@@ -1083,12 +1109,14 @@ lslu_status lslu_vjp(lslu_ctx* c, const lslu_op* op, int32_t k, const void* xbar
       a.un = take(esz * n);
       a.pm = take(esz * m);
       a.pn = take(esz * n);
-      a.part = reinterpret_cast<double*>(take(sizeof(double) * adjoint_part_doubles(K)));
+      a.part = reinterpret_cast<double*>(take(sizeof(double) * adjoint_part_doubles(K, std::max(m, n))));
       a.M = reinterpret_cast<double*>(take(sizeof(double) * K * K));
       a.Hbar = reinterpret_cast<double*>(take(sizeof(double) * (K + 1) * K));
       a.corr = reinterpret_cast<double*>(take(sizeof(double) * (K + 2)));
       a.scal = reinterpret_cast<double*>(take(sizeof(double) * 4));
       a.fail = reinterpret_cast<int*>(take(sizeof(int)));
+      a.inv_t = reinterpret_cast<int*>(take(sizeof(int) * m));
+      a.inv_g = reinterpret_cast<int*>(take(sizeof(int) * n));
       return align_up(off, 256);
     };
     const size_t need = carve_adj(nullptr);
@@ -1107,9 +1135,12 @@ lslu_status lslu_vjp(lslu_ctx* c, const lslu_op* op, int32_t k, const void* xbar
     a.n = n;
     a.K = K;
     a.k = k;
+    a.n_l = c->last_nl;
     a.n_d = c->last_nd;
     a.L = l.L;
     a.D = l.D;
+    a.TL = l.TL;
+    a.TD = l.TD;
     a.rsL = c->bs.rsL;
     a.csL = c->bs.csL;
     a.rsD = c->bs.rsD;

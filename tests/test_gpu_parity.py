@@ -400,3 +400,32 @@ def test_graph_replays_match_eager(lib, ctx):
         assert np.allclose(G2["X"], 2.0 * ref["X"], rtol=1e-12, atol=0)
     finally:
         lib.lslu_op_destroy(op)
+
+
+def test_graph_cache_never_replays_a_destroyed_operator(lib, ctx):
+    """Operators of the same shape created and destroyed in turn (their host
+    handles and device arrays are often allocated where the previous ones
+    lived), each solved with the same b, X and x_out buffers: every captured
+    solve must use its own operator, i.e. match an eager solve of it."""
+    import torch
+    b = torch.zeros(40, dtype=torch.float64, device="cuda")
+    X = torch.zeros((8, 30), dtype=torch.float64, device="cuda")
+    x = torch.zeros(30, dtype=torch.float64, device="cuda")
+    for seed in range(5):
+        prob = random_dense(40, 30, seed=100 + seed, nu=0.01)
+        b.copy_(torch.tensor(prob.b, dtype=torch.float64))
+        # an operator of another size first, so that the device arrays of
+        # this one move while its host handle may take the previous address
+        spacer = lib.make_operator(ctx, random_dense(20 + 7 * seed, 10, seed=seed),
+                                   lib.LSLU_FP64)
+        op = lib.make_operator(ctx, prob, lib.LSLU_FP64)
+        try:
+            lib.lslu_solve(ctx, op, b, 8, reg="fixed", lam=0.05, X=X, x_out=x)
+            torch.cuda.synchronize()
+            got = X.clone()
+            lib.lslu_solve(ctx, op, b, 8, reg="fixed", lam=0.05, X=X, x_out=x, eager=True)
+            torch.cuda.synchronize()
+            assert torch.equal(got, X), seed
+        finally:
+            lib.lslu_op_destroy(op)
+            lib.lslu_op_destroy(spacer)
