@@ -436,29 +436,47 @@ struct PsfPixels {
 };
 
 // --------------------------------------------------------------- PSF tile --
-// A 32 x 64 output tile and its halo are staged in LDS; each lane owns one
-// output column and 8 consecutive output rows, walks the PSF column by column,
-// keeps a vertical strip of 8 + ph - 1 inputs in registers and reads each
-// weight as a wave-uniform (scalar) operand.
+// An R*4 x 64 output tile and its halo are staged in LDS; each lane owns one
+// output column and R consecutive output rows, walks the PSF column by column,
+// keeps a vertical strip of R + ph - 1 inputs in registers and reads each
+// weight as a wave-uniform (scalar) operand.  R = 8 reuses each staged input
+// most; R = 2 makes four times as many tiles, which keeps more of the chip
+// busy on small images (psf_rows_per_lane).
 constexpr int kPsfTW = 64;          // tile width = lanes of a wavefront
-constexpr int kPsfR = 8;            // output rows per lane
 constexpr int kPsfWaves = 4;        // wavefronts per block
-constexpr int kPsfTH = kPsfR * kPsfWaves;  // tile height
+template <int R>
+__host__ __device__ constexpr int psf_th() { return R * kPsfWaves; }  // tile height
 
-template <typename Acc, int PH>
+template <typename Acc, int PH, int R>
 __host__ __device__ constexpr size_t psf_lds_bytes(int pw) {
-  return sizeof(Acc) * (kPsfTH + PH - 1) * (kPsfTW + pw - 1);
+  return sizeof(Acc) * (psf_th<R>() + PH - 1) * (kPsfTW + pw - 1);
+}
+
+// Output rows per lane for a rows x cols image: 8 when that still gives at
+// least two tiles per compute unit (512 tiles), else 2.
+inline int psf_rows_per_lane(int64_t rows, int64_t cols) {
+  const int64_t t8 = ((cols + kPsfTW - 1) / kPsfTW) * ((rows + psf_th<8>() - 1) / psf_th<8>());
+  return t8 >= 512 ? 8 : 2;
+}
+
+// Calls f(std::integral_constant<int, R>) for psf_rows_per_lane(rows, cols).
+template <typename F>
+void with_psf_r(int64_t rows, int64_t cols, F&& f) {
+  if (psf_rows_per_lane(rows, cols) == 8)
+    f(std::integral_constant<int, 8>{});
+  else
+    f(std::integral_constant<int, 2>{});
 }
 
 // acc[p] = y[i0 + r0 + p, j0 + lane] for the tile at (i0, j0), with
 // y[i,j] = sum_{a,b} Wt[a,b] * x[i + a - PH/2, j + b - pw/2]  (zero outside),
-// r0 = 8 * wavefront.  Ends with the tile still in LDS (no trailing barrier).
-template <typename T, typename Acc, int PH, int kIn>
+// r0 = R * wavefront.  Ends with the tile still in LDS (no trailing barrier).
+template <typename T, typename Acc, int PH, int kIn, int R>
 __device__ inline void psf_tile(const T* __restrict__ x, int rows, int cols,
                                 const Acc* __restrict__ Wt, int pw, int i0,
-                                int j0, Acc* tile, Acc (&acc)[kPsfR]) {
+                                int j0, Acc* tile, Acc (&acc)[R]) {
   const int ch = PH / 2, cw = pw / 2;
-  const int TR = kPsfTH + PH - 1;
+  const int TR = psf_th<R>() + PH - 1;
   const int TC = kPsfTW + pw - 1;
   for (int e = threadIdx.x; e < TR * TC; e += blockDim.x) {
     const int tr = e / TC, tc = e - tr * TC;
@@ -470,18 +488,18 @@ __device__ inline void psf_tile(const T* __restrict__ x, int rows, int cols,
   }
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
-  const int r0 = (threadIdx.x / kWave) * kPsfR;
+  const int r0 = (threadIdx.x / kWave) * R;
 #pragma unroll
-  for (int p = 0; p < kPsfR; ++p) acc[p] = 0;
+  for (int p = 0; p < R; ++p) acc[p] = 0;
   for (int b = 0; b < pw; ++b) {
-    Acc s[kPsfR + PH - 1];
+    Acc s[R + PH - 1];
 #pragma unroll
-    for (int q = 0; q < kPsfR + PH - 1; ++q) s[q] = tile[(r0 + q) * TC + lane + b];
+    for (int q = 0; q < R + PH - 1; ++q) s[q] = tile[(r0 + q) * TC + lane + b];
 #pragma unroll
     for (int a = 0; a < PH; ++a) {
       const Acc wv = Wt[a * pw + b];
 #pragma unroll
-      for (int p = 0; p < kPsfR; ++p) acc[p] = fma(wv, s[p + a], acc[p]);
+      for (int p = 0; p < R; ++p) acc[p] = fma(wv, s[p + a], acc[p]);
     }
   }
 }

@@ -41,22 +41,22 @@ __global__ __launch_bounds__(kRowBlock) void k_rows(
   if (sub == 0) y[r] = static_cast<T>(acc);
 }
 
-template <typename T, typename Acc, int PH, int kIn>
+template <typename T, typename Acc, int PH, int kIn, int R>
 __global__ __launch_bounds__(kPsfWaves * kWave) void k_psf_corr(
     const T* __restrict__ x, T* __restrict__ y, int rows, int cols,
     const Acc* __restrict__ Wt, int pw, const int* stop) {
   if (stop && *stop) return;
   extern __shared__ unsigned char smem_raw[];
   Acc* tile = reinterpret_cast<Acc*>(smem_raw);
-  const int i0 = blockIdx.y * kPsfTH, j0 = blockIdx.x * kPsfTW;
-  Acc acc[kPsfR];
-  psf_tile<T, Acc, PH, kIn>(x, rows, cols, Wt, pw, i0, j0, tile, acc);
+  const int i0 = blockIdx.y * psf_th<R>(), j0 = blockIdx.x * kPsfTW;
+  Acc acc[R];
+  psf_tile<T, Acc, PH, kIn, R>(x, rows, cols, Wt, pw, i0, j0, tile, acc);
   const int lane = threadIdx.x & (kWave - 1);
-  const int r0 = (threadIdx.x / kWave) * kPsfR;
+  const int r0 = (threadIdx.x / kWave) * R;
   const int gj = j0 + lane;
   if (gj < cols) {
 #pragma unroll
-    for (int p = 0; p < kPsfR; ++p) {
+    for (int p = 0; p < R; ++p) {
       const int gi = i0 + r0 + p;
       if (gi < rows) y[(int64_t)gi * cols + gj] = static_cast<T>(acc[p]);
     }
@@ -91,10 +91,13 @@ void apply_t(const DeviceOp& op, int tr, const T* x, T* y, const int* stop,
       const int R = static_cast<int>(op.rows), C = static_cast<int>(op.cols);
       with_ph(op.ph, [&](auto phc) {
         constexpr int PH = decltype(phc)::value;
-        dim3 g((C + kPsfTW - 1) / kPsfTW, (R + kPsfTH - 1) / kPsfTH);
-        k_psf_corr<T, Acc, PH, kB><<<g, kPsfWaves * kWave,
-                                     psf_lds_bytes<Acc, PH>(op.pw), s>>>(
-            x, y, R, C, psf_weights<Acc>(op, tr), op.pw, stop);
+        with_psf_r(R, C, [&](auto rc) {
+          constexpr int PR = decltype(rc)::value;
+          dim3 g((C + kPsfTW - 1) / kPsfTW, (R + psf_th<PR>() - 1) / psf_th<PR>());
+          k_psf_corr<T, Acc, PH, kB, PR><<<g, kPsfWaves * kWave,
+                                           psf_lds_bytes<Acc, PH, PR>(op.pw), s>>>(
+              x, y, R, C, psf_weights<Acc>(op, tr), op.pw, stop);
+        });
       });
     }
   });

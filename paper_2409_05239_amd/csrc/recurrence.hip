@@ -668,12 +668,12 @@ __global__ __launch_bounds__(kThreads, half_min_waves<T>()) void k_half_rows(Hal
 // --------------------------------------------------- PSF consumer blocks --
 // The tile of the normalised input: each staged entry is u divided by the
 // pivot value, then (BF16 mode) rounded to bfloat16.
-template <typename T, typename Acc, int PH, int kIn>
+template <typename T, typename Acc, int PH, int kIn, int R>
 __device__ inline void psf_tile_norm(const T* __restrict__ u, const Normaliser<T>& nz, int rows,
                                      int cols, const Acc* __restrict__ Wt, int pw,
-                                     int i0, int j0, Acc* tile, Acc (&acc)[kPsfR]) {
+                                     int i0, int j0, Acc* tile, Acc (&acc)[R]) {
   const int ch = PH / 2, cw = pw / 2;
-  const int TR = kPsfTH + PH - 1, TC = kPsfTW + pw - 1;
+  const int TR = psf_th<R>() + PH - 1, TC = kPsfTW + pw - 1;
   for (int e = threadIdx.x; e < TR * TC; e += kThreads) {
     const int tr = e / TC, tc = e - tr * TC;
     const int gi = i0 - ch + tr, gj = j0 - cw + tc;
@@ -684,18 +684,18 @@ __device__ inline void psf_tile_norm(const T* __restrict__ u, const Normaliser<T
   }
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
-  const int r0 = (threadIdx.x / kWave) * kPsfR;
+  const int r0 = (threadIdx.x / kWave) * R;
 #pragma unroll
-  for (int p = 0; p < kPsfR; ++p) acc[p] = 0;
+  for (int p = 0; p < R; ++p) acc[p] = 0;
   for (int b = 0; b < pw; ++b) {
-    Acc s[kPsfR + PH - 1];
+    Acc s[R + PH - 1];
 #pragma unroll
-    for (int q = 0; q < kPsfR + PH - 1; ++q) s[q] = tile[(r0 + q) * TC + lane + b];
+    for (int q = 0; q < R + PH - 1; ++q) s[q] = tile[(r0 + q) * TC + lane + b];
 #pragma unroll
     for (int aa = 0; aa < PH; ++aa) {
       const Acc wv = Wt[aa * pw + b];
 #pragma unroll
-      for (int p = 0; p < kPsfR; ++p) acc[p] = fma(wv, s[p + aa], acc[p]);
+      for (int p = 0; p < R; ++p) acc[p] = fma(wv, s[p + aa], acc[p]);
     }
   }
   __syncthreads();  // the tile may be restaged next
@@ -703,16 +703,17 @@ __device__ inline void psf_tile_norm(const T* __restrict__ u, const Normaliser<T
 
 // Persistent over tiles cb, cb + ncons, ...: products first (parked in out),
 // then the coefficients, then the elimination.
-template <typename T, typename Acc, int PH, int kIn>
+template <typename T, typename Acc, int PH, int kIn, int R>
 __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
                               int rows, int cols, int pw, DevState* st, int cb,
                               int ncons, unsigned char* lds) {
   __shared__ double cf[kMaxIter];
   Acc* tile = reinterpret_cast<Acc*>(lds);
   const int lane = threadIdx.x & (kWave - 1);
-  const int r0 = (threadIdx.x / kWave) * kPsfR;
+  constexpr int TH = psf_th<R>();
+  const int r0 = (threadIdx.x / kWave) * R;
   const int tiles_x = (cols + kPsfTW - 1) / kPsfTW;
-  const int ntiles = a.rows > 0 ? tiles_x * ((rows + kPsfTH - 1) / kPsfTH) : 0;
+  const int ntiles = a.rows > 0 ? tiles_x * ((rows + TH - 1) / TH) : 0;
   const int nb = a.nb;
   NormStage<T> ns;
   normalise_stage(a, cb, ncons, ns);
@@ -722,12 +723,12 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
   const Normaliser<T> nz(static_cast<T>(val));
   normalise_share(a, cb, ncons, pick, nz, ns);
   for (int t = cb; t < ntiles; t += ncons) {
-    const int i0 = (t / tiles_x) * kPsfTH, j0 = (t % tiles_x) * kPsfTW;
-    Acc acc[kPsfR];
-    psf_tile_norm<T, Acc, PH, kIn>(a.up, nz, rows, cols, Wt, pw, i0, j0, tile, acc);
+    const int i0 = (t / tiles_x) * TH, j0 = (t % tiles_x) * kPsfTW;
+    Acc acc[R];
+    psf_tile_norm<T, Acc, PH, kIn, R>(a.up, nz, rows, cols, Wt, pw, i0, j0, tile, acc);
     const int gj = j0 + lane;
 #pragma unroll
-    for (int p = 0; p < kPsfR; ++p) {
+    for (int p = 0; p < R; ++p) {
       const int gi = i0 + r0 + p;
       if (gi < rows && gj < cols) a.out[(int64_t)gi * cols + gj] = static_cast<T>(acc[p]);
     }
@@ -737,34 +738,34 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
   double best = 0.0;
   int bidx = INT_MAX;
   for (int t = cb; t < ntiles; t += ncons) {
-    const int i0 = (t / tiles_x) * kPsfTH, j0 = (t % tiles_x) * kPsfTW;
+    const int i0 = (t / tiles_x) * TH, j0 = (t % tiles_x) * kPsfTW;
     const int gj = j0 + lane;
-    int64_t pix[kPsfR];
-    bool ok[kPsfR];
-    unsigned char mk[kPsfR];
+    int64_t pix[R];
+    bool ok[R];
+    unsigned char mk[R];
 #pragma unroll
-    for (int p = 0; p < kPsfR; ++p) {
+    for (int p = 0; p < R; ++p) {
       const int gi = i0 + r0 + p;
       ok[p] = gi < rows && gj < cols;
       pix[p] = ok[p] ? (int64_t)gi * cols + gj : 0;  // in bounds either way
       mk[p] = a.mask[pix[p]];
     }
-    double e[kPsfR];
+    double e[R];
 #pragma unroll
-    for (int p = 0; p < kPsfR; ++p) e[p] = 0.0;
+    for (int p = 0; p < R; ++p) e[p] = 0.0;
     int j = 0;
     for (; j + 2 <= nb; j += 2) {
       const T* c0 = a.basis + (int64_t)j * a.cs;
       const T* c1 = c0 + a.cs;
-      T b0[kPsfR], b1[kPsfR];
+      T b0[R], b1[R];
 #pragma unroll
-      for (int p = 0; p < kPsfR; ++p) {
+      for (int p = 0; p < R; ++p) {
         b0[p] = c0[pix[p]];
         b1[p] = c1[pix[p]];
       }
       const double w0 = cf[j], w1 = cf[j + 1];
 #pragma unroll
-      for (int p = 0; p < kPsfR; ++p) {
+      for (int p = 0; p < R; ++p) {
         e[p] = fma(w0, static_cast<double>(b0[p]), e[p]);
         e[p] = fma(w1, static_cast<double>(b1[p]), e[p]);
       }
@@ -773,10 +774,10 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
       const T* c0 = a.basis + (int64_t)j * a.cs;
       const double w0 = cf[j];
 #pragma unroll
-      for (int p = 0; p < kPsfR; ++p) e[p] = fma(w0, static_cast<double>(c0[pix[p]]), e[p]);
+      for (int p = 0; p < R; ++p) e[p] = fma(w0, static_cast<double>(c0[pix[p]]), e[p]);
     }
 #pragma unroll
-    for (int p = 0; p < kPsfR; ++p) {
+    for (int p = 0; p < R; ++p) {
       if (!ok[p]) continue;
       const double q0 = static_cast<double>(a.out[pix[p]]);
       const T o = mk[p] ? T(0) : static_cast<T>(q0 - e[p]);
@@ -792,7 +793,7 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
   if (threadIdx.x == 0) write_part(a.parts_out, cb, best, bidx);
 }
 
-template <typename T, typename Acc, int PH, int kIn, bool kTriLds>
+template <typename T, typename Acc, int PH, int kIn, bool kTriLds, int R>
 __global__ __launch_bounds__(kThreads) void k_half_psf(
     HalfArgs<T> a, PsfPixels<Acc, kIn> op, const Acc* __restrict__ Wt) {
   extern __shared__ unsigned char lds[];
@@ -803,7 +804,7 @@ __global__ __launch_bounds__(kThreads) void k_half_psf(
   else if ((int)blockIdx.x < a.nlead)
     pivot_entries<T, PsfPixels<Acc, kIn>>(a, op, st);
   else
-    consume_tiles<T, Acc, PH, kIn>(a, Wt, op.rows, op.cols, op.pw, st,
+    consume_tiles<T, Acc, PH, kIn, R>(a, Wt, op.rows, op.cols, op.pw, st,
                                      blockIdx.x - a.nlead, gridDim.x - a.nlead, lds);
 }
 
@@ -866,28 +867,38 @@ int launch_rows(HalfArgs<T>& a, const RowOp& op, size_t lds_bytes, hipStream_t s
   return launch_rows_g<T, RowOp, 16>(a, op, tb, in_lds, s);
 }
 
-template <typename T, typename Acc, int PH, int kIn>
-int launch_tiles(HalfArgs<T>& a, const PsfPixels<Acc, kIn>& op, const Acc* Wt,
-                 size_t lds_bytes, hipStream_t s) {
-  const int ntiles = ((op.cols + kPsfTW - 1) / kPsfTW) * ((op.rows + kPsfTH - 1) / kPsfTH);
+template <typename T, typename Acc, int PH, int kIn, int R>
+int launch_tiles_r(HalfArgs<T>& a, const PsfPixels<Acc, kIn>& op, const Acc* Wt,
+                   size_t lds_bytes, hipStream_t s) {
+  const int ntiles = ((op.cols + kPsfTW - 1) / kPsfTW) * ((op.rows + psf_th<R>() - 1) / psf_th<R>());
   const int64_t want = a.rows > 0 ? ntiles
                                   : (a.lenp + kThreads * kNormBatch - 1) / (kThreads * kNormBatch);
   const int nbk = a.rows > 0 ? a.nb : 0;
   a.nlead = 1 + (nbk + kWaves - 1) / kWaves;
   const size_t tb = tri_bytes<T>(nbk);
-  const size_t pb = psf_lds_bytes<Acc, PH>(op.pw);
+  const size_t pb = psf_lds_bytes<Acc, PH, R>(op.pw);
   const bool in_lds = tb > 0 && tb <= kTriLdsMax && std::max(tb, pb) + 16 * 1024 <= lds_bytes;
   if (in_lds) {
-    auto k = k_half_psf<T, Acc, PH, kIn, true>;
+    auto k = k_half_psf<T, Acc, PH, kIn, true, R>;
     const size_t dyn = std::max(tb, pb);
     const int ncons = consumer_blocks(want, a.nlead, resident_blocks((const void*)k, dyn));
     k<<<a.nlead + ncons, kThreads, dyn, s>>>(a, op, Wt);
     return ncons;
   }
-  auto k = k_half_psf<T, Acc, PH, kIn, false>;
+  auto k = k_half_psf<T, Acc, PH, kIn, false, R>;
   const int ncons = consumer_blocks(want, a.nlead, resident_blocks((const void*)k, pb));
   k<<<a.nlead + ncons, kThreads, pb, s>>>(a, op, Wt);
   return ncons;
+}
+
+template <typename T, typename Acc, int PH, int kIn>
+int launch_tiles(HalfArgs<T>& a, const PsfPixels<Acc, kIn>& op, const Acc* Wt,
+                 size_t lds_bytes, hipStream_t s) {
+  int n = 0;
+  with_psf_r(op.rows, op.cols, [&](auto rc) {
+    n = launch_tiles_r<T, Acc, PH, kIn, decltype(rc)::value>(a, op, Wt, lds_bytes, s);
+  });
+  return n;
 }
 
 }  // namespace
