@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LSLU_ABI_VERSION 7
+#define LSLU_ABI_VERSION 8
 
 typedef enum lslu_status {
   LSLU_OK = 0,
@@ -127,11 +127,26 @@ lslu_status lslu_op_csr(lslu_ctx* ctx, int64_t m, int64_t n, int64_t nnz,
  *   (A x)[i,j] = sum_{a,b} psf[a,b] x[i-a+ph/2, j-b+pw/2]
  * and A^T the matching correlation
  *   (A^T y)[i,j] = sum_{a,b} psf[a,b] y[i+a-ph/2, j+b-pw/2],
- * entries outside the image read as zero.  ph, pw <= 63.
- * Errors: LSLU_EINVAL, LSLU_ENONFINITE, LSLU_ENOMEM. */
+ * entries outside the image read as zero.  ph, pw odd and <= 31.  The tile
+ * shape of its products is measured on the device at creation (as
+ * lslu_op_tile with rows_per_lane = 0; a few products, about a millisecond
+ * on a 1024 x 1024 image).
+ * Errors: LSLU_EINVAL, LSLU_ENONFINITE, LSLU_ENOMEM, LSLU_EDEVICE. */
 lslu_status lslu_op_psf(lslu_ctx* ctx, int64_t rows, int64_t cols, int32_t ph,
                         int32_t pw, const double* psf, int32_t precision,
                         lslu_op** out);
+
+/* Tile shape of a PSF operator's products (in lslu_op_apply and inside
+ * lslu_solve): each lane of a 4-wavefront block computes rows_per_lane = 2, 4
+ * or 8 consecutive output rows of a (4 rows_per_lane) x 64 tile.  0 measures
+ * the three on the device (one A and one A^T product each, after a warm-up,
+ * timed with HIP events on the context's stream) and keeps the fastest.
+ * Every shape sums each output in the same order, so results do not depend on
+ * it.  *chosen (may be NULL) receives the shape in use.  Synchronous.
+ * Errors: LSLU_EUNSUPPORTED (not a PSF operator), LSLU_EINVAL,
+ * LSLU_ENOMEM, LSLU_EDEVICE. */
+lslu_status lslu_op_tile(lslu_ctx* ctx, lslu_op* op, int32_t rows_per_lane,
+                         int32_t* chosen);
 
 /* y = A x (transpose = 0; x has n entries, y has m) or y = A^T x
  * (transpose = 1; x has m entries, y has n), on the context's stream, with

@@ -42,7 +42,7 @@ EXPORTS = (
     "lslu_create", "lslu_destroy", "lslu_last_error", "lslu_status_name",
     "lslu_abi_version", "lslu_op_dense", "lslu_op_csr", "lslu_op_psf",
     "lslu_op_apply", "lslu_op_info", "lslu_op_destroy", "lslu_solve",
-    "lslu_wait", "lslu_get_basis", "lslu_vjp",
+    "lslu_wait", "lslu_get_basis", "lslu_vjp", "lslu_op_tile",
 )
 
 
@@ -143,6 +143,7 @@ def _load():
         "lslu_get_basis": (c_int, [vp, c_int32, c_int32, vp]),
         "lslu_wait": (c_int, [vp]),
         "lslu_vjp": (c_int, [vp, vp, c_int32, vp, vp, POINTER(c_double)]),
+        "lslu_op_tile": (c_int, [vp, vp, c_int32, POINTER(c_int32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -239,6 +240,14 @@ def lslu_op_psf(ctx, rows, cols, psf, precision=LSLU_FP64):
 def lslu_op_apply(ctx, op, transpose, x, y):
     """``x``/``y``: torch device tensors in the operator's working precision."""
     _check(ctx, lib.lslu_op_apply(ctx, op, int(transpose), _dptr(x), _dptr(y)))
+
+
+def lslu_op_tile(ctx, op, rows_per_lane=0):
+    """Set (2, 4, 8) or measure (0) the tile shape of a PSF operator's
+    products; returns the shape in use."""
+    r = c_int32(0)
+    _check(ctx, lib.lslu_op_tile(ctx, op, int(rows_per_lane), ctypes.byref(r)))
+    return r.value
 
 
 def lslu_op_info(op):

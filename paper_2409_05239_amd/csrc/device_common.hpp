@@ -441,7 +441,8 @@ struct PsfPixels {
 // keeps a vertical strip of R + ph - 1 inputs in registers and reads each
 // weight as a wave-uniform (scalar) operand.  R = 8 reuses each staged input
 // most; R = 2 makes four times as many tiles, which keeps more of the chip
-// busy on small images (psf_rows_per_lane).
+// busy on small images (psf_rows_per_lane); an operator can also carry a
+// choice measured on the device (lslu_op_tile).
 constexpr int kPsfTW = 64;          // tile width = lanes of a wavefront
 constexpr int kPsfWaves = 4;        // wavefronts per block
 template <int R>
@@ -459,13 +460,15 @@ inline int psf_rows_per_lane(int64_t rows, int64_t cols) {
   return t8 >= 512 ? 8 : 2;
 }
 
-// Calls f(std::integral_constant<int, R>) for psf_rows_per_lane(rows, cols).
+// Calls f(std::integral_constant<int, R>) for R = r (2, 4 or 8; the
+// operator's tuned choice), or psf_rows_per_lane(rows, cols) when r is 0.
 template <typename F>
-void with_psf_r(int64_t rows, int64_t cols, F&& f) {
-  if (psf_rows_per_lane(rows, cols) == 8)
-    f(std::integral_constant<int, 8>{});
-  else
-    f(std::integral_constant<int, 2>{});
+void with_psf_r(int r, int64_t rows, int64_t cols, F&& f) {
+  switch (r ? r : psf_rows_per_lane(rows, cols)) {
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    default: f(std::integral_constant<int, 8>{}); break;
+  }
 }
 
 // acc[p] = y[i0 + r0 + p, j0 + lane] for the tile at (i0, j0), with

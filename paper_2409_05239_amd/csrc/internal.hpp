@@ -142,6 +142,7 @@ struct DeviceOp {
   // psf
   int64_t rows = 0, cols = 0;
   int ph = 0, pw = 0;
+  int psf_r = 0;  // output rows per lane of the PSF tiles (2, 4, 8); 0: by size
   double* psf = nullptr;       // correlation weights for A^T (as given)
   double* psf_flip = nullptr;  // correlation weights for A (rotated 180)
   float* psf32 = nullptr;

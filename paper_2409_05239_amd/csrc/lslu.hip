@@ -572,6 +572,58 @@ void copy_out(T* dst, const T* src, size_t count) {
   if (dst) std::memcpy(dst, src, sizeof(T) * count);
 }
 
+// The PSF tile shape (output rows per lane) that runs one A and one A^T
+// product fastest on this device, by HIP events on the context's stream:
+// each candidate is warmed up, then timed over a few product pairs.  Every
+// candidate sums each output in the same order, so the choice changes
+// timing only.
+lslu_status tune_psf(lslu_ctx* c, lslu_op* op, int* chosen) {
+  const int64_t n = op->d.n;
+  const size_t esz = prec_size(op->d.prec);
+  void *x = nullptr, *y = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  struct Free {
+    void **x, **y;
+    hipEvent_t *e0, *e1;
+    ~Free() {
+      if (*x) (void)hipFree(*x);
+      if (*y) (void)hipFree(*y);
+      if (*e0) (void)hipEventDestroy(*e0);
+      if (*e1) (void)hipEventDestroy(*e1);
+    }
+  } guard{&x, &y, &e0, &e1};
+  LSLU_HIP(c, hipMalloc(&x, esz * n));
+  LSLU_HIP(c, hipMalloc(&y, esz * n));
+  LSLU_HIP(c, hipEventCreate(&e0));
+  LSLU_HIP(c, hipEventCreate(&e1));
+  const hipStream_t s = c->stream;
+  if (esz == sizeof(double))
+    launch_fill<double>(static_cast<double*>(x), 1.0, n, s);
+  else
+    launch_fill<float>(static_cast<float*>(x), 1.0f, n, s);
+  const int saved = op->d.psf_r;
+  float best = 0.f;
+  int pick = 0;
+  for (int r : {2, 4, 8}) {
+    op->d.psf_r = r;
+    for (int i = 0; i < 2; ++i) op_apply(op->d, i & 1, x, y, nullptr, s);
+    LSLU_HIP(c, hipEventRecord(e0, s));
+    for (int i = 0; i < 6; ++i) op_apply(op->d, i & 1, x, y, nullptr, s);
+    LSLU_HIP(c, hipEventRecord(e1, s));
+    LSLU_HIP(c, hipEventSynchronize(e1));
+    float ms = 0.f;
+    LSLU_HIP(c, hipEventElapsedTime(&ms, e0, e1));
+    if (pick == 0 || ms < best) {
+      best = ms;
+      pick = r;
+    }
+  }
+  op->d.psf_r = saved;
+  LSLU_HIP(c, hipGetLastError());
+  *chosen = pick;
+  return LSLU_OK;
+}
+
 }  // namespace
 
 // =========================================================================
@@ -803,12 +855,41 @@ lslu_status lslu_op_psf(lslu_ctx* c, int64_t rows, int64_t cols, int32_t ph,
     if (st == LSLU_OK) st = upload(c, reinterpret_cast<void**>(&op->d.psf_flip), pf.data(), sizeof(double) * np);
     if (st == LSLU_OK) st = upload(c, reinterpret_cast<void**>(&op->d.psf32), p32.data(), sizeof(float) * np);
     if (st == LSLU_OK) st = upload(c, reinterpret_cast<void**>(&op->d.psf32_flip), pf32.data(), sizeof(float) * np);
+    int r = 0;
+    if (st == LSLU_OK) st = tune_psf(c, op, &r);
     if (st != LSLU_OK) {
       free_op(op->d);
       delete op;
       return st;
     }
+    op->d.psf_r = r;
     *out = op;
+    return LSLU_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(c, LSLU_ENOMEM, "host allocation failed");
+  }
+}
+
+
+lslu_status lslu_op_tile(lslu_ctx* c, lslu_op* op, int32_t rows_per_lane, int32_t* chosen) {
+  if (!c) return LSLU_EINVAL;
+  if (!op) return fail(c, LSLU_EINVAL, "NULL argument");
+  if (op->ctx != c) return fail(c, LSLU_EINVAL, "operator belongs to another context");
+  if (op->d.kind != 2) return fail(c, LSLU_EUNSUPPORTED, "only PSF operators have a tile shape");
+  if (c->pending)
+    return fail(c, LSLU_EINVAL, "an asynchronous solve is pending on this context (lslu_wait)");
+  if (rows_per_lane != 0 && rows_per_lane != 2 && rows_per_lane != 4 && rows_per_lane != 8)
+    return fail(c, LSLU_EINVAL, "rows_per_lane must be 0 (measure), 2, 4 or 8");
+  try {
+    LSLU_HIP(c, hipSetDevice(c->device));
+    int r = rows_per_lane;
+    if (r == 0) {
+      lslu_status st = tune_psf(c, op, &r);
+      if (st != LSLU_OK) return st;
+    }
+    if (r != op->d.psf_r) drop_op_graphs(c, op->serial);  // captured with the old shape
+    op->d.psf_r = r;
+    if (chosen) *chosen = r;
     return LSLU_OK;
   } catch (const std::bad_alloc&) {
     return fail(c, LSLU_ENOMEM, "host allocation failed");

@@ -91,7 +91,7 @@ void apply_t(const DeviceOp& op, int tr, const T* x, T* y, const int* stop,
       const int R = static_cast<int>(op.rows), C = static_cast<int>(op.cols);
       with_ph(op.ph, [&](auto phc) {
         constexpr int PH = decltype(phc)::value;
-        with_psf_r(R, C, [&](auto rc) {
+        with_psf_r(op.psf_r, R, C, [&](auto rc) {
           constexpr int PR = decltype(rc)::value;
           dim3 g((C + kPsfTW - 1) / kPsfTW, (R + psf_th<PR>() - 1) / psf_th<PR>());
           k_psf_corr<T, Acc, PH, kB, PR><<<g, kPsfWaves * kWave,

@@ -892,10 +892,10 @@ int launch_tiles_r(HalfArgs<T>& a, const PsfPixels<Acc, kIn>& op, const Acc* Wt,
 }
 
 template <typename T, typename Acc, int PH, int kIn>
-int launch_tiles(HalfArgs<T>& a, const PsfPixels<Acc, kIn>& op, const Acc* Wt,
+int launch_tiles(HalfArgs<T>& a, const PsfPixels<Acc, kIn>& op, const Acc* Wt, int psf_r,
                  size_t lds_bytes, hipStream_t s) {
   int n = 0;
-  with_psf_r(op.rows, op.cols, [&](auto rc) {
+  with_psf_r(psf_r, op.rows, op.cols, [&](auto rc) {
     n = launch_tiles_r<T, Acc, PH, kIn, decltype(rc)::value>(a, op, Wt, lds_bytes, s);
   });
   return n;
@@ -928,7 +928,7 @@ int launch_half(HalfArgs<T>& a, const DeviceOp& op, int tr, size_t lds_bytes,
                             op.ph, op.pw};
       with_ph(op.ph, [&](auto phc) {
         constexpr int PH = decltype(phc)::value;
-        nparts = launch_tiles<T, Acc, PH, kB>(a, ro, wt, lds_bytes, s);
+        nparts = launch_tiles<T, Acc, PH, kB>(a, ro, wt, op.psf_r, lds_bytes, s);
       });
     }
   });
