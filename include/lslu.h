@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LSLU_ABI_VERSION 8
+#define LSLU_ABI_VERSION 9
 
 typedef enum lslu_status {
   LSLU_OK = 0,
@@ -281,6 +281,19 @@ typedef struct lslu_result {
 lslu_status lslu_solve(lslu_ctx* ctx, const lslu_op* op, const void* b_dev,
                        const void* x0_dev, const lslu_opts* opts,
                        void* x_out_dev, lslu_result* res);
+
+/* lslu_solve with host arrays: b_host (m doubles), x0_host (n doubles, or
+ * NULL for x_0 = 0) and x_out_host (n doubles, written) are converted to and
+ * from the working precision (rounded to float outside FP64) and moved
+ * through device staging buffers that the context keeps and reuses (so
+ * repeated calls replay the same captured solve).  The device pointers in
+ * opts (x_true_dev, X_dev) stay device pointers.  Synchronous: the
+ * returned status is lslu_solve's, and x_out_host is written when it is not
+ * negative.  Errors: as lslu_solve, plus LSLU_ENONFINITE for NaN/Inf in b or
+ * x0 and LSLU_EINVAL with LSLU_FLAG_ASYNC. */
+lslu_status lslu_solve_host(lslu_ctx* ctx, const lslu_op* op, const double* b_host,
+                            const double* x0_host, const lslu_opts* opts,
+                            double* x_out_host, lslu_result* res);
 
 /* Completes the pending LSLU_FLAG_ASYNC solve of the context: waits for its
  * stream, fills the lslu_result given to lslu_solve and returns the solve's

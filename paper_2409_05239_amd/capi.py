@@ -42,7 +42,7 @@ EXPORTS = (
     "lslu_create", "lslu_destroy", "lslu_last_error", "lslu_status_name",
     "lslu_abi_version", "lslu_op_dense", "lslu_op_csr", "lslu_op_psf",
     "lslu_op_apply", "lslu_op_info", "lslu_op_destroy", "lslu_solve",
-    "lslu_wait", "lslu_get_basis", "lslu_vjp", "lslu_op_tile",
+    "lslu_wait", "lslu_get_basis", "lslu_vjp", "lslu_op_tile", "lslu_solve_host",
 )
 
 
@@ -144,6 +144,9 @@ def _load():
         "lslu_wait": (c_int, [vp]),
         "lslu_vjp": (c_int, [vp, vp, c_int32, vp, vp, POINTER(c_double)]),
         "lslu_op_tile": (c_int, [vp, vp, c_int32, POINTER(c_int32)]),
+        "lslu_solve_host": (c_int, [vp, vp, POINTER(c_double), POINTER(c_double),
+                                    POINTER(lslu_opts), POINTER(c_double),
+                                    POINTER(lslu_result)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -288,13 +291,20 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
     ``asynchronous=True`` enqueues the solve and returns a ``Pending``;
     ``lslu_wait(ctx, pending)`` completes it and returns the same triple.
     ``grad_lambda=True`` (needs ``x_true``) adds ``info["dloss_dlambda"]``.
+    With ``b`` (and ``x0``) given as NumPy arrays the call goes through
+    ``lslu_solve_host`` (host arrays in FP64, synchronous) and ``x_out`` is a
+    NumPy array.
     Returns ``(status, x_out, info)`` where ``info`` holds the host-side
     results as NumPy arrays."""
     import torch
     m, n, prec = lslu_op_info(op)
     K = int(maxiter)
+    host_io = isinstance(b, np.ndarray)
+    if host_io and asynchronous:
+        raise ValueError("host arrays need a synchronous solve")
     if x_out is None:
-        x_out = torch.empty(n, dtype=_torch_dtype(prec), device=b.device)
+        x_out = (np.empty(n) if host_io
+                 else torch.empty(n, dtype=_torch_dtype(prec), device=b.device))
     o = lslu_opts()
     o.maxiter = K
     o.reg = REGS[reg] if isinstance(reg, str) else int(reg)
@@ -341,6 +351,15 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
         ct = c_int32 if arr.dtype == np.int32 else c_double
         setattr(r, name, arr.ctypes.data_as(POINTER(ct)))
     _SERIAL[ctx.value] = _SERIAL.get(ctx.value, 0) + 1  # any solve replaces the last
+    if host_io:
+        bh, pb = _np(b, np.float64)
+        x0h = None if x0 is None else _np(x0, np.float64)
+        if x_out.dtype != np.float64 or not x_out.flags.c_contiguous or x_out.shape != (n,):
+            raise ValueError("x_out must be a contiguous float64 array of n entries")
+        st = _check(ctx, lib.lslu_solve_host(
+            ctx, op, pb, None if x0h is None else x0h[1], ctypes.byref(o),
+            x_out.ctypes.data_as(POINTER(c_double)), ctypes.byref(r)))
+        return st, x_out, _info(st, r, host, timing)
     st = _check(ctx, lib.lslu_solve(ctx, op, _dptr(b), _dptr(x0), ctypes.byref(o),
                                     _dptr(x_out), ctypes.byref(r)))
     if asynchronous:

@@ -149,6 +149,10 @@ struct lslu_ctx {
   unsigned char* adj = nullptr;
   size_t adj_bytes = 0;
   double* adj_host = nullptr;
+  // device staging of lslu_solve_host (b, x_0, x_out), grown on demand and
+  // reused, so that its solves keep replaying the same captured graph
+  unsigned char* hio = nullptr;
+  size_t hio_bytes = 0;
   // captured solve (replayed while the key matches)
   // captured solves, replayed while the key (pointers, sizes, options)
   // matches; the least recently captured is dropped beyond kGraphCache
@@ -692,6 +696,7 @@ lslu_status lslu_destroy(lslu_ctx* c) {
   drop_graph(c);
   if (c->ws) (void)hipFree(c->ws);
   if (c->adj) (void)hipFree(c->adj);
+  if (c->hio) (void)hipFree(c->hio);
   if (c->host) (void)hipHostFree(c->host);
   if (c->adj_host) (void)hipHostFree(c->adj_host);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -1138,6 +1143,65 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
       return LSLU_OK;
     }
     return complete_solve(c, K, res, &pe);
+  } catch (const std::bad_alloc&) {
+    return fail(c, LSLU_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(c, LSLU_EDEVICE, "unexpected exception");
+  }
+}
+
+lslu_status lslu_solve_host(lslu_ctx* c, const lslu_op* op, const double* b,
+                            const double* x0, const lslu_opts* o, double* x_out,
+                            lslu_result* res) {
+  if (!c) return LSLU_EINVAL;
+  if (!op || !b || !o || !x_out) return fail(c, LSLU_EINVAL, "NULL argument");
+  if (op->ctx != c) return fail(c, LSLU_EINVAL, "operator belongs to another context");
+  if (o->flags & LSLU_FLAG_ASYNC)
+    return fail(c, LSLU_EINVAL, "lslu_solve_host is synchronous (no LSLU_FLAG_ASYNC)");
+  const int64_t m = op->d.m, n = op->d.n;
+  if (!finite_all(b, m) || (x0 && !finite_all(x0, n)))
+    return fail(c, LSLU_ENONFINITE, "b or x0 has NaN/Inf");
+  try {
+    LSLU_HIP(c, hipSetDevice(c->device));
+    const bool dbl = op->d.prec == kFP64;
+    const size_t esz = dbl ? sizeof(double) : sizeof(float);
+    const size_t ob = align_up(esz * m, 256), ox = align_up(esz * n, 256);
+    const size_t need = ob + 2 * ox;
+    if (need > c->hio_bytes) {
+      if (c->hio) LSLU_HIP(c, hipFree(c->hio));
+      c->hio = nullptr;
+      c->hio_bytes = 0;
+      LSLU_HIP(c, hipMalloc(&c->hio, need));
+      c->hio_bytes = need;
+    }
+    unsigned char* bd = c->hio;
+    unsigned char* x0d = c->hio + ob;
+    unsigned char* xd = c->hio + ob + ox;
+    // working precision: FP64, or each value rounded to float
+    auto put = [&](void* dst, const double* src, int64_t len) -> lslu_status {
+      if (dbl) {
+        LSLU_HIP(c, hipMemcpy(dst, src, sizeof(double) * len, hipMemcpyHostToDevice));
+      } else {
+        std::vector<float> t(static_cast<size_t>(len));
+        for (int64_t i = 0; i < len; ++i) t[i] = static_cast<float>(src[i]);
+        LSLU_HIP(c, hipMemcpy(dst, t.data(), sizeof(float) * len, hipMemcpyHostToDevice));
+      }
+      return LSLU_OK;
+    };
+    LSLU_HIP(c, hipStreamSynchronize(c->stream));
+    lslu_status st = put(bd, b, m);
+    if (st == LSLU_OK && x0) st = put(x0d, x0, n);
+    if (st != LSLU_OK) return st;
+    const lslu_status ss = lslu_solve(c, op, bd, x0 ? x0d : nullptr, o, xd, res);
+    if (ss < 0) return ss;
+    if (dbl) {
+      LSLU_HIP(c, hipMemcpy(x_out, xd, sizeof(double) * n, hipMemcpyDeviceToHost));
+    } else {
+      std::vector<float> t(static_cast<size_t>(n));
+      LSLU_HIP(c, hipMemcpy(t.data(), xd, sizeof(float) * n, hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < n; ++i) x_out[i] = t[i];
+    }
+    return ss;
   } catch (const std::bad_alloc&) {
     return fail(c, LSLU_ENOMEM, "host allocation failed");
   } catch (...) {

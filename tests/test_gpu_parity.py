@@ -429,3 +429,37 @@ def test_graph_cache_never_replays_a_destroyed_operator(lib, ctx):
         finally:
             lib.lslu_op_destroy(op)
             lib.lslu_op_destroy(spacer)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_host_array_solve_matches_device_solve(lib, ctx, prec):
+    """lslu_solve_host: FP64 host arrays in and out, converted to the working
+    precision exactly as a device tensor of that precision would be."""
+    import torch
+    prob = config_problem("tomo32")
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    op = lib.make_operator(ctx, prob, lib.PRECISIONS[prec])
+    try:
+        x0 = np.random.default_rng(3).standard_normal(prob.n) * 0.01
+        grid = lambda_grid()
+        sh, xh, ih = lib.lslu_solve(ctx, op, prob.b, 15, reg="wgcv", grid=grid,
+                                    grid_relative=True, x0=x0)
+        b = torch.tensor(prob.b, dtype=dt, device="cuda")
+        x0d = torch.tensor(x0, dtype=dt, device="cuda")
+        sd, xd, idd = lib.lslu_solve(ctx, op, b, 15, reg="wgcv", grid=grid,
+                                     grid_relative=True, x0=x0d)
+        torch.cuda.synchronize()
+        assert sh == sd and ih["k_done"] == idd["k_done"]
+        assert np.array_equal(ih["piv_t"], idd["piv_t"]) and np.array_equal(ih["H"], idd["H"])
+        assert np.array_equal(xh, xd.double().cpu().numpy())
+        # repeated calls reuse the staging buffers (and the captured solve)
+        sh2, xh2, _ = lib.lslu_solve(ctx, op, prob.b, 15, reg="wgcv", grid=grid,
+                                     grid_relative=True, x0=x0)
+        assert np.array_equal(xh, xh2)
+        bad = prob.b.copy()
+        bad[3] = np.nan
+        with pytest.raises(lib.LsluError) as ei:
+            lib.lslu_solve(ctx, op, bad, 15, reg="wgcv", grid=grid, grid_relative=True)
+        assert ei.value.status == lib.LSLU_ENONFINITE
+    finally:
+        lib.lslu_op_destroy(op)
