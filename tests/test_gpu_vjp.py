@@ -255,3 +255,53 @@ def test_vjp_is_deterministic_and_checks_its_arguments(lib, ctx):
             lib.lslu_vjp(ctx, op3, 5, xb)
     finally:
         lib.lslu_op_destroy(op3)
+
+
+def test_vjp_with_x0_and_sampled_pivots(lib, ctx):
+    """The reverse pass holds whatever pivots the solve took (here the sampled
+    rule of Section 2.2) and x_0 fixed: b enters only through r_0 = b - A x_0."""
+    import torch
+    from workloads import pivot_sample_lists
+    prob = tomography(16, 12, 23, 0.02, seed=5)
+    K, lam = 10, 0.05
+    op = lib.make_operator(ctx, prob, lib.PRECISIONS["fp64"])
+    try:
+        x0 = np.random.default_rng(2).standard_normal(prob.n) * 0.05
+        rows = pivot_sample_lists(prob.m, prob.n, K, 6, seed=4)
+        b = torch.tensor(prob.b, dtype=torch.float64, device="cuda")
+        st, x, info = lib.lslu_solve(ctx, op, b, K, reg="fixed", lam=lam, pivot_sample=(rows, 6),
+                                     x0=torch.tensor(x0, device="cuda"))
+        k = info["k_done"]
+        pt, pg = _pivots(info)
+        xbar = np.random.default_rng(3).standard_normal(prob.n)
+        g, lb = _vjp(lib, ctx, op, k, xbar, "fp64")
+        oop = make_operator(prob)
+        ref = vjp_full(oop, prob.b, k, lam, pt, pg, xbar, x0=x0)
+        assert np.abs(g - ref).max() <= 1e-9 * np.abs(ref).max()
+        lref = vjp_lambda(oop, prob.b, k, lam, pt, pg, xbar, x0=x0)
+        assert abs(lb - lref) <= 1e-9 * abs(lref)
+    finally:
+        lib.lslu_op_destroy(op)
+
+
+@pytest.mark.parametrize("prec", ["bf16op", "fp16op"])
+def test_vjp_16bit_operator_error(lib, ctx, prec):
+    """16-bit operator modes: the reverse pass uses the same rounded products,
+    so it approximates the FP64 derivative to the operator's precision; the
+    error is reported and bounded loosely."""
+    prob = config_problem("deblur96")
+    K, lam = 20, 0.05
+    op = lib.make_operator(ctx, prob, lib.PRECISIONS[prec])
+    try:
+        info = _solve(lib, ctx, op, prob, prec, K, lam=lam)
+        pt, pg = _pivots(info)
+        k = info["k_done"]
+        xbar = 2.0 * (info["X"][:, k - 1] - prob.x_true)
+        g, lb = _vjp(lib, ctx, op, k, xbar, prec)
+        v = np.random.default_rng(4).standard_normal(prob.m)
+        ref = vjp_directional(make_operator(prob), prob.b, k, lam, pt, pg, xbar, v)
+        e = abs(v @ g - ref) / (np.linalg.norm(v) * np.linalg.norm(g))
+        print(f"[vjp] deblur96 {prec}: direction error {e:.2e}")
+        assert e <= 5e-2
+    finally:
+        lib.lslu_op_destroy(op)
