@@ -371,10 +371,12 @@ def run_vjp(args):
 
 def run_batch(args):
     """Many uneven problems (workloads.batch_problems: tomography and deblurring
-    of different sizes), BF16 operator with FP32 bases, 60 iterations each:
-    asynchronous solves on several contexts (one stream each) against the
-    same solves one at a time, and against one-at-a-time plain FP64 solves.
-    Prints one JSON line; value = problem-iterations/s of the concurrent run."""
+    of different sizes), BF16 operator with FP32 bases, 60 iterations each.
+    value: all problems as asynchronous solves on S contexts (one stream
+    each), in waves of S.  Also timed: the same one at a time, FP64 one at a
+    time, and for the tomography (CSR) half alone the merged batch
+    (lslu_solve_batch: each recurrence launch covers every problem) against
+    waves on S contexts and one at a time.  Prints one JSON line."""
     import numpy as np
     import torch
 
@@ -385,19 +387,23 @@ def run_batch(args):
     probs = batch_problems(P, seed=0)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    ctxs = [capi.lslu_create(0) for _ in range(S)]
     grid = lambda_grid()
+    rr = [capi.lslu_create(0) for _ in range(S)]  # round-robin contexts
 
-    def prepare(prec):
+    def prepare(prec, ctxs, sel):
         dt = torch.float64 if prec == "fp64" else torch.float32
         items = []
-        for i, prob in enumerate(probs):
-            c = ctxs[i % S]
+        for i, prob in enumerate(sel):
+            c = ctxs[i % len(ctxs)]
             op = capi.make_operator(c, prob, capi.PRECISIONS[prec])
             items.append((c, op, torch.tensor(prob.b, dtype=dt, device=dev),
                           torch.zeros((K, prob.n), dtype=dt, device=dev)))
         torch.cuda.synchronize()
         return items
+
+    def release(items):
+        for it in items:
+            capi.lslu_op_destroy(it[1])
 
     def solve(it, asynchronous=False):
         c, op, b, X = it
@@ -415,6 +421,11 @@ def run_batch(args):
             for it, pd in zip(wave, pend):
                 capi.lslu_wait(it[0], pd)
 
+    def merged(items):
+        capi.lslu_solve_batch([it[0] for it in items], [it[1] for it in items],
+                              [it[2] for it in items], K, reg="wgcv", grid=grid,
+                              grid_relative=True)
+
     def timed(fn, items):
         for _ in range(args.warmup):
             fn(items)
@@ -425,28 +436,38 @@ def run_batch(args):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / args.steps
 
-    lo = prepare("bf16op")
+    def errors(items, sel):
+        errs = []
+        for it, prob in zip(items, sel):
+            X = it[3].double().cpu().numpy()
+            e = np.linalg.norm(X - prob.x_true[None, :], axis=1) / np.linalg.norm(prob.x_true)
+            errs.append(float(e.min()))
+        return errs
+
+    lo = prepare("bf16op", rr, probs)
     t_conc = timed(concurrent, lo)
     t_seq = timed(one_at_a_time, lo)
-    errs = []
-    for it, prob in zip(lo, probs):
-        X = it[3].double().cpu().numpy()
-        e = np.linalg.norm(X - prob.x_true[None, :], axis=1) / np.linalg.norm(prob.x_true)
-        errs.append(float(e.min()))
-    for it in lo:
-        capi.lslu_op_destroy(it[1])
-    hi = prepare("fp64")
+    errs = errors(lo, probs)
+    release(lo)
+    hi = prepare("fp64", rr, probs)
     t_64 = timed(one_at_a_time, hi)
-    errs64 = []
-    for it, prob in zip(hi, probs):
-        X = it[3].double().cpu().numpy()
-        e = np.linalg.norm(X - prob.x_true[None, :], axis=1) / np.linalg.norm(prob.x_true)
-        errs64.append(float(e.min()))
-    for it in hi:
-        capi.lslu_op_destroy(it[1])
-    for c in ctxs:
+    errs64 = errors(hi, probs)
+    release(hi)
+    tomo = [p for p in probs if p.kind == "csr"]
+    own = [capi.lslu_create(0) for _ in tomo]  # the merged batch: one context each
+    mo = prepare("bf16op", own, tomo)
+    t_tm = timed(merged, mo)
+    release(mo)
+    for c in own:
+        capi.lslu_destroy(c)
+    to = prepare("bf16op", rr, tomo)
+    t_tc = timed(concurrent, to)
+    t_ts = timed(one_at_a_time, to)
+    release(to)
+    for c in rr:
         capi.lslu_destroy(c)
     it_total = P * K
+    it_tomo = len(tomo) * K
     out = {
         "metric": "Batched Hybrid LSLU problem-iterations/s (uneven problems, concurrent contexts)",
         "value": round(it_total / t_conc, 1),
@@ -464,6 +485,10 @@ def run_batch(args):
                    "iters": K, "contexts": S, "reg": "wgcv", "grid_relative": True},
         "one_at_a_time": {"value": round(it_total / t_seq, 1), "ms_per_step": round(t_seq * 1e3, 3)},
         "fp64_one_at_a_time": {"value": round(it_total / t_64, 1), "ms_per_step": round(t_64 * 1e3, 3)},
+        "tomography_half": {"problems": len(tomo),
+                            "merged_launches": round(it_tomo / t_tm, 1),
+                            "concurrent": round(it_tomo / t_tc, 1),
+                            "one_at_a_time": round(it_tomo / t_ts, 1)},
         "median_min_rel_err": {"bf16op": float(np.median(errs)), "fp64": float(np.median(errs64))},
     }
     print(json.dumps(out), flush=True)

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LSLU_ABI_VERSION 9
+#define LSLU_ABI_VERSION 10
 
 typedef enum lslu_status {
   LSLU_OK = 0,
@@ -294,6 +294,25 @@ lslu_status lslu_solve(lslu_ctx* ctx, const lslu_op* op, const void* b_dev,
 lslu_status lslu_solve_host(lslu_ctx* ctx, const lslu_op* op, const double* b_host,
                             const double* x0_host, const lslu_opts* opts,
                             double* x_out_host, lslu_result* res);
+
+/* Solves count problems together: problem i is op[i] (created on ctxs[i]),
+ * b_dev[i] (m_i entries, wp), x_out_dev[i] (n_i entries, wp, written) and
+ * res[i] (may be NULL, or res itself NULL), all with the same opts.  Launch
+ * j of the recurrence (one per half-iteration, Algorithm 5) of every problem
+ * runs in one merged kernel launch whose blocks are split among the problems,
+ * so many small problems fill the GPU together (on ctxs[0]'s stream); the
+ * projected problems and the assembly of each problem then run on its own
+ * context's stream.  Results are bit-identical to solving each problem
+ * alone.  Each problem needs its own context (its workspace); the call
+ * returns when all are done.  Requirements: dense or CSR operators of one kind and one
+ * precision on one device; opts without x_true_dev, X_dev, sampled pivots,
+ * replays, LSLU_REG_OPTIMAL and the ASYNC, TIMING and GRAD_LAMBDA flags;
+ * x_0 = 0.  Returns LSLU_OK, or the first negative status of a problem
+ * (message on ctxs[0]); breakdowns are reported per problem in res[i].
+ * Errors: LSLU_EINVAL, LSLU_ENOMEM, LSLU_EDEVICE. */
+lslu_status lslu_solve_batch(int32_t count, lslu_ctx* const* ctxs, const lslu_op* const* ops,
+                             const void* const* b_dev, const lslu_opts* opts,
+                             void* const* x_out_dev, lslu_result* const* res);
 
 /* Completes the pending LSLU_FLAG_ASYNC solve of the context: waits for its
  * stream, fills the lslu_result given to lslu_solve and returns the solve's

@@ -43,6 +43,7 @@ EXPORTS = (
     "lslu_abi_version", "lslu_op_dense", "lslu_op_csr", "lslu_op_psf",
     "lslu_op_apply", "lslu_op_info", "lslu_op_destroy", "lslu_solve",
     "lslu_wait", "lslu_get_basis", "lslu_vjp", "lslu_op_tile", "lslu_solve_host",
+    "lslu_solve_batch",
 )
 
 
@@ -147,6 +148,9 @@ def _load():
         "lslu_solve_host": (c_int, [vp, vp, POINTER(c_double), POINTER(c_double),
                                     POINTER(lslu_opts), POINTER(c_double),
                                     POINTER(lslu_result)]),
+        "lslu_solve_batch": (c_int, [c_int32, POINTER(c_void_p), POINTER(c_void_p),
+                                     POINTER(c_void_p), POINTER(lslu_opts), POINTER(c_void_p),
+                                     POINTER(POINTER(lslu_result))]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -366,6 +370,59 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
         # everything the library may still write or read stays referenced
         return Pending(r, host, keep, x_out, (b, x0, X, x_true), timing)
     return st, x_out, _info(st, r, host, timing)
+
+
+def lslu_solve_batch(ctxs, ops, bs, maxiter, reg="none", lam=0.0, grid=None,
+                     grid_relative=False, omega=0.0, stop_tol=0.0, early_stop=False):
+    """Solve len(ops) problems together (merged recurrence launches); one
+    context per problem, all dense or all CSR in one precision.  ``bs`` are
+    device tensors.  Returns ``(status, [(x_out, info), ...])``."""
+    import torch
+    P = len(ops)
+    K = int(maxiter)
+    o = lslu_opts()
+    o.maxiter = K
+    o.reg = REGS[reg] if isinstance(reg, str) else int(reg)
+    o.lambda_ = float(lam)
+    keep = []
+    if grid is not None:
+        g, pg = _np(grid, np.float64)
+        keep.append(g)
+        o.lambda_grid = pg
+        o.n_grid = g.shape[0]
+    o.grid_relative = 1 if grid_relative else 0
+    o.omega = float(omega)
+    o.stop_tol = float(stop_tol)
+    o.early_stop = 1 if early_stop else 0
+    xs, rs, hosts = [], [], []
+    for op, b in zip(ops, bs):
+        m, n, prec = lslu_op_info(op)
+        xs.append(torch.empty(n, dtype=_torch_dtype(prec), device=b.device))
+        r = lslu_result()
+        host = dict(
+            piv_t=np.full(K + 1, -1, np.int32), piv_g=np.full(K, -1, np.int32),
+            own_piv_t=np.full(K + 1, -1, np.int32), own_piv_g=np.full(K, -1, np.int32),
+            H=np.zeros((K, K + 1)), W=np.zeros((K, K)), Y=np.zeros((K, K)),
+            lambda_k=np.zeros(K), lambda_idx=np.zeros(K, np.int32), ghat=np.zeros(K),
+            sep_lambda=np.zeros(K), sigma_max=np.zeros(K), sigma_min=np.zeros(K))
+        for name, arr in host.items():
+            ct = c_int32 if arr.dtype == np.int32 else c_double
+            setattr(r, name, arr.ctypes.data_as(POINTER(ct)))
+        rs.append(r)
+        hosts.append(host)
+    for c in ctxs:
+        _SERIAL[c.value] = _SERIAL.get(c.value, 0) + 1
+    arr_c = (c_void_p * P)(*[c.value for c in ctxs])
+    arr_o = (c_void_p * P)(*[op.value for op in ops])
+    arr_b = (c_void_p * P)(*[b.data_ptr() for b in bs])
+    arr_x = (c_void_p * P)(*[x.data_ptr() for x in xs])
+    arr_r = (POINTER(lslu_result) * P)(*[ctypes.pointer(r) for r in rs])
+    st = _check(ctxs[0], lib.lslu_solve_batch(P, arr_c, arr_o, arr_b, ctypes.byref(o),
+                                              arr_x, arr_r))
+    out = []
+    for x, r, host in zip(xs, rs, hosts):
+        out.append((x, _info(r.status, r, host, False)))
+    return st, out
 
 
 class Pending:

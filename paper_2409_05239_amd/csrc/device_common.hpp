@@ -406,6 +406,7 @@ template <typename AccT, int kIn>
 struct PsfPixels {
   using Acc = AccT;
   using Val = AccT;
+  static constexpr int kInMode = kIn;
   const Acc* wt;
   int rows, cols, ph, pw;
   template <int G, typename XF>
@@ -434,6 +435,11 @@ struct PsfPixels {
     return partial<G>(s.row, static_cast<int>(s.next), xf);
   }
 };
+
+template <typename RO>
+struct is_psf_pixels : std::false_type {};
+template <typename AccT, int kIn>
+struct is_psf_pixels<PsfPixels<AccT, kIn>> : std::true_type {};
 
 // --------------------------------------------------------------- PSF tile --
 // An R*4 x 64 output tile and its halo are staged in LDS; each lane owns one

@@ -211,6 +211,23 @@ struct HalfArgs {
 template <typename T>
 int launch_half(HalfArgs<T>& a, const DeviceOp& op, int transpose,
                 size_t lds_bytes, hipStream_t s);
+// The launch launch_half would make, without making it: sets a.nlead and
+// returns its consumer count (the candidates it writes).
+template <typename T>
+int plan_half(HalfArgs<T>& a, const DeviceOp& op, int transpose, size_t lds_bytes);
+// Row access of an operator as the batched kernels read it (device copies,
+// one per solve): its size, and the bytes for one direction.
+size_t row_op_bytes(const DeviceOp& op);
+void row_op_write(const DeviceOp& op, int transpose, void* dst);
+// One merged launch of the same half-iteration of P planned solves: dargs
+// (P HalfArgs), dops (P row accesses), dfirst (P + 1 block offsets, the
+// last = blocks) on the device.  a0 and op0 (any of the solves) select the
+// kernel; the solves must share the operator kind (dense or CSR) and
+// precision.
+template <typename T>
+void launch_half_batch(HalfArgs<T>& a0, const DeviceOp& op0, int transpose, size_t lds_bytes,
+                       const HalfArgs<T>* dargs, const void* dops, const int* dfirst, int P,
+                       int blocks, hipStream_t s);
 void recurrence_init_attributes(size_t lds_bytes);
 
 // Basis recurrence helpers (basis.hip).

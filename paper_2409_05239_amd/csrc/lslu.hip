@@ -149,6 +149,9 @@ struct lslu_ctx {
   unsigned char* adj = nullptr;
   size_t adj_bytes = 0;
   double* adj_host = nullptr;
+  // merged-launch arguments of lslu_solve_batch, grown on demand
+  unsigned char* bat = nullptr;
+  size_t bat_bytes = 0;
   // device staging of lslu_solve_host (b, x_0, x_out), grown on demand and
   // reused, so that its solves keep replaying the same captured graph
   unsigned char* hio = nullptr;
@@ -200,6 +203,17 @@ lslu_status fail(lslu_ctx* c, lslu_status s, const std::string& msg) {
                   std::string(#expr) + ": " + hipGetErrorString(e_));        \
   } while (0)
 
+// Host <-> device copy ordered on the context's stream and waited for.  (A
+// copy on the null stream would synchronise with every blocking stream,
+// which breaks a graph being captured on another context's stream by
+// another thread.)
+lslu_status copy_sync(lslu_ctx* c, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+  if (bytes == 0) return LSLU_OK;
+  LSLU_HIP(c, hipMemcpyAsync(dst, src, bytes, kind, c->stream));
+  LSLU_HIP(c, hipStreamSynchronize(c->stream));
+  return LSLU_OK;
+}
+
 bool finite_all(const double* p, int64_t count) {
   for (int64_t i = 0; i < count; ++i)
     if (!std::isfinite(p[i])) return false;
@@ -232,7 +246,10 @@ std::vector<unsigned char> convert_values(const double* v, int64_t count, int pr
 
 lslu_status upload(lslu_ctx* c, void** dst, const void* src, size_t bytes) {
   LSLU_HIP(c, hipMalloc(dst, bytes > 0 ? bytes : 1));
-  if (bytes) LSLU_HIP(c, hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+  if (bytes) {
+    const lslu_status st = copy_sync(c, *dst, src, bytes, hipMemcpyHostToDevice);
+    if (st != LSLU_OK) return st;
+  }
   return LSLU_OK;
 }
 
@@ -314,11 +331,24 @@ struct PhaseEvents {
   }
 };
 
+// One half-iteration launch as planned for a merged (batched) launch.
+template <typename T>
+struct PlannedHalf {
+  HalfArgs<T> a;
+  int tr;
+  int ncons;
+};
+
+// part 0: the whole solve on stream s (default: the context's stream);
+// part 1: the set-up kernels, with the half-iteration launches planned into
+// rec instead of launched; part 2: everything after the recurrence.
 template <typename T>
 void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
                    const lslu_opts* o, T* x_out, T* X, bool replay_t,
-                   bool replay_g, bool replay_lam, PhaseEvents* pe) {
-  const hipStream_t s = c->stream;
+                   bool replay_g, bool replay_lam, PhaseEvents* pe,
+                   hipStream_t s_in = nullptr, int part = 0,
+                   std::vector<PlannedHalf<T>>* rec = nullptr) {
+  const hipStream_t s = s_in ? s_in : c->stream;
   const Layout& l = c->lay;
   const int K = c->K;
   const int64_t m = c->m, n = c->n;
@@ -330,6 +360,7 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
   DevState* st = l.st;
   const size_t lds = c->lds_max;
 
+  if (part != 2) {
   launch_state_reset(st, s);
   launch_fill<unsigned char>(l.mask_t, 0, m, s);
   launch_fill<unsigned char>(l.mask_g, 0, n, s);
@@ -406,7 +437,12 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
     a.pslot = reinterpret_cast<uint64_t*>(a.entries + 2 * (K + 1));
     a.fail = l.flags + launch++;
     a.parts_out = parts[cur ^ 1];
-    nparts = launch_half<T>(a, op, tr, lds, s);
+    if (rec) {
+      nparts = plan_half<T>(a, op, tr, lds);
+      rec->push_back(PlannedHalf<T>{a, tr, nparts});
+    } else {
+      nparts = launch_half<T>(a, op, tr, lds, s);
+    }
     cur ^= 1;
   };
 
@@ -474,6 +510,8 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
   run(af, 1);
   pe->launches = launch;
   pe->mark(1, s);
+  }
+  if (part == 1) return;
 
   ProjParams pp{};
   pp.K = K;
@@ -697,6 +735,7 @@ lslu_status lslu_destroy(lslu_ctx* c) {
   if (c->ws) (void)hipFree(c->ws);
   if (c->adj) (void)hipFree(c->adj);
   if (c->hio) (void)hipFree(c->hio);
+  if (c->bat) (void)hipFree(c->bat);
   if (c->host) (void)hipHostFree(c->host);
   if (c->adj_host) (void)hipHostFree(c->adj_host);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -1180,11 +1219,11 @@ lslu_status lslu_solve_host(lslu_ctx* c, const lslu_op* op, const double* b,
     // working precision: FP64, or each value rounded to float
     auto put = [&](void* dst, const double* src, int64_t len) -> lslu_status {
       if (dbl) {
-        LSLU_HIP(c, hipMemcpy(dst, src, sizeof(double) * len, hipMemcpyHostToDevice));
+        return copy_sync(c, dst, src, sizeof(double) * len, hipMemcpyHostToDevice);
       } else {
         std::vector<float> t(static_cast<size_t>(len));
         for (int64_t i = 0; i < len; ++i) t[i] = static_cast<float>(src[i]);
-        LSLU_HIP(c, hipMemcpy(dst, t.data(), sizeof(float) * len, hipMemcpyHostToDevice));
+        return copy_sync(c, dst, t.data(), sizeof(float) * len, hipMemcpyHostToDevice);
       }
       return LSLU_OK;
     };
@@ -1195,10 +1234,12 @@ lslu_status lslu_solve_host(lslu_ctx* c, const lslu_op* op, const double* b,
     const lslu_status ss = lslu_solve(c, op, bd, x0 ? x0d : nullptr, o, xd, res);
     if (ss < 0) return ss;
     if (dbl) {
-      LSLU_HIP(c, hipMemcpy(x_out, xd, sizeof(double) * n, hipMemcpyDeviceToHost));
+      const lslu_status cs = copy_sync(c, x_out, xd, sizeof(double) * n, hipMemcpyDeviceToHost);
+      if (cs != LSLU_OK) return cs;
     } else {
       std::vector<float> t(static_cast<size_t>(n));
-      LSLU_HIP(c, hipMemcpy(t.data(), xd, sizeof(float) * n, hipMemcpyDeviceToHost));
+      const lslu_status cs = copy_sync(c, t.data(), xd, sizeof(float) * n, hipMemcpyDeviceToHost);
+      if (cs != LSLU_OK) return cs;
       for (int64_t i = 0; i < n; ++i) x_out[i] = t[i];
     }
     return ss;
@@ -1206,6 +1247,152 @@ lslu_status lslu_solve_host(lslu_ctx* c, const lslu_op* op, const double* b,
     return fail(c, LSLU_ENOMEM, "host allocation failed");
   } catch (...) {
     return fail(c, LSLU_EDEVICE, "unexpected exception");
+  }
+}
+
+lslu_status lslu_solve_batch(int32_t count, lslu_ctx* const* ctxs, const lslu_op* const* ops,
+                             const void* const* b, const lslu_opts* o, void* const* x_out,
+                             lslu_result* const* res) {
+  if (count < 1 || !ctxs || !ctxs[0]) return LSLU_EINVAL;
+  lslu_ctx* c0 = ctxs[0];
+  if (!ops || !b || !o || !x_out) return fail(c0, LSLU_EINVAL, "NULL argument");
+  if (o->flags & (LSLU_FLAG_ASYNC | LSLU_FLAG_TIMING | LSLU_FLAG_GRAD_LAMBDA))
+    return fail(c0, LSLU_EINVAL, "batched solves take no ASYNC, TIMING or GRAD_LAMBDA flag");
+  if (o->reg == LSLU_REG_OPTIMAL || o->x_true_dev || o->X_dev || o->sample_rows ||
+      o->replay_piv_t || o->replay_piv_g || o->replay_lambda_idx)
+    return fail(c0, LSLU_EINVAL,
+                "batched solves take no per-problem device arrays in opts (x_true_dev, X_dev), "
+                "sampled pivots or replays");
+  for (int i = 0; i < count; ++i) {
+    lslu_ctx* c = ctxs[i];
+    if (!c || !ops[i] || !b[i] || !x_out[i]) return fail(c0, LSLU_EINVAL, "NULL argument");
+    if (ops[i]->ctx != c) return fail(c0, LSLU_EINVAL, "operator belongs to another context");
+    if (c->device != c0->device) return fail(c0, LSLU_EINVAL, "contexts on different devices");
+    if (c->pending) return fail(c0, LSLU_EINVAL, "an asynchronous solve is pending");
+    if (ops[i]->d.kind == 2 || ops[i]->d.kind != ops[0]->d.kind || ops[i]->d.prec != ops[0]->d.prec)
+      return fail(c0, LSLU_EINVAL,
+                  "a batch needs dense or CSR operators of one kind and one precision");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == c) return fail(c0, LSLU_EINVAL, "each problem needs its own context");
+    const lslu_status vs = validate_opts(c, ops[i], o);
+    if (vs != LSLU_OK) return fail(c0, vs, "problem " + std::to_string(i) + ": " + c->err);
+  }
+  try {
+    LSLU_HIP(c0, hipSetDevice(c0->device));
+    const int K = o->maxiter;
+    const int P = count;
+    const size_t esz = prec_size(ops[0]->d.prec);
+    const hipStream_t s = c0->stream;
+    std::vector<double> grid;
+    if (o->reg == LSLU_REG_WGCV || o->reg == LSLU_REG_GCV)
+      grid.assign(o->lambda_grid, o->lambda_grid + o->n_grid);
+    for (int i = 0; i < P; ++i) {
+      lslu_ctx* c = ctxs[i];
+      const lslu_status ws = ensure_ws(c, ops[i]->d.m, ops[i]->d.n, K, esz, true);
+      if (ws != LSLU_OK) return fail(c0, ws, c->err);
+      LSLU_HIP(c0, hipStreamSynchronize(c->stream));  // nothing else uses the workspace
+      if (!grid.empty())
+      {
+        const lslu_status cs = copy_sync(c, c->lay.grid, grid.data(),
+                                         sizeof(double) * grid.size(), hipMemcpyHostToDevice);
+        if (cs != LSLU_OK) return fail(c0, cs, c->err);
+      }
+      c->up_grid.clear();  // the single-solve upload cache no longer describes it
+      c->last_ok = false;
+      c->last_op = ops[i];
+    }
+    auto run = [&](auto tag) -> lslu_status {
+      using T = decltype(tag);
+      std::vector<std::vector<PlannedHalf<T>>> plans(P);
+      PhaseEvents none;
+      for (int i = 0; i < P; ++i)
+        enqueue_solve<T>(ctxs[i], ops[i]->d, static_cast<const T*>(b[i]), nullptr, o,
+                         static_cast<T*>(x_out[i]), static_cast<T*>(ctxs[i]->lay.X), false,
+                         false, false, &none, s, 1, &plans[i]);
+      const size_t nh = plans[0].size();
+      for (int i = 1; i < P; ++i)
+        if (plans[i].size() != nh) return fail(c0, LSLU_EDEVICE, "inconsistent batch plan");
+      // device copies: every launch's P argument blocks, the row access of
+      // each operator in both directions, and the block offsets
+      const size_t opb = row_op_bytes(ops[0]->d);
+      const size_t sz_args = sizeof(HalfArgs<T>) * nh * P;
+      const size_t off_ops = align_up(sz_args, 256);
+      const size_t off_first = align_up(off_ops + 2 * opb * P, 256);
+      const size_t total = off_first + sizeof(int) * nh * (P + 1);
+      std::vector<unsigned char> hb(total, 0);
+      std::vector<int> blocks(nh);
+      for (size_t h = 0; h < nh; ++h) {
+        int* first = reinterpret_cast<int*>(hb.data() + off_first) + h * (P + 1);
+        int off = 0;
+        for (int i = 0; i < P; ++i) {
+          const PlannedHalf<T>& ph = plans[i][h];
+          if (ph.tr != plans[0][h].tr) return fail(c0, LSLU_EDEVICE, "inconsistent batch plan");
+          std::memcpy(hb.data() + sizeof(HalfArgs<T>) * (h * P + i), &ph.a, sizeof(HalfArgs<T>));
+          first[i] = off;
+          off += ph.a.nlead + ph.ncons;
+        }
+        first[P] = off;
+        blocks[h] = off;
+      }
+      for (int tr = 0; tr < 2; ++tr)
+        for (int i = 0; i < P; ++i)
+          row_op_write(ops[i]->d, tr, hb.data() + off_ops + opb * (tr * P + i));
+      if (total > c0->bat_bytes) {
+        if (c0->bat) LSLU_HIP(c0, hipFree(c0->bat));
+        c0->bat = nullptr;
+        c0->bat_bytes = 0;
+        LSLU_HIP(c0, hipMalloc(&c0->bat, total));
+        c0->bat_bytes = total;
+      }
+      {
+        const lslu_status cs = copy_sync(c0, c0->bat, hb.data(), total, hipMemcpyHostToDevice);
+        if (cs != LSLU_OK) return cs;
+      }
+      const HalfArgs<T>* dargs = reinterpret_cast<const HalfArgs<T>*>(c0->bat);
+      for (size_t h = 0; h < nh; ++h) {
+        const int tr = plans[0][h].tr;
+        launch_half_batch<T>(plans[0][h].a, ops[0]->d, tr, c0->lds_max, dargs + h * P,
+                             c0->bat + off_ops + opb * tr * P,
+                             reinterpret_cast<const int*>(c0->bat + off_first) + h * (P + 1), P,
+                             blocks[h], s);
+      }
+      // The projected problems and the assembly of each problem on its own
+      // context's stream, after the merged recurrence.
+      hipEvent_t done = nullptr;
+      LSLU_HIP(c0, hipEventCreateWithFlags(&done, hipEventDisableTiming));
+      struct EvGuard {
+        hipEvent_t e;
+        ~EvGuard() { (void)hipEventDestroy(e); }
+      } evg{done};
+      LSLU_HIP(c0, hipEventRecord(done, s));
+      for (int i = 0; i < P; ++i) {
+        lslu_ctx* c = ctxs[i];
+        LSLU_HIP(c0, hipStreamWaitEvent(c->stream, done, 0));
+        enqueue_solve<T>(c, ops[i]->d, static_cast<const T*>(b[i]), nullptr, o,
+                         static_cast<T*>(x_out[i]), static_cast<T*>(c->lay.X), false, false,
+                         false, &none, c->stream, 2, nullptr);
+        LSLU_HIP(c0, hipMemcpyAsync(c->host, c->lay.res, c->lay.res_bytes,
+                                    hipMemcpyDeviceToHost, c->stream));
+      }
+      LSLU_HIP(c0, hipGetLastError());
+      for (int i = 0; i < P; ++i) LSLU_HIP(c0, hipStreamSynchronize(ctxs[i]->stream));
+      return LSLU_OK;
+    };
+    const lslu_status rs = esz == sizeof(double) ? run(double{}) : run(float{});
+    if (rs != LSLU_OK) return rs;
+    lslu_status worst = LSLU_OK;
+    for (int i = 0; i < P; ++i) {
+      const lslu_status st = complete_solve(ctxs[i], K, res ? res[i] : nullptr, nullptr);
+      if (st < 0 && worst >= 0) {
+        worst = st;
+        c0->err = "problem " + std::to_string(i) + ": " + ctxs[i]->err;
+      }
+    }
+    return worst;
+  } catch (const std::bad_alloc&) {
+    return fail(c0, LSLU_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(c0, LSLU_EDEVICE, "unexpected exception");
   }
 }
 

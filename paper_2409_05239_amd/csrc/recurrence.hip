@@ -38,6 +38,7 @@
 // unnormalised vector) is issued before the wait.  Every wait is bounded: a
 // wait that runs out counts a device error and the launch finishes.  Results
 // do not depend on timing or on the launch configuration.
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -423,10 +424,11 @@ __device__ void lead(const HalfArgs<T>& a, DevState* st, unsigned char* lds) {
 }
 
 // ------------------------------------------------- pivot-entry blocks -----
+// bid: this block's index within its solve's blocks (1..nlead-1).
 template <typename T, class RowOp>
-__device__ void pivot_entries(const HalfArgs<T>& a, const RowOp& op, DevState* st) {
+__device__ void pivot_entries(const HalfArgs<T>& a, const RowOp& op, DevState* st, int bid) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-  const int jr = (blockIdx.x - 1) * kWaves + w;
+  const int jr = (bid - 1) * kWaves + w;
   const bool act = jr < a.nb;
   RowStage<typename RowOp::Val, T, kEntryStage> sg;
   if (act) op.template stage<kWave, kEntryStage>(a.piv[jr], lane, a.up, sg);
@@ -660,7 +662,7 @@ __global__ __launch_bounds__(kThreads, half_min_waves<T>()) void k_half_rows(Hal
   if (blockIdx.x == 0)
     lead<T, kTriLds>(a, st, lds);
   else if ((int)blockIdx.x < a.nlead)
-    pivot_entries<T, RowOp>(a, op, st);
+    pivot_entries<T, RowOp>(a, op, st, blockIdx.x);
   else
     consume_rows<G, T, RowOp>(a, op, st, blockIdx.x - a.nlead, gridDim.x - a.nlead);
 }
@@ -802,13 +804,49 @@ __global__ __launch_bounds__(kThreads) void k_half_psf(
   if (blockIdx.x == 0)
     lead<T, kTriLds>(a, st, lds);
   else if ((int)blockIdx.x < a.nlead)
-    pivot_entries<T, PsfPixels<Acc, kIn>>(a, op, st);
+    pivot_entries<T, PsfPixels<Acc, kIn>>(a, op, st, blockIdx.x);
   else
     consume_tiles<T, Acc, PH, kIn, R>(a, Wt, op.rows, op.cols, op.pw, st,
                                      blockIdx.x - a.nlead, gridDim.x - a.nlead, lds);
 }
 
 static_assert(kPsfWaves * kWave == kThreads, "PSF tiles use the launch's block size");
+
+// ------------------------------------------------ several solves at once --
+// One launch of the same half-iteration of P solves: solve p owns blocks
+// first[p] .. first[p+1]-1 and runs exactly the roles of its own launch
+// (lead, pivot entries, consumers) on its own workspace.  Every wait is on a
+// lower-numbered block of the same solve, dispatched earlier, so the merged
+// launch needs no more residency than the single ones.
+__device__ inline int batch_solve_of_block(const int* __restrict__ first, int P) {
+  int lo = 0, hi = P - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= (int)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T, class RowOp, bool kTriLds, int G>
+__global__ __launch_bounds__(kThreads, half_min_waves<T>()) void k_half_rows_batch(
+    const HalfArgs<T>* __restrict__ args, const RowOp* __restrict__ ops,
+    const int* __restrict__ first, int P) {
+  extern __shared__ unsigned char lds[];
+  const int p = batch_solve_of_block(first, P);
+  const HalfArgs<T>& a = args[p];
+  const RowOp& op = ops[p];
+  DevState* st = a.job.st;
+  if (st->stopped) return;
+  const int bid = (int)blockIdx.x - first[p], nblk = first[p + 1] - first[p];
+  if (bid == 0)
+    lead<T, kTriLds>(a, st, lds);
+  else if (bid < a.nlead)
+    pivot_entries<T, RowOp>(a, op, st, bid);
+  else
+    consume_rows<G, T, RowOp>(a, op, st, bid - a.nlead, nblk - a.nlead);
+}
+
 
 // ------------------------------------------------------------- launchers --
 template <typename T>
@@ -843,15 +881,30 @@ int consumer_blocks(int64_t want, int nlead, int resident) {
   return static_cast<int>(c);
 }
 
+// Batched launches (launch_half_batch) pass the merged launch instead of s.
+template <typename T, class RowOp>
+struct RowsBatch {
+  const HalfArgs<T>* args;
+  const RowOp* ops;
+  const int* first;
+  int P, blocks;
+};
+
 template <typename T, class RowOp, int G>
-int launch_rows_g(HalfArgs<T>& a, const RowOp& op, size_t tb, bool in_lds, hipStream_t s) {
+int launch_rows_g(HalfArgs<T>& a, const RowOp& op, size_t tb, bool in_lds, hipStream_t s,
+                  bool dry = false, const RowsBatch<T, RowOp>* batch = nullptr) {
   constexpr int kRows = kThreads / G;
   const int64_t want = a.rows > 0 ? (a.rows + kRows - 1) / kRows
                                   : (a.lenp + kThreads * kNormBatch - 1) / (kThreads * kNormBatch);
   auto k = in_lds ? k_half_rows<T, RowOp, true, G> : k_half_rows<T, RowOp, false, G>;
   const size_t dyn = in_lds ? tb : 0;
   const int ncons = consumer_blocks(want, a.nlead, resident_blocks((const void*)k, dyn));
-  k<<<a.nlead + ncons, kThreads, dyn, s>>>(a, op);
+  if (batch) {
+    auto kb = in_lds ? k_half_rows_batch<T, RowOp, true, G> : k_half_rows_batch<T, RowOp, false, G>;
+    kb<<<batch->blocks, kThreads, dyn, s>>>(batch->args, batch->ops, batch->first, batch->P);
+  } else if (!dry) {
+    k<<<a.nlead + ncons, kThreads, dyn, s>>>(a, op);
+  }
   return ncons;
 }
 
@@ -859,17 +912,18 @@ int launch_rows_g(HalfArgs<T>& a, const RowOp& op, size_t tb, bool in_lds, hipSt
 // tomography one pass over the rows, measured slower: the longer per-lane
 // chains of dependent loads cost more than the second pass.)
 template <typename T, class RowOp>
-int launch_rows(HalfArgs<T>& a, const RowOp& op, size_t lds_bytes, hipStream_t s) {
+int launch_rows(HalfArgs<T>& a, const RowOp& op, size_t lds_bytes, hipStream_t s,
+                bool dry = false, const RowsBatch<T, RowOp>* batch = nullptr) {
   const int nbk = a.rows > 0 ? a.nb : 0;
   a.nlead = 1 + (nbk + kWaves - 1) / kWaves;
   const size_t tb = tri_bytes<T>(nbk);
   const bool in_lds = tb > 0 && tb <= kTriLdsMax && tb + 16 * 1024 <= lds_bytes;
-  return launch_rows_g<T, RowOp, 16>(a, op, tb, in_lds, s);
+  return launch_rows_g<T, RowOp, 16>(a, op, tb, in_lds, s, dry, batch);
 }
 
 template <typename T, typename Acc, int PH, int kIn, int R>
 int launch_tiles_r(HalfArgs<T>& a, const PsfPixels<Acc, kIn>& op, const Acc* Wt,
-                   size_t lds_bytes, hipStream_t s) {
+                   size_t lds_bytes, hipStream_t s, bool dry = false) {
   const int ntiles = ((op.cols + kPsfTW - 1) / kPsfTW) * ((op.rows + psf_th<R>() - 1) / psf_th<R>());
   const int64_t want = a.rows > 0 ? ntiles
                                   : (a.lenp + kThreads * kNormBatch - 1) / (kThreads * kNormBatch);
@@ -882,23 +936,73 @@ int launch_tiles_r(HalfArgs<T>& a, const PsfPixels<Acc, kIn>& op, const Acc* Wt,
     auto k = k_half_psf<T, Acc, PH, kIn, true, R>;
     const size_t dyn = std::max(tb, pb);
     const int ncons = consumer_blocks(want, a.nlead, resident_blocks((const void*)k, dyn));
-    k<<<a.nlead + ncons, kThreads, dyn, s>>>(a, op, Wt);
+    if (!dry) k<<<a.nlead + ncons, kThreads, dyn, s>>>(a, op, Wt);
     return ncons;
   }
   auto k = k_half_psf<T, Acc, PH, kIn, false, R>;
   const int ncons = consumer_blocks(want, a.nlead, resident_blocks((const void*)k, pb));
-  k<<<a.nlead + ncons, kThreads, pb, s>>>(a, op, Wt);
+  if (!dry) k<<<a.nlead + ncons, kThreads, pb, s>>>(a, op, Wt);
   return ncons;
 }
 
 template <typename T, typename Acc, int PH, int kIn>
 int launch_tiles(HalfArgs<T>& a, const PsfPixels<Acc, kIn>& op, const Acc* Wt, int psf_r,
-                 size_t lds_bytes, hipStream_t s) {
+                 size_t lds_bytes, hipStream_t s, bool dry = false) {
   int n = 0;
   with_psf_r(psf_r, op.rows, op.cols, [&](auto rc) {
-    n = launch_tiles_r<T, Acc, PH, kIn, decltype(rc)::value>(a, op, Wt, lds_bytes, s);
+    n = launch_tiles_r<T, Acc, PH, kIn, decltype(rc)::value>(a, op, Wt, lds_bytes, s, dry);
   });
   return n;
+}
+
+// The row access of an operator for one direction (tr: A^T), and its
+// value / sum types, passed to f(row_op).
+template <typename T, typename F>
+void with_row_op(const DeviceOp& op, int tr, F&& f) {
+  with_mode<T>(op.prec, [&](auto v, auto acc, auto bf) {
+    using V = decltype(v);
+    using Acc = decltype(acc);
+    constexpr int kB = decltype(bf)::value;
+    if (op.kind == 0) {
+      f(DenseRows<V, Acc, kB>{static_cast<const V*>(tr ? op.AT : op.A), tr ? op.m : op.n});
+    } else if (op.kind == 1) {
+      f(CsrRows<V, Acc, kB>{tr ? op.rpT : op.rp, tr ? op.ciT : op.ci,
+                            static_cast<const V*>(tr ? op.valT : op.val)});
+    } else {
+      const Acc* wt;
+      if constexpr (std::is_same_v<Acc, double>)
+        wt = tr ? op.psf : op.psf_flip;
+      else
+        wt = tr ? op.psf32 : op.psf32_flip;
+      f(PsfPixels<Acc, kB>{wt, static_cast<int>(op.rows), static_cast<int>(op.cols), op.ph,
+                           op.pw});
+    }
+  });
+}
+
+// mode 0: launch; 1: plan only (sets a.nlead, returns the consumer count);
+// 2: the merged launch of a batch (a and op stand for every solve of it).
+template <typename T>
+int half_dispatch(HalfArgs<T>& a, const DeviceOp& op, int tr, size_t lds_bytes, hipStream_t s,
+                  int mode, const void* bargs, const void* bops, const int* bfirst, int P,
+                  int blocks) {
+  int nparts = 0;
+  with_row_op<T>(op, tr, [&](auto ro) {
+    using RO = decltype(ro);
+    if constexpr (is_psf_pixels<RO>::value) {
+      // (merged launches are built for the row operators only)
+      with_ph(op.ph, [&](auto phc) {
+        constexpr int PH = decltype(phc)::value;
+        nparts = launch_tiles<T, typename RO::Acc, PH, RO::kInMode>(a, ro, ro.wt, op.psf_r,
+                                                                    lds_bytes, s, mode != 0);
+      });
+    } else {
+      RowsBatch<T, RO> b{static_cast<const HalfArgs<T>*>(bargs), static_cast<const RO*>(bops),
+                         bfirst, P, blocks};
+      nparts = launch_rows<T, RO>(a, ro, lds_bytes, s, mode == 1, mode == 2 ? &b : nullptr);
+    }
+  });
+  return nparts;
 }
 
 }  // namespace
@@ -906,33 +1010,35 @@ int launch_tiles(HalfArgs<T>& a, const PsfPixels<Acc, kIn>& op, const Acc* Wt, i
 template <typename T>
 int launch_half(HalfArgs<T>& a, const DeviceOp& op, int tr, size_t lds_bytes,
                 hipStream_t s) {
-  int nparts = 0;
-  with_mode<T>(op.prec, [&](auto v, auto acc, auto bf) {
-    using V = decltype(v);
-    using Acc = decltype(acc);
-    constexpr int kB = decltype(bf)::value;
-    if (op.kind == 0) {
-      DenseRows<V, Acc, kB> ro{static_cast<const V*>(tr ? op.AT : op.A), tr ? op.m : op.n};
-      nparts = launch_rows<T, decltype(ro)>(a, ro, lds_bytes, s);
-    } else if (op.kind == 1) {
-      CsrRows<V, Acc, kB> ro{tr ? op.rpT : op.rp, tr ? op.ciT : op.ci,
-                             static_cast<const V*>(tr ? op.valT : op.val)};
-      nparts = launch_rows<T, decltype(ro)>(a, ro, lds_bytes, s);
-    } else {
-      const Acc* wt;
-      if constexpr (std::is_same_v<Acc, double>)
-        wt = tr ? op.psf : op.psf_flip;
-      else
-        wt = tr ? op.psf32 : op.psf32_flip;
-      PsfPixels<Acc, kB> ro{wt, static_cast<int>(op.rows), static_cast<int>(op.cols),
-                            op.ph, op.pw};
-      with_ph(op.ph, [&](auto phc) {
-        constexpr int PH = decltype(phc)::value;
-        nparts = launch_tiles<T, Acc, PH, kB>(a, ro, wt, op.psf_r, lds_bytes, s);
-      });
-    }
-  });
-  return nparts;
+  return half_dispatch<T>(a, op, tr, lds_bytes, s, 0, nullptr, nullptr, nullptr, 0, 0);
+}
+
+template <typename T>
+int plan_half(HalfArgs<T>& a, const DeviceOp& op, int tr, size_t lds_bytes) {
+  return half_dispatch<T>(a, op, tr, lds_bytes, nullptr, 1, nullptr, nullptr, nullptr, 0, 0);
+}
+
+size_t row_op_bytes(const DeviceOp& op) {
+  size_t n = 0;
+  if (op.prec == kFP64)
+    with_row_op<double>(op, 0, [&](auto ro) { n = sizeof(ro); });
+  else
+    with_row_op<float>(op, 0, [&](auto ro) { n = sizeof(ro); });
+  return n;
+}
+
+void row_op_write(const DeviceOp& op, int tr, void* dst) {
+  if (op.prec == kFP64)
+    with_row_op<double>(op, tr, [&](auto ro) { std::memcpy(dst, &ro, sizeof(ro)); });
+  else
+    with_row_op<float>(op, tr, [&](auto ro) { std::memcpy(dst, &ro, sizeof(ro)); });
+}
+
+template <typename T>
+void launch_half_batch(HalfArgs<T>& a0, const DeviceOp& op0, int tr, size_t lds_bytes,
+                       const HalfArgs<T>* dargs, const void* dops, const int* dfirst, int P,
+                       int blocks, hipStream_t s) {
+  (void)half_dispatch<T>(a0, op0, tr, lds_bytes, s, 2, dargs, dops, dfirst, P, blocks);
 }
 
 void recurrence_init_attributes(size_t lds_bytes) {
@@ -943,5 +1049,13 @@ void recurrence_init_attributes(size_t lds_bytes) {
 
 template int launch_half<double>(HalfArgs<double>&, const DeviceOp&, int, size_t, hipStream_t);
 template int launch_half<float>(HalfArgs<float>&, const DeviceOp&, int, size_t, hipStream_t);
+template int plan_half<double>(HalfArgs<double>&, const DeviceOp&, int, size_t);
+template int plan_half<float>(HalfArgs<float>&, const DeviceOp&, int, size_t);
+template void launch_half_batch<double>(HalfArgs<double>&, const DeviceOp&, int, size_t,
+                                        const HalfArgs<double>*, const void*, const int*, int,
+                                        int, hipStream_t);
+template void launch_half_batch<float>(HalfArgs<float>&, const DeviceOp&, int, size_t,
+                                       const HalfArgs<float>*, const void*, const int*, int,
+                                       int, hipStream_t);
 
 }  // namespace lslu

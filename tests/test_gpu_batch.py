@@ -99,3 +99,79 @@ def test_pending_solve_rules(lib):
             lib.lslu_op_destroy(op)
     finally:
         lib.lslu_destroy(c)
+
+
+def _tomo_set(count, seed):
+    from workloads import tomography
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        side = int(rng.integers(20, 49))
+        out.append(tomography(side, side, side + 1, 0.02, seed=seed * 1000 + i))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16op", "fp64"])
+def test_merged_launch_batch_matches_single_solves(lib, prec):
+    """lslu_solve_batch runs launch j of every problem's recurrence in one
+    kernel launch: each problem's results must equal its solve alone."""
+    import torch
+    from workloads import random_dense
+    probs = _tomo_set(6, 7) if prec != "fp64" else [random_dense(60 + 7 * i, 40 + 3 * i, seed=i)
+                                                    for i in range(5)]
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    ctxs = [lib.lslu_create(0) for _ in probs]
+    ops = []
+    try:
+        for c, prob in zip(ctxs, probs):
+            ops.append(lib.make_operator(c, prob, lib.PRECISIONS[prec]))
+        bs = [torch.tensor(p.b, dtype=dt, device="cuda") for p in probs]
+        grid = lambda_grid()
+        print(f"[batch] merged {prec}: " + ", ".join(p.name for p in probs), flush=True)
+        st, out = lib.lslu_solve_batch(ctxs, ops, bs, K, reg="wgcv", grid=grid, grid_relative=True)
+        torch.cuda.synchronize()
+        for i, (c, op, b) in enumerate(zip(ctxs, ops, bs)):
+            st1, x1, i1 = lib.lslu_solve(c, op, b, K, reg="wgcv", grid=grid, grid_relative=True)
+            torch.cuda.synchronize()
+            xb, ib = out[i]
+            assert ib["k_done"] == i1["k_done"], i
+            assert np.array_equal(ib["piv_t"], i1["piv_t"]) and np.array_equal(ib["piv_g"], i1["piv_g"])
+            assert np.array_equal(ib["H"], i1["H"]) and np.array_equal(ib["lambda_k"], i1["lambda_k"])
+            assert torch.equal(xb, x1), i
+        # a second batch on the same contexts reuses their workspaces
+        st2, out2 = lib.lslu_solve_batch(ctxs, ops, bs, K, reg="wgcv", grid=grid, grid_relative=True)
+        torch.cuda.synchronize()
+        for (xa, ia), (xb2, ib2) in zip(out, out2):
+            assert torch.equal(xa, xb2) and np.array_equal(ia["H"], ib2["H"])
+    finally:
+        for op in ops:
+            lib.lslu_op_destroy(op)
+        for c in ctxs:
+            lib.lslu_destroy(c)
+
+
+def test_merged_launch_batch_rejects_what_it_cannot_merge(lib):
+    import torch
+    from workloads import psf_deblur, random_dense
+    probs = [random_dense(30, 20, seed=1), psf_deblur(16, 2, 1.0, 0.01, seed=2)]
+    ctxs = [lib.lslu_create(0) for _ in range(3)]
+    ops = []
+    try:
+        ops = [lib.make_operator(ctxs[0], probs[0], lib.LSLU_FP64),
+               lib.make_operator(ctxs[1], probs[1], lib.LSLU_FP64),
+               lib.make_operator(ctxs[2], probs[0], lib.LSLU_FP32)]
+        bs = [torch.tensor(p.b, dtype=torch.float64, device="cuda") for p in probs]
+        for sel in ([0, 1], [0, 2]):  # a PSF operator; mixed precisions
+            with pytest.raises(lib.LsluError) as ei:
+                lib.lslu_solve_batch([ctxs[i] for i in sel], [ops[i] for i in sel],
+                                     [bs[0], bs[0]], 5)
+            assert ei.value.status == lib.LSLU_EINVAL
+        op_b = lib.make_operator(ctxs[0], probs[0], lib.LSLU_FP64)
+        ops.append(op_b)
+        with pytest.raises(lib.LsluError):  # two problems on one context
+            lib.lslu_solve_batch([ctxs[0], ctxs[0]], [ops[0], op_b], [bs[0], bs[0]], 5)
+    finally:
+        for op in ops:
+            lib.lslu_op_destroy(op)
+        for c in ctxs:
+            lib.lslu_destroy(c)
