@@ -32,7 +32,7 @@ namespace lslu {
 
 namespace {
 
-constexpr int kPT = 256;            // threads per projected problem
+constexpr int kPT = 512;            // threads per projected problem
 constexpr int kBL = 8;              // lanes per column (row) of a reflector update
 constexpr int kSectRounds1 = 8;     // multisection rounds for sigma_1
 constexpr int kSectRoundsMin = 8;   // multisection rounds for sigma_min
