@@ -139,8 +139,9 @@ lslu_status lslu_op_psf(lslu_ctx* ctx, int64_t rows, int64_t cols, int32_t ph,
 /* Tile shape of a PSF operator's products (in lslu_op_apply and inside
  * lslu_solve): each lane of a 4-wavefront block computes rows_per_lane = 2, 4
  * or 8 consecutive output rows of a (4 rows_per_lane) x 64 tile.  0 measures
- * the three on the device (one A and one A^T product each, after a warm-up,
- * timed with HIP events on the context's stream) and keeps the fastest.
+ * the three on the device (pairs of A and A^T products after a warm-up, the
+ * fastest of three timings with HIP events on the context's stream) and keeps
+ * the fastest shape.
  * Every shape sums each output in the same order, so results do not depend on
  * it.  *chosen (may be NULL) receives the shape in use.  Synchronous.
  * Errors: LSLU_EUNSUPPORTED (not a PSF operator), LSLU_EINVAL,

@@ -65,13 +65,14 @@ __global__ __launch_bounds__(kAT) void k_dots(const T* __restrict__ B, int64_t r
 #pragma unroll
   for (int u = 0; u < kDotRowsPerThread; ++u) {
     const int64_t r = r0 + threadIdx.x + (int64_t)u * kAT;
-    if (r >= len) break;
-    double v = static_cast<double>(v1[r]);
-    if (v2) v += static_cast<double>(v2[r]);
-    const T* row = B + r * rs + (int64_t)c0 * cs;
+    if (r < len) {  // predicated, so the loads of all rows can be in flight together
+      double v = static_cast<double>(v1[r]);
+      if (v2) v += static_cast<double>(v2[r]);
+      const T* row = B + r * rs + (int64_t)c0 * cs;
 #pragma unroll
-    for (int c = 0; c < kDotCols; ++c)
-      if (c < nc) acc[c] = fma(v, static_cast<double>(row[(int64_t)c * cs]), acc[c]);
+      for (int c = 0; c < kDotCols; ++c)
+        if (c < nc) acc[c] = fma(v, static_cast<double>(row[(int64_t)c * cs]), acc[c]);
+    }
   }
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
@@ -295,10 +296,22 @@ __global__ __launch_bounds__(kAT) void k_adj_update(
     const int pi = inv[r];
     const double cr = (pi >= 0 && pi <= top) ? scr[pi] : 0.0;
     out[r] = static_cast<T>(vt + cr);
-    for (int j = 0; j < p; ++j) {
-      T* e = Bbar + (int64_t)j * ldb + r;
-      const double u = (j < pi) ? vt + cr : vt;
-      *e = static_cast<T>(fma(-sc[j], u, static_cast<double>(*e)));
+    // eight columns at a time: their loads are issued together before the
+    // stores (stores to Bbar could otherwise alias the next column's load)
+    constexpr int kU = 8;
+    for (int j0 = 0; j0 < p; j0 += kU) {
+      T old[kU];
+#pragma unroll
+      for (int q = 0; q < kU; ++q)
+        if (j0 + q < p) old[q] = Bbar[(int64_t)(j0 + q) * ldb + r];
+#pragma unroll
+      for (int q = 0; q < kU; ++q) {
+        const int j = j0 + q;
+        if (j < p) {
+          const double u = (j < pi) ? vt + cr : vt;
+          Bbar[(int64_t)j * ldb + r] = static_cast<T>(fma(-sc[j], u, static_cast<double>(old[q])));
+        }
+      }
     }
   }
 }

@@ -649,14 +649,18 @@ lslu_status tune_psf(lslu_ctx* c, lslu_op* op, int* chosen) {
   for (int r : {2, 4, 8}) {
     op->d.psf_r = r;
     for (int i = 0; i < 2; ++i) op_apply(op->d, i & 1, x, y, nullptr, s);
-    LSLU_HIP(c, hipEventRecord(e0, s));
-    for (int i = 0; i < 6; ++i) op_apply(op->d, i & 1, x, y, nullptr, s);
-    LSLU_HIP(c, hipEventRecord(e1, s));
-    LSLU_HIP(c, hipEventSynchronize(e1));
-    float ms = 0.f;
-    LSLU_HIP(c, hipEventElapsedTime(&ms, e0, e1));
-    if (pick == 0 || ms < best) {
-      best = ms;
+    float fastest = 0.f;
+    for (int trial = 0; trial < 3; ++trial) {  // the fastest of three timings
+      LSLU_HIP(c, hipEventRecord(e0, s));
+      for (int i = 0; i < 4; ++i) op_apply(op->d, i & 1, x, y, nullptr, s);
+      LSLU_HIP(c, hipEventRecord(e1, s));
+      LSLU_HIP(c, hipEventSynchronize(e1));
+      float ms = 0.f;
+      LSLU_HIP(c, hipEventElapsedTime(&ms, e0, e1));
+      if (trial == 0 || ms < fastest) fastest = ms;
+    }
+    if (pick == 0 || fastest < best) {
+      best = fastest;
       pick = r;
     }
   }
