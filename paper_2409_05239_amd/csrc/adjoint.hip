@@ -62,18 +62,23 @@ __global__ __launch_bounds__(kAT) void k_dots(const T* __restrict__ B, int64_t r
   double acc[kDotCols];
 #pragma unroll
   for (int c = 0; c < kDotCols; ++c) acc[c] = 0.0;
+  // all loads of the thread first (rows beyond len and columns beyond nc
+  // read as 0), then the sums, row by row in order
+  double vv[kDotRowsPerThread];
+  T bb[kDotRowsPerThread][kDotCols];
 #pragma unroll
   for (int u = 0; u < kDotRowsPerThread; ++u) {
     const int64_t r = r0 + threadIdx.x + (int64_t)u * kAT;
-    if (r < len) {  // predicated, so the loads of all rows can be in flight together
-      double v = static_cast<double>(v1[r]);
-      if (v2) v += static_cast<double>(v2[r]);
-      const T* row = B + r * rs + (int64_t)c0 * cs;
+    const bool in = r < len;
+    vv[u] = in ? static_cast<double>(v1[r]) + (v2 ? static_cast<double>(v2[r]) : 0.0) : 0.0;
+    const T* row = B + (in ? r : 0) * rs + (int64_t)c0 * cs;
 #pragma unroll
-      for (int c = 0; c < kDotCols; ++c)
-        if (c < nc) acc[c] = fma(v, static_cast<double>(row[(int64_t)c * cs]), acc[c]);
-    }
+    for (int c = 0; c < kDotCols; ++c) bb[u][c] = (in && c < nc) ? row[(int64_t)c * cs] : T(0);
   }
+#pragma unroll
+  for (int u = 0; u < kDotRowsPerThread; ++u)
+#pragma unroll
+    for (int c = 0; c < kDotCols; ++c) acc[c] = fma(vv[u], static_cast<double>(bb[u][c]), acc[c]);
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
   for (int c = 0; c < kDotCols; ++c) {
