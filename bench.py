@@ -426,6 +426,16 @@ def run_batch(args):
                               [it[2] for it in items], K, reg="wgcv", grid=grid,
                               grid_relative=True)
 
+    def merged_groups(groups):
+        # problems of similar size merged, the groups side by side (one host
+        # thread each; the library call releases the interpreter)
+        import threading
+        ths = [threading.Thread(target=merged, args=(g,)) for g in groups]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+
     def timed(fn, items):
         for _ in range(args.warmup):
             fn(items)
@@ -457,6 +467,12 @@ def run_batch(args):
     own = [capi.lslu_create(0) for _ in tomo]  # the merged batch: one context each
     mo = prepare("bf16op", own, tomo)
     t_tm = timed(merged, mo)
+    order = sorted(range(len(tomo)), key=lambda i: tomo[i].m)
+    ng = 4
+    groups = [[mo[i] for i in order[g::ng]] for g in range(ng)]  # interleaved by size
+    groups = [[mo[i] for i in order[g * len(order) // ng:(g + 1) * len(order) // ng]]
+              for g in range(ng)]  # contiguous size classes
+    t_tg = timed(merged_groups, groups)
     release(mo)
     for c in own:
         capi.lslu_destroy(c)
@@ -487,6 +503,7 @@ def run_batch(args):
         "fp64_one_at_a_time": {"value": round(it_total / t_64, 1), "ms_per_step": round(t_64 * 1e3, 3)},
         "tomography_half": {"problems": len(tomo),
                             "merged_launches": round(it_tomo / t_tm, 1),
+                            "merged_by_size_4_threads": round(it_tomo / t_tg, 1),
                             "concurrent": round(it_tomo / t_tc, 1),
                             "one_at_a_time": round(it_tomo / t_ts, 1)},
         "median_min_rel_err": {"bf16op": float(np.median(errs)), "fp64": float(np.median(errs64))},

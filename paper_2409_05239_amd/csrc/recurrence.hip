@@ -833,9 +833,12 @@ __global__ __launch_bounds__(kThreads, half_min_waves<T>()) void k_half_rows_bat
     const HalfArgs<T>* __restrict__ args, const RowOp* __restrict__ ops,
     const int* __restrict__ first, int P) {
   extern __shared__ unsigned char lds[];
-  const int p = batch_solve_of_block(first, P);
-  const HalfArgs<T>& a = args[p];
-  const RowOp& op = ops[p];
+  // p is the same in every lane: loaded by value from a wave-uniform
+  // address, the arguments can live in scalar registers as a kernel
+  // argument would
+  const int p = __builtin_amdgcn_readfirstlane(batch_solve_of_block(first, P));
+  const HalfArgs<T> a = args[p];
+  const RowOp op = ops[p];
   DevState* st = a.job.st;
   if (st->stopped) return;
   const int bid = (int)blockIdx.x - first[p], nblk = first[p + 1] - first[p];
