@@ -301,9 +301,11 @@ lslu_status lslu_solve_host(lslu_ctx* ctx, const lslu_op* op, const double* b_ho
  * res[i] (may be NULL, or res itself NULL), all with the same opts.  Launch
  * j of the recurrence (one per half-iteration, Algorithm 5) of every problem
  * runs in one merged kernel launch whose blocks are split among the problems,
- * so many small problems fill the GPU together (on ctxs[0]'s stream); the
- * projected problems and the assembly of each problem then run on its own
- * context's stream.  Results are bit-identical to solving each problem
+ * so many small problems fill the GPU together.  The problems are split by
+ * size (rows) into up to 4 classes whose merged launches run side by side on
+ * the stream of each class's first context (a merged launch lasts as long as
+ * its largest problem's half-iteration); the projected problems and the
+ * assembly of each problem then run on its own context's stream.  Results are bit-identical to solving each problem
  * alone.  Each problem needs its own context (its workspace); the call
  * returns when all are done.  Requirements: dense or CSR operators of one kind and one
  * precision on one device; opts without x_true_dev, X_dev, sampled pivots,

@@ -1316,31 +1316,58 @@ lslu_status lslu_solve_batch(int32_t count, lslu_ctx* const* ctxs, const lslu_op
       const size_t nh = plans[0].size();
       for (int i = 1; i < P; ++i)
         if (plans[i].size() != nh) return fail(c0, LSLU_EDEVICE, "inconsistent batch plan");
-      // device copies: every launch's P argument blocks, the row access of
-      // each operator in both directions, and the block offsets
+      // Size classes: the problems sorted by rows, split into up to
+      // kBatchStreams groups of consecutive sizes.  Each group's merged
+      // launches go to the stream of its first problem's context, so the
+      // groups run side by side and a group waits only for its own largest
+      // problem at each launch.
+      constexpr int kBatchStreams = 4;
+      std::vector<int> order(P);
+      for (int i = 0; i < P; ++i) order[i] = i;
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return ops[x]->d.m < ops[y]->d.m;
+      });
+      const int G = std::min(kBatchStreams, P);
+      std::vector<std::vector<int>> groups(G);
+      for (int g = 0; g < G; ++g)
+        for (int q = g * P / G; q < (g + 1) * P / G; ++q) groups[g].push_back(order[q]);
+      // device copies per group: every launch's argument blocks, the row
+      // access of each operator in both directions, and the block offsets
       const size_t opb = row_op_bytes(ops[0]->d);
-      const size_t sz_args = sizeof(HalfArgs<T>) * nh * P;
-      const size_t off_ops = align_up(sz_args, 256);
-      const size_t off_first = align_up(off_ops + 2 * opb * P, 256);
-      const size_t total = off_first + sizeof(int) * nh * (P + 1);
-      std::vector<unsigned char> hb(total, 0);
-      std::vector<int> blocks(nh);
-      for (size_t h = 0; h < nh; ++h) {
-        int* first = reinterpret_cast<int*>(hb.data() + off_first) + h * (P + 1);
-        int off = 0;
-        for (int i = 0; i < P; ++i) {
-          const PlannedHalf<T>& ph = plans[i][h];
-          if (ph.tr != plans[0][h].tr) return fail(c0, LSLU_EDEVICE, "inconsistent batch plan");
-          std::memcpy(hb.data() + sizeof(HalfArgs<T>) * (h * P + i), &ph.a, sizeof(HalfArgs<T>));
-          first[i] = off;
-          off += ph.a.nlead + ph.ncons;
-        }
-        first[P] = off;
-        blocks[h] = off;
+      struct Seg {
+        size_t args, ops, first;
+      };
+      std::vector<Seg> seg(G);
+      size_t total = 0;
+      for (int g = 0; g < G; ++g) {
+        const size_t pg = groups[g].size();
+        seg[g].args = align_up(total, 256);
+        seg[g].ops = align_up(seg[g].args + sizeof(HalfArgs<T>) * nh * pg, 256);
+        seg[g].first = align_up(seg[g].ops + 2 * opb * pg, 256);
+        total = seg[g].first + sizeof(int) * nh * (pg + 1);
       }
-      for (int tr = 0; tr < 2; ++tr)
-        for (int i = 0; i < P; ++i)
-          row_op_write(ops[i]->d, tr, hb.data() + off_ops + opb * (tr * P + i));
+      std::vector<unsigned char> hb(total, 0);
+      std::vector<std::vector<int>> blocks(G, std::vector<int>(nh));
+      for (int g = 0; g < G; ++g) {
+        const int pg = static_cast<int>(groups[g].size());
+        for (size_t h = 0; h < nh; ++h) {
+          int* first = reinterpret_cast<int*>(hb.data() + seg[g].first) + h * (pg + 1);
+          int off = 0;
+          for (int q = 0; q < pg; ++q) {
+            const PlannedHalf<T>& ph = plans[groups[g][q]][h];
+            if (ph.tr != plans[0][h].tr) return fail(c0, LSLU_EDEVICE, "inconsistent batch plan");
+            std::memcpy(hb.data() + seg[g].args + sizeof(HalfArgs<T>) * (h * pg + q), &ph.a,
+                        sizeof(HalfArgs<T>));
+            first[q] = off;
+            off += ph.a.nlead + ph.ncons;
+          }
+          first[pg] = off;
+          blocks[g][h] = off;
+        }
+        for (int tr = 0; tr < 2; ++tr)
+          for (int q = 0; q < pg; ++q)
+            row_op_write(ops[groups[g][q]]->d, tr, hb.data() + seg[g].ops + opb * (tr * pg + q));
+      }
       if (total > c0->bat_bytes) {
         if (c0->bat) LSLU_HIP(c0, hipFree(c0->bat));
         c0->bat = nullptr;
@@ -1352,26 +1379,44 @@ lslu_status lslu_solve_batch(int32_t count, lslu_ctx* const* ctxs, const lslu_op
         const lslu_status cs = copy_sync(c0, c0->bat, hb.data(), total, hipMemcpyHostToDevice);
         if (cs != LSLU_OK) return cs;
       }
-      const HalfArgs<T>* dargs = reinterpret_cast<const HalfArgs<T>*>(c0->bat);
+      // events: set-up done (on s), and each group's recurrence done
+      std::vector<hipEvent_t> evs(G + 1, nullptr);
+      struct EvGuard {
+        std::vector<hipEvent_t>& e;
+        ~EvGuard() {
+          for (auto x : e)
+            if (x) (void)hipEventDestroy(x);
+        }
+      } evg{evs};
+      for (auto& e : evs) LSLU_HIP(c0, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      LSLU_HIP(c0, hipEventRecord(evs[G], s));
+      std::vector<hipStream_t> gs(G);
+      for (int g = 0; g < G; ++g) {
+        gs[g] = ctxs[groups[g][0]]->stream;
+        LSLU_HIP(c0, hipStreamWaitEvent(gs[g], evs[G], 0));
+      }
       for (size_t h = 0; h < nh; ++h) {
         const int tr = plans[0][h].tr;
-        launch_half_batch<T>(plans[0][h].a, ops[0]->d, tr, c0->lds_max, dargs + h * P,
-                             c0->bat + off_ops + opb * tr * P,
-                             reinterpret_cast<const int*>(c0->bat + off_first) + h * (P + 1), P,
-                             blocks[h], s);
+        for (int g = 0; g < G; ++g) {
+          const int pg = static_cast<int>(groups[g].size());
+          const int lead = groups[g][0];
+          launch_half_batch<T>(plans[lead][h].a, ops[lead]->d, tr, c0->lds_max,
+                               reinterpret_cast<const HalfArgs<T>*>(c0->bat + seg[g].args) + h * pg,
+                               c0->bat + seg[g].ops + opb * tr * pg,
+                               reinterpret_cast<const int*>(c0->bat + seg[g].first) + h * (pg + 1),
+                               pg, blocks[g][h], gs[g]);
+        }
+      }
+      std::vector<int> group_of(P);
+      for (int g = 0; g < G; ++g) {
+        LSLU_HIP(c0, hipEventRecord(evs[g], gs[g]));
+        for (int i : groups[g]) group_of[i] = g;
       }
       // The projected problems and the assembly of each problem on its own
-      // context's stream, after the merged recurrence.
-      hipEvent_t done = nullptr;
-      LSLU_HIP(c0, hipEventCreateWithFlags(&done, hipEventDisableTiming));
-      struct EvGuard {
-        hipEvent_t e;
-        ~EvGuard() { (void)hipEventDestroy(e); }
-      } evg{done};
-      LSLU_HIP(c0, hipEventRecord(done, s));
+      // context's stream, after its group's recurrence.
       for (int i = 0; i < P; ++i) {
         lslu_ctx* c = ctxs[i];
-        LSLU_HIP(c0, hipStreamWaitEvent(c->stream, done, 0));
+        LSLU_HIP(c0, hipStreamWaitEvent(c->stream, evs[group_of[i]], 0));
         enqueue_solve<T>(c, ops[i]->d, static_cast<const T*>(b[i]), nullptr, o,
                          static_cast<T*>(x_out[i]), static_cast<T*>(c->lay.X), false, false,
                          false, &none, c->stream, 2, nullptr);
