@@ -199,19 +199,20 @@ struct SideArgs {
 
 // The coefficient adjoints of one half-iteration.  All threads reduce the
 // partial dot products (a fixed split of the chunks, added in a fixed
-// order) and stage the triangle; then one wavefront runs the triangular
-// recurrence for corr_j, one pivot row per step: lane l holds j = l, l + 64,
-// ..., and corr_i, final once the rows below i are folded in, is broadcast
-// from its lane by readlane.
+// order) and stage the triangle (tri, tri_cap entries of LDS; rows beyond it
+// are read from memory); then one wavefront runs the triangular recurrence
+// for corr_j, one pivot row per step: lane l holds j = l, l + 64, ..., and
+// corr_i, final once the rows below i are folded in, is broadcast from its
+// lane by readlane.  Writes corr_0..corr_p and 1/pivot, and ends with a
+// barrier.  red: 4 rows of red_ld doubles of LDS.
 template <typename T>
-__global__ __launch_bounds__(kAT) void k_adj_side(SideArgs a) {
-  __shared__ double tri[kTriCap];
-  __shared__ double red[4][kMaxIter + 2];
+__device__ void side_solve(const SideArgs& a, double* tri, int64_t tri_cap, double* red,
+                           int red_ld, double* corr, double* alpha_out) {
   const int tid = threadIdx.x, p = a.p;
   const int ncol = a.has_next ? p + 1 : 0;
   const T* Tp = static_cast<const T*>(a.Tp);
   const int64_t ntri = tri_row(p + 1);  // rows 0..p
-  const bool in_lds = ntri <= kTriCap;
+  const bool in_lds = ntri <= tri_cap;
   if (in_lds)
     for (int64_t e = tid; e < ntri; e += kAT) tri[e] = static_cast<double>(Tp[e]);
   const int nsplit = ncol <= 64 ? 4 : (ncol <= 128 ? 2 : 1);
@@ -220,60 +221,69 @@ __global__ __launch_bounds__(kAT) void k_adj_side(SideArgs a) {
     for (int j = tid % span; j < ncol; j += span) {
       double t = 0.0;
       for (int c = part_i; c < a.nchunks; c += nsplit) t += a.part[(size_t)c * ncol + j];
-      red[part_i][j] = t;
+      red[part_i * red_ld + j] = t;
     }
   }
   __syncthreads();
-  if (tid >= kWave) return;
-  const int lane = tid;
-  auto dot = [&](int j) {
-    double t = 0.0;
-    for (int i = 0; i < nsplit; ++i) t += red[i][j];
-    return t;
-  };
-  double alpha = 0.0, cp = 0.0;
-  if (a.has_next) {
-    alpha = 1.0 / *a.pivval;
-    cp = (a.pivbar ? *a.pivbar : 0.0) - dot(p) * alpha;
-  }
-  constexpr int kQ = kMaxIter / kWave;
-  double acc[kQ];
-#pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    const int j = lane + q * kWave;
-    acc[q] = 0.0;
-    if (j < p) acc[q] = (a.cbar ? a.cbar[j] : 0.0) - (a.has_next ? dot(j) * alpha : 0.0);
-  }
-  for (int i = p; i >= 1; --i) {
-    double ci = cp;
-    if (i < p) {
-      double src = acc[0];
-#pragma unroll
-      for (int q = 1; q < kQ; ++q)
-        if (q == (i >> 6)) src = acc[q];
-      ci = readlane_d(src, i & (kWave - 1));
+  if (tid < kWave) {
+    const int lane = tid;
+    auto dot = [&](int j) {
+      double t = 0.0;
+      for (int i = 0; i < nsplit; ++i) t += red[i * red_ld + j];
+      return t;
+    };
+    double alpha = 0.0, cp = 0.0;
+    if (a.has_next) {
+      alpha = 1.0 / *a.pivval;
+      cp = (a.pivbar ? *a.pivbar : 0.0) - dot(p) * alpha;
     }
-    if ((i < p || a.has_next) && ci != 0.0) {
-      const int64_t row = tri_row(i);
+    constexpr int kQ = kMaxIter / kWave;
+    double acc[kQ];
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) {
-        const int j = lane + q * kWave;
-        if (j < i) {
-          const double t = in_lds ? tri[row + j] : static_cast<double>(Tp[row + j]);
-          acc[q] = fma(-ci, t, acc[q]);
+    for (int q = 0; q < kQ; ++q) {
+      const int j = lane + q * kWave;
+      acc[q] = 0.0;
+      if (j < p) acc[q] = (a.cbar ? a.cbar[j] : 0.0) - (a.has_next ? dot(j) * alpha : 0.0);
+    }
+    for (int i = p; i >= 1; --i) {
+      double ci = cp;
+      if (i < p) {
+        double src = acc[0];
+#pragma unroll
+        for (int q = 1; q < kQ; ++q)
+          if (q == (i >> 6)) src = acc[q];
+        ci = readlane_d(src, i & (kWave - 1));
+      }
+      if ((i < p || a.has_next) && ci != 0.0) {
+        const int64_t row = tri_row(i);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+          const int j = lane + q * kWave;
+          if (j < i) {
+            const double t = in_lds ? tri[row + j] : static_cast<double>(Tp[row + j]);
+            acc[q] = fma(-ci, t, acc[q]);
+          }
         }
       }
     }
-  }
-  if (lane == 0) {
-    *a.alpha = alpha;
-    a.corr[p] = cp;
-  }
+    if (lane == 0) {
+      *alpha_out = alpha;
+      corr[p] = cp;
+    }
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    const int j = lane + q * kWave;
-    if (j < p) a.corr[j] = acc[q];
+    for (int q = 0; q < kQ; ++q) {
+      const int j = lane + q * kWave;
+      if (j < p) corr[j] = acc[q];
+    }
   }
+  __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kAT) void k_adj_side(SideArgs a) {
+  __shared__ double tri[kTriCap];
+  __shared__ double red[4 * (kMaxIter + 2)];
+  side_solve<T>(a, tri, kTriCap, red, kMaxIter + 2, a.corr, a.alpha);
 }
 
 // Streaming part of one half-iteration, with the pivot-row terms folded in:
@@ -303,6 +313,57 @@ __global__ __launch_bounds__(kAT) void k_adj_update(
     out[r] = static_cast<T>(vt + cr);
     // eight columns at a time: their loads are issued together before the
     // stores (stores to Bbar could otherwise alias the next column's load)
+    constexpr int kU = 8;
+    for (int j0 = 0; j0 < p; j0 += kU) {
+      T old[kU];
+#pragma unroll
+      for (int q = 0; q < kU; ++q)
+        if (j0 + q < p) old[q] = Bbar[(int64_t)(j0 + q) * ldb + r];
+#pragma unroll
+      for (int q = 0; q < kU; ++q) {
+        const int j = j0 + q;
+        if (j < p) {
+          const double u = (j < pi) ? vt + cr : vt;
+          Bbar[(int64_t)j * ldb + r] = static_cast<T>(fma(-sc[j], u, static_cast<double>(old[q])));
+        }
+      }
+    }
+  }
+}
+
+// k_adj_side and k_adj_update in one launch for small p: every block forms
+// the coefficient adjoints itself (the same sums in the same order, so all
+// blocks hold bitwise the same values) and then streams its rows; no block
+// waits for another.  Dynamic LDS: fused_lds_doubles(p).
+__host__ __device__ inline int64_t fused_lds_doubles(int p) {
+  return tri_row(p + 1) + 4 * (int64_t)(p + 2) + (p + 2) + p;
+}
+constexpr int kFusedMaxP = 64;
+
+template <typename T>
+__global__ __launch_bounds__(kAT) void k_adj_side_update(
+    SideArgs a, int64_t len, int top, const T* __restrict__ v1, const T* __restrict__ v2,
+    const double* __restrict__ coef, const int* __restrict__ inv, T* __restrict__ Bbar,
+    int64_t ldb, T* __restrict__ out) {
+  extern __shared__ double dyn[];
+  __shared__ double s_alpha;
+  const int p = a.p;
+  double* tri = dyn;
+  double* red = tri + tri_row(p + 1);
+  double* scr = red + 4 * (p + 2);
+  double* sc = scr + (p + 2);
+  for (int j = threadIdx.x; j < p; j += kAT) sc[j] = coef[j];
+  side_solve<T>(a, tri, tri_row(p + 1), red, p + 2, scr, &s_alpha);
+  const double alpha = s_alpha;
+  for (int64_t r = (int64_t)blockIdx.x * kAT + threadIdx.x; r < len;
+       r += (int64_t)gridDim.x * kAT) {
+    double v = 0.0;
+    if (v1) v = static_cast<double>(v1[r]);
+    if (v2) v += static_cast<double>(v2[r]);
+    const double vt = alpha * v;
+    const int pi = inv[r];
+    const double cr = (pi >= 0 && pi <= top) ? scr[pi] : 0.0;
+    out[r] = static_cast<T>(vt + cr);
     constexpr int kU = 8;
     for (int j0 = 0; j0 < p; j0 += kU) {
       T old[kU];
@@ -370,6 +431,19 @@ int run_vjp(const VjpArgs& v, hipStream_t s) {
     return ch;
   };
 
+  // the coefficient adjoints, then the streaming update of one half-iteration
+  auto side_update = [&](const SideArgs& a, int64_t len, int top, const T* v1, const T* v2,
+                         const double* coef, const int* inv, T* Bbar, int64_t ldb, T* out) {
+    if (a.p <= kFusedMaxP) {
+      k_adj_side_update<T><<<stream_grid(len), kAT, sizeof(double) * fused_lds_doubles(a.p), s>>>(
+          a, len, top, v1, v2, coef, inv, Bbar, ldb, out);
+    } else {
+      k_adj_side<T><<<1, kAT, 0, s>>>(a);
+      k_adj_update<T><<<stream_grid(len), kAT, 0, s>>>(len, a.p, top, a.alpha, v1, v2, coef,
+                                                       a.corr, inv, Bbar, ldb, out);
+    }
+  };
+
   launch_fill<T>(Dbar, T(0), v.ldd * (int64_t)(K + 1), s);
   launch_fill<int>(v.inv_t, -1, v.m, s);
   launch_fill<int>(v.inv_g, -1, v.n, s);
@@ -396,11 +470,8 @@ int run_vjp(const VjpArgs& v, hipStream_t s) {
       a.Tp = v.TD;
       a.alpha = v.scal + 2;
       a.corr = v.corr;
-      k_adj_side<T><<<1, kAT, 0, s>>>(a);
-      const double* coef = v.H + (size_t)(kk - 1) * ldh;
-      k_adj_update<T><<<stream_grid(v.m), kAT, 0, s>>>(v.m, kk, a.has_next ? kk : kk - 1,
-                                                       v.scal + 2, v1, pm_in, coef, v.corr,
-                                                       v.inv_t, Dbar, v.ldd, um);
+      side_update(a, v.m, a.has_next ? kk : kk - 1, v1, pm_in, v.H + (size_t)(kk - 1) * ldh,
+                  v.inv_t, Dbar, v.ldd, um);
       op_apply(*v.op, 1, um, pn, nullptr, s);
     }
     // l-side of iteration kk: b = l, p = kk - 1, c = W(1:kk-1, kk), pivot W(kk, kk)
@@ -417,10 +488,7 @@ int run_vjp(const VjpArgs& v, hipStream_t s) {
       a.Tp = v.TL;
       a.alpha = v.scal + 2;
       a.corr = v.corr;
-      k_adj_side<T><<<1, kAT, 0, s>>>(a);
-      const double* coef = v.W + (size_t)(kk - 1) * K;
-      k_adj_update<T><<<stream_grid(v.n), kAT, 0, s>>>(v.n, kk - 1, kk - 1, v.scal + 2, v1, pn,
-                                                       coef, v.corr, v.inv_g, Lbar, v.ldl, un);
+      side_update(a, v.n, kk - 1, v1, pn, v.W + (size_t)(kk - 1) * K, v.inv_g, Lbar, v.ldl, un);
       op_apply(*v.op, 0, un, pm, nullptr, s);
       pm_in = pm;
     }
@@ -439,10 +507,7 @@ int run_vjp(const VjpArgs& v, hipStream_t s) {
     a.Tp = v.TD;
     a.alpha = v.scal + 2;
     a.corr = v.corr;
-    k_adj_side<T><<<1, kAT, 0, s>>>(a);
-    k_adj_update<T><<<stream_grid(v.m), kAT, 0, s>>>(v.m, 0, 0, v.scal + 2, v1, pm_in, nullptr,
-                                                     v.corr, v.inv_t, Dbar, v.ldd,
-                                                     static_cast<T*>(v.bbar));
+    side_update(a, v.m, 0, v1, pm_in, nullptr, v.inv_t, Dbar, v.ldd, static_cast<T*>(v.bbar));
   }
   return 0;
 }

@@ -305,3 +305,28 @@ def test_vjp_16bit_operator_error(lib, ctx, prec):
         assert e <= 5e-2
     finally:
         lib.lslu_op_destroy(op)
+
+
+def test_vjp_more_than_64_coefficients(lib, ctx):
+    """Half-iterations with more than 64 earlier basis vectors take the
+    two-kernel path of the reverse pass (coefficient adjoints in one block,
+    then the streaming update); fewer take the fused one.  Both against the
+    complex-step oracle in random directions."""
+    prob = random_dense(140, 110, seed=12, nu=0.01)
+    K, lam = 90, 0.05
+    op = lib.make_operator(ctx, prob, lib.PRECISIONS["fp64"])
+    try:
+        info = _solve(lib, ctx, op, prob, "fp64", K, lam=lam)
+        pt, pg = _pivots(info)
+        oop = make_operator(prob)
+        rng = np.random.default_rng(5)
+        for k in (40, info["k_done"]):
+            xbar = rng.standard_normal(prob.n)
+            g, lb = _vjp(lib, ctx, op, k, xbar, "fp64")
+            for _ in range(2):
+                v = rng.standard_normal(prob.m)
+                ref = vjp_directional(oop, prob.b, k, lam, pt, pg, xbar, v)
+                e = abs(v @ g - ref) / (np.linalg.norm(v) * np.linalg.norm(g))
+                assert e <= 1e-8, (k, e)
+    finally:
+        lib.lslu_op_destroy(op)
