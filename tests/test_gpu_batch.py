@@ -175,3 +175,31 @@ def test_merged_launch_batch_rejects_what_it_cannot_merge(lib):
             lib.lslu_op_destroy(op)
         for c in ctxs:
             lib.lslu_destroy(c)
+
+
+def test_merged_launch_batch_early_stop(lib):
+    """The stopping rule and the early-stop iterate of a merged batch equal
+    those of single solves."""
+    import torch
+    probs = _tomo_set(4, 9)
+    ctxs = [lib.lslu_create(0) for _ in probs]
+    ops = []
+    try:
+        for c, prob in zip(ctxs, probs):
+            ops.append(lib.make_operator(c, prob, lib.PRECISIONS["fp32"]))
+        bs = [torch.tensor(p.b, dtype=torch.float32, device="cuda") for p in probs]
+        grid = lambda_grid()
+        st, out = lib.lslu_solve_batch(ctxs, ops, bs, K, reg="wgcv", grid=grid,
+                                       grid_relative=True, stop_tol=1e-3, early_stop=True)
+        torch.cuda.synchronize()
+        for i, (c, op, b) in enumerate(zip(ctxs, ops, bs)):
+            st1, x1, i1 = lib.lslu_solve(c, op, b, K, reg="wgcv", grid=grid, grid_relative=True,
+                                         stop_tol=1e-3, early_stop=True)
+            torch.cuda.synchronize()
+            xb, ib = out[i]
+            assert ib["k_stop"] == i1["k_stop"] and torch.equal(xb, x1), i
+    finally:
+        for op in ops:
+            lib.lslu_op_destroy(op)
+        for c in ctxs:
+            lib.lslu_destroy(c)
