@@ -42,15 +42,15 @@ def _kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def _load_traffic(kernel, workload):
+def _load_traffic(kernel, workload, prec):
     """HBM bytes per launch from committed rocprofv3 counter runs, or None when
-    absent or taken on a different kernel source."""
+    absent, taken in another precision mode or on a different kernel source."""
     try:
         with open(PROFILE_TRAFFIC) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    ent = rec.get(f"{workload}:{kernel}")
+    ent = rec.get(f"{workload}:{prec}:{kernel}")
     if not ent or ent.get("source_hash") != _kernel_source_hash():
         return None
     return ent.get("bytes_per_launch")
@@ -164,7 +164,7 @@ def run(args):
     # average launch duration is the recurrence's device time (HIP events the
     # library records on its stream around the 2K + 1 launches) per launch.
     esz = 8 if prec == "fp64" else 4
-    vsz = {"fp64": 8, "fp32": 4, "bf16op": 2, "fp16op": 2}[prec]
+    vsz = {"fp64": 8, "fp32": 4, "bf16op": 2, "fp16op": 2, "fp8op": 1}[prec]
     n_launch = tm["n_recurrence_launches"]
     t_launch = tm["t_recurrence_ms"] * 1e-3 / n_launch
     nbytes = recurrence_bytes(prob, K, vsz, esz) / n_launch
@@ -173,7 +173,7 @@ def run(args):
     roof = dict(bound="hbm", kernel=f"{kname} (one half-iteration: product, "
                 "elimination, pivot)", achieved=round(achieved, 1),
                 peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                traffic=_load_traffic(kname, args.workload),
+                traffic=_load_traffic(kname, args.workload, prec),
                 us_per_launch=round(t_launch * 1e6, 3), bytes_per_launch=int(nbytes),
                 launches_per_step=n_launch,
                 phase_ms=dict(recurrence=round(tm["t_recurrence_ms"], 4),
@@ -197,7 +197,8 @@ def run(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16op": "bf16-op/f32", "fp16op": "f16-op/f32"}[prec],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16op": "bf16-op/f32", "fp16op": "f16-op/f32",
+                  "fp8op": "f8-op/f32"}[prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "m": prob.m, "n": prob.n,
                    "nnz": prob.nnz, "iters": K, "precision": prec,

@@ -21,7 +21,7 @@
  *   given to lslu_solve/lslu_op_apply are only borrowed for the duration of the
  *   call.  No caller pointer is kept after a call returns.
  * - "Working precision" (wp) is the vector type of an operator: double for
- *   LSLU_FP64, float for LSLU_FP32, LSLU_BF16OP and LSLU_FP16OP.  Device vectors passed to
+ *   LSLU_FP64, float for LSLU_FP32, LSLU_BF16OP, LSLU_FP16OP and LSLU_FP8OP.  Device vectors passed to
  *   the library are contiguous arrays of that type.
  * - All work of one context is enqueued on that context's HIP stream (the one
  *   given to lslu_create, or one it made).  Calls on one context must not
@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LSLU_ABI_VERSION 10
+#define LSLU_ABI_VERSION 11
 
 typedef enum lslu_status {
   LSLU_OK = 0,
@@ -56,8 +56,14 @@ typedef enum lslu_precision {
   LSLU_FP32 = 1,  /* operator, bases and vectors in float; sums in double */
   LSLU_BF16OP = 2, /* operator values and its input in bfloat16, products summed
                       in float; bases and vectors in float */
-  LSLU_FP16OP = 3  /* operator values and its input in IEEE binary16, products
+  LSLU_FP16OP = 3, /* operator values and its input in IEEE binary16, products
                       summed in float; bases and vectors in float */
+  LSLU_FP8OP = 4   /* operator values and its input in 8-bit E4M3 (3 fraction
+                      bits, exponent bias 7, subnormals down to 2^-9, largest
+                      448, saturating, ties to even), products summed in float;
+                      bases and vectors in float.  Values are rounded once from
+                      the double the caller gives; scale the operator so that
+                      its entries lie well inside [2^-6, 448] */
 } lslu_precision;
 
 typedef enum lslu_reg {

@@ -29,9 +29,9 @@ LSLU_EDEVICE = -3
 LSLU_ENONFINITE = -4
 LSLU_EUNSUPPORTED = -5
 
-LSLU_FP64, LSLU_FP32, LSLU_BF16OP, LSLU_FP16OP = 0, 1, 2, 3
+LSLU_FP64, LSLU_FP32, LSLU_BF16OP, LSLU_FP16OP, LSLU_FP8OP = 0, 1, 2, 3, 4
 PRECISIONS = {"fp64": LSLU_FP64, "fp32": LSLU_FP32, "bf16op": LSLU_BF16OP,
-              "fp16op": LSLU_FP16OP}
+              "fp16op": LSLU_FP16OP, "fp8op": LSLU_FP8OP}
 
 LSLU_REG_NONE, LSLU_REG_FIXED, LSLU_REG_WGCV, LSLU_REG_GCV, LSLU_REG_OPTIMAL = range(5)
 REGS = {"none": LSLU_REG_NONE, "fixed": LSLU_REG_FIXED, "wgcv": LSLU_REG_WGCV,

@@ -26,6 +26,28 @@ template <>
 struct ValTraits<uint16_t> {
   __device__ static float get(uint16_t v) { return bf16_to_f32(v); }
 };
+// E4M3: (8 + m) 2^(e - 10), subnormals m 2^-9 (exact in float).
+__device__ inline float fp8_decode(uint8_t b) {
+  const int e = (b >> 3) & 15, m = b & 7;
+  const float v = (e == 0) ? __builtin_ldexpf(static_cast<float>(m), -9)
+                           : __builtin_ldexpf(static_cast<float>(8 + m), e - 10);
+  const float r = (e == 15 && m == 7) ? __builtin_nanf("") : v;
+  return (b & 0x80) ? -r : r;
+}
+// The nearest E4M3 value of a float, ties to even, saturated to +-448.
+__device__ inline float fp8_round(float x) {
+  const float a = __builtin_fabsf(x);
+  int e2 = 0;
+  (void)__builtin_frexpf(a, &e2);
+  const int e = (e2 - 1 > -6) ? e2 - 1 : -6;
+  float r = __builtin_ldexpf(__builtin_rintf(__builtin_ldexpf(a, 3 - e)), e - 3);
+  r = (r > 448.0f) ? 448.0f : r;
+  return (a != a) ? x : __builtin_copysignf(r, x);
+}
+template <>
+struct ValTraits<Fp8> {
+  __device__ static float get(Fp8 v) { return fp8_decode(v.bits); }
+};
 template <>
 struct ValTraits<Half> {
   __device__ static float get(Half v) {
@@ -33,7 +55,7 @@ struct ValTraits<Half> {
   }
 };
 
-// Input rounding of the operator modes (kIn: kInNone, kInBf16, kInFp16):
+// Input rounding of the operator modes (kIn: kInNone, kInBf16, kInFp16, kInFp8):
 // in the 16-bit operator modes a product's input entries are rounded to the
 // operator's format, so every term is a product of two 16-bit numbers, exact
 // in float.
@@ -41,6 +63,8 @@ template <int kIn, typename T>
 __device__ inline auto in_val(T v) {
   if constexpr (kIn == kInBf16)
     return bf16_to_f32(f32_to_bf16(static_cast<float>(v)));
+  else if constexpr (kIn == kInFp8)
+    return fp8_round(static_cast<float>(v));
   else if constexpr (kIn == kInFp16)
     return static_cast<float>(static_cast<_Float16>(static_cast<float>(v)));
   else
@@ -268,6 +292,15 @@ struct Quad<uint16_t> {
     const uint2 q = *reinterpret_cast<const uint2*>(p);
     v[0] = static_cast<uint16_t>(q.x & 0xffffu); v[1] = static_cast<uint16_t>(q.x >> 16);
     v[2] = static_cast<uint16_t>(q.y & 0xffffu); v[3] = static_cast<uint16_t>(q.y >> 16);
+  }
+};
+
+template <>
+struct Quad<Fp8> {
+  __device__ static void load(const Fp8* p, Fp8 (&v)[4]) {
+    const uint32_t q = *reinterpret_cast<const uint32_t*>(p);
+    v[0].bits = static_cast<uint8_t>(q & 0xffu); v[1].bits = static_cast<uint8_t>((q >> 8) & 0xffu);
+    v[2].bits = static_cast<uint8_t>((q >> 16) & 0xffu); v[3].bits = static_cast<uint8_t>(q >> 24);
   }
 };
 
@@ -538,6 +571,7 @@ void with_mode(int prec, F&& f) {
     if (prec == kFP32) f(float{}, double{}, std::integral_constant<int, kInNone>{});
     else if (prec == kBF16) f(uint16_t{}, float{}, std::integral_constant<int, kInBf16>{});
     else if (prec == kFP16) f(Half{}, float{}, std::integral_constant<int, kInFp16>{});
+    else if (prec == kFP8) f(Fp8{}, float{}, std::integral_constant<int, kInFp8>{});
   }
 }
 

@@ -18,13 +18,20 @@ constexpr int kMaxParts = 4096;  // pivot candidates per streaming pass
 // finite values produces it.
 constexpr uint64_t kSlotEmpty = 0x7ff4dead0000beefull;
 
-enum Prec : int { kFP64 = 0, kFP32 = 1, kBF16 = 2, kFP16 = 3 };
-// Input rounding of a product (the 16-bit operator modes).
-enum InMode : int { kInNone = 0, kInBf16 = 1, kInFp16 = 2 };
+enum Prec : int { kFP64 = 0, kFP32 = 1, kBF16 = 2, kFP16 = 3, kFP8 = 4 };
+// Input rounding of a product (the 16- and 8-bit operator modes).
+enum InMode : int { kInNone = 0, kInBf16 = 1, kInFp16 = 2, kInFp8 = 3 };
 // An IEEE binary16 operator value (its bits).
 struct Half {
   uint16_t bits;
   __host__ __device__ constexpr Half(int z = 0) : bits(static_cast<uint16_t>(z)) {}
+};
+// An 8-bit E4M3 operator value (its bits): 1 sign, 4 exponent bits with bias
+// 7, 3 fraction bits, no infinities, 0x7f / 0xff the NaNs, largest finite
+// 448, subnormals 2^-9 m.
+struct Fp8 {
+  uint8_t bits;
+  __host__ __device__ constexpr Fp8(int z = 0) : bits(static_cast<uint8_t>(z)) {}
 };
 enum Reg : int { kNone = 0, kFixed = 1, kWGCV = 2, kGCV = 3, kOptimal = 4 };
 enum Status : int {
@@ -119,6 +126,40 @@ inline float f16_to_f32(uint16_t h) {
   if (e == 0) return sign * std::ldexp(static_cast<float>(m), -24);
   if (e == 31) return m ? NAN : sign * INFINITY;
   return sign * std::ldexp(1.0f + static_cast<float>(m) / 1024.0f, e - 15);
+}
+
+// ----------------------------------------------------------------- fp8 ----
+// E4M3 on the host: a double rounded once to the nearest E4M3 value, ties to
+// even, magnitudes beyond 448 saturated to 448 (NaN stays NaN), and back.
+inline double fp8_round_host(double d) {
+  if (std::isnan(d)) return d;
+  const double a = std::fabs(d);
+  int e2 = 0;
+  (void)std::frexp(a, &e2);                              // a in [2^(e2-1), 2^e2)
+  const int e = std::max(e2 - 1, -6);                     // subnormal spacing 2^-9
+  double r = std::ldexp(std::nearbyint(std::ldexp(a, 3 - e)), e - 3);  // exact scaling, RNE
+  if (r > 448.0) r = 448.0;
+  return std::copysign(r, d);
+}
+inline uint8_t f64_to_fp8(double d) {
+  if (std::isnan(d)) return 0x7f;
+  const double r = fp8_round_host(d);
+  const uint8_t sign = std::signbit(d) ? 0x80 : 0;
+  const double a = std::fabs(r);
+  if (a == 0.0) return sign;
+  if (a < 0x1p-6) return sign | static_cast<uint8_t>(std::ldexp(a, 9));  // subnormal m
+  int e2 = 0;
+  (void)std::frexp(a, &e2);
+  const int e = e2 - 1;                                   // a in [2^e, 2^(e+1)), e >= -6
+  const int m = static_cast<int>(std::ldexp(a, 3 - e)) - 8;
+  return sign | static_cast<uint8_t>(((e + 7) << 3) | m);
+}
+inline float fp8_to_f32(uint8_t b) {
+  const int e = (b >> 3) & 15, m = b & 7;
+  const float sign = (b & 0x80) ? -1.0f : 1.0f;
+  if (e == 15 && m == 7) return NAN;
+  if (e == 0) return sign * std::ldexp(static_cast<float>(m), -9);
+  return sign * std::ldexp(static_cast<float>(8 + m), e - 10);
 }
 
 // ------------------------------------------------------------- launchers ---

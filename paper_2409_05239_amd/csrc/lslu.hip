@@ -236,6 +236,9 @@ std::vector<unsigned char> convert_values(const double* v, int64_t count, int pr
     out.resize(sizeof(uint16_t) * count);
     uint16_t* o = reinterpret_cast<uint16_t*>(out.data());
     for (int64_t i = 0; i < count; ++i) o[i] = f32_to_bf16(static_cast<float>(v[i]));
+  } else if (prec == kFP8) {  // E4M3, rounded once from the given double
+    out.resize(count);
+    for (int64_t i = 0; i < count; ++i) out[i] = f64_to_fp8(v[i]);
   } else {  // binary16, rounded once from the given double
     out.resize(sizeof(uint16_t) * count);
     uint16_t* o = reinterpret_cast<uint16_t*>(out.data());
@@ -753,7 +756,7 @@ lslu_status lslu_op_dense(lslu_ctx* c, int64_t m, int64_t n, const double* A,
   if (!out || !A) return fail(c, LSLU_EINVAL, "NULL argument");
   *out = nullptr;
   if (m < 1 || n < 1) return fail(c, LSLU_EINVAL, "m and n must be >= 1");
-  if (prec < LSLU_FP64 || prec > LSLU_FP16OP) return fail(c, LSLU_EINVAL, "bad precision");
+  if (prec < LSLU_FP64 || prec > LSLU_FP8OP) return fail(c, LSLU_EINVAL, "bad precision");
   if (m > INT32_MAX || n > INT32_MAX) return fail(c, LSLU_EINVAL, "size too large");
   try {
     if (!finite_all(A, m * n)) return fail(c, LSLU_ENONFINITE, "A has NaN/Inf");
@@ -794,7 +797,7 @@ lslu_status lslu_op_csr(lslu_ctx* c, int64_t m, int64_t n, int64_t nnz,
   if (m < 1 || n < 1 || nnz < 0) return fail(c, LSLU_EINVAL, "bad shape");
   if (m > INT32_MAX - 1 || n > INT32_MAX - 1 || nnz > INT32_MAX - 1)
     return fail(c, LSLU_EINVAL, "sizes must be < 2^31");
-  if (prec < LSLU_FP64 || prec > LSLU_FP16OP) return fail(c, LSLU_EINVAL, "bad precision");
+  if (prec < LSLU_FP64 || prec > LSLU_FP8OP) return fail(c, LSLU_EINVAL, "bad precision");
   try {
     if (indptr[0] != 0 || indptr[m] != nnz)
       return fail(c, LSLU_EINVAL, "indptr[0] must be 0 and indptr[m] must be nnz");
@@ -869,7 +872,7 @@ lslu_status lslu_op_psf(lslu_ctx* c, int64_t rows, int64_t cols, int32_t ph,
     return fail(c, LSLU_EINVAL, "bad image shape");
   if (ph < 1 || pw < 1 || ph % 2 == 0 || pw % 2 == 0 || ph > 31 || pw > 31)
     return fail(c, LSLU_EINVAL, "PSF sizes must be odd and <= 31");
-  if (prec < LSLU_FP64 || prec > LSLU_FP16OP) return fail(c, LSLU_EINVAL, "bad precision");
+  if (prec < LSLU_FP64 || prec > LSLU_FP8OP) return fail(c, LSLU_EINVAL, "bad precision");
   if (!finite_all(psf, (int64_t)ph * pw)) return fail(c, LSLU_ENONFINITE, "PSF has NaN/Inf");
   try {
     LSLU_HIP(c, hipSetDevice(c->device));
@@ -883,6 +886,9 @@ lslu_status lslu_op_psf(lslu_ctx* c, int64_t rows, int64_t cols, int32_t ph,
       if (prec == kFP16) {
         p32[i] = f16_to_f32(f64_to_f16(p[i]));
         pf32[i] = f16_to_f32(f64_to_f16(pf[i]));
+      } else if (prec == kFP8) {
+        p32[i] = fp8_to_f32(f64_to_fp8(p[i]));
+        pf32[i] = fp8_to_f32(f64_to_fp8(pf[i]));
       } else {
         p32[i] = bf16_to_f32(f32_to_bf16(static_cast<float>(p[i])));
         pf32[i] = bf16_to_f32(f32_to_bf16(static_cast<float>(pf[i])));

@@ -5,8 +5,20 @@ from __future__ import annotations
 
 import numpy as np
 
-TAU = {"fp64": 1e-9, "fp32": 1e-3, "bf16op": 1e-2, "fp16op": 1e-2}
+TAU = {"fp64": 1e-9, "fp32": 1e-3, "bf16op": 1e-2, "fp16op": 1e-2, "fp8op": 1e-1}
 TOL = {"fp64": 1e-10, "fp32": 1e-4}
+
+
+def e4m3(x):
+    """Round to the 8-bit E4M3 format in its finite, saturating form: 3
+    fraction bits, exponent bias 7 (normal exponents -6..8), subnormal spacing
+    2^-9, ties to even, largest finite 448."""
+    x = np.asarray(x, dtype=np.float64)
+    a = np.abs(x)
+    e = np.maximum(np.floor(np.log2(np.where(a > 0, a, 1.0))), -6.0)
+    q = 2.0 ** (e - 3)
+    r = np.minimum(np.round(a / q) * q, 448.0)  # np.round: half to even
+    return np.copysign(np.where(a > 0, r, 0.0), x)
 
 
 def torch_dtype(prec):

@@ -100,12 +100,14 @@ def _compare(lib, ctx, prob, prec, K, kind, relative, lam=0.05, replay=True,
 # --------------------------------------------------------------- operators
 
 def _bound(Aabs_x, prec, nterms):
-    u = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "bf16op": 2.0 ** -8, "fp16op": 2.0 ** -11}[prec]
-    acc = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -53, "bf16op": 2.0 ** -24, "fp16op": 2.0 ** -24}[prec]
+    u = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "bf16op": 2.0 ** -8, "fp16op": 2.0 ** -11,
+         "fp8op": 2.0 ** -4}[prec]
+    acc = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -53, "bf16op": 2.0 ** -24, "fp16op": 2.0 ** -24,
+           "fp8op": 2.0 ** -24}[prec]
     return (4 * u + nterms * acc) * Aabs_x + 1e-300
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16op", "fp16op"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16op", "fp16op", "fp8op"])
 @pytest.mark.parametrize("which", ["dense", "csr", "psf31", "psf_nonsym"])
 def test_operator_products(lib, ctx, which, prec):
     import torch
@@ -144,8 +146,25 @@ def test_operator_products(lib, ctx, which, prec):
                 aop = absop(np.abs(prob.psf), prob.image_shape)
             mag = aop.rmatvec(np.abs(x)) if tr else aop.matvec(np.abs(x))
             nterms = 600
+            bound = _bound(mag, prec, nterms)
+            if prec == "fp8op":
+                # E4M3's smallest spacing is 2^-9: an entry of A or x below
+                # 2^-6 rounds with an absolute error up to 2^-10, not a
+                # relative one (short ray segments flush to zero), so each
+                # term adds 2^-10 (|x_j| + |a_ij|) beyond the relative part.
+                if prob.kind == "dense":
+                    pat = absop((prob.A != 0).astype(float))
+                elif prob.kind == "csr":
+                    pat = absop(prob.m, prob.n, prob.indptr, prob.indices,
+                                np.ones_like(prob.data))
+                else:
+                    pat = absop((prob.psf != 0).astype(float), prob.image_shape)
+                ones = np.ones(nin)
+                bound = bound + 2.0 ** -9 * (
+                    (pat.rmatvec(np.abs(x)) + aop.rmatvec(ones)) if tr
+                    else (pat.matvec(np.abs(x)) + aop.matvec(ones)))
             assert np.all(np.isfinite(y))
-            assert np.all(np.abs(y - ref) <= _bound(mag, prec, nterms)), which
+            assert np.all(np.abs(y - ref) <= bound), which
     finally:
         lib.lslu_op_destroy(op)
 
@@ -265,6 +284,75 @@ def test_16bit_operator_error(lib, ctx, prec, name):
     print(f"[{name} {prec}] rel err vs x_true: min {e_lo.min():.4f} at k={int(e_lo.argmin()) + 1}, "
           f"final {e_lo[-1]:.4f} (fp64 oracle: min {e_64.min():.4f}, final {e_64[-1]:.4f})")
     assert e_lo.min() < 1.5 * e_64.min()
+
+
+def _fp8_cases():
+    """Code points, midpoints (ties), values in the subnormal range, values
+    past the largest finite one, both signs."""
+    from gpu_helpers import e4m3
+    pts = np.array([m * 2.0 ** -9 for m in range(8)]
+                   + [(8 + mm) * 2.0 ** (e - 10) for e in range(1, 16) for mm in range(8)
+                      if not (e == 15 and mm == 7)])
+    mids = (pts[1:] + pts[:-1]) / 2
+    rng = np.random.default_rng(11)
+    extra = np.concatenate([rng.standard_normal(200) * 4, rng.uniform(0, 2.0 ** -6, 50),
+                            [449.0, 463.9, 464.0, 1000.0, 3e5]])
+    v = np.concatenate([pts, mids, extra])
+    v = np.concatenate([v, -v]).astype(np.float32).astype(np.float64)
+    assert np.all(np.abs(e4m3(v)) <= 448.0)
+    return v
+
+
+@pytest.mark.parametrize("kind", ["dense", "csr", "psf"])
+def test_fp8_rounding_is_exact(lib, ctx, kind):
+    """FP8 operator mode: the operator's values (rounded once on the host)
+    and the product's input (rounded in the kernel) follow E4M3 exactly.  A
+    product of two E4M3 values is exact in float, so a diagonal operator
+    diag(a) applied to x gives e4m3(a) * e4m3(x) to the bit."""
+    import torch
+    from gpu_helpers import e4m3
+    v = _fp8_cases()
+    n = len(v)
+    a = np.roll(v, 17)
+    if kind == "dense":
+        op = lib.lslu_op_dense(ctx, np.diag(a), lib.PRECISIONS["fp8op"])
+    elif kind == "csr":
+        op = lib.lslu_op_csr(ctx, n, n, np.arange(n + 1), np.arange(n, dtype=np.int32), a,
+                             lib.PRECISIONS["fp8op"])
+    else:  # a 1x1 PSF is a scalar multiple of the identity
+        a = np.full(n, 0.8125)
+        op = lib.lslu_op_psf(ctx, 1, n, np.array([[0.8125]]), lib.PRECISIONS["fp8op"])
+    try:
+        for tr in (0, 1):
+            xt = torch.tensor(v, dtype=torch.float32, device="cuda")
+            yt = torch.full((n,), np.nan, dtype=torch.float32, device="cuda")
+            lib.lslu_op_apply(ctx, op, tr, xt, yt)
+            torch.cuda.synchronize()
+            y = yt.double().cpu().numpy()
+            ref = e4m3(a) * e4m3(v)
+            bad = np.flatnonzero(y != ref)
+            assert bad.size == 0, (kind, tr, [(a[i], v[i], y[i], ref[i]) for i in bad[:5]])
+    finally:
+        lib.lslu_op_destroy(op)
+
+
+@pytest.mark.parametrize("name", ["deblur96", "tomo32"])
+def test_8bit_operator_error(lib, ctx, name):
+    """The E4M3 operator mode (values and product inputs with 3 fraction
+    bits, sums and bases in float): exact pivot structure, and the error to
+    x_true stated against the FP64 oracle's (looser than the 16-bit modes:
+    each operator entry carries up to 6 % rounding)."""
+    prob = config_problem(name)
+    op = make_operator(prob)
+    K = 40 if name == "deblur96" else 30
+    R = hybrid_lslu(op, prob.b, K, _reg("wgcv", True))
+    G = gpu_solve(lib, ctx, prob, "fp8op", K, "wgcv", grid=lambda_grid(), grid_relative=True)
+    check_basis_invariants(G, prob.m, prob.n)
+    e_lo = np.array([rel(G["X"][:, k], prob.x_true) for k in range(G["k_done"])])
+    e_64 = np.array([rel(R.X[:, k], prob.x_true) for k in range(R.k_done)])
+    print(f"[{name} fp8op] rel err vs x_true: min {e_lo.min():.4f} at k={int(e_lo.argmin()) + 1}, "
+          f"final {e_lo[-1]:.4f} (fp64 oracle: min {e_64.min():.4f}, final {e_64[-1]:.4f})")
+    assert e_lo.min() < 3.0 * e_64.min()
 
 
 # -------------------------------------------------------------- edge cases
