@@ -37,7 +37,7 @@ def _solve(lib, item, asynchronous=False):
                           X=X, asynchronous=asynchronous)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16op"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16op", "fp8op"])
 def test_concurrent_solves_match_one_at_a_time(lib, prec):
     import torch
     probs = batch_problems(8, seed=3)
@@ -111,7 +111,7 @@ def _tomo_set(count, seed):
     return out
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16op", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16op", "fp8op", "fp64"])
 def test_merged_launch_batch_matches_single_solves(lib, prec):
     """lslu_solve_batch runs launch j of every problem's recurrence in one
     kernel launch: each problem's results must equal its solve alone."""

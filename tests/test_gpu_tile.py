@@ -17,7 +17,7 @@ def ctx(lib):
     lib.lslu_destroy(c)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16op"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16op", "fp8op"])
 @pytest.mark.parametrize("shape", [(96, 96, 7), (40, 70, 3), (130, 33, 15)])
 def test_tile_shapes_give_identical_results(lib, ctx, prec, shape):
     import torch
