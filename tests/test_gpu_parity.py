@@ -455,6 +455,15 @@ def test_invalid_options_are_rejected(lib, ctx):
             assert ei.value.status == lib.LSLU_EINVAL
         with pytest.raises(lib.LsluError):
             lib.lslu_op_dense(ctx, np.full((2, 2), np.nan))
+        for bad in (-1, 5):  # precision modes are 0 (FP64) .. 4 (FP8 operator)
+            for make in (lambda pr: lib.lslu_op_dense(ctx, np.eye(3), pr),
+                         lambda pr: lib.lslu_op_csr(ctx, 2, 2, np.array([0, 1, 2]),
+                                                    np.array([0, 1], np.int32),
+                                                    np.ones(2), pr),
+                         lambda pr: lib.lslu_op_psf(ctx, 4, 4, np.ones((3, 3)), pr)):
+                with pytest.raises(lib.LsluError) as ei:
+                    make(bad)
+                assert ei.value.status == lib.LSLU_EINVAL
     finally:
         lib.lslu_op_destroy(op)
 
