@@ -303,25 +303,47 @@ def _fp8_cases():
     return v
 
 
+def _bf16(x):
+    """bfloat16 rounding of float32 values (nearest, ties to even)."""
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _16bit_cases():
+    """Normal values of both signs, binary16 subnormals, and midpoints of
+    both 16-bit formats near 1 (ties)."""
+    rng = np.random.default_rng(12)
+    v = np.concatenate([rng.standard_normal(300) * 4, rng.uniform(1e-7, 6e-5, 40),
+                        1 + (2 * np.arange(20) + 1) / 2048.0, 1 + (2 * np.arange(20) + 1) / 256.0,
+                        [0.0, 65504.0, 3.0e4]])
+    v = np.concatenate([v, -v])
+    return v.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("prec", ["bf16op", "fp16op", "fp8op"])
 @pytest.mark.parametrize("kind", ["dense", "csr", "psf"])
-def test_fp8_rounding_is_exact(lib, ctx, kind):
-    """FP8 operator mode: the operator's values (rounded once on the host)
-    and the product's input (rounded in the kernel) follow E4M3 exactly.  A
-    product of two E4M3 values is exact in float, so a diagonal operator
-    diag(a) applied to x gives e4m3(a) * e4m3(x) to the bit."""
+def test_low_precision_rounding_is_exact(lib, ctx, kind, prec):
+    """The 16- and 8-bit operator modes: the operator's values (rounded on the
+    host; bfloat16 through float) and the product's input (rounded in the
+    kernel) follow the format exactly.  A product of two such values is exact
+    in float, so a diagonal operator diag(a) applied to x gives
+    round(a) * round(x) to the bit."""
     import torch
     from gpu_helpers import e4m3
-    v = _fp8_cases()
+    rnd = {"bf16op": _bf16, "fp8op": e4m3,
+           "fp16op": lambda z: np.asarray(z, np.float64).astype(np.float16).astype(np.float64)}[prec]
+    v = _fp8_cases() if prec == "fp8op" else _16bit_cases()
     n = len(v)
     a = np.roll(v, 17)
     if kind == "dense":
-        op = lib.lslu_op_dense(ctx, np.diag(a), lib.PRECISIONS["fp8op"])
+        op = lib.lslu_op_dense(ctx, np.diag(a), lib.PRECISIONS[prec])
     elif kind == "csr":
         op = lib.lslu_op_csr(ctx, n, n, np.arange(n + 1), np.arange(n, dtype=np.int32), a,
-                             lib.PRECISIONS["fp8op"])
+                             lib.PRECISIONS[prec])
     else:  # a 1x1 PSF is a scalar multiple of the identity
         a = np.full(n, 0.8125)
-        op = lib.lslu_op_psf(ctx, 1, n, np.array([[0.8125]]), lib.PRECISIONS["fp8op"])
+        op = lib.lslu_op_psf(ctx, 1, n, np.array([[0.8125]]), lib.PRECISIONS[prec])
     try:
         for tr in (0, 1):
             xt = torch.tensor(v, dtype=torch.float32, device="cuda")
@@ -329,7 +351,7 @@ def test_fp8_rounding_is_exact(lib, ctx, kind):
             lib.lslu_op_apply(ctx, op, tr, xt, yt)
             torch.cuda.synchronize()
             y = yt.double().cpu().numpy()
-            ref = e4m3(a) * e4m3(v)
+            ref = rnd(a) * rnd(v)
             bad = np.flatnonzero(y != ref)
             assert bad.size == 0, (kind, tr, [(a[i], v[i], y[i], ref[i]) for i in bad[:5]])
     finally:
