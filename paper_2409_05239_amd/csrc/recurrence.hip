@@ -739,6 +739,69 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
   if (!fetch_coef(a, st, cf)) return;
   double best = 0.0;
   int bidx = INT_MAX;
+  if constexpr (std::is_same_v<T, float>) {
+    // Float bases with an even row length and column stride: the elimination
+    // takes pixel pairs (8-byte loads, half the load instructions), lane l
+    // on columns j0 + 2 (l % 32) + {0, 1} of the rows r0 + 2p + l / 32 of
+    // its wavefront; the same pixels per wavefront and the same sums per
+    // pixel as the one-column mapping below.
+    if ((cols & 1) == 0 && (a.cs & 1) == 0 &&
+        (reinterpret_cast<uintptr_t>(a.basis) & 7) == 0) {
+      __syncthreads();  // products of this block's tiles, written by other lanes
+      constexpr int RP = R / 2;
+      const int cp = lane & 31, hr = lane >> 5;
+      for (int t = cb; t < ntiles; t += ncons) {
+        const int i0 = (t / tiles_x) * TH, j0 = (t % tiles_x) * kPsfTW;
+        const int gj = j0 + 2 * cp;
+        int64_t pix[RP];
+        bool ok[RP];
+        unsigned char m0[RP], m1[RP];
+#pragma unroll
+        for (int p = 0; p < RP; ++p) {
+          const int gi = i0 + r0 + 2 * p + hr;
+          ok[p] = gi < rows && gj < cols;  // then gj + 1 < cols too (cols even)
+          pix[p] = ok[p] ? (int64_t)gi * cols + gj : 0;  // even, in bounds either way
+          m0[p] = a.mask[pix[p]];
+          m1[p] = a.mask[pix[p] + 1];
+        }
+        double e0[RP], e1[RP];
+#pragma unroll
+        for (int p = 0; p < RP; ++p) e0[p] = e1[p] = 0.0;
+        for (int j = 0; j < nb; ++j) {
+          const float* c0 = a.basis + (int64_t)j * a.cs;
+          float2 bq[RP];
+#pragma unroll
+          for (int p = 0; p < RP; ++p) bq[p] = *reinterpret_cast<const float2*>(c0 + pix[p]);
+          const double w0 = cf[j];
+#pragma unroll
+          for (int p = 0; p < RP; ++p) {
+            e0[p] = fma(w0, static_cast<double>(bq[p].x), e0[p]);
+            e1[p] = fma(w0, static_cast<double>(bq[p].y), e1[p]);
+          }
+        }
+#pragma unroll
+        for (int p = 0; p < RP; ++p) {
+          if (!ok[p]) continue;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int64_t q = pix[p] + h;
+            const bool mk = (h ? m1[p] : m0[p]) != 0;
+            const double q0 = static_cast<double>(a.out[q]);
+            const T o = mk ? T(0) : static_cast<T>(q0 - (h ? e1[p] : e0[p]));
+            a.out[q] = o;
+            const double k2 = mk ? 0.0 : static_cast<double>(o);
+            if (better(k2, (int)q, best, bidx)) {
+              best = k2;
+              bidx = (int)q;
+            }
+          }
+        }
+      }
+      block_argmax<kThreads>(best, bidx);
+      if (threadIdx.x == 0) write_part(a.parts_out, cb, best, bidx);
+      return;
+    }
+  }
   for (int t = cb; t < ntiles; t += ncons) {
     const int i0 = (t / tiles_x) * TH, j0 = (t % tiles_x) * kPsfTW;
     const int gj = j0 + lane;
