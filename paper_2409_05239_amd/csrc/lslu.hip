@@ -647,26 +647,34 @@ lslu_status tune_psf(lslu_ctx* c, lslu_op* op, int* chosen) {
   else
     launch_fill<float>(static_cast<float*>(x), 1.0f, n, s);
   const int saved = op->d.psf_r;
-  float best = 0.f;
-  int pick = 0;
-  for (int r : {2, 4, 8}) {
+  constexpr int kShapes[3] = {2, 4, 8};
+  for (int r : kShapes) {  // warm-up: each shape's kernels loaded and run once
     op->d.psf_r = r;
     for (int i = 0; i < 2; ++i) op_apply(op->d, i & 1, x, y, nullptr, s);
-    float fastest = 0.f;
-    for (int trial = 0; trial < 3; ++trial) {  // the fastest of three timings
+  }
+  // The fastest of five timings per shape, the shapes interleaved within each
+  // round so that a slow stretch of the device (clocks, a profiler's
+  // per-dispatch work) does not fall on one shape alone.
+  float fastest[3] = {0.f, 0.f, 0.f};
+  for (int trial = 0; trial < 5; ++trial) {
+    for (int k = 0; k < 3; ++k) {
+      op->d.psf_r = kShapes[k];
       LSLU_HIP(c, hipEventRecord(e0, s));
       for (int i = 0; i < 4; ++i) op_apply(op->d, i & 1, x, y, nullptr, s);
       LSLU_HIP(c, hipEventRecord(e1, s));
       LSLU_HIP(c, hipEventSynchronize(e1));
       float ms = 0.f;
       LSLU_HIP(c, hipEventElapsedTime(&ms, e0, e1));
-      if (trial == 0 || ms < fastest) fastest = ms;
-    }
-    if (pick == 0 || fastest < best) {
-      best = fastest;
-      pick = r;
+      if (trial == 0 || ms < fastest[k]) fastest[k] = ms;
     }
   }
+  int pick = kShapes[0];
+  float best = fastest[0];
+  for (int k = 1; k < 3; ++k)
+    if (fastest[k] < best) {
+      best = fastest[k];
+      pick = kShapes[k];
+    }
   op->d.psf_r = saved;
   LSLU_HIP(c, hipGetLastError());
   *chosen = pick;

@@ -739,14 +739,15 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
   if (!fetch_coef(a, st, cf)) return;
   double best = 0.0;
   int bidx = INT_MAX;
-  if constexpr (std::is_same_v<T, float>) {
-    // Float bases with an even row length and column stride: the elimination
-    // takes pixel pairs (8-byte loads, half the load instructions), lane l
+  {
+    // An even row length and column stride: the elimination takes pixel
+    // pairs (8- or 16-byte loads, half the load instructions), lane l
     // on columns j0 + 2 (l % 32) + {0, 1} of the rows r0 + 2p + l / 32 of
     // its wavefront; the same pixels per wavefront and the same sums per
     // pixel as the one-column mapping below.
     if ((cols & 1) == 0 && (a.cs & 1) == 0 &&
-        (reinterpret_cast<uintptr_t>(a.basis) & 7) == 0) {
+        (reinterpret_cast<uintptr_t>(a.basis) & (2 * sizeof(T) - 1)) == 0) {
+      using T2 = std::conditional_t<std::is_same_v<T, float>, float2, double2>;
       __syncthreads();  // products of this block's tiles, written by other lanes
       constexpr int RP = R / 2;
       const int cp = lane & 31, hr = lane >> 5;
@@ -768,10 +769,10 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
 #pragma unroll
         for (int p = 0; p < RP; ++p) e0[p] = e1[p] = 0.0;
         for (int j = 0; j < nb; ++j) {
-          const float* c0 = a.basis + (int64_t)j * a.cs;
-          float2 bq[RP];
+          const T* c0 = a.basis + (int64_t)j * a.cs;
+          T2 bq[RP];
 #pragma unroll
-          for (int p = 0; p < RP; ++p) bq[p] = *reinterpret_cast<const float2*>(c0 + pix[p]);
+          for (int p = 0; p < RP; ++p) bq[p] = *reinterpret_cast<const T2*>(c0 + pix[p]);
           const double w0 = cf[j];
 #pragma unroll
           for (int p = 0; p < RP; ++p) {
