@@ -177,6 +177,60 @@ def _dptr(t):
     return None if t is None else c_void_p(t.data_ptr())
 
 
+# device of each context made through this binding, and the (m, n, precision)
+# of the last solve started on it (what lslu_get_basis copies from)
+_CTX_DEVICE = {}
+_CTX_SHAPE = {}
+
+
+def _vec(t, count, precision, name, device=None, at_least=False):
+    """Checks a device vector argument before its pointer crosses the C ABI,
+    which cannot check it: a contiguous CUDA tensor of the working precision
+    (float64 for LSLU_FP64, else float32) holding ``count`` entries (at least
+    ``count`` with ``at_least``) on ``device`` (when known).  Returns the
+    pointer; raises ValueError otherwise."""
+    import torch
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{name} must be a CUDA tensor")
+    want = torch.float64 if precision == LSLU_FP64 else torch.float32
+    if t.dtype != want:
+        raise ValueError(f"{name} must be {want} for this operator (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    got = t.numel()
+    if (got < count) if at_least else (got != count):
+        need = f"at least {count}" if at_least else f"{count}"
+        raise ValueError(f"{name} must hold {need} entries (got {got})")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{name} is on cuda:{t.device.index}, the context on cuda:{device}")
+    return c_void_p(t.data_ptr())
+
+
+def _opt_vec(t, count, precision, name, device=None, at_least=False):
+    return None if t is None else _vec(t, count, precision, name, device, at_least)
+
+
+def _sample_rows(rows, K):
+    """Candidate rows of the sampled pivot searches: a 2-D int32 array with
+    at least 2 K + 1 rows (the library reads the first 2 K + 1) of 1..512
+    entries."""
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    if rows.ndim != 2 or rows.shape[0] < 2 * K + 1 or not 1 <= rows.shape[1] <= 512:
+        raise ValueError(f"pivot_sample rows must be (>= {2 * K + 1}) x (1..512), "
+                         f"got {rows.shape}")
+    return rows[:2 * K + 1]
+
+
+def _host_ints(arr, min_len, name):
+    """A host int32 array argument the library reads ``min_len`` entries of."""
+    a = np.ascontiguousarray(arr, dtype=np.int32).reshape(-1)
+    if a.shape[0] < min_len:
+        raise ValueError(f"{name} must hold at least {min_len} entries (got {a.shape[0]})")
+    return a
+
+
 def _np(a, dtype):
     a = np.ascontiguousarray(a, dtype=dtype)
     return a, a.ctypes.data_as(POINTER(np.ctypeslib.as_ctypes_type(dtype)))
@@ -204,10 +258,13 @@ def lslu_create(device: int = 0, stream=None):
     st = lib.lslu_create(int(device), c_void_p(handle), ctypes.byref(out))
     if st < 0:
         raise LsluError(st, "lslu_create failed (no gfx950 device?)")
+    _CTX_DEVICE[out.value] = int(device)
     return out
 
 
 def lslu_destroy(ctx):
+    _CTX_DEVICE.pop(ctx.value, None)
+    _CTX_SHAPE.pop(ctx.value, None)
     return lib.lslu_destroy(ctx)
 
 
@@ -245,8 +302,14 @@ def lslu_op_psf(ctx, rows, cols, psf, precision=LSLU_FP64):
 
 
 def lslu_op_apply(ctx, op, transpose, x, y):
-    """``x``/``y``: torch device tensors in the operator's working precision."""
-    _check(ctx, lib.lslu_op_apply(ctx, op, int(transpose), _dptr(x), _dptr(y)))
+    """``x``/``y``: torch device tensors in the operator's working precision
+    (n and m entries for A x, m and n for A^T x)."""
+    m, n, prec = lslu_op_info(op)
+    nin, nout = (m, n) if transpose else (n, m)
+    dev = _CTX_DEVICE.get(ctx.value)
+    px = _vec(x, nin, prec, "x", dev)
+    py = _vec(y, nout, prec, "y", dev)
+    _check(ctx, lib.lslu_op_apply(ctx, op, int(transpose), px, py))
 
 
 def lslu_op_tile(ctx, op, rows_per_lane=0):
@@ -306,16 +369,24 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
     host_io = isinstance(b, np.ndarray)
     if host_io and asynchronous:
         raise ValueError("host arrays need a synchronous solve")
+    dev = _CTX_DEVICE.get(ctx.value)
+    if not host_io:
+        _vec(b, m, prec, "b", dev)
+        _opt_vec(x0, n, prec, "x0", dev)
     if x_out is None:
         x_out = (np.empty(n) if host_io
                  else torch.empty(n, dtype=_torch_dtype(prec), device=b.device))
+    elif not host_io:
+        _vec(x_out, n, prec, "x_out", dev)
+    _opt_vec(X, n * K, prec, "X", dev, at_least=True)
+    _opt_vec(x_true, n, prec, "x_true", dev)
     o = lslu_opts()
     o.maxiter = K
     o.reg = REGS[reg] if isinstance(reg, str) else int(reg)
     o.lambda_ = float(lam)
     keep = []
     if grid is not None:
-        g, pg = _np(grid, np.float64)
+        g, pg = _np(np.asarray(grid, dtype=np.float64).reshape(-1), np.float64)
         keep.append(g)
         o.lambda_grid = pg
         o.n_grid = g.shape[0]
@@ -328,15 +399,17 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
     o.flags = ((LSLU_FLAG_EAGER if eager else 0) | (LSLU_FLAG_TIMING if timing else 0)
                | (LSLU_FLAG_ASYNC if asynchronous else 0)
                | (LSLU_FLAG_GRAD_LAMBDA if grad_lambda else 0))
-    for name, arr in (("replay_piv_t", replay_piv_t), ("replay_piv_g", replay_piv_g),
-                      ("replay_lambda_idx", replay_lambda_idx)):
+    # the library reads K + 1, K and K entries of the replay arrays
+    for name, arr, need in (("replay_piv_t", replay_piv_t, K + 1),
+                            ("replay_piv_g", replay_piv_g, K),
+                            ("replay_lambda_idx", replay_lambda_idx, K)):
         if arr is not None:
-            a, pa = _np(arr, np.int32)
+            a, pa = _np(_host_ints(arr, need, name), np.int32)
             keep.append(a)
             setattr(o, name, pa)
     if pivot_sample is not None:
         rows, ssz = pivot_sample
-        rows = np.ascontiguousarray(rows, dtype=np.int32)
+        rows = _sample_rows(rows, K)
         a, pa = _np(rows.reshape(-1), np.int32)
         keep.append(a)
         o.sample_rows = pa
@@ -355,9 +428,12 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
         ct = c_int32 if arr.dtype == np.int32 else c_double
         setattr(r, name, arr.ctypes.data_as(POINTER(ct)))
     _SERIAL[ctx.value] = _SERIAL.get(ctx.value, 0) + 1  # any solve replaces the last
+    _CTX_SHAPE[ctx.value] = (m, n, prec)
     if host_io:
         bh, pb = _np(b, np.float64)
         x0h = None if x0 is None else _np(x0, np.float64)
+        if bh.shape != (m,) or (x0h is not None and x0h[0].shape != (n,)):
+            raise ValueError("b must hold m and x0 n float64 values")
         if x_out.dtype != np.float64 or not x_out.flags.c_contiguous or x_out.shape != (n,):
             raise ValueError("x_out must be a contiguous float64 array of n entries")
         st = _check(ctx, lib.lslu_solve_host(
@@ -395,8 +471,12 @@ def lslu_solve_batch(ctxs, ops, bs, maxiter, reg="none", lam=0.0, grid=None,
     o.stop_tol = float(stop_tol)
     o.early_stop = 1 if early_stop else 0
     xs, rs, hosts = [], [], []
-    for op, b in zip(ops, bs):
+    if not (len(ctxs) == len(ops) == len(bs)):
+        raise ValueError("one context, operator and b per problem")
+    for i, (c, op, b) in enumerate(zip(ctxs, ops, bs)):
         m, n, prec = lslu_op_info(op)
+        _vec(b, m, prec, f"b[{i}]", _CTX_DEVICE.get(c.value))
+        _CTX_SHAPE[c.value] = (m, n, prec)
         xs.append(torch.empty(n, dtype=_torch_dtype(prec), device=b.device))
         r = lslu_result()
         host = dict(
@@ -476,12 +556,24 @@ def lslu_vjp(ctx, op, k, xbar, bbar=None):
     d x_k/d lambda``, pivots, x_0 and lambda_k held fixed."""
     import torch
     m, n, prec = lslu_op_info(op)
+    dev = _CTX_DEVICE.get(ctx.value)
+    px = _vec(xbar, n, prec, "xbar", dev)
     if bbar is None:
         bbar = torch.empty(m, dtype=_torch_dtype(prec), device=xbar.device)
+    pb = _vec(bbar, m, prec, "bbar", dev)
     lb = c_double(0.0)
-    _check(ctx, lib.lslu_vjp(ctx, op, int(k), _dptr(xbar), _dptr(bbar), ctypes.byref(lb)))
+    _check(ctx, lib.lslu_vjp(ctx, op, int(k), px, pb, ctypes.byref(lb)))
     return bbar, lb.value
 
 
 def lslu_get_basis(ctx, which, count, dst):
-    _check(ctx, lib.lslu_get_basis(ctx, int(which), int(count), _dptr(dst)))
+    """Copies ``count`` basis vectors of the context's last solve (L for
+    ``which`` = 0, D for 1) into the device tensor ``dst`` (at least count
+    vectors of n, resp. m, entries)."""
+    shape = _CTX_SHAPE.get(ctx.value)
+    if shape is None:
+        raise ValueError("no solve was started on this context through this binding")
+    m, n, prec = shape
+    p = _vec(dst, int(count) * (n if which == 0 else m), prec, "dst",
+             _CTX_DEVICE.get(ctx.value), at_least=True)
+    _check(ctx, lib.lslu_get_basis(ctx, int(which), int(count), p))

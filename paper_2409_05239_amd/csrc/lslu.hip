@@ -886,6 +886,10 @@ lslu_status lslu_op_psf(lslu_ctx* c, int64_t rows, int64_t cols, int32_t ph,
     LSLU_HIP(c, hipSetDevice(c->device));
     const int np = ph * pw;
     std::vector<double> p(psf, psf + np), pf(np);
+    // FP32: the weights are float values (held in double, the type the FP32
+    // products sum in), as the dense and CSR operators store theirs.
+    if (prec == kFP32)
+      for (double& w : p) w = static_cast<double>(static_cast<float>(w));
     for (int a = 0; a < ph; ++a)
       for (int b = 0; b < pw; ++b) pf[a * pw + b] = psf[(ph - 1 - a) * pw + (pw - 1 - b)];
     // float copies of the weights in the 16-bit operator formats

@@ -88,3 +88,63 @@ def test_fp8_values_are_e4m3():
     r = e4m3(mids)
     idx = np.searchsorted(vals, r)
     assert np.all(vals[idx] == r) and np.all((idx % 2 == 0) | (idx == len(vals) - 1))
+
+
+class _FakeDeviceTensor:
+    """The attributes the binding's argument checks read from a torch CUDA
+    tensor, without a GPU (the checks run before any pointer crosses the C
+    ABI)."""
+
+    def __init__(self, numel, dtype, device=0, contiguous=True, cuda=True):
+        import types
+        self._n, self.dtype, self._c = numel, dtype, contiguous
+        self.is_cuda = cuda
+        self.device = types.SimpleNamespace(index=device)
+
+    def numel(self):
+        return self._n
+
+    def is_contiguous(self):
+        return self._c
+
+    def data_ptr(self):
+        return 0x1000
+
+
+def test_device_vector_checks(capi):
+    import torch
+    F = _FakeDeviceTensor
+    f32, f64 = torch.float32, torch.float64
+    assert capi._vec(F(10, f32), 10, capi.LSLU_FP32, "b", 0).value == 0x1000
+    assert capi._vec(F(10, f64), 10, capi.LSLU_FP64, "b", None).value == 0x1000
+    assert capi._vec(F(12, f32), 10, capi.LSLU_BF16OP, "X", 0, at_least=True).value
+    bad = [
+        (F(10, f32, cuda=False), 10, capi.LSLU_FP32, {}, "CUDA tensor"),
+        (torch.zeros(10), 10, capi.LSLU_FP32, {}, "CUDA tensor"),
+        (F(10, f32), 10, capi.LSLU_FP64, {}, "float64"),
+        (F(10, f64), 10, capi.LSLU_FP8OP, {}, "float32"),
+        (F(10, f32, contiguous=False), 10, capi.LSLU_FP32, {}, "contiguous"),
+        (F(9, f32), 10, capi.LSLU_FP32, {}, "10 entries"),
+        (F(11, f32), 10, capi.LSLU_FP32, {}, "10 entries"),
+        (F(9, f32), 10, capi.LSLU_FP32, {"at_least": True}, "at least 10"),
+        (F(10, f32, device=1), 10, capi.LSLU_FP32, {"device": 0}, "cuda:1"),
+    ]
+    for t, n, prec, kw, msg in bad:
+        with pytest.raises(ValueError, match=msg):
+            capi._vec(t, n, prec, "v", kw.get("device"), kw.get("at_least", False))
+    with pytest.raises(ValueError, match="required"):
+        capi._vec(None, 3, capi.LSLU_FP32, "b")
+    assert capi._opt_vec(None, 3, capi.LSLU_FP32, "x0") is None
+
+
+def test_host_array_checks(capi):
+    K = 5
+    a = capi._host_ints(np.arange(K + 1), K + 1, "replay_piv_t")
+    assert a.dtype == np.int32 and a.shape == (K + 1,)
+    with pytest.raises(ValueError, match="at least 6"):
+        capi._host_ints(np.arange(K), K + 1, "replay_piv_t")
+    rows = capi._sample_rows(np.zeros((2 * K + 3, 7), np.int64), K)
+    assert rows.shape == (2 * K + 1, 7) and rows.dtype == np.int32 and rows.flags.c_contiguous
+    for shape in [(2 * K, 7), (2 * K + 1, 0), (2 * K + 1, 513), (2 * K + 1,)]:
+        with pytest.raises(ValueError, match="pivot_sample"):
+            capi._sample_rows(np.zeros(shape, np.int32), K)

@@ -358,6 +358,40 @@ def test_low_precision_rounding_is_exact(lib, ctx, kind, prec):
         lib.lslu_op_destroy(op)
 
 
+@pytest.mark.parametrize("kind", ["dense", "csr", "psf"])
+def test_fp32_operator_values_are_float(lib, ctx, kind):
+    """FP32 operators hold float values and sum in double: diag(a) (a 1x1 PSF
+    for the stencil) applied to float x gives float(float(a) * x) to the bit.
+    The weight 0.3 is not a float, so an operator that kept the given double
+    differs from this on about half of the entries."""
+    import torch
+    v = _16bit_cases()
+    n = len(v)
+    w = 0.3
+    a = np.full(n, w)
+    if kind == "dense":
+        op = lib.lslu_op_dense(ctx, np.diag(a), lib.LSLU_FP32)
+    elif kind == "csr":
+        op = lib.lslu_op_csr(ctx, n, n, np.arange(n + 1), np.arange(n, dtype=np.int32), a,
+                             lib.LSLU_FP32)
+    else:
+        op = lib.lslu_op_psf(ctx, 1, n, np.array([[w]]), lib.LSLU_FP32)
+    try:
+        ref = (np.float32(w).astype(np.float64) * v).astype(np.float32).astype(np.float64)
+        unrounded = (w * v).astype(np.float32).astype(np.float64)
+        assert np.count_nonzero(ref != unrounded) > n // 4  # the case tells the two apart
+        for tr in (0, 1):
+            xt = torch.tensor(v, dtype=torch.float32, device="cuda")
+            yt = torch.full((n,), np.nan, dtype=torch.float32, device="cuda")
+            lib.lslu_op_apply(ctx, op, tr, xt, yt)
+            torch.cuda.synchronize()
+            y = yt.double().cpu().numpy()
+            bad = np.flatnonzero(y != ref)
+            assert bad.size == 0, (kind, tr, [(v[i], y[i], ref[i]) for i in bad[:5]])
+    finally:
+        lib.lslu_op_destroy(op)
+
+
 @pytest.mark.parametrize("name", ["deblur96", "tomo32"])
 def test_8bit_operator_error(lib, ctx, name):
     """The E4M3 operator mode (values and product inputs with 3 fraction
