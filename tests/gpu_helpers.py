@@ -108,6 +108,19 @@ def well_separated_prefix(R, tau, k_max):
     return k_ok
 
 
+#: Relative tolerance of Ghat(k) (eq. stop2) where x_k is held to TOL: Ghat is
+#: a ratio of the projected residual and a trace, both smooth in H_{k+1,k};
+#: the library evaluates the residual/trace form from a bidiagonalisation,
+#: the oracle the SVD form, so only rounding separates them.
+GHAT_TOL = {"fp64": 1e-8, "fp32": 1e-3}
+
+
+def check_ghat(G, R, k, prec):
+    """Ghat(k) of the library against the oracle's at iteration k."""
+    g, r = G["ghat"][k - 1], R.ghat[k - 1]
+    assert abs(g - r) <= GHAT_TOL[prec] * abs(r), (k, g, r)
+
+
 def rel(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)

@@ -160,11 +160,14 @@ def test_merged_launch_batch_rejects_what_it_cannot_merge(lib):
         ops = [lib.make_operator(ctxs[0], probs[0], lib.LSLU_FP64),
                lib.make_operator(ctxs[1], probs[1], lib.LSLU_FP64),
                lib.make_operator(ctxs[2], probs[0], lib.LSLU_FP32)]
-        bs = [torch.tensor(p.b, dtype=torch.float64, device="cuda") for p in probs]
+        # a well-formed b for each operator, so the library itself refuses
+        bs = [torch.tensor(probs[0].b, dtype=torch.float64, device="cuda"),
+              torch.tensor(probs[1].b, dtype=torch.float64, device="cuda"),
+              torch.tensor(probs[0].b, dtype=torch.float32, device="cuda")]
         for sel in ([0, 1], [0, 2]):  # a PSF operator; mixed precisions
             with pytest.raises(lib.LsluError) as ei:
                 lib.lslu_solve_batch([ctxs[i] for i in sel], [ops[i] for i in sel],
-                                     [bs[0], bs[0]], 5)
+                                     [bs[i] for i in sel], 5)
             assert ei.value.status == lib.LSLU_EINVAL
         op_b = lib.make_operator(ctxs[0], probs[0], lib.LSLU_FP64)
         ops.append(op_b)
@@ -198,6 +201,78 @@ def test_merged_launch_batch_early_stop(lib):
             torch.cuda.synchronize()
             xb, ib = out[i]
             assert ib["k_stop"] == i1["k_stop"] and torch.equal(xb, x1), i
+    finally:
+        for op in ops:
+            lib.lslu_op_destroy(op)
+        for c in ctxs:
+            lib.lslu_destroy(c)
+
+
+def _oracle_checks(prob, info, x, prec, K):
+    """One batched problem against the FP64 oracle run alone: FP64 -- pivots
+    over the oracle's well-separated prefix, and where that prefix covers the
+    whole solve, H, W, the lambda indices, Ghat and the final iterate; the
+    low-precision modes -- the error to x_true at K against the oracle's."""
+    from gpu_helpers import TAU, check_ghat, pivot_prefix, rel, well_separated_prefix
+    from oracle import RegParam, make_operator
+    from oracle.hessenberg import hybrid_lslu
+    R = hybrid_lslu(make_operator(prob), prob.b, K,
+                    RegParam("wgcv", grid=lambda_grid(), grid_relative=True))
+    xg = x.double().cpu().numpy()
+    if prec != "fp64":
+        e_g, e_r = rel(xg, prob.x_true), rel(R.x, prob.x_true)
+        print(f"[batch oracle] {prob.name} {prec}: err at K {e_g:.4f} (fp64 oracle {e_r:.4f})")
+        assert e_g <= 1.05 * e_r + 1e-3, (prob.name, e_g, e_r)
+        return
+    kd = min(R.k_done, info["k_done"])
+    kp = pivot_prefix(R, TAU["fp64"], kd)
+    assert list(info["piv_g"][:kp]) == R.piv_g[:kp], prob.name
+    assert list(info["piv_t"][:kp]) == R.piv_t[:kp], prob.name
+    k_ok = well_separated_prefix(R, TAU["fp64"], kd)
+    Hs, Ws = np.abs(R.H).max(), np.abs(R.W).max()
+    assert np.abs(info["H"][:k_ok + 1, :k_ok] - R.H[:k_ok + 1, :k_ok]).max() <= 1e-9 * Hs
+    assert np.abs(info["W"][:k_ok, :k_ok] - R.W[:k_ok, :k_ok]).max() <= 1e-9 * Ws
+    for k in range(1, k_ok + 1):
+        assert info["lambda_idx"][k - 1] == R.lambda_idx[k - 1], (prob.name, k)
+        check_ghat(info, R, k, "fp64")
+    if k_ok == kd == K:
+        assert rel(xg, R.x) <= 1e-10, prob.name
+    print(f"[batch oracle] {prob.name}: pivots equal for k <= {kp}, "
+          f"separated prefix {k_ok} of {kd}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16op"])
+def test_batched_solves_match_oracle(lib, prec):
+    """Problems of the batched workload's kinds (tomography with side = angles,
+    side + 1 bins; deblurring with a Gaussian PSF) solved together --
+    tomography through merged launches (lslu_solve_batch), deblurring as
+    concurrent solves on their own contexts -- against the FP64 oracle."""
+    import torch
+    from workloads import psf_deblur
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    tomo = _tomo_set(4, 11)
+    blur = [psf_deblur(s, int(np.ceil(3 * sg)), sg, 0.01, seed=2000 + s)
+            for s, sg in ((40, 1.5), (56, 2.5), (48, 4.0))]
+    ctxs = [lib.lslu_create(0) for _ in tomo + blur]
+    ops = []
+    try:
+        for c, prob in zip(ctxs, tomo + blur):
+            ops.append(lib.make_operator(c, prob, lib.PRECISIONS[prec]))
+        bs = [torch.tensor(p.b, dtype=dt, device="cuda") for p in tomo + blur]
+        grid = lambda_grid()
+        nt = len(tomo)
+        print(f"[batch oracle] {prec}: " + ", ".join(p.name for p in tomo + blur), flush=True)
+        st, out = lib.lslu_solve_batch(ctxs[:nt], ops[:nt], bs[:nt], K, reg="wgcv", grid=grid,
+                                       grid_relative=True)
+        pend = [lib.lslu_solve(c, op, b, K, reg="wgcv", grid=grid, grid_relative=True,
+                               asynchronous=True)
+                for c, op, b in zip(ctxs[nt:], ops[nt:], bs[nt:])]
+        for c, pd in zip(ctxs[nt:], pend):
+            st1, x1, i1 = lib.lslu_wait(c, pd)
+            out.append((x1, i1))
+        torch.cuda.synchronize()
+        for prob, (x, info) in zip(tomo + blur, out):
+            _oracle_checks(prob, info, x, prec, K)
     finally:
         for op in ops:
             lib.lslu_op_destroy(op)

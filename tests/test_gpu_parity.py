@@ -13,9 +13,9 @@ Tolerances on ||x_k - x_oracle||/||x_oracle|| and on the relative residual gap:
 import numpy as np
 import pytest
 
-from gpu_helpers import (TAU, TOL, check_basis_invariants, check_relations,
-                         gpu_solve, pivot_prefix, rel, replay_from,
-                         residual_gap, well_separated_prefix)
+from gpu_helpers import (TAU, TOL, check_basis_invariants, check_ghat,
+                         check_relations, gpu_solve, pivot_prefix, rel,
+                         replay_from, residual_gap, well_separated_prefix)
 from oracle import RegParam, make_operator
 from oracle.hessenberg import Status, hybrid_lslu
 from workloads import (config_problem, lambda_grid, psf_deblur, random_dense,
@@ -61,6 +61,8 @@ def _compare(lib, ctx, prob, prec, K, kind, relative, lam=0.05, replay=True,
                 if kappa_cap and G["sigma_max"][k - 1] / G["sigma_min"][k - 1] > kappa_cap:
                     break
                 assert rel(G["X"][:, k - 1], R.X[:, k - 1]) <= tol, k
+                assert G["lambda_idx"][k - 1] == R.lambda_idx[k - 1] or R.lambda_idx[k - 1] < 0
+                check_ghat(G, R, k, prec)
     if replay:
         Kr = min(K, R.k_done)
         ps = None
@@ -80,6 +82,7 @@ def _compare(lib, ctx, prob, prec, K, kind, relative, lam=0.05, replay=True,
             worst.append((k, e, g, kap))
             if kappa_cap is None or kap <= kappa_cap:
                 assert e <= tol and g <= tol, (k, e, g, kap)
+                check_ghat(G, R, k, prec)
         print(f"[{prob.name} {prec} {kind}] max x err "
               f"{max(w[1] for w in worst):.3e} max residual gap "
               f"{max(w[2] for w in worst):.3e}")

@@ -603,3 +603,59 @@ def test_dloss_dlambda_against_central_differences(lam):
         dy = -2 * lam * np.linalg.solve(Hk.T @ Hk + lam * lam * np.eye(k), y)
         assert np.allclose(tikhonov_coeffs_dlambda(r.beta, s, c, V, lam), dy,
                            rtol=1e-7, atol=1e-9 * np.abs(dy).max())
+
+
+# ---------------------------------------------------------------------------
+# The lambda choice itself: grid index and value of the GCV and weighted-GCV
+# rules, by brute force from the trace forms
+# ---------------------------------------------------------------------------
+
+def _trace_form_index(H, beta, k, omega, grid):
+    """Index of the smallest G(omega, lambda) over the grid (ties: smallest
+    index), with G the weighted GCV function of the projected problem in its
+    trace form (eq. wgcv_projected1; omega = 1 is eq. gcv1):
+        k ||(I - H H_lam^+) beta e_1||^2 / trace(I - omega H H_lam^+)^2,
+    H_lam^+ = (H^T H + lam^2 I)^-1 H^T formed explicitly."""
+    e1 = np.zeros(k + 1)
+    e1[0] = beta
+    vals = []
+    for lam in grid:
+        P = H @ np.linalg.solve(H.T @ H + lam * lam * np.eye(k), H.T)
+        res = np.linalg.norm(e1 - P @ e1) ** 2
+        vals.append(k * res / np.trace(np.eye(k + 1) - omega * P) ** 2)
+    vals = np.array(vals)
+    return int(np.flatnonzero(vals == vals.min())[0])
+
+
+@pytest.mark.parametrize("rule", ["wgcv", "gcv"])
+@pytest.mark.parametrize("prob,K", [(None, 30), ("tomo", 25)], ids=["blur48", "tomo16"])
+def test_lambda_choice_by_brute_force(rule, prob, K):
+    """At every k the oracle's lambda_k is sigma_1(H_{k+1,k}) times the grid
+    value minimising the trace form with omega = (k+1)/m for weighted GCV (the
+    weight the end of Section 3.2.1 adopts) and omega = 1 for GCV; sigma_1
+    from numpy's singular values of the stored H.  On the 48-row problem
+    (omega from 2/48 to 31/48) omega = k/m or (k+2)/m, or a grid scaled by
+    sigma_k, picks a different lambda at some k, so an off-by-one weight or
+    the wrong scale does not pass."""
+    from workloads import dense_blur_1d
+    prob = (dense_blur_1d(48, 2.0, 0.05, seed=3) if prob is None
+            else tomography(16, 12, 23, 0.02, seed=5))
+    grid = lambda_grid(120)
+    r = hybrid_lslu(make_operator(prob), prob.b, K,
+                    RegParam(rule, grid=grid, grid_relative=True))
+    assert r.k_done == K
+    m = prob.m
+    shifted = {0: 0, 2: 0, "smin": 0}
+    for k in range(1, K + 1):
+        H = r.H[:k + 1, :k]
+        sv = np.linalg.svd(H, compute_uv=False)
+        omega = (k + 1) / m if rule == "wgcv" else 1.0
+        idx = _trace_form_index(H, r.beta, k, omega, sv[0] * grid)
+        assert r.lambda_idx[k - 1] == idx, (k, r.lambda_idx[k - 1], idx)
+        assert np.isclose(r.lambdas[k - 1], sv[0] * grid[idx], rtol=1e-13, atol=0)
+        if rule == "wgcv" and m == 48:
+            for d in (0, 2):
+                shifted[d] += _trace_form_index(H, r.beta, k, (k + d) / m, sv[0] * grid) != idx
+            shifted["smin"] += _trace_form_index(H, r.beta, k, omega, sv[-1] * grid) != idx
+    if rule == "wgcv" and m == 48:
+        assert all(v > 0 for v in shifted.values()), shifted
