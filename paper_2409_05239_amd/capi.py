@@ -428,7 +428,6 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
         ct = c_int32 if arr.dtype == np.int32 else c_double
         setattr(r, name, arr.ctypes.data_as(POINTER(ct)))
     _SERIAL[ctx.value] = _SERIAL.get(ctx.value, 0) + 1  # any solve replaces the last
-    _CTX_SHAPE[ctx.value] = (m, n, prec)
     if host_io:
         bh, pb = _np(b, np.float64)
         x0h = None if x0 is None else _np(x0, np.float64)
@@ -439,9 +438,11 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
         st = _check(ctx, lib.lslu_solve_host(
             ctx, op, pb, None if x0h is None else x0h[1], ctypes.byref(o),
             x_out.ctypes.data_as(POINTER(c_double)), ctypes.byref(r)))
+        _CTX_SHAPE[ctx.value] = (m, n, prec)  # the solve the context now holds
         return st, x_out, _info(st, r, host, timing)
     st = _check(ctx, lib.lslu_solve(ctx, op, _dptr(b), _dptr(x0), ctypes.byref(o),
                                     _dptr(x_out), ctypes.byref(r)))
+    _CTX_SHAPE[ctx.value] = (m, n, prec)
     if asynchronous:
         # everything the library may still write or read stays referenced
         return Pending(r, host, keep, x_out, (b, x0, X, x_true), timing)
@@ -476,7 +477,6 @@ def lslu_solve_batch(ctxs, ops, bs, maxiter, reg="none", lam=0.0, grid=None,
     for i, (c, op, b) in enumerate(zip(ctxs, ops, bs)):
         m, n, prec = lslu_op_info(op)
         _vec(b, m, prec, f"b[{i}]", _CTX_DEVICE.get(c.value))
-        _CTX_SHAPE[c.value] = (m, n, prec)
         xs.append(torch.empty(n, dtype=_torch_dtype(prec), device=b.device))
         r = lslu_result()
         host = dict(
@@ -499,6 +499,8 @@ def lslu_solve_batch(ctxs, ops, bs, maxiter, reg="none", lam=0.0, grid=None,
     arr_r = (POINTER(lslu_result) * P)(*[ctypes.pointer(r) for r in rs])
     st = _check(ctxs[0], lib.lslu_solve_batch(P, arr_c, arr_o, arr_b, ctypes.byref(o),
                                               arr_x, arr_r))
+    for c, op in zip(ctxs, ops):
+        _CTX_SHAPE[c.value] = lslu_op_info(op)
     out = []
     for x, r, host in zip(xs, rs, hosts):
         out.append((x, _info(r.status, r, host, False)))

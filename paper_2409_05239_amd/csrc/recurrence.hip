@@ -1,1069 +1,43 @@
-// One half-iteration of the pivoted rectangular Hessenberg process
-// (Algorithm 4; the basis part of Algorithm 5) in one launch.
-//
-// The l side at iteration k (the d side mirrors it with A, D and t): the
-// previous launch left u, the unnormalised d-side vector (zero at t(1..k-1)),
-// and its per-block pivot candidates.
-//   block 0           t(k) = the row of the largest |u| among the candidates
-//                     (smallest row among equals), the breakdown test,
-//                     H(k,k-1) (or beta at k = 1) and the new triangle row
-//                     (d_1..d_{k-1})(t(k)); publishes (t(k), H(k,k-1)).  Then
-//                     solves T_L w = (A^T d_k)(g(1..k-1)) by forward
-//                     substitution and publishes w = W(1:k-1,k).
-//   blocks 1..nlead-1 (A^T d_k)(g(j)), one wavefront per j.
-//   other blocks      their rows of q0 = A^T d_k, d_k = u / H(k,k-1) into its
-//                     basis column (IEEE division: exactly 1 at t(k)), then
-//                     q = q0 - L_{k-1} w, q = 0 at g(1..k-1), and per block the
-//                     largest remaining |q|.
-// w equals the values the sequential loop of Algorithm 5 reads at g(j): l_i is
-// 1 at g(i) and 0 at g(j), j < i.  The forward substitution gives each row j
-// its subtractions in increasing i, as that loop does; floating-point
-// contraction is disabled there so each step rounds like a multiply then a
-// subtract.
-//
-// Products read the normalised vector as they gather it: each input is u(c)
-// divided by the pivot value with the value of IEEE division (Normaliser), the
-// same value the normalised basis column holds, so products and exact
-// cancellations are those of the normalised vector.  The products therefore start once the pivot is
-// published; the triangular solve of block 0 overlaps them.
-//
-// Synchronisation inside the launch: blocks only ever wait for values written
-// by lower-numbered blocks, which never wait for higher-numbered ones;
-// workgroups are dispatched in order, so the blocks that publish are resident
-// first.  Everything published inside a launch (the pivot, its value, the
-// pivot entries, the coefficients) goes through slots that hold a sentinel
-// until written once; a waiter polls the slot itself, so no flag has to order
-// other memory and nobody fences.  Every load a product needs that does not
-// depend on the pivot (indices, values and the gathered entries of the
-// unnormalised vector) is issued before the wait.  Every wait is bounded: a
-// wait that runs out counts a device error and the launch finishes.  Results
-// do not depend on timing or on the launch configuration.
+// One half-iteration of the pivoted rectangular Hessenberg process: the
+// launch dispatch and the entry points the solve driver calls.  The kernels
+// and their launch helpers are in recurrence_impl.hpp; the PSF launches of
+// each precision mode are in recurrence_psf_<mode>.hip.
 #include <cstring>
-#include <map>
-#include <mutex>
-#include <tuple>
 
-#include "device_common.hpp"
+#include "recurrence_impl.hpp"
 
 namespace lslu {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / kWave;
-constexpr int kCoefPerLane = 16;  // coefficients per lane of the elimination
-constexpr int kPartsPerThread = kMaxParts / kThreads;  // 16
-constexpr int kStage = 8;
-constexpr int kEntryStage = 8;   // staged terms per lane of a pivot-entry row
-constexpr int kRowStage = 8;     // staged terms per lane of a consumer's first row
-constexpr int kNormBatch = 8;
-constexpr int kNormStage = 2;  // entries of the normalisation share loaded before the pivot
-constexpr int kSpinLimit = 1 << 20;
-constexpr int kTriB = 32;  // rows of a diagonal block of the triangular solve
-constexpr uint64_t kSentinel = kSlotEmpty;
-constexpr size_t kTriLdsMax = 32 * 1024;
-static_assert(sizeof(ArgPart) == 16, "candidates are read as 16-byte vectors");
-
-__host__ __device__ inline int64_t packed_row(int j) { return (int64_t)j * (j - 1) / 2; }
-
-// ------------------------------------------------------------------ slots --
-// Slots are written once per launch with device-coherent stores and polled
-// with device-coherent loads (they bypass the non-coherent caches, so no
-// fence is needed on either side: a device-scope fence writes back and
-// invalidates the whole L2 of the XCD).
-__device__ inline void store_u64(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ inline uint64_t load_u64(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ inline uint64_t load_u64(const double* p) {
-  return load_u64(reinterpret_cast<const uint64_t*>(p));
-}
-
-__device__ inline int load_i(const int* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ inline uint64_t dbits(double v) { return __builtin_bit_cast(uint64_t, v); }
-
-// Block-wide bounded wait for the pivot of the previous half.  Returns true
-// with its row and value when one was found, false on breakdown or when the
-// bound ran out (counted as a device error).
+// The PSF launch of the operator's precision mode.
 template <typename T>
-__device__ inline bool wait_pivot(const HalfArgs<T>& a, DevState* st, int& pick,
-                                  double& val) {
-  __shared__ uint64_t sv, sp;
-  if (threadIdx.x == 0) {
-    uint64_t v = kSentinel, p = kSentinel;
-    for (int it = 0; it < kSpinLimit; ++it) {
-      v = load_u64(a.pslot);
-      p = load_u64(a.pslot + 1);
-      if (v != kSentinel && p != kSentinel) break;
-      __builtin_amdgcn_s_sleep(1);
-    }
-    if (v == kSentinel || p == kSentinel) {
-      atomicAdd(&st->spin_timeouts, 1);
-      p = 0;  // state 0: stop
-    }
-    sv = v;
-    sp = p;
-  }
-  __syncthreads();
-  const uint64_t p = sp;
-  pick = static_cast<int>(static_cast<uint32_t>(p));
-  val = __builtin_bit_cast(double, sv);
-  return (p >> 32) == 1;
-}
-
-// ------------------------------------------------------- triangular solve --
-// T g = g in place for the nb x nb unit lower triangular T packed by rows
-// (row j at offset j(j-1)/2 holds T(j, 0..j-1)), in 32-row blocks:
-// wavefront 0 keeps its lanes' rows of the diagonal block in registers (zero
-// above the diagonal) and runs the dependent chain with w_i broadcast by
-// readlane; the workgroup then updates the rows below.
-template <typename T>
-__device__ __attribute__((always_inline)) inline void trisolve_inplace(
-    double* g, int nb, const T* __restrict__ tp) {
-#pragma clang fp contract(off)
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-  for (int b0 = 0; b0 < nb; b0 += kTriB) {
-    const int bs = min(kTriB, nb - b0);
-    if (w == 0) {
-      const int j = b0 + lane;
-      const bool act = lane < bs;
-      const T* row = tp + packed_row(act ? j : b0) + b0;  // T(j, b0 + i) = row[i]
-      T tr[kTriB];
-#pragma unroll
-      for (int i = 0; i < kTriB; ++i) tr[i] = (act && i < lane) ? row[i] : T(0);
-      double gl = act ? g[j] : 0.0;
-#pragma unroll
-      for (int i = 0; i < kTriB; ++i) {
-        const double wi = readlane_d(gl, i);
-        gl = gl - static_cast<double>(tr[i]) * wi;  // tr[i] == 0 unless i < lane
-      }
-      if (act) g[j] = gl;
-    }
-    __syncthreads();
-    for (int j = b0 + bs + tid; j < nb; j += kThreads) {
-      const T* row = tp + packed_row(j) + b0;
-      double gj = g[j];
-      int i = 0;
-      for (; i + 8 <= bs; i += 8) {
-        double tv[8], wv8[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          tv[u] = static_cast<double>(row[i + u]);
-          wv8[u] = g[b0 + i + u];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) gj = gj - tv[u] * wv8[u];
-      }
-      for (; i < bs; ++i) gj = gj - static_cast<double>(row[i]) * g[b0 + i];
-      g[j] = gj;
-    }
-    __syncthreads();
-  }
-}
-
-// T g = g in place for 2 <= nb <= 64 S by one wavefront, the unit lower
-// triangular T packed by rows in LDS: row j lives in lane j % 64, slot
-// j / 64; step i broadcasts w_i = g_i by readlane and every later row
-// subtracts T(j,i) w_i, so each row sees the sequential order.  The entries
-// of the next 8 steps are loaded ahead (indices clamped into the triangle;
-// rows not updated by a step keep their value), so no step waits on LDS.
-template <typename T, int S>
-__device__ __attribute__((always_inline)) inline void trisolve_wave(double* g, int nb,
-                                                                    const T* __restrict__ tp) {
-#pragma clang fp contract(off)
-  const int lane = threadIdx.x & (kWave - 1);
-  if (threadIdx.x < kWave) {
-    const int64_t P = packed_row(nb);
-    double gr[S];
-    int64_t base[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int j = lane + kWave * s;
-      gr[s] = j < nb ? g[j] : 0.0;
-      base[s] = j < nb ? packed_row(j) : 0;
-    }
-#pragma unroll
-    for (int s0 = 0; s0 < S; ++s0) {
-      const int ib = kWave * s0, ie = min(nb, kWave * (s0 + 1));
-      for (int i0 = ib; i0 < ie; i0 += 8) {
-        T t[S][8];
-#pragma unroll
-        for (int s = s0; s < S; ++s)
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int64_t q = base[s] + i0 + u;
-            t[s][u] = tp[q < P ? q : P - 1];
-          }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int i = i0 + u;
-          if (i >= ie) break;
-          const double wi = readlane_d(gr[s0], i - ib);
-#pragma unroll
-          for (int s = s0; s < S; ++s) {
-            const int j = lane + kWave * s;
-            const double nv = gr[s] - static_cast<double>(t[s][u]) * wi;
-            gr[s] = (j > i && j < nb) ? nv : gr[s];
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int j = lane + kWave * s;
-      if (j < nb) g[j] = gr[s];
-    }
-  }
-  __syncthreads();
-}
-
-// Sampled pivot search (the variant of Section 2.2): among the first
-// sample_s listed rows that are not earlier pivots, the entry of largest
-// magnitude (ties: smallest row), as a signed key; 0 when all are 0.  The
-// rank of a listed row among the eligible ones comes from a block-wide
-// ballot prefix count in list order.
-template <typename T>
-__device__ inline void sampled_search(const HalfArgs<T>& a, double& key, int& idx) {
-  __shared__ int wcount[kWaves];
-  const PivotJob& job = a.job;
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-  key = 0.0;
-  idx = INT_MAX;
-  int base = 0;
-  for (int c0 = 0; c0 < job.sample_len; c0 += kThreads) {
-    const int li = c0 + tid;
-    const int row = li < job.sample_len ? job.sample[li] : -1;
-    bool elig = false;
-    double v = 0.0;
-    if (row >= 0) {
-      elig = job.mask[row] == 0;
-      v = static_cast<double>(a.up[row]);
-    }
-    const uint64_t bal = __ballot(elig);
-    const int below = __popcll(bal & ((1ull << lane) - 1ull));
-    if (lane == 0) wcount[w] = __popcll(bal);
-    __syncthreads();
-    int before = base, total = 0;
-#pragma unroll
-    for (int i = 0; i < kWaves; ++i) {
-      if (i < w) before += wcount[i];
-      total += wcount[i];
-    }
-    __syncthreads();
-    if (elig && before + below < job.sample_s && better(v, row, key, idx)) {
-      key = v;
-      idx = row;
-    }
-    base += total;
-  }
-  block_argmax<kThreads>(key, idx);
-}
-
-// ------------------------------------------------------------ block 0 -----
-template <typename T, bool kTriLds>
-__device__ void lead(const HalfArgs<T>& a, DevState* st, unsigned char* lds) {
-  __shared__ double g[kMaxIter + 1];
-  __shared__ int all_in;
-  const int tid = threadIdx.x;
-  const int nb = a.rows > 0 ? a.nb : 0;
-  // The triangle's first pass and the candidates are loaded before either is
-  // used.
-  T tbuf[kStage];
-  const int64_t P = (kTriLds && nb > 1) ? packed_row(nb) : 0;
-#pragma unroll
-  for (int u = 0; u < kStage; ++u) {
-    const int64_t p = (int64_t)u * kThreads + tid;
-    tbuf[u] = (p < P) ? a.Tp[p] : T(0);
-  }
-  double key = 0.0;
-  int idx = INT_MAX;
-  constexpr int kHalf = kPartsPerThread / 2;
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    int4 raw[kHalf];
-#pragma unroll
-    for (int u = 0; u < kHalf; ++u) {
-      const int i = tid + (h * kHalf + u) * kThreads;
-      raw[u] = (i < a.nparts_in) ? reinterpret_cast<const int4*>(a.parts_in)[i]
-                                 : make_int4(0, 0, INT_MAX, 0);
-    }
-#pragma unroll
-    for (int u = 0; u < kHalf; ++u) {
-      const double k2 = __builtin_bit_cast(
-          double, (static_cast<uint64_t>(static_cast<uint32_t>(raw[u].y)) << 32) |
-                      static_cast<uint32_t>(raw[u].x));
-      if (better(k2, raw[u].z, key, idx)) {
-        key = k2;
-        idx = raw[u].z;
-      }
-    }
-  }
-  block_argmax<kThreads>(key, idx);
-  const PivotJob& job = a.job;
-  if (job.sample) {  // a sample whose entries are all 0 keeps the full search
-    double skey;
-    int sidx;
-    sampled_search(a, skey, sidx);
-    if (fabs(skey) > 0.0) {
-      key = skey;
-      idx = sidx;
-    }
-  }
-  const int own = (job.eligible && fabs(key) > 0.0) ? idx : -1;
-  const int pick = job.replay ? (job.eligible ? job.replay[job.piv_pos] : -1) : own;
-  // The winning candidate carries the pivot value; a replayed pivot is read.
-  const double val = pick < 0 ? 0.0
-                     : (job.replay ? static_cast<double>(a.up[pick]) : key);
-  const bool brk = (pick < 0 || val == 0.0);
-  if (tid == 0) {
-    store_u64(a.pslot, dbits(brk ? 0.0 : val));
-    store_u64(a.pslot + 1, static_cast<uint32_t>(pick) | (static_cast<uint64_t>(brk ? 2 : 1) << 32));
-    if (job.own_list) job.own_list[job.piv_pos] = own;
-    if (job.replay && pick != own) {
-      if (job.side == 0) st->mismatch_g += 1; else st->mismatch_t += 1;
-    }
-    if (brk) {
-      // Breakdown: no eligible nonzero entry (Algorithm 4, "else break").
-      st->stopped = 1;
-      if (job.side == 2) {
-        st->status = kZeroRHS;
-        st->k_done = 0;
-      } else if (job.side == 0) {
-        st->status = kBreakQ;  // x stays x_{k-1}
-      } else {
-        *job.piv_val = 0.0;    // H(k+1,k) = 0; x_k is still formed
-        st->status = kBreakU;
-        st->k_done = job.k;
-      }
-    } else {
-      *job.piv_val = val;
-      job.piv_list[job.piv_pos] = pick;
-      job.mask[pick] = 1;
-      if (job.side == 2) {
-        st->beta = val;
-        st->n_d = 1;
-      } else if (job.side == 0) {
-        st->n_l = job.k;
-      } else {
-        st->n_d = job.k + 1;
-        st->k_done = job.k;
-      }
-    }
-  }
-  if (brk) return;
-  if (a.Trowp) {  // needed by later launches only
-    for (int j = tid; j < a.nbp; j += kThreads)
-      a.Trowp[j] = a.basisp[(int64_t)pick * a.rsp + (int64_t)j * a.csp];
-  }
-  if (nb == 0) return;
-  if constexpr (kTriLds) {
-    T* lt = reinterpret_cast<T*>(lds);
-#pragma unroll
-    for (int u = 0; u < kStage; ++u) {
-      const int64_t p = (int64_t)u * kThreads + tid;
-      if (p < P) lt[p] = tbuf[u];
-    }
-    for (int64_t p0 = (int64_t)kThreads * kStage; p0 < P; p0 += (int64_t)kThreads * kStage) {
-#pragma unroll
-      for (int u = 0; u < kStage; ++u) {
-        const int64_t p = p0 + (int64_t)u * kThreads + tid;
-        tbuf[u] = (p < P) ? a.Tp[p] : T(0);
-      }
-#pragma unroll
-      for (int u = 0; u < kStage; ++u) {
-        const int64_t p = p0 + (int64_t)u * kThreads + tid;
-        if (p < P) lt[p] = tbuf[u];
-      }
-    }
-  }
-  // The pivot entries of the product, written once by blocks 1..nlead-1.
-  bool got = true;
-  for (int j = tid; j < nb; j += kThreads) {
-    uint64_t bits = kSentinel;
-    for (int it = 0; it < kSpinLimit; ++it) {
-      bits = load_u64(a.entries + j);
-      if (bits != kSentinel) break;
-      __builtin_amdgcn_s_sleep(1);
-    }
-    if (bits == kSentinel) got = false;
-    g[j] = __builtin_bit_cast(double, bits);
-  }
-  if (tid == 0) all_in = 1;
-  __syncthreads();
-  if (!got) all_in = 0;
-  __syncthreads();
-  if (!all_in) {
-    if (tid == 0) {
-      atomicAdd(&st->spin_timeouts, 1);
-      __hip_atomic_store(a.fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    return;
-  }
-  if constexpr (kTriLds) {
-    const T* lt = reinterpret_cast<const T*>(lds);
-    if (nb >= 2 && nb <= kWave)
-      trisolve_wave<T, 1>(g, nb, lt);
-    else if (nb > kWave && nb <= 2 * kWave)
-      trisolve_wave<T, 2>(g, nb, lt);
-    else
-      trisolve_inplace<T>(g, nb, lt);
+int launch_psf_half(HalfArgs<T>& a, const DeviceOp& op, int tr, size_t lds_bytes, hipStream_t s,
+                    bool dry) {
+  if constexpr (std::is_same_v<T, double>) {
+    return launch_psf_half_fp64(a, op, tr, lds_bytes, s, dry);
   } else {
-    trisolve_inplace<T>(g, nb, a.Tp);
-  }
-  for (int j = tid; j < nb; j += kThreads) {
-    store_u64(reinterpret_cast<uint64_t*>(a.cslot) + j, dbits(g[j]));
-    a.coef[j] = g[j];
-  }
-}
-
-// ------------------------------------------------- pivot-entry blocks -----
-// bid: this block's index within its solve's blocks (1..nlead-1).
-template <typename T, class RowOp>
-__device__ void pivot_entries(const HalfArgs<T>& a, const RowOp& op, DevState* st, int bid) {
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-  const int jr = (bid - 1) * kWaves + w;
-  const bool act = jr < a.nb;
-  RowStage<typename RowOp::Val, T, kEntryStage> sg;
-  if (act) op.template stage<kWave, kEntryStage>(a.piv[jr], lane, a.up, sg);
-  int pick;
-  double val;
-  if (!wait_pivot(a, st, pick, val)) return;
-  if (!act) return;
-  const Normaliser<T> nz(static_cast<T>(val));
-  auto xf = [&](int64_t c) -> T { return nz(a.up[c]); };
-  typename RowOp::Acc acc = op.template finish<kWave, kEntryStage>(sg, nz, xf);
-  acc = group_sum<kWave>(acc);
-  if (lane == 0)
-    store_u64(reinterpret_cast<uint64_t*>(a.entries) + jr,
-              dbits(static_cast<double>(static_cast<T>(acc))));
-}
-
-// Normalise this block's share of the previous vector into its basis column:
-// entries i = cb * 256 + tid + u * ncons * 256.  The first kNormStage of a
-// thread's entries are loaded before the pivot is known (stage), the rest
-// after it.
-template <typename T>
-struct NormStage {
-  T v[kNormStage];
-};
-
-template <typename T>
-__device__ inline void normalise_stage(const HalfArgs<T>& a, int cb, int ncons, NormStage<T>& s) {
-  const int64_t step = (int64_t)ncons * kThreads;
-  const int64_t i0 = (int64_t)cb * kThreads + threadIdx.x;
-#pragma unroll
-  for (int u = 0; u < kNormStage; ++u) {
-    const int64_t i = i0 + u * step;
-    s.v[u] = (i < a.lenp) ? a.up[i] : T(0);
-  }
-}
-
-template <typename T>
-__device__ inline void normalise_share(const HalfArgs<T>& a, int cb, int ncons,
-                                       int pick, const Normaliser<T>& nz,
-                                       const NormStage<T>& s) {
-  const int64_t step = (int64_t)ncons * kThreads;
-  const int64_t i0 = (int64_t)cb * kThreads + threadIdx.x;
-#pragma unroll
-  for (int u = 0; u < kNormStage; ++u) {
-    const int64_t i = i0 + u * step;
-    if (i < a.lenp) a.dstp[i * a.dstp_stride] = (i == pick) ? T(1) : nz(s.v[u]);
-  }
-  for (int64_t j0 = i0 + kNormStage * step; j0 < a.lenp; j0 += step * kNormStage) {
-    T vv[kNormStage];
-#pragma unroll
-    for (int u = 0; u < kNormStage; ++u) {
-      const int64_t i = j0 + u * step;
-      vv[u] = (i < a.lenp) ? a.up[i] : T(0);
-    }
-#pragma unroll
-    for (int u = 0; u < kNormStage; ++u) {
-      const int64_t i = j0 + u * step;
-      if (i < a.lenp) a.dstp[i * a.dstp_stride] = (i == pick) ? T(1) : nz(vv[u]);
+    switch (op.prec) {
+      case kFP32: return launch_psf_half_fp32(a, op, tr, lds_bytes, s, dry);
+      case kBF16: return launch_psf_half_bf16(a, op, tr, lds_bytes, s, dry);
+      case kFP16: return launch_psf_half_fp16(a, op, tr, lds_bytes, s, dry);
+      default: return launch_psf_half_fp8(a, op, tr, lds_bytes, s, dry);
     }
   }
-}
-
-__device__ inline void write_part(ArgPart* parts, int b, double key, int idx) {
-  parts[b].key = key;
-  parts[b].idx = idx;
-}
-
-// Waits for the coefficients and stages them in LDS (wavefront 0 polls all
-// nb slots at once); false when the launch is to end (block 0 could not form
-// them, or the bound ran out).
-template <typename T>
-__device__ inline bool fetch_coef(const HalfArgs<T>& a, DevState* st, double* cf) {
-  __shared__ int ok_s;
-  const int nb = a.nb;
-  if (nb == 0) return true;
-  if (threadIdx.x < kWave) {
-    constexpr int kPer = kMaxIter / kWave;
-    const int lane = threadIdx.x;
-    const uint64_t* cs = reinterpret_cast<const uint64_t*>(a.cslot);
-    uint64_t bits[kPer];
-    bool ok = false, failed = false;
-    for (int it = 0; it < kSpinLimit; ++it) {
-      bool miss = false;
-#pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        const int j = lane + u * kWave;
-        bits[u] = j < nb ? load_u64(cs + j) : 0;
-        miss = miss || (j < nb && bits[u] == kSentinel);
-      }
-      if (__ballot(miss) == 0) {
-        ok = true;
-        break;
-      }
-      if (load_i(a.fail) != 0) {
-        failed = true;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int j = lane + u * kWave;
-      if (j < nb) cf[j] = __builtin_bit_cast(double, bits[u]);
-    }
-    if (lane == 0) {
-      ok_s = ok ? 1 : 0;
-      if (!ok && !failed) atomicAdd(&st->spin_timeouts, 1);
-    }
-  }
-  __syncthreads();
-  return ok_s != 0;
-}
-
-// --------------------------------------------------- row consumer blocks --
-// G lanes per row, 256 / G rows per block.  Persistent over rows
-// r = (cb + i ncons) * (256 / G) + group: the loads of the first row's first
-// terms before the pivot is known, then every product (the first kept in a
-// register, the others parked in out[r]), the elimination inputs of the first
-// row, one wait for the coefficients, then the elimination.  A waiting block
-// therefore never holds resources that undispatched work needs.
-template <int G, typename T>
-__device__ inline void load_basis_row(const HalfArgs<T>& a, int64_t r, int sub,
-                                      T (&bv)[kCoefPerLane]) {
-  const T* brow = a.basis + r * a.rs;
-#pragma unroll
-  for (int u = 0; u < kCoefPerLane; ++u) {
-    const int j = sub + u * G;
-    bv[u] = (j < a.nb) ? brow[(int64_t)j * a.cs] : T(0);
-  }
-}
-
-template <int G, typename T, class RowOp>
-__device__ void consume_rows(const HalfArgs<T>& a, const RowOp& op, DevState* st,
-                             int cb, int ncons) {
-  using Acc = typename RowOp::Acc;
-  constexpr int kRows = kThreads / G;  // rows per block and pass
-  static_assert(G * kCoefPerLane >= kMaxIter, "one pass over the coefficients");
-  __shared__ double cf[kMaxIter];
-  __shared__ double sk[kRows];
-  __shared__ int si[kRows];
-  const int tid = threadIdx.x, sub = tid % G, rl = tid / G;
-  const int nb = a.nb;
-  const int64_t stride = (int64_t)ncons * kRows;
-  const int64_t r0 = (int64_t)cb * kRows + rl;
-  const bool has0 = r0 < a.rows;
-  RowStage<typename RowOp::Val, T, kRowStage> sg;
-  if (has0) op.template stage<G, kRowStage>(r0, sub, a.up, sg);
-  NormStage<T> ns;
-  normalise_stage(a, cb, ncons, ns);
-  int pick;
-  double val;
-  if (!wait_pivot(a, st, pick, val)) return;
-  const Normaliser<T> nz(static_cast<T>(val));
-  normalise_share(a, cb, ncons, pick, nz, ns);
-  auto xf = [&](int64_t c) -> T { return nz(a.up[c]); };
-  T q_first = T(0);
-  if (has0) {
-    Acc acc = op.template finish<G, kRowStage>(sg, nz, xf);
-    q_first = static_cast<T>(group_sum<G>(acc));
-  }
-  for (int64_t r = r0 + stride; r < a.rows; r += stride) {
-    Acc acc = op.template partial<G>(r, sub, xf);
-    acc = group_sum<G>(acc);
-    if (sub == 0) a.out[r] = static_cast<T>(acc);
-  }
-  if (a.rows == 0) return;
-  // Elimination inputs of the first row, loaded before the coefficients.
-  T bv0[kCoefPerLane];
-  bool piv0 = true;
-  if (has0) {
-    piv0 = a.mask[r0] != 0;
-    load_basis_row<G>(a, r0, sub, bv0);
-  }
-  if (!fetch_coef(a, st, cf)) return;
-  double key = 0.0;
-  int idx = INT_MAX;
-  for (int64_t r = r0; r < a.rows; r += stride) {
-    const bool first = r == r0;
-    const bool piv = first ? piv0 : a.mask[r] != 0;
-    T bv[kCoefPerLane];
-    if (first) {
-#pragma unroll
-      for (int u = 0; u < kCoefPerLane; ++u) bv[u] = bv0[u];
-    } else {
-      load_basis_row<G>(a, r, sub, bv);
-    }
-    double e = 0.0;
-#pragma unroll
-    for (int u = 0; u < kCoefPerLane; ++u) {
-      const int j = sub + u * G;
-      if (j < nb) e = fma(cf[j], static_cast<double>(bv[u]), e);
-    }
-    e = group_sum<G>(e);
-    if (sub == 0) {
-      const double q0 = static_cast<double>(first ? q_first : a.out[r]);
-      const T o = piv ? T(0) : static_cast<T>(q0 - e);
-      a.out[r] = o;
-      const double k2 = piv ? 0.0 : static_cast<double>(o);
-      if (better(k2, (int)r, key, idx)) {
-        key = k2;
-        idx = (int)r;
-      }
-    }
-  }
-  if (sub == 0) {
-    sk[rl] = key;
-    si[rl] = idx;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    for (int i = 1; i < kRows; ++i)
-      if (better(sk[i], si[i], key, idx)) {
-        key = sk[i];
-        idx = si[i];
-      }
-    write_part(a.parts_out, cb, key, idx);
-  }
-}
-
-// Occupancy floor: 5 wavefronts per SIMD for FP32 vectors (1280 resident
-// blocks, so the 1024 row groups of a 16384-row side run in one pass), 4 for
-// FP64.
-template <typename T>
-constexpr int half_min_waves() { return sizeof(T) == 4 ? 5 : 4; }
-
-template <typename T, class RowOp, bool kTriLds, int G>
-__global__ __launch_bounds__(kThreads, half_min_waves<T>()) void k_half_rows(HalfArgs<T> a, RowOp op) {
-  extern __shared__ unsigned char lds[];
-  DevState* st = a.job.st;
-  if (st->stopped) return;
-  if (blockIdx.x == 0)
-    lead<T, kTriLds>(a, st, lds);
-  else if ((int)blockIdx.x < a.nlead)
-    pivot_entries<T, RowOp>(a, op, st, blockIdx.x);
-  else
-    consume_rows<G, T, RowOp>(a, op, st, blockIdx.x - a.nlead, gridDim.x - a.nlead);
-}
-
-// --------------------------------------------------- PSF consumer blocks --
-// The tile of the normalised input: each staged entry is u divided by the
-// pivot value, then (BF16 mode) rounded to bfloat16.
-template <typename T, typename Acc, int PH, int kIn, int R>
-__device__ inline void psf_tile_norm(const T* __restrict__ u, const Normaliser<T>& nz, int rows,
-                                     int cols, const Acc* __restrict__ Wt, int pw,
-                                     int i0, int j0, Acc* tile, Acc (&acc)[R]) {
-  const int ch = PH / 2, cw = pw / 2;
-  const int TR = psf_th<R>() + PH - 1, TC = kPsfTW + pw - 1;
-  for (int e = threadIdx.x; e < TR * TC; e += kThreads) {
-    const int tr = e / TC, tc = e - tr * TC;
-    const int gi = i0 - ch + tr, gj = j0 - cw + tc;
-    Acc v = 0;
-    if (gi >= 0 && gi < rows && gj >= 0 && gj < cols)
-      v = static_cast<Acc>(in_val<kIn>(nz(u[(int64_t)gi * cols + gj])));
-    tile[e] = v;
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & (kWave - 1);
-  const int r0 = (threadIdx.x / kWave) * R;
-#pragma unroll
-  for (int p = 0; p < R; ++p) acc[p] = 0;
-  for (int b = 0; b < pw; ++b) {
-    Acc s[R + PH - 1];
-#pragma unroll
-    for (int q = 0; q < R + PH - 1; ++q) s[q] = tile[(r0 + q) * TC + lane + b];
-#pragma unroll
-    for (int aa = 0; aa < PH; ++aa) {
-      const Acc wv = Wt[aa * pw + b];
-#pragma unroll
-      for (int p = 0; p < R; ++p) acc[p] = fma(wv, s[p + aa], acc[p]);
-    }
-  }
-  __syncthreads();  // the tile may be restaged next
-}
-
-// Persistent over tiles cb, cb + ncons, ...: products first (parked in out),
-// then the coefficients, then the elimination.
-template <typename T, typename Acc, int PH, int kIn, int R>
-__device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
-                              int rows, int cols, int pw, DevState* st, int cb,
-                              int ncons, unsigned char* lds) {
-  __shared__ double cf[kMaxIter];
-  Acc* tile = reinterpret_cast<Acc*>(lds);
-  const int lane = threadIdx.x & (kWave - 1);
-  constexpr int TH = psf_th<R>();
-  const int r0 = (threadIdx.x / kWave) * R;
-  const int tiles_x = (cols + kPsfTW - 1) / kPsfTW;
-  const int ntiles = a.rows > 0 ? tiles_x * ((rows + TH - 1) / TH) : 0;
-  const int nb = a.nb;
-  NormStage<T> ns;
-  normalise_stage(a, cb, ncons, ns);
-  int pick;
-  double val;
-  if (!wait_pivot(a, st, pick, val)) return;
-  const Normaliser<T> nz(static_cast<T>(val));
-  normalise_share(a, cb, ncons, pick, nz, ns);
-  for (int t = cb; t < ntiles; t += ncons) {
-    const int i0 = (t / tiles_x) * TH, j0 = (t % tiles_x) * kPsfTW;
-    Acc acc[R];
-    psf_tile_norm<T, Acc, PH, kIn, R>(a.up, nz, rows, cols, Wt, pw, i0, j0, tile, acc);
-    const int gj = j0 + lane;
-#pragma unroll
-    for (int p = 0; p < R; ++p) {
-      const int gi = i0 + r0 + p;
-      if (gi < rows && gj < cols) a.out[(int64_t)gi * cols + gj] = static_cast<T>(acc[p]);
-    }
-  }
-  if (a.rows == 0) return;
-  if (!fetch_coef(a, st, cf)) return;
-  double best = 0.0;
-  int bidx = INT_MAX;
-  {
-    // An even row length and column stride: the elimination takes pixel
-    // pairs (8- or 16-byte loads, half the load instructions), lane l
-    // on columns j0 + 2 (l % 32) + {0, 1} of the rows r0 + 2p + l / 32 of
-    // its wavefront; the same pixels per wavefront and the same sums per
-    // pixel as the one-column mapping below.
-    if ((cols & 1) == 0 && (a.cs & 1) == 0 &&
-        (reinterpret_cast<uintptr_t>(a.basis) & (2 * sizeof(T) - 1)) == 0) {
-      using T2 = std::conditional_t<std::is_same_v<T, float>, float2, double2>;
-      __syncthreads();  // products of this block's tiles, written by other lanes
-      constexpr int RP = R / 2;
-      const int cp = lane & 31, hr = lane >> 5;
-      for (int t = cb; t < ntiles; t += ncons) {
-        const int i0 = (t / tiles_x) * TH, j0 = (t % tiles_x) * kPsfTW;
-        const int gj = j0 + 2 * cp;
-        int64_t pix[RP];
-        bool ok[RP];
-        unsigned char m0[RP], m1[RP];
-#pragma unroll
-        for (int p = 0; p < RP; ++p) {
-          const int gi = i0 + r0 + 2 * p + hr;
-          ok[p] = gi < rows && gj < cols;  // then gj + 1 < cols too (cols even)
-          pix[p] = ok[p] ? (int64_t)gi * cols + gj : 0;  // even, in bounds either way
-          m0[p] = a.mask[pix[p]];
-          m1[p] = a.mask[pix[p] + 1];
-        }
-        double e0[RP], e1[RP];
-#pragma unroll
-        for (int p = 0; p < RP; ++p) e0[p] = e1[p] = 0.0;
-        for (int j = 0; j < nb; ++j) {
-          const T* c0 = a.basis + (int64_t)j * a.cs;
-          T2 bq[RP];
-#pragma unroll
-          for (int p = 0; p < RP; ++p) bq[p] = *reinterpret_cast<const T2*>(c0 + pix[p]);
-          const double w0 = cf[j];
-#pragma unroll
-          for (int p = 0; p < RP; ++p) {
-            e0[p] = fma(w0, static_cast<double>(bq[p].x), e0[p]);
-            e1[p] = fma(w0, static_cast<double>(bq[p].y), e1[p]);
-          }
-        }
-#pragma unroll
-        for (int p = 0; p < RP; ++p) {
-          if (!ok[p]) continue;
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int64_t q = pix[p] + h;
-            const bool mk = (h ? m1[p] : m0[p]) != 0;
-            const double q0 = static_cast<double>(a.out[q]);
-            const T o = mk ? T(0) : static_cast<T>(q0 - (h ? e1[p] : e0[p]));
-            a.out[q] = o;
-            const double k2 = mk ? 0.0 : static_cast<double>(o);
-            if (better(k2, (int)q, best, bidx)) {
-              best = k2;
-              bidx = (int)q;
-            }
-          }
-        }
-      }
-      block_argmax<kThreads>(best, bidx);
-      if (threadIdx.x == 0) write_part(a.parts_out, cb, best, bidx);
-      return;
-    }
-  }
-  for (int t = cb; t < ntiles; t += ncons) {
-    const int i0 = (t / tiles_x) * TH, j0 = (t % tiles_x) * kPsfTW;
-    const int gj = j0 + lane;
-    int64_t pix[R];
-    bool ok[R];
-    unsigned char mk[R];
-#pragma unroll
-    for (int p = 0; p < R; ++p) {
-      const int gi = i0 + r0 + p;
-      ok[p] = gi < rows && gj < cols;
-      pix[p] = ok[p] ? (int64_t)gi * cols + gj : 0;  // in bounds either way
-      mk[p] = a.mask[pix[p]];
-    }
-    double e[R];
-#pragma unroll
-    for (int p = 0; p < R; ++p) e[p] = 0.0;
-    int j = 0;
-    for (; j + 2 <= nb; j += 2) {
-      const T* c0 = a.basis + (int64_t)j * a.cs;
-      const T* c1 = c0 + a.cs;
-      T b0[R], b1[R];
-#pragma unroll
-      for (int p = 0; p < R; ++p) {
-        b0[p] = c0[pix[p]];
-        b1[p] = c1[pix[p]];
-      }
-      const double w0 = cf[j], w1 = cf[j + 1];
-#pragma unroll
-      for (int p = 0; p < R; ++p) {
-        e[p] = fma(w0, static_cast<double>(b0[p]), e[p]);
-        e[p] = fma(w1, static_cast<double>(b1[p]), e[p]);
-      }
-    }
-    if (j < nb) {
-      const T* c0 = a.basis + (int64_t)j * a.cs;
-      const double w0 = cf[j];
-#pragma unroll
-      for (int p = 0; p < R; ++p) e[p] = fma(w0, static_cast<double>(c0[pix[p]]), e[p]);
-    }
-#pragma unroll
-    for (int p = 0; p < R; ++p) {
-      if (!ok[p]) continue;
-      const double q0 = static_cast<double>(a.out[pix[p]]);
-      const T o = mk[p] ? T(0) : static_cast<T>(q0 - e[p]);
-      a.out[pix[p]] = o;
-      const double k2 = mk[p] ? 0.0 : static_cast<double>(o);
-      if (better(k2, (int)pix[p], best, bidx)) {
-        best = k2;
-        bidx = (int)pix[p];
-      }
-    }
-  }
-  block_argmax<kThreads>(best, bidx);
-  if (threadIdx.x == 0) write_part(a.parts_out, cb, best, bidx);
-}
-
-template <typename T, typename Acc, int PH, int kIn, bool kTriLds, int R>
-__global__ __launch_bounds__(kThreads) void k_half_psf(
-    HalfArgs<T> a, PsfPixels<Acc, kIn> op, const Acc* __restrict__ Wt) {
-  extern __shared__ unsigned char lds[];
-  DevState* st = a.job.st;
-  if (st->stopped) return;
-  if (blockIdx.x == 0)
-    lead<T, kTriLds>(a, st, lds);
-  else if ((int)blockIdx.x < a.nlead)
-    pivot_entries<T, PsfPixels<Acc, kIn>>(a, op, st, blockIdx.x);
-  else
-    consume_tiles<T, Acc, PH, kIn, R>(a, Wt, op.rows, op.cols, op.pw, st,
-                                     blockIdx.x - a.nlead, gridDim.x - a.nlead, lds);
-}
-
-static_assert(kPsfWaves * kWave == kThreads, "PSF tiles use the launch's block size");
-
-// ------------------------------------------------ several solves at once --
-// One launch of the same half-iteration of P solves: solve p owns blocks
-// first[p] .. first[p+1]-1 and runs exactly the roles of its own launch
-// (lead, pivot entries, consumers) on its own workspace.  Every wait is on a
-// lower-numbered block of the same solve, dispatched earlier, so the merged
-// launch needs no more residency than the single ones.
-__device__ inline int batch_solve_of_block(const int* __restrict__ first, int P) {
-  int lo = 0, hi = P - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (first[mid] <= (int)blockIdx.x) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
-template <typename T, class RowOp, bool kTriLds, int G>
-__global__ __launch_bounds__(kThreads, half_min_waves<T>()) void k_half_rows_batch(
-    const HalfArgs<T>* __restrict__ args, const RowOp* __restrict__ ops,
-    const int* __restrict__ first, int P) {
-  extern __shared__ unsigned char lds[];
-  // p is the same in every lane: loaded by value from a wave-uniform
-  // address, the arguments can live in scalar registers as a kernel
-  // argument would
-  const int p = __builtin_amdgcn_readfirstlane(batch_solve_of_block(first, P));
-  const HalfArgs<T> a = args[p];
-  const RowOp op = ops[p];
-  DevState* st = a.job.st;
-  if (st->stopped) return;
-  const int bid = (int)blockIdx.x - first[p], nblk = first[p + 1] - first[p];
-  if (bid == 0)
-    lead<T, kTriLds>(a, st, lds);
-  else if (bid < a.nlead)
-    pivot_entries<T, RowOp>(a, op, st, bid);
-  else
-    consume_rows<G, T, RowOp>(a, op, st, bid - a.nlead, nblk - a.nlead);
-}
-
-
-// ------------------------------------------------------------- launchers --
-template <typename T>
-size_t tri_bytes(int nb) {
-  return nb > 1 ? sizeof(T) * (size_t)packed_row(nb) : 0;
-}
-
-// Blocks of `kernel` that fit on the device at once (cached per kernel, LDS
-// size and device); 0 if the runtime cannot tell.
-int resident_blocks(const void* kernel, size_t dyn_lds) {
-  static std::mutex mu;
-  static std::map<std::tuple<const void*, size_t, int>, int> cache;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  const auto key = std::make_tuple(kernel, dyn_lds, dev);
-  std::lock_guard<std::mutex> lock(mu);
-  auto it = cache.find(key);
-  if (it != cache.end()) return it->second;
-  int per_cu = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, dyn_lds) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return 0;
-  cache[key] = per_cu * cus;
-  return per_cu * cus;
-}
-
-// Consumer blocks: enough for the work, at most kMaxParts, and (persistent)
-// no more than fit beside the leading blocks.
-int consumer_blocks(int64_t want, int nlead, int resident) {
-  int64_t c = std::min<int64_t>(std::max<int64_t>(want, 1), kMaxParts);
-  if (resident > nlead) c = std::min<int64_t>(c, resident - nlead);
-  return static_cast<int>(c);
-}
-
-// Batched launches (launch_half_batch) pass the merged launch instead of s.
-template <typename T, class RowOp>
-struct RowsBatch {
-  const HalfArgs<T>* args;
-  const RowOp* ops;
-  const int* first;
-  int P, blocks;
-};
-
-template <typename T, class RowOp, int G>
-int launch_rows_g(HalfArgs<T>& a, const RowOp& op, size_t tb, bool in_lds, hipStream_t s,
-                  bool dry = false, const RowsBatch<T, RowOp>* batch = nullptr) {
-  constexpr int kRows = kThreads / G;
-  const int64_t want = a.rows > 0 ? (a.rows + kRows - 1) / kRows
-                                  : (a.lenp + kThreads * kNormBatch - 1) / (kThreads * kNormBatch);
-  auto k = in_lds ? k_half_rows<T, RowOp, true, G> : k_half_rows<T, RowOp, false, G>;
-  const size_t dyn = in_lds ? tb : 0;
-  const int ncons = consumer_blocks(want, a.nlead, resident_blocks((const void*)k, dyn));
-  if (batch) {
-    auto kb = in_lds ? k_half_rows_batch<T, RowOp, true, G> : k_half_rows_batch<T, RowOp, false, G>;
-    kb<<<batch->blocks, kThreads, dyn, s>>>(batch->args, batch->ops, batch->first, batch->P);
-  } else if (!dry) {
-    k<<<a.nlead + ncons, kThreads, dyn, s>>>(a, op);
-  }
-  return ncons;
-}
-
-// 16 lanes per row.  (8 lanes per row, which makes the d side of the
-// tomography one pass over the rows, measured slower: the longer per-lane
-// chains of dependent loads cost more than the second pass.)
-template <typename T, class RowOp>
-int launch_rows(HalfArgs<T>& a, const RowOp& op, size_t lds_bytes, hipStream_t s,
-                bool dry = false, const RowsBatch<T, RowOp>* batch = nullptr) {
-  const int nbk = a.rows > 0 ? a.nb : 0;
-  a.nlead = 1 + (nbk + kWaves - 1) / kWaves;
-  const size_t tb = tri_bytes<T>(nbk);
-  const bool in_lds = tb > 0 && tb <= kTriLdsMax && tb + 16 * 1024 <= lds_bytes;
-  return launch_rows_g<T, RowOp, 16>(a, op, tb, in_lds, s, dry, batch);
-}
-
-template <typename T, typename Acc, int PH, int kIn, int R>
-int launch_tiles_r(HalfArgs<T>& a, const PsfPixels<Acc, kIn>& op, const Acc* Wt,
-                   size_t lds_bytes, hipStream_t s, bool dry = false) {
-  const int ntiles = ((op.cols + kPsfTW - 1) / kPsfTW) * ((op.rows + psf_th<R>() - 1) / psf_th<R>());
-  const int64_t want = a.rows > 0 ? ntiles
-                                  : (a.lenp + kThreads * kNormBatch - 1) / (kThreads * kNormBatch);
-  const int nbk = a.rows > 0 ? a.nb : 0;
-  a.nlead = 1 + (nbk + kWaves - 1) / kWaves;
-  const size_t tb = tri_bytes<T>(nbk);
-  const size_t pb = psf_lds_bytes<Acc, PH, R>(op.pw);
-  const bool in_lds = tb > 0 && tb <= kTriLdsMax && std::max(tb, pb) + 16 * 1024 <= lds_bytes;
-  if (in_lds) {
-    auto k = k_half_psf<T, Acc, PH, kIn, true, R>;
-    const size_t dyn = std::max(tb, pb);
-    const int ncons = consumer_blocks(want, a.nlead, resident_blocks((const void*)k, dyn));
-    if (!dry) k<<<a.nlead + ncons, kThreads, dyn, s>>>(a, op, Wt);
-    return ncons;
-  }
-  auto k = k_half_psf<T, Acc, PH, kIn, false, R>;
-  const int ncons = consumer_blocks(want, a.nlead, resident_blocks((const void*)k, pb));
-  if (!dry) k<<<a.nlead + ncons, kThreads, pb, s>>>(a, op, Wt);
-  return ncons;
-}
-
-template <typename T, typename Acc, int PH, int kIn>
-int launch_tiles(HalfArgs<T>& a, const PsfPixels<Acc, kIn>& op, const Acc* Wt, int psf_r,
-                 size_t lds_bytes, hipStream_t s, bool dry = false) {
-  int n = 0;
-  with_psf_r(psf_r, op.rows, op.cols, [&](auto rc) {
-    n = launch_tiles_r<T, Acc, PH, kIn, decltype(rc)::value>(a, op, Wt, lds_bytes, s, dry);
-  });
-  return n;
-}
-
-// The row access of an operator for one direction (tr: A^T), and its
-// value / sum types, passed to f(row_op).
-template <typename T, typename F>
-void with_row_op(const DeviceOp& op, int tr, F&& f) {
-  with_mode<T>(op.prec, [&](auto v, auto acc, auto bf) {
-    using V = decltype(v);
-    using Acc = decltype(acc);
-    constexpr int kB = decltype(bf)::value;
-    if (op.kind == 0) {
-      f(DenseRows<V, Acc, kB>{static_cast<const V*>(tr ? op.AT : op.A), tr ? op.m : op.n});
-    } else if (op.kind == 1) {
-      f(CsrRows<V, Acc, kB>{tr ? op.rpT : op.rp, tr ? op.ciT : op.ci,
-                            static_cast<const V*>(tr ? op.valT : op.val)});
-    } else {
-      const Acc* wt;
-      if constexpr (std::is_same_v<Acc, double>)
-        wt = tr ? op.psf : op.psf_flip;
-      else
-        wt = tr ? op.psf32 : op.psf32_flip;
-      f(PsfPixels<Acc, kB>{wt, static_cast<int>(op.rows), static_cast<int>(op.cols), op.ph,
-                           op.pw});
-    }
-  });
 }
 
 // mode 0: launch; 1: plan only (sets a.nlead, returns the consumer count);
-// 2: the merged launch of a batch (a and op stand for every solve of it).
+// 2: the merged launch of a batch (a and op stand for every solve of it;
+// merged launches are built for the row operators only).
 template <typename T>
 int half_dispatch(HalfArgs<T>& a, const DeviceOp& op, int tr, size_t lds_bytes, hipStream_t s,
                   int mode, const void* bargs, const void* bops, const int* bfirst, int P,
                   int blocks) {
+  if (op.kind == 2) return launch_psf_half<T>(a, op, tr, lds_bytes, s, mode != 0);
   int nparts = 0;
   with_row_op<T>(op, tr, [&](auto ro) {
     using RO = decltype(ro);
-    if constexpr (is_psf_pixels<RO>::value) {
-      // (merged launches are built for the row operators only)
-      with_ph(op.ph, [&](auto phc) {
-        constexpr int PH = decltype(phc)::value;
-        nparts = launch_tiles<T, typename RO::Acc, PH, RO::kInMode>(a, ro, ro.wt, op.psf_r,
-                                                                    lds_bytes, s, mode != 0);
-      });
-    } else {
+    if constexpr (!is_psf_pixels<RO>::value) {
       RowsBatch<T, RO> b{static_cast<const HalfArgs<T>*>(bargs), static_cast<const RO*>(bops),
                          bfirst, P, blocks};
       nparts = launch_rows<T, RO>(a, ro, lds_bytes, s, mode == 1, mode == 2 ? &b : nullptr);
