@@ -205,8 +205,9 @@ void op_apply(const DeviceOp& op, int transpose, const void* x, void* y,
 //                      basis column once the pivot is published, and subtract
 //                      the earlier basis vectors once the coefficients are,
 //                      writing per-block pivot candidates.
-// Later blocks only ever wait for values written by earlier ones, which never
-// wait for later ones; every wait is bounded.  Everything published inside a
+// Entry blocks and consumers wait only for block 0, which publishes the
+// pivot before waiting for the entry blocks (dispatched right after it and
+// before any consumer); every wait is bounded.  Everything published inside a
 // launch goes through slots that hold kSlotEmpty until written once, so a
 // waiter reads the value itself and no flag orders other memory.
 //

@@ -891,7 +891,7 @@ lslu_status lslu_op_psf(lslu_ctx* c, int64_t rows, int64_t cols, int32_t ph,
     if (prec == kFP32)
       for (double& w : p) w = static_cast<double>(static_cast<float>(w));
     for (int a = 0; a < ph; ++a)
-      for (int b = 0; b < pw; ++b) pf[a * pw + b] = psf[(ph - 1 - a) * pw + (pw - 1 - b)];
+      for (int b = 0; b < pw; ++b) pf[a * pw + b] = p[(ph - 1 - a) * pw + (pw - 1 - b)];
     // float copies of the weights in the 16-bit operator formats
     std::vector<float> p32(np), pf32(np);
     for (int i = 0; i < np; ++i) {

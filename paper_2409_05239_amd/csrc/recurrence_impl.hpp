@@ -27,10 +27,13 @@
 // cancellations are those of the normalised vector.  The products therefore start once the pivot is
 // published; the triangular solve of block 0 overlaps them.
 //
-// Synchronisation inside the launch: blocks only ever wait for values written
-// by lower-numbered blocks, which never wait for higher-numbered ones;
-// workgroups are dispatched in order, so the blocks that publish are resident
-// first.  Everything published inside a launch (the pivot, its value, the
+// Synchronisation inside the launch: the pivot-entry blocks and the
+// consumers wait only for block 0; block 0 publishes the pivot before it
+// waits for anything, and then waits only for the pivot-entry blocks, which
+// follow it directly (blocks 1..nlead-1, a few dozen at most).  Workgroups
+// are dispatched in order, so block 0 and its entry blocks are resident
+// before any consumer, and every wait ends whatever else occupies the
+// device.  Everything published inside a launch (the pivot, its value, the
 // pivot entries, the coefficients) goes through slots that hold a sentinel
 // until written once; a waiter polls the slot itself, so no flag has to order
 // other memory and nobody fences.  Every load a product needs that does not
@@ -881,9 +884,13 @@ static_assert(kPsfWaves * kWave == kThreads, "PSF tiles use the launch's block s
 // ------------------------------------------------ several solves at once --
 // One launch of the same half-iteration of P solves: solve p owns blocks
 // first[p] .. first[p+1]-1 and runs exactly the roles of its own launch
-// (lead, pivot entries, consumers) on its own workspace.  Every wait is on a
-// lower-numbered block of the same solve, dispatched earlier, so the merged
-// launch needs no more residency than the single ones.
+// (lead, pivot entries, consumers) on its own workspace, so every wait is
+// within one solve: its entry blocks and consumers wait for its lead, and
+// its lead (after publishing the pivot) for its entry blocks, which are
+// dispatched right after it and before its consumers.  Solve p's blocks
+// never wait for a later solve's, so solve 0 completes whatever follows it,
+// then solve 1, and so on: the merged launch needs no more residency than
+// the single ones.
 __device__ inline int batch_solve_of_block(const int* __restrict__ first, int P) {
   int lo = 0, hi = P - 1;
   while (lo < hi) {

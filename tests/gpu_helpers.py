@@ -121,6 +121,19 @@ def check_ghat(G, R, k, prec):
     assert abs(g - r) <= GHAT_TOL[prec] * abs(r), (k, g, r)
 
 
+def stated_prefix(H, K, prec):
+    """Largest k <= K such that 10 k' u kappa(H_{k'+1,k'}) <= TOL[prec] for
+    every k' <= k, from the oracle's H: where rounding of relative size u,
+    amplified by the conditioning of the projected problem, stays within the
+    stated tolerance.  Beyond it the stated tolerance is not asserted (the
+    tests record k, kappa and the error instead)."""
+    u = 2.0 ** -53 if prec == "fp64" else 2.0 ** -24
+    for k in range(1, K + 1):
+        if 10.0 * k * u * np.linalg.cond(H[:k + 1, :k]) > TOL[prec]:
+            return k - 1
+    return K
+
+
 def rel(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
