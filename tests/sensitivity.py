@@ -83,3 +83,33 @@ def step_tolerances(s, u, stated):
     forward sensitivity does not allow the stated one."""
     k = np.arange(1, len(s) + 1)
     return np.maximum(stated, 10.0 * k * u * s)
+
+
+def measured_prefix(prob, R, reg, K, u, stated, eps=1e-9, seeds=(1, 2)):
+    """Largest k <= K at which the stated tolerance still applies by the
+    oracle's measured forward sensitivity: 10 k' u s_k' <= stated for every
+    k' <= k, with s_k the larger of the sensitivity of x_k (sensitivity_at)
+    and of column k of H (max_j |H_p(j,k) - H(j,k)| / (max|H| eps)) over
+    perturbed oracle runs.  A perturbed run whose pivots differ from R's
+    ends the prefix where they first differ."""
+    runs, stop = [], K
+    for seed in seeds:
+        P = _perturbed(prob, eps, seed)
+        Rp = hybrid_lslu(make_operator(P), P.b, K, reg)
+        for k in range(1, K + 1):
+            if Rp.piv_g[:k] != R.piv_g[:k] or Rp.piv_t[:k + 1] != R.piv_t[:k + 1]:
+                stop = min(stop, k - 1)
+                break
+        runs.append(Rp)
+    kk = min(stop, R.k_done)
+    if kk < 1:
+        return 0
+    sx = sensitivity_at(runs, R.lambdas, R.X, kk, eps)
+    Hs = np.abs(R.H).max()
+    sh = np.zeros(kk)
+    for Rp in runs:
+        d = np.abs(Rp.H[:kk + 1, :kk] - R.H[:kk + 1, :kk]).max(axis=0)
+        sh = np.maximum(sh, d / (Hs * eps))
+    k = np.arange(1, kk + 1)
+    ok = 10.0 * k * u * np.maximum(sx, sh) <= stated
+    return kk if ok.all() else int(np.argmin(ok))

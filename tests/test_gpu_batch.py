@@ -213,12 +213,12 @@ def _oracle_checks(prob, info, x, prec, K):
     over the oracle's well-separated prefix, and where that prefix covers the
     whole solve, H, W, the lambda indices, Ghat and the final iterate; the
     low-precision modes -- the error to x_true at K against the oracle's."""
-    from gpu_helpers import (TAU, check_ghat, pivot_prefix, rel, stated_prefix,
-                             well_separated_prefix)
+    from gpu_helpers import TAU, check_ghat, pivot_prefix, rel, well_separated_prefix
     from oracle import RegParam, make_operator
     from oracle.hessenberg import hybrid_lslu
-    R = hybrid_lslu(make_operator(prob), prob.b, K,
-                    RegParam("wgcv", grid=lambda_grid(), grid_relative=True))
+    from sensitivity import measured_prefix
+    reg = RegParam("wgcv", grid=lambda_grid(), grid_relative=True)
+    R = hybrid_lslu(make_operator(prob), prob.b, K, reg)
     xg = x.double().cpu().numpy()
     if prec != "fp64":
         e_g, e_r = rel(xg, prob.x_true), rel(R.x, prob.x_true)
@@ -229,8 +229,8 @@ def _oracle_checks(prob, info, x, prec, K):
     kp = pivot_prefix(R, TAU["fp64"], kd)
     assert list(info["piv_g"][:kp]) == R.piv_g[:kp], prob.name
     assert list(info["piv_t"][:kp]) == R.piv_t[:kp], prob.name
-    # the stated 1e-10 holds where 10 k u kappa(H_{k+1,k}) allows it
-    ks = stated_prefix(R.H, kd, "fp64")
+    # the stated 1e-10 holds where the problem's measured sensitivity allows it
+    ks = measured_prefix(prob, R, reg, kd, 2.0 ** -53, 1e-10)
     k_ok = min(well_separated_prefix(R, TAU["fp64"], kd), ks)
     # H and W depend on the pivots only (not on lambda)
     kh = min(kp, ks)
@@ -243,6 +243,11 @@ def _oracle_checks(prob, info, x, prec, K):
         check_ghat(info, R, k, "fp64")
     if k_ok == kd == K:
         assert rel(xg, R.x) <= 1e-10, prob.name
+    if kd > ks:
+        dH = np.abs(info["H"][:kd + 1, :kd] - R.H[:kd + 1, :kd]).max(axis=0) / Hs
+        print(f"[batch oracle] {prob.name}: beyond k = {ks} (k, kappa(H), max |dH|/max|H|): "
+              + ", ".join(f"({k}, {np.linalg.cond(R.H[:k + 1, :k]):.0f}, {dH[k - 1]:.1e})"
+                          for k in range(ks + 1, kd + 1, 3)))
     print(f"[batch oracle] {prob.name}: pivots equal for k <= {kp}, stated tolerance "
           f"applies for k <= {ks}, separated prefix {k_ok} of {kd}")
 
