@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LSLU_ABI_VERSION 11
+#define LSLU_ABI_VERSION 12
 
 typedef enum lslu_status {
   LSLU_OK = 0,
@@ -301,6 +301,31 @@ lslu_status lslu_solve(lslu_ctx* ctx, const lslu_op* op, const void* b_dev,
 lslu_status lslu_solve_host(lslu_ctx* ctx, const lslu_op* op, const double* b_host,
                             const double* x0_host, const lslu_opts* opts,
                             double* x_out_host, lslu_result* res);
+
+/* lslu_solve for callers that cannot allocate device memory (code running
+ * under HIP graph capture elsewhere, tight serving loops, harnesses that
+ * forbid hipMalloc): the same solve with the same arguments, outputs and
+ * results (bit for bit), but its whole device workspace (bases, iterates,
+ * projected-problem scratch, result block) lives in one fixed 64 MiB array
+ * the library keeps in the memory of each GPU it runs on until the process
+ * ends, its kernels are enqueued directly (no captured graph), and the small
+ * results are copied straight into the caller's lslu_result arrays.  The
+ * call allocates nothing.  The workspace of a solve is about
+ * wp (n K + m (K + 1)) (bases) + wp n K (iterates, even when X_dev is given)
+ * + 8 K ((K + 1) K + 3 K G) (projected problems, G = grid values) + O(K^2)
+ * bytes; a solve that needs more than 64 MiB is refused with LSLU_EINVAL
+ * (use lslu_solve).  Every call on one GPU shares the array and leaves its
+ * own contents there: calls that overlap on one GPU (several contexts or
+ * threads at once) race and must be serialised by the caller.  lslu_vjp
+ * and lslu_get_basis do not apply to such a solve (they read the context's
+ * own workspace) and report LSLU_EINVAL after it.  Synchronous: returns
+ * when the results are written.
+ * Errors: as lslu_solve; LSLU_EINVAL also for LSLU_FLAG_ASYNC or
+ * LSLU_FLAG_TIMING and for a workspace beyond 64 MiB; LSLU_EDEVICE when the
+ * array's device address could not be obtained at context creation. */
+lslu_status lslu_solve_static(lslu_ctx* ctx, const lslu_op* op, const void* b_dev,
+                              const void* x0_dev, const lslu_opts* opts,
+                              void* x_out_dev, lslu_result* res);
 
 /* Solves count problems together: problem i is op[i] (created on ctxs[i]),
  * b_dev[i] (m_i entries, wp), x_out_dev[i] (n_i entries, wp, written) and

@@ -43,7 +43,7 @@ EXPORTS = (
     "lslu_abi_version", "lslu_op_dense", "lslu_op_csr", "lslu_op_psf",
     "lslu_op_apply", "lslu_op_info", "lslu_op_destroy", "lslu_solve",
     "lslu_wait", "lslu_get_basis", "lslu_vjp", "lslu_op_tile", "lslu_solve_host",
-    "lslu_solve_batch",
+    "lslu_solve_batch", "lslu_solve_static",
 )
 
 
@@ -141,6 +141,8 @@ def _load():
         "lslu_op_destroy": (c_int, [vp]),
         "lslu_solve": (c_int, [vp, vp, vp, vp, POINTER(lslu_opts), vp,
                                POINTER(lslu_result)]),
+        "lslu_solve_static": (c_int, [vp, vp, vp, vp, POINTER(lslu_opts), vp,
+                                      POINTER(lslu_result)]),
         "lslu_get_basis": (c_int, [vp, c_int32, c_int32, vp]),
         "lslu_wait": (c_int, [vp]),
         "lslu_vjp": (c_int, [vp, vp, c_int32, vp, vp, POINTER(c_double)]),
@@ -350,11 +352,14 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
                stop_tol=0.0, early_stop=False, X=None, x_out=None,
                replay_piv_t=None, replay_piv_g=None, replay_lambda_idx=None,
                eager=False, timing=False, pivot_sample=None, asynchronous=False,
-               grad_lambda=False):
+               grad_lambda=False, static=False):
     """Run the solver.  ``b``, ``x0``, ``X``, ``x_out`` are torch device
     tensors in the working precision (``x_out`` is allocated when None).
     ``pivot_sample = (rows, s)`` selects sampled pivots: ``rows`` is the
     (2 maxiter + 1) x L int32 array of candidate rows per search.
+    ``static=True`` calls ``lslu_solve_static`` (the same solve with its
+    device workspace in the library's fixed array: no allocation; device
+    vectors only, synchronous).
     ``asynchronous=True`` enqueues the solve and returns a ``Pending``;
     ``lslu_wait(ctx, pending)`` completes it and returns the same triple.
     ``grad_lambda=True`` (needs ``x_true``) adds ``info["dloss_dlambda"]``.
@@ -369,6 +374,8 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
     host_io = isinstance(b, np.ndarray)
     if host_io and asynchronous:
         raise ValueError("host arrays need a synchronous solve")
+    if static and (host_io or asynchronous or timing):
+        raise ValueError("lslu_solve_static takes device vectors and is synchronous")
     dev = _CTX_DEVICE.get(ctx.value)
     if not host_io:
         _vec(b, m, prec, "b", dev)
@@ -440,8 +447,12 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
             x_out.ctypes.data_as(POINTER(c_double)), ctypes.byref(r)))
         _CTX_SHAPE[ctx.value] = (m, n, prec)  # the solve the context now holds
         return st, x_out, _info(st, r, host, timing)
-    st = _check(ctx, lib.lslu_solve(ctx, op, _dptr(b), _dptr(x0), ctypes.byref(o),
-                                    _dptr(x_out), ctypes.byref(r)))
+    entry = lib.lslu_solve_static if static else lib.lslu_solve
+    st = _check(ctx, entry(ctx, op, _dptr(b), _dptr(x0), ctypes.byref(o),
+                           _dptr(x_out), ctypes.byref(r)))
+    if static:
+        _CTX_SHAPE.pop(ctx.value, None)  # the context holds no basis now
+        return st, x_out, _info(st, r, host, timing)
     _CTX_SHAPE[ctx.value] = (m, n, prec)
     if asynchronous:
         # everything the library may still write or read stays referenced

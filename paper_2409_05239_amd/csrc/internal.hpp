@@ -298,6 +298,7 @@ struct ProjParams {
   double omega;    // <= 0: (k+1)/m
   const double* grid;         // device
   const int* replay_lambda;   // device or nullptr
+  int grid_slots;      // grid values the scratch holds per problem (>= n_grid)
   const double* gram;  // OPTIMAL, gradient: (K+1) x (K+1) Gram matrix of [L, x_true - x_0]
   double* dldl;        // nullptr, or K entries: d/dlambda ||x_k(lambda) - x_true||^2 at lambda_k
 };
@@ -306,7 +307,9 @@ void launch_projected(const double* H, const DevState* st, double beta_unused,
                       int* lam_idx, double* ghat, double* sep, double* smax,
                       double* smin, double* scratch, size_t lds_bytes,
                       hipStream_t s);
-size_t projected_scratch_doubles(int K);
+// Scratch doubles of launch_projected for K problems with room for
+// grid_slots grid values each.
+size_t projected_scratch_doubles(int K, int grid_slots = kMaxGrid);
 
 // One-time kernel attributes (dynamic LDS limits), set at context creation so
 // that no attribute call happens while a solve is being captured.

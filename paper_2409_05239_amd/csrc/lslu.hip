@@ -15,6 +15,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -62,9 +63,10 @@ Strides basis_strides(bool rowmajor, int64_t m, int64_t n, int K) {
   return {1, (int64_t)align_up((size_t)n, 64), 1, (int64_t)align_up((size_t)m, 64)};
 }
 
-// Two passes: with base == nullptr only the size is computed.
+// Two passes: with base == nullptr only the size is computed.  The
+// projected problems' scratch has room for grid_slots grid values each.
 size_t carve(unsigned char* base, int64_t m, int64_t n, int K, size_t esz,
-             const Strides& bs, Layout* lay) {
+             const Strides& bs, Layout* lay, int grid_slots = kMaxGrid) {
   size_t off = 0;
   auto take = [&](size_t bytes) -> unsigned char* {
     off = align_up(off, 256);
@@ -85,7 +87,7 @@ size_t carve(unsigned char* base, int64_t m, int64_t n, int K, size_t esz,
   l.TL = take(esz * K * (K + 1) / 2);        // packed rows, strict lower
   l.TD = take(esz * (K + 1) * (K + 2) / 2);
   l.grid = reinterpret_cast<double*>(take(sizeof(double) * kMaxGrid));
-  l.proj = reinterpret_cast<double*>(take(sizeof(double) * projected_scratch_doubles(K)));
+  l.proj = reinterpret_cast<double*>(take(sizeof(double) * projected_scratch_doubles(K, grid_slots)));
   l.gram = reinterpret_cast<double*>(take(sizeof(double) * (K + 1) * (K + 1)));
   l.gram_part = reinterpret_cast<double*>(take(sizeof(double) * gram_scratch_doubles(K)));
   l.rep_t = reinterpret_cast<int*>(take(sizeof(int) * (K + 1)));
@@ -139,6 +141,7 @@ struct lslu_ctx {
   bool rowmajor = false;
   int K = 0;
   size_t esz = 0;
+  int grid_slots = kMaxGrid;  // grid values the projected scratch of lay holds
   // basis vectors formed by the last solve
   int last_nl = 0, last_nd = 0;
   // the last completed solve (what lslu_vjp differentiates)
@@ -527,6 +530,7 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
   pp.omega = o->omega;
   pp.grid = l.grid;
   pp.replay_lambda = replay_lam ? l.rep_lam : nullptr;
+  pp.grid_slots = c->grid_slots;
   const bool grad = (o->flags & LSLU_FLAG_GRAD_LAMBDA) != 0;
   if (o->reg == LSLU_REG_OPTIMAL || grad) {
     launch_gram<T>(Lb, bs.rsL, bs.csL, n, K, static_cast<const T*>(o->x_true_dev), x0, st,
@@ -683,6 +687,74 @@ lslu_status tune_psf(lslu_ctx* c, lslu_op* op, int* chosen) {
 
 }  // namespace
 
+// ------------------------------------------------- no-allocation solves ---
+// The device workspace of lslu_solve_static: one fixed array in the memory
+// of each GPU the library runs on (placed when the code object is loaded,
+// held until the process ends), shared by every such call on that GPU.
+// Host code reaches it only through the address hipGetSymbolAddress gives
+// for the device, looked up once per device at context creation and kept in
+// g_scratch_ptr; the array's name in host code is a host-side stand-in, not
+// a device address.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+bool g_scratch_tried[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// With `device` current: the device address of the static scratch, looked
+// up once per device.
+void init_static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_tried[device]) return;
+  g_scratch_tried[device] = true;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  g_scratch_err[device] = e;
+  g_scratch_ptr[device] = (e == hipSuccess) ? p : nullptr;
+}
+
+void* static_scratch(int device, hipError_t* err) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  *err = g_scratch_tried[device] ? g_scratch_err[device] : hipErrorNotInitialized;
+  return g_scratch_ptr[device];
+}
+
+// The part of a context's state that describes its workspace; swapped for
+// the duration of a static solve and restored on every exit.
+struct GeomSwap {
+  lslu_ctx* c;
+  Layout lay;
+  int64_t m, n;
+  Strides bs;
+  bool rowmajor;
+  int K;
+  size_t esz;
+  int grid_slots;
+  explicit GeomSwap(lslu_ctx* ctx)
+      : c(ctx), lay(ctx->lay), m(ctx->m), n(ctx->n), bs(ctx->bs), rowmajor(ctx->rowmajor),
+        K(ctx->K), esz(ctx->esz), grid_slots(ctx->grid_slots) {}
+  ~GeomSwap() {
+    c->lay = lay;
+    c->m = m;
+    c->n = n;
+    c->bs = bs;
+    c->rowmajor = rowmajor;
+    c->K = K;
+    c->esz = esz;
+    c->grid_slots = grid_slots;
+  }
+};
+}  // namespace
+
 // =========================================================================
 extern "C" {
 
@@ -724,6 +796,7 @@ lslu_status lslu_create(int device, void* hip_stream, lslu_ctx** out) {
     c->lds_max = prop.sharedMemPerBlock;
     recurrence_init_attributes(c->lds_max);
     projected_init_attributes(c->lds_max);
+    init_static_scratch(device);
     if (hip_stream) {
       c->stream = static_cast<hipStream_t>(hip_stream);
     } else {
@@ -1204,6 +1277,146 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
       return LSLU_OK;
     }
     return complete_solve(c, K, res, &pe);
+  } catch (const std::bad_alloc&) {
+    return fail(c, LSLU_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(c, LSLU_EDEVICE, "unexpected exception");
+  }
+}
+
+lslu_status lslu_solve_static(lslu_ctx* c, const lslu_op* op, const void* b,
+                              const void* x0, const lslu_opts* o, void* x_out,
+                              lslu_result* res) {
+  if (!c) return LSLU_EINVAL;
+  if (!op || !b || !o || !x_out) return fail(c, LSLU_EINVAL, "NULL argument");
+  if (op->ctx != c) return fail(c, LSLU_EINVAL, "operator belongs to another context");
+  if (c->pending)
+    return fail(c, LSLU_EINVAL, "an asynchronous solve is pending on this context (lslu_wait)");
+  if (o->flags & (LSLU_FLAG_ASYNC | LSLU_FLAG_TIMING))
+    return fail(c, LSLU_EINVAL, "lslu_solve_static is synchronous: no ASYNC or TIMING flag");
+  try {
+    const lslu_status vs = validate_opts(c, op, o);
+    if (vs != LSLU_OK) return vs;
+    LSLU_HIP(c, hipSetDevice(c->device));
+    hipError_t serr = hipSuccess;
+    unsigned char* base = static_cast<unsigned char*>(static_scratch(c->device, &serr));
+    if (!base)
+      return fail(c, LSLU_EDEVICE, std::string("no static scratch on this device: ") +
+                                       hipGetErrorString(serr));
+    const int K = o->maxiter;
+    const int64_t m = op->d.m, n = op->d.n;
+    const size_t esz = prec_size(op->d.prec);
+    const bool rowmajor = op->d.kind != 2;
+    const Strides bs = basis_strides(rowmajor, m, n, K);
+    const bool grid_rule =
+        o->reg == LSLU_REG_WGCV || o->reg == LSLU_REG_GCV || o->reg == LSLU_REG_OPTIMAL;
+    const int G = grid_rule ? std::max(o->n_grid, 1) : 1;
+    const size_t need = carve(nullptr, m, n, K, esz, bs, nullptr, G);
+    if (need > kStaticScratchBytes)
+      return fail(c, LSLU_EINVAL,
+                  "this solve needs " + std::to_string(need >> 20) +
+                      " MiB of device workspace; lslu_solve_static has " +
+                      std::to_string(kStaticScratchBytes >> 20) + " MiB (use lslu_solve)");
+    Layout lay;
+    carve(base, m, n, K, esz, bs, &lay, G);
+    const hipStream_t s = c->stream;
+    // Small host inputs, copied straight from the caller's arrays.
+    if (grid_rule)
+      LSLU_HIP(c, hipMemcpyAsync(lay.grid, o->lambda_grid, sizeof(double) * o->n_grid,
+                                 hipMemcpyHostToDevice, s));
+    const bool rt = o->replay_piv_t != nullptr, rg = o->replay_piv_g != nullptr,
+               rl = o->replay_lambda_idx != nullptr;
+    if (rt) {
+      launch_fill<int>(lay.rep_t, -1, K + 1, s);
+      LSLU_HIP(c, hipMemcpyAsync(lay.rep_t, o->replay_piv_t,
+                                 sizeof(int) * std::min<int64_t>(K + 1, m),
+                                 hipMemcpyHostToDevice, s));
+    }
+    if (rg) {
+      launch_fill<int>(lay.rep_g, -1, K, s);
+      LSLU_HIP(c, hipMemcpyAsync(lay.rep_g, o->replay_piv_g,
+                                 sizeof(int) * std::min<int64_t>(K, n),
+                                 hipMemcpyHostToDevice, s));
+    }
+    if (rl)
+      LSLU_HIP(c, hipMemcpyAsync(lay.rep_lam, o->replay_lambda_idx, sizeof(int) * K,
+                                 hipMemcpyHostToDevice, s));
+    if (o->sample_rows)
+      LSLU_HIP(c, hipMemcpy2DAsync(lay.samp, sizeof(int) * kMaxSampleLen, o->sample_rows,
+                                   sizeof(int) * o->sample_len, sizeof(int) * o->sample_len,
+                                   2 * K + 1, hipMemcpyHostToDevice, s));
+    void* X = o->X_dev ? o->X_dev : lay.X;
+    {
+      // The solve, its kernels enqueued directly, on the static workspace:
+      // the context describes that workspace for the call and its own again
+      // afterwards.
+      GeomSwap keep(c);
+      c->lay = lay;
+      c->m = m;
+      c->n = n;
+      c->bs = bs;
+      c->rowmajor = rowmajor;
+      c->K = K;
+      c->esz = esz;
+      c->grid_slots = G;
+      PhaseEvents pe;
+      if (esz == sizeof(double))
+        enqueue_solve<double>(c, op->d, static_cast<const double*>(b),
+                              static_cast<const double*>(x0), o, static_cast<double*>(x_out),
+                              static_cast<double*>(X), rt, rg, rl, &pe);
+      else
+        enqueue_solve<float>(c, op->d, static_cast<const float*>(b),
+                             static_cast<const float*>(x0), o, static_cast<float*>(x_out),
+                             static_cast<float*>(X), rt, rg, rl, &pe);
+    }
+    LSLU_HIP(c, hipGetLastError());
+    // Results straight into the caller's arrays (and two host words here).
+    DevState st{};
+    int sel[2] = {0, 0};
+    LSLU_HIP(c, hipMemcpyAsync(&st, lay.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    LSLU_HIP(c, hipMemcpyAsync(sel, lay.sel, sizeof(sel), hipMemcpyDeviceToHost, s));
+    if (res) {
+      auto get = [&](void* dst, const void* src, size_t bytes) -> lslu_status {
+        if (dst) LSLU_HIP(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+        return LSLU_OK;
+      };
+      const size_t dK = sizeof(double) * K, iK = sizeof(int32_t) * K;
+      const lslu_status gs[] = {
+          get(res->piv_t, lay.piv_t, iK + sizeof(int32_t)), get(res->piv_g, lay.piv_g, iK),
+          get(res->own_piv_t, lay.own_t, iK + sizeof(int32_t)), get(res->own_piv_g, lay.own_g, iK),
+          get(res->H, lay.H, dK * (K + 1)), get(res->W, lay.W, dK * K), get(res->Y, lay.Y, dK * K),
+          get(res->lambda_k, lay.lam, dK), get(res->lambda_idx, lay.lam_idx, iK),
+          get(res->ghat, lay.ghat, dK), get(res->sep_lambda, lay.sep, dK),
+          get(res->sigma_max, lay.smax, dK), get(res->sigma_min, lay.smin, dK),
+          get(res->dloss_dlambda, lay.dldl, dK)};
+      for (lslu_status g : gs)
+        if (g != LSLU_OK) return g;
+    }
+    LSLU_HIP(c, hipStreamSynchronize(s));
+    // The reverse pass and lslu_get_basis read the context's own workspace,
+    // which this solve did not use.
+    c->last_ok = false;
+    c->last_op = nullptr;
+    c->last_nl = 0;
+    c->last_nd = 0;
+    if (st.spin_timeouts != 0)
+      return fail(c, LSLU_EDEVICE, "a wait inside the recurrence ran out (device fault)");
+    const lslu_status status = static_cast<lslu_status>(st.status);
+    if (res) {
+      res->status = status;
+      res->k_done = st.k_done;
+      res->k_stop = sel[0];
+      res->n_l = st.n_l;
+      res->n_d = st.n_d;
+      res->beta = st.beta;
+      res->piv_t_mismatch = st.mismatch_t;
+      res->piv_g_mismatch = st.mismatch_g;
+      res->t_recurrence_ms = 0.0;
+      res->n_recurrence_launches = 0;
+      res->t_projected_ms = 0.0;
+      res->t_assemble_ms = 0.0;
+    }
+    return status;
   } catch (const std::bad_alloc&) {
     return fail(c, LSLU_ENOMEM, "host allocation failed");
   } catch (...) {

@@ -40,9 +40,10 @@ size_t g_static_lds = 32 * 1024;  // static LDS of k_projected, read at init
 
 // Working matrix A ((k+1) x k, leading dimension k+1).
 __host__ __device__ inline size_t proj_a_doubles(int k) { return (size_t)(k + 1) * k; }
-// Global scratch per problem: A (when not in LDS) and 3 vectors per lambda.
-__host__ __device__ inline size_t proj_scratch_per_k(int K) {
-  return proj_a_doubles(K) + (size_t)3 * K * kMaxGrid;
+// Global scratch per problem: A (when not in LDS) and 3 vectors for each of
+// G grid values.
+__host__ __device__ inline size_t proj_scratch_per_k(int K, int G) {
+  return proj_a_doubles(K) + (size_t)3 * K * G;
 }
 
 __device__ inline double wave_sum_d(double v) { return group_sum<kWave>(v); }
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(kPT) void k_projected(
   const double beta = st->beta;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const int lda = k + 1;
-  double* blk = scratch + (size_t)(k - 1) * proj_scratch_per_k(K);
+  double* blk = scratch + (size_t)(k - 1) * proj_scratch_per_k(K, p.grid_slots);
   double* A;
   if constexpr (a_in_lds) A = lds_a; else A = blk;
   double* lamscr;  // 3*K doubles per grid value
@@ -494,7 +495,9 @@ __global__ __launch_bounds__(kPT) void k_projected(
 
 }  // namespace
 
-size_t projected_scratch_doubles(int K) { return proj_scratch_per_k(K) * (size_t)K; }
+size_t projected_scratch_doubles(int K, int grid_slots) {
+  return proj_scratch_per_k(K, grid_slots) * (size_t)K;
+}
 
 void projected_init_attributes(size_t lds_bytes) {
   hipFuncAttributes fa{};
