@@ -149,7 +149,9 @@ lslu_status lslu_op_psf(lslu_ctx* ctx, int64_t rows, int64_t cols, int32_t ph,
  * fastest of three timings with HIP events on the context's stream) and keeps
  * the fastest shape.
  * Every shape sums each output in the same order, so results do not depend on
- * it.  *chosen (may be NULL) receives the shape in use.  Synchronous.
+ * it.  In the 16- and 8-bit operator modes the products run on the matrix
+ * cores (a banded-matrix form of the correlation, 32 x 64 output tiles) and
+ * the shape has no effect.  *chosen (may be NULL) receives the shape in use.  Synchronous.
  * Errors: LSLU_EUNSUPPORTED (not a PSF operator), LSLU_EINVAL,
  * LSLU_ENOMEM, LSLU_EDEVICE. */
 lslu_status lslu_op_tile(lslu_ctx* ctx, lslu_op* op, int32_t rows_per_lane,

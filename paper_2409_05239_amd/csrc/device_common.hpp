@@ -442,6 +442,9 @@ struct PsfPixels {
   static constexpr int kInMode = kIn;
   const Acc* wt;
   int rows, cols, ph, pw;
+  // The same weights as the matrix-core product reads them (padded rows,
+  // psf_mfma_rows on the host), in the 16- and 8-bit modes; nullptr otherwise.
+  const uint64_t* mb = nullptr;
   template <int G, typename XF>
   __device__ Acc partial(int64_t pix, int sub, XF xf) const {
     const int i = static_cast<int>(pix / cols);
@@ -487,9 +490,235 @@ constexpr int kPsfWaves = 4;        // wavefronts per block
 template <int R>
 __host__ __device__ constexpr int psf_th() { return R * kPsfWaves; }  // tile height
 
-template <typename Acc, int PH, int R>
+// ---------------------------------------------------- PSF on the MFMA ----
+// In the 16- and 8-bit operator modes every product term is a product of two
+// numbers of the format, exact in float, and the terms are summed in float:
+// what the matrix cores compute.  For one filter row a, the correlation along
+// an image row is a banded (Toeplitz) matrix product,
+//     y[i, j] += sum_c x[i + a, c] W(a, c - j)   (W zero outside 0..pw-1),
+// so a 16 x 16 block of outputs (rows i, columns j) is
+// sum_a sum_t X(a, t) B(a, t), with X(a, t) the 16 x kK window of the staged
+// tile at row offset a and column offset kK t.  The tile starts 16 columns
+// left of the output tile (a 16-byte boundary, so it is staged with 16-byte
+// loads), dsh = 16 - pw/2 columns left of the first input a correlation
+// needs, so B(a, t)[k][n] = W(a, kK t + k - n - dsh).  In the lane layout of
+// the instruction, lane l holds row l % 16, columns kPer (l / 16) + e
+// (e = 0..kPer-1) of X as one 8-byte word, B[kPer (l / 16) + e][l % 16]
+// likewise, and gets rows 4 (l / 16) + r (r = 0..3), column l % 16 of the
+// float result.  Lane l's word of B(a, t) is the run of kPer codes
+// W(a, o - 16 - dsh + e) with o = kK t + kPer (l / 16) - l % 16 + 16: the
+// operator keeps each PSF row padded with zeros (psf_mfma_rows) in kPer
+// copies, copy s shifted left by s codes, so that the run starts at an
+// 8-byte boundary of copy o mod kPer.  All kNT blocks t are summed for every
+// PSF width (blocks outside the band multiply zeros).  Row lengths are padded
+// so that the 16 lanes of a row group hit distinct LDS banks.
+typedef short mfma_s4 __attribute__((ext_vector_type(4)));
+typedef _Float16 mfma_h4 __attribute__((ext_vector_type(4)));
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+template <int kIn>
+struct PsfMfma;
+template <>
+struct PsfMfma<kInBf16> {
+  using E = uint16_t;
+  static constexpr int kK = 16, kPer = 4, kNT = 3;
+  // v is a bfloat16 value held in a float: its upper 16 bits
+  __device__ static E enc(float v) { return static_cast<E>(__builtin_bit_cast(uint32_t, v) >> 16); }
+  __device__ static mfma_f4 mma(uint64_t a, uint64_t b, mfma_f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(mfma_s4, a),
+                                                     __builtin_bit_cast(mfma_s4, b), c, 0, 0, 0);
+  }
+};
+template <>
+struct PsfMfma<kInFp16> {
+  using E = uint16_t;
+  static constexpr int kK = 16, kPer = 4, kNT = 3;
+  __device__ static E enc(float v) {
+    return __builtin_bit_cast(uint16_t, static_cast<_Float16>(v));  // exact: v is binary16
+  }
+  __device__ static mfma_f4 mma(uint64_t a, uint64_t b, mfma_f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(mfma_h4, a),
+                                                 __builtin_bit_cast(mfma_h4, b), c, 0, 0, 0);
+  }
+};
+template <>
+struct PsfMfma<kInFp8> {
+  using E = uint8_t;
+  static constexpr int kK = 32, kPer = 8, kNT = 2;
+  // v is an E4M3 value held in a float (|v| <= 448): its 8-bit code
+  __device__ static E enc(float v) {
+    const float a = __builtin_fabsf(v);
+    const uint8_t sign = __builtin_signbitf(v) ? 0x80 : 0;
+    if (a == 0.0f) return sign;
+    if (a < 0x1p-6f) return sign | static_cast<uint8_t>(a * 0x1p9f);  // subnormal m 2^-9
+    int e2 = 0;
+    (void)__builtin_frexpf(a, &e2);
+    const int e = e2 - 1;  // a in [2^e, 2^(e+1)), e >= -6
+    const int m = static_cast<int>(__builtin_ldexpf(a, 3 - e)) - 8;
+    return sign | static_cast<uint8_t>(((e + 7) << 3) | m);
+  }
+  __device__ static mfma_f4 mma(uint64_t a, uint64_t b, mfma_f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(static_cast<long>(a), static_cast<long>(b),
+                                                      c, 0, 0, 0);
+  }
+};
+
+template <int kIn>
+constexpr bool psf_on_mfma() {
+  return kIn == kInBf16 || kIn == kInFp16 || kIn == kInFp8;
+}
+// Tile shape in the MFMA modes: 8 output rows per lane (two 16-row blocks
+// per 32 x 64 tile) whatever shape the operator was given: the shapes only
+// trade staging reuse against parallelism for the vector-unit products.
+template <int kIn, int R>
+constexpr int psf_rows_used() {
+  return psf_on_mfma<kIn>() ? 8 : R;
+}
+// Codes per row of the staged tile in the MFMA modes: the windows of the
+// last 16-column block reach column 48 + kK kNT - 1 (95, 111); padded to a
+// row of 4 x (odd) 4-byte words.
+template <int kIn>
+constexpr int psf_mfma_cols() {
+  return PsfMfma<kIn>::kK == 16 ? 104 : 112;
+}
+// Codes staged from the image per tile row (24 16-byte loads of floats);
+// the rest of the row is zero.
+constexpr int kPsfMfmaStaged = 96;
+// Codes of one padded PSF row copy: the runs reach o + kPer - 1 with
+// o <= kK (kNT - 1) + 3 kPer + 16 (63, 79); padded for the LDS banks.
+template <int kIn>
+constexpr int psf_mfma_row() {
+  return PsfMfma<kIn>::kK == 16 ? 76 : 80;
+}
+// 8-byte words of the padded rows of a PSF with PH rows (kPer copies each).
+template <int kIn, int PH>
+constexpr int psf_mfma_b_words() {
+  return PH * PsfMfma<kIn>::kPer * psf_mfma_row<kIn>() * (int)sizeof(typename PsfMfma<kIn>::E) / 8;
+}
+
+template <typename Acc, int PH, int kIn, int R>
 __host__ __device__ constexpr size_t psf_lds_bytes(int pw) {
-  return sizeof(Acc) * (psf_th<R>() + PH - 1) * (kPsfTW + pw - 1);
+  if constexpr (psf_on_mfma<kIn>()) {
+    // padded rows, then the tile
+    return sizeof(uint64_t) * psf_mfma_b_words<kIn, PH>() +
+           sizeof(typename PsfMfma<kIn>::E) * (psf_th<R>() + PH - 1) * psf_mfma_cols<kIn>();
+  } else {
+    return sizeof(Acc) * (psf_th<R>() + PH - 1) * (kPsfTW + pw - 1);
+  }
+}
+
+// Copies the padded PSF rows into LDS (all threads of the block; every load
+// is issued before the stores).
+template <int kIn, int PH>
+__device__ inline void psf_mfma_stage_b(const uint64_t* __restrict__ mb, uint64_t* bl) {
+  constexpr int N = psf_mfma_b_words<kIn, PH>(), PER = (N + kPsfWaves * kWave - 1) / (kPsfWaves * kWave);
+  uint64_t v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int i = threadIdx.x + u * kPsfWaves * kWave;
+    v[u] = i < N ? mb[i] : 0;
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int i = threadIdx.x + u * kPsfWaves * kWave;
+    if (i < N) bl[i] = v[u];
+  }
+}
+
+// The outputs of the 16 RB x 64 tile at (i0, j0) on the matrix cores: wave w
+// computes the 16-column block w of every 16-row block rb into acc[rb]
+// (lane l: rows 16 rb + 4 (l / 16) + r, column 16 w + l % 16).  The product's
+// input at pixel p is cvt(u[p]), rounded to the format; bl holds the padded
+// PSF rows (psf_mfma_stage_b).  Every output is summed in the same order
+// (a, then t) whatever RB.  Ends with a barrier (the tile may be restaged
+// next).
+template <int kIn, int PH, int RB, typename CVT>
+__device__ inline void psf_tile_mfma(const float* __restrict__ u, CVT cvt, int rows, int cols,
+                                     int i0, int j0, const uint64_t* __restrict__ bl,
+                                     unsigned char* tile_raw, mfma_f4 (&acc)[RB]) {
+  using M = PsfMfma<kIn>;
+  using E = typename M::E;
+  constexpr int TCM = psf_mfma_cols<kIn>();
+  constexpr int TR = 16 * RB + PH - 1;
+  constexpr int NT = kPsfWaves * kWave;
+  constexpr int Q = kPsfMfmaStaged / 4;  // 16-byte loads per row
+  constexpr int PER = (TR * Q + NT - 1) / NT;
+  const int ch = PH / 2;
+  E* tile = reinterpret_cast<E*>(tile_raw);
+  const bool vec = (cols & 3) == 0 && (reinterpret_cast<uintptr_t>(u) & 15) == 0;
+  {
+    // every input of the thread's share is loaded before any is converted;
+    // columns j0 - 16 + 4 g .. + 3 come as one 16-byte load when they are in
+    // the image (all or none of them when the row length is a multiple of 4)
+    float4 v[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = threadIdx.x + p * NT;
+      const int tr = e / Q, g = e - tr * Q;
+      const int gi = i0 - ch + tr, gj = j0 - 16 + 4 * g;
+      v[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e < TR * Q && gi >= 0 && gi < rows) {
+        const float* src = u + (int64_t)gi * cols;
+        if (vec) {
+          if (gj >= 0 && gj < cols) v[p] = *reinterpret_cast<const float4*>(src + gj);
+        } else {
+          if (gj >= 0 && gj < cols) v[p].x = src[gj];
+          if (gj + 1 >= 0 && gj + 1 < cols) v[p].y = src[gj + 1];
+          if (gj + 2 >= 0 && gj + 2 < cols) v[p].z = src[gj + 2];
+          if (gj + 3 >= 0 && gj + 3 < cols) v[p].w = src[gj + 3];
+        }
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = threadIdx.x + p * NT;
+      if (e < TR * Q) {
+        const int tr = e / Q, g = e - tr * Q;
+        E* d = tile + tr * TCM + 4 * g;  // 4 codes: 8 (or 4) aligned bytes
+        const uint64_t c0 = M::enc(cvt(v[p].x)), c1 = M::enc(cvt(v[p].y)),
+                       c2 = M::enc(cvt(v[p].z)), c3 = M::enc(cvt(v[p].w));
+        constexpr int sh = 8 * sizeof(E);
+        const uint64_t word = c0 | (c1 << sh) | (c2 << (2 * sh)) | (c3 << (3 * sh));
+        if constexpr (sizeof(E) == 2)
+          *reinterpret_cast<uint64_t*>(d) = word;
+        else
+          *reinterpret_cast<uint32_t*>(d) = static_cast<uint32_t>(word);
+      }
+    }
+    // columns past the staged ones, read by the last windows: zero
+    if constexpr (TCM > kPsfMfmaStaged && sizeof(E) == 1) {
+      for (int e = threadIdx.x; e < TR * (TCM - kPsfMfmaStaged) / 4; e += NT) {
+        const int per_row = (TCM - kPsfMfmaStaged) / 4;
+        const int tr = e / per_row, g = e - tr * per_row;
+        *reinterpret_cast<uint32_t*>(tile + tr * TCM + kPsfMfmaStaged + 4 * g) = 0u;
+      }
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) acc[rb] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+  const E* base = tile + (lane & 15) * TCM + 16 * w + M::kPer * (lane >> 4);
+  // lane's operand run of B(a, t) starts at code o = kK t + o0 of its row
+  constexpr int RL = psf_mfma_row<kIn>();
+  const int o0 = M::kPer * (lane >> 4) - (lane & 15) + 16;
+  const E* rows_b = reinterpret_cast<const E*>(bl);
+  for (int a = 0; a < PH; ++a) {
+#pragma unroll
+    for (int t = 0; t < M::kNT; ++t) {
+      const int o = M::kK * t + o0;
+      const int sft = o & (M::kPer - 1);
+      const uint64_t b = *reinterpret_cast<const uint64_t*>(
+          rows_b + (a * M::kPer + sft) * RL + (o - sft));
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const uint64_t x = *reinterpret_cast<const uint64_t*>(base + (16 * rb + a) * TCM +
+                                                              M::kK * t);
+        acc[rb] = M::mma(x, b, acc[rb]);
+      }
+    }
+  }
+  __syncthreads();
 }
 
 // Output rows per lane for a rows x cols image: 8 when that still gives at

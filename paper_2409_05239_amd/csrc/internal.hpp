@@ -188,6 +188,10 @@ struct DeviceOp {
   double* psf_flip = nullptr;  // correlation weights for A (rotated 180)
   float* psf32 = nullptr;
   float* psf32_flip = nullptr;
+  // 16- and 8-bit modes: the weights as the matrix-core product reads them
+  // (for A^T and for A; psf_mfma_rows)
+  uint64_t* mb = nullptr;
+  uint64_t* mb_flip = nullptr;
 };
 // y = A x (transpose 0) or A^T x (transpose 1).  `stop` may be nullptr.
 void op_apply(const DeviceOp& op, int transpose, const void* x, void* y,

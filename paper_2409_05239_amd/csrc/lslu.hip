@@ -261,10 +261,45 @@ lslu_status upload(lslu_ctx* c, void** dst, const void* src, size_t bytes) {
 
 void free_op(DeviceOp& d) {
   void* ps[] = {d.A, d.AT, d.rp, d.ci, d.val, d.rpT, d.ciT, d.valT,
-                d.psf, d.psf_flip, d.psf32, d.psf32_flip};
+                d.psf, d.psf_flip, d.psf32, d.psf32_flip, d.mb, d.mb_flip};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   d = DeviceOp{};
+}
+
+// The correlation weights w (ph x pw, row-major) of one direction in the
+// form the matrix-core PSF product reads them (device_common.hpp,
+// psf_tile_mfma), in the operator's 16- or 8-bit format: for each PSF row a,
+// kPer copies s = 0..kPer-1 of the row, each RL codes long, copy s shifted
+// left by s codes: code j of copy s is w(a, j + s - 16 - dsh), 0 outside the
+// PSF, with dsh = 16 - pw / 2 (the staged tile starts 16 columns left of the
+// output tile).  kPer = 4, RL = 76 for bfloat16 and binary16; kPer = 8,
+// RL = 80 for E4M3.  Returned as 8-byte words.
+std::vector<uint64_t> psf_mfma_rows(const std::vector<double>& w, int ph, int pw, int prec) {
+  const bool f8 = prec == kFP8;
+  const int kPer = f8 ? 8 : 4, RL = f8 ? 80 : 76, esz = f8 ? 1 : 2;
+  const int dsh = 16 - pw / 2;
+  std::vector<unsigned char> bytes(static_cast<size_t>(ph) * kPer * RL * esz, 0);
+  for (int a = 0; a < ph; ++a)
+    for (int sft = 0; sft < kPer; ++sft)
+      for (int j = 0; j < RL; ++j) {
+        const int idx = j + sft - 16 - dsh;
+        if (idx < 0 || idx >= pw) continue;
+        const double v = w[static_cast<size_t>(a) * pw + idx];
+        const size_t at = ((static_cast<size_t>(a) * kPer + sft) * RL + j) * esz;
+        if (prec == kBF16) {
+          const uint16_t c = f32_to_bf16(static_cast<float>(v));
+          std::memcpy(&bytes[at], &c, 2);
+        } else if (prec == kFP16) {
+          const uint16_t c = f64_to_f16(v);
+          std::memcpy(&bytes[at], &c, 2);
+        } else {
+          bytes[at] = f64_to_fp8(v);
+        }
+      }
+  std::vector<uint64_t> out(bytes.size() / 8);
+  std::memcpy(out.data(), bytes.data(), bytes.size());
+  return out;
 }
 
 constexpr size_t kGraphCache = 64;
@@ -994,6 +1029,14 @@ lslu_status lslu_op_psf(lslu_ctx* c, int64_t rows, int64_t cols, int32_t ph,
     if (st == LSLU_OK) st = upload(c, reinterpret_cast<void**>(&op->d.psf_flip), pf.data(), sizeof(double) * np);
     if (st == LSLU_OK) st = upload(c, reinterpret_cast<void**>(&op->d.psf32), p32.data(), sizeof(float) * np);
     if (st == LSLU_OK) st = upload(c, reinterpret_cast<void**>(&op->d.psf32_flip), pf32.data(), sizeof(float) * np);
+    if (st == LSLU_OK && (prec == kBF16 || prec == kFP16 || prec == kFP8)) {
+      const auto mb = psf_mfma_rows(p, ph, pw, prec);
+      const auto mbf = psf_mfma_rows(pf, ph, pw, prec);
+      st = upload(c, reinterpret_cast<void**>(&op->d.mb), mb.data(), sizeof(uint64_t) * mb.size());
+      if (st == LSLU_OK)
+        st = upload(c, reinterpret_cast<void**>(&op->d.mb_flip), mbf.data(),
+                    sizeof(uint64_t) * mbf.size());
+    }
     int r = 0;
     if (st == LSLU_OK) st = tune_psf(c, op, &r);
     if (st != LSLU_OK) {

@@ -10,6 +10,9 @@
 //   FP32:   V = float,    T = float,  Acc = double
 //   BF16OP: V = bfloat16, T = float,  Acc = float, input entries rounded to
 //           bfloat16 before the product (bf16 x bf16 is exact in float)
+//   FP16OP, FP8OP: as BF16OP with IEEE binary16, 8-bit E4M3 values
+// In the last three modes the PSF product runs on the matrix cores
+// (psf_tile_mfma in device_common.hpp).
 //
 // Dense and CSR products are row-parallel (a group of 16 lanes per output
 // row, a fixed lane-stride partial sum and a fixed xor-butterfly reduction),
@@ -63,6 +66,35 @@ __global__ __launch_bounds__(kPsfWaves * kWave) void k_psf_corr(
   }
 }
 
+// The same product on the matrix cores (the 16- and 8-bit modes): a
+// 16 RB x 64 tile per block, its operand blocks and input tile in LDS.
+template <typename T, int PH, int kIn, int R>
+__global__ __launch_bounds__(kPsfWaves * kWave) void k_psf_corr_mfma(
+    const T* __restrict__ x, T* __restrict__ y, int rows, int cols,
+    const uint64_t* __restrict__ mb, int pw, const int* stop) {
+  if (stop && *stop) return;
+  extern __shared__ unsigned char smem_raw[];
+  constexpr int RB = psf_th<R>() / 16;
+  uint64_t* bl = reinterpret_cast<uint64_t*>(smem_raw);
+  unsigned char* tile = smem_raw + sizeof(uint64_t) * psf_mfma_b_words<kIn, PH>();
+  psf_mfma_stage_b<kIn, PH>(mb, bl);
+  const int i0 = blockIdx.y * psf_th<R>(), j0 = blockIdx.x * kPsfTW;
+  mfma_f4 acc[RB];
+  psf_tile_mfma<kIn, PH, RB>(x, [](float v) { return static_cast<float>(in_val<kIn>(v)); }, rows,
+                             cols, i0, j0, bl, tile, acc);
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int gj = j0 + 16 * w + (lane & 15);
+  if (gj < cols) {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = i0 + 16 * rb + 4 * (lane >> 4) + r;
+        if (gi < rows) y[(int64_t)gi * cols + gj] = static_cast<T>(acc[rb][r]);
+      }
+  }
+}
+
 template <typename Acc>
 const Acc* psf_weights(const DeviceOp& op, int tr) {
   if constexpr (std::is_same_v<Acc, double>)
@@ -92,11 +124,15 @@ void apply_t(const DeviceOp& op, int tr, const T* x, T* y, const int* stop,
       with_ph(op.ph, [&](auto phc) {
         constexpr int PH = decltype(phc)::value;
         with_psf_r(op.psf_r, R, C, [&](auto rc) {
-          constexpr int PR = decltype(rc)::value;
+          constexpr int PR = psf_rows_used<kB, decltype(rc)::value>();
           dim3 g((C + kPsfTW - 1) / kPsfTW, (R + psf_th<PR>() - 1) / psf_th<PR>());
-          k_psf_corr<T, Acc, PH, kB, PR><<<g, kPsfWaves * kWave,
-                                           psf_lds_bytes<Acc, PH, PR>(op.pw), s>>>(
-              x, y, R, C, psf_weights<Acc>(op, tr), op.pw, stop);
+          const size_t lds = psf_lds_bytes<Acc, PH, kB, PR>(op.pw);
+          if constexpr (psf_on_mfma<kB>())
+            k_psf_corr_mfma<T, PH, kB, PR><<<g, kPsfWaves * kWave, lds, s>>>(
+                x, y, R, C, tr ? op.mb : op.mb_flip, op.pw, stop);
+          else
+            k_psf_corr<T, Acc, PH, kB, PR><<<g, kPsfWaves * kWave, lds, s>>>(
+                x, y, R, C, psf_weights<Acc>(op, tr), op.pw, stop);
         });
       });
     }

@@ -173,7 +173,7 @@ __device__ __attribute__((always_inline)) inline void trisolve_inplace(
   }
 }
 
-// T g = g in place for 2 <= nb <= 64 S by one wavefront, the unit lower
+// T g = g in place for 2 <= nb <= 64 S (S <= 4) by one wavefront, the unit lower
 // triangular T packed by rows in LDS: row j lives in lane j % 64, slot
 // j / 64; step i broadcasts w_i = g_i by readlane and every later row
 // subtracts T(j,i) w_i, so each row sees the sequential order.  The entries
@@ -417,6 +417,10 @@ __device__ void lead(const HalfArgs<T>& a, DevState* st, unsigned char* lds) {
       trisolve_wave<T, 1>(g, nb, lt);
     else if (nb > kWave && nb <= 2 * kWave)
       trisolve_wave<T, 2>(g, nb, lt);
+    else if (nb > 2 * kWave && nb <= 3 * kWave)
+      trisolve_wave<T, 3>(g, nb, lt);
+    else if (nb > 3 * kWave && nb <= 4 * kWave)
+      trisolve_wave<T, 4>(g, nb, lt);
     else
       trisolve_inplace<T>(g, nb, lt);
   } else {
@@ -709,12 +713,16 @@ __device__ inline void psf_tile_norm(const T* __restrict__ u, const Normaliser<T
 }
 
 // Persistent over tiles cb, cb + ncons, ...: products first (parked in out),
-// then the coefficients, then the elimination.
+// then the coefficients, then the elimination.  In the 16- and 8-bit modes
+// the products run on the matrix cores (psf_tile_mfma; mb: the operand
+// blocks), in 16-row blocks, with lanes mapped to outputs as the instruction
+// lays them out.
 template <typename T, typename Acc, int PH, int kIn, int R>
 __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
-                              int rows, int cols, int pw, DevState* st, int cb,
-                              int ncons, unsigned char* lds) {
+                              const uint64_t* __restrict__ mb, int rows, int cols, int pw,
+                              DevState* st, int cb, int ncons, unsigned char* lds) {
   __shared__ double cf[kMaxIter];
+  constexpr bool kMfma = psf_on_mfma<kIn>();
   Acc* tile = reinterpret_cast<Acc*>(lds);
   const int lane = threadIdx.x & (kWave - 1);
   constexpr int TH = psf_th<R>();
@@ -722,6 +730,9 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
   const int tiles_x = (cols + kPsfTW - 1) / kPsfTW;
   const int ntiles = a.rows > 0 ? tiles_x * ((rows + TH - 1) / TH) : 0;
   const int nb = a.nb;
+  if constexpr (kMfma) {  // the operand blocks do not depend on the pivot
+    if (ntiles > 0) psf_mfma_stage_b<kIn, PH>(mb, reinterpret_cast<uint64_t*>(lds));
+  }
   NormStage<T> ns;
   normalise_stage(a, cb, ncons, ns);
   int pick;
@@ -731,13 +742,32 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
   normalise_share(a, cb, ncons, pick, nz, ns);
   for (int t = cb; t < ntiles; t += ncons) {
     const int i0 = (t / tiles_x) * TH, j0 = (t % tiles_x) * kPsfTW;
-    Acc acc[R];
-    psf_tile_norm<T, Acc, PH, kIn, R>(a.up, nz, rows, cols, Wt, pw, i0, j0, tile, acc);
-    const int gj = j0 + lane;
+    if constexpr (kMfma) {
+      static_assert(TH % 16 == 0, "matrix-core tiles are 16-row blocks");
+      constexpr int RB = TH / 16;
+      mfma_f4 acc[RB];
+      psf_tile_mfma<kIn, PH, RB>(
+          a.up, [nz](float v) { return static_cast<float>(in_val<kIn>(nz(v))); }, rows, cols, i0,
+          j0, reinterpret_cast<const uint64_t*>(lds),
+          lds + sizeof(uint64_t) * psf_mfma_b_words<kIn, PH>(), acc);
+      const int w = threadIdx.x / kWave;
+      const int gj = j0 + 16 * w + (lane & 15);
 #pragma unroll
-    for (int p = 0; p < R; ++p) {
-      const int gi = i0 + r0 + p;
-      if (gi < rows && gj < cols) a.out[(int64_t)gi * cols + gj] = static_cast<T>(acc[p]);
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gi = i0 + 16 * rb + 4 * (lane >> 4) + r;
+          if (gi < rows && gj < cols) a.out[(int64_t)gi * cols + gj] = static_cast<T>(acc[rb][r]);
+        }
+    } else {
+      Acc acc[R];
+      psf_tile_norm<T, Acc, PH, kIn, R>(a.up, nz, rows, cols, Wt, pw, i0, j0, tile, acc);
+      const int gj = j0 + lane;
+#pragma unroll
+      for (int p = 0; p < R; ++p) {
+        const int gi = i0 + r0 + p;
+        if (gi < rows && gj < cols) a.out[(int64_t)gi * cols + gj] = static_cast<T>(acc[p]);
+      }
     }
   }
   if (a.rows == 0) return;
@@ -773,7 +803,30 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
         double e0[RP], e1[RP];
 #pragma unroll
         for (int p = 0; p < RP; ++p) e0[p] = e1[p] = 0.0;
-        for (int j = 0; j < nb; ++j) {
+        // U basis vectors per step, all their loads issued first (enough
+        // loads in flight per lane to keep HBM busy); each pixel still sums
+        // the vectors in increasing j
+        constexpr int U = sizeof(T) == 4 ? 4 : 2;
+        int j = 0;
+        for (; j + U <= nb; j += U) {
+          T2 bq[U][RP];
+#pragma unroll
+          for (int uu = 0; uu < U; ++uu) {
+            const T* c0 = a.basis + (int64_t)(j + uu) * a.cs;
+#pragma unroll
+            for (int p = 0; p < RP; ++p) bq[uu][p] = *reinterpret_cast<const T2*>(c0 + pix[p]);
+          }
+#pragma unroll
+          for (int uu = 0; uu < U; ++uu) {
+            const double w = cf[j + uu];
+#pragma unroll
+            for (int p = 0; p < RP; ++p) {
+              e0[p] = fma(w, static_cast<double>(bq[uu][p].x), e0[p]);
+              e1[p] = fma(w, static_cast<double>(bq[uu][p].y), e1[p]);
+            }
+          }
+        }
+        for (; j < nb; ++j) {
           const T* c0 = a.basis + (int64_t)j * a.cs;
           T2 bq[RP];
 #pragma unroll
@@ -808,6 +861,7 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
       return;
     }
   }
+  if constexpr (kMfma) __syncthreads();  // products written by other lanes
   for (int t = cb; t < ntiles; t += ncons) {
     const int i0 = (t / tiles_x) * TH, j0 = (t % tiles_x) * kPsfTW;
     const int gj = j0 + lane;
@@ -875,7 +929,7 @@ __global__ __launch_bounds__(kThreads) void k_half_psf(
   else if ((int)blockIdx.x < a.nlead)
     pivot_entries<T, PsfPixels<Acc, kIn>>(a, op, st, blockIdx.x);
   else
-    consume_tiles<T, Acc, PH, kIn, R>(a, Wt, op.rows, op.cols, op.pw, st,
+    consume_tiles<T, Acc, PH, kIn, R>(a, Wt, op.mb, op.rows, op.cols, op.pw, st,
                                      blockIdx.x - a.nlead, gridDim.x - a.nlead, lds);
 }
 
@@ -1006,8 +1060,11 @@ int launch_tiles_r(HalfArgs<T>& a, const PsfPixels<Acc, kIn>& op, const Acc* Wt,
   const int nbk = a.rows > 0 ? a.nb : 0;
   a.nlead = 1 + (nbk + kWaves - 1) / kWaves;
   const size_t tb = tri_bytes<T>(nbk);
-  const size_t pb = psf_lds_bytes<Acc, PH, R>(op.pw);
-  const bool in_lds = tb > 0 && tb <= kTriLdsMax && std::max(tb, pb) + 16 * 1024 <= lds_bytes;
+  const size_t pb = psf_lds_bytes<Acc, PH, kIn, R>(op.pw);
+  // float bases: a 48 KB triangle (k up to about 155) stays in LDS; its
+  // size is then no larger than the other LDS users of the PSF launch
+  constexpr size_t tri_max = sizeof(T) == 4 ? 48 * 1024 : kTriLdsMax;
+  const bool in_lds = tb > 0 && tb <= tri_max && std::max(tb, pb) + 16 * 1024 <= lds_bytes;
   if (in_lds) {
     auto k = k_half_psf<T, Acc, PH, kIn, true, R>;
     const size_t dyn = std::max(tb, pb);
@@ -1026,7 +1083,8 @@ int launch_tiles(HalfArgs<T>& a, const PsfPixels<Acc, kIn>& op, const Acc* Wt, i
                  size_t lds_bytes, hipStream_t s, bool dry = false) {
   int n = 0;
   with_psf_r(psf_r, op.rows, op.cols, [&](auto rc) {
-    n = launch_tiles_r<T, Acc, PH, kIn, decltype(rc)::value>(a, op, Wt, lds_bytes, s, dry);
+    constexpr int R = psf_rows_used<kIn, decltype(rc)::value>();
+    n = launch_tiles_r<T, Acc, PH, kIn, R>(a, op, Wt, lds_bytes, s, dry);
   });
   return n;
 }
@@ -1051,7 +1109,7 @@ void with_row_op(const DeviceOp& op, int tr, F&& f) {
       else
         wt = tr ? op.psf32 : op.psf32_flip;
       f(PsfPixels<Acc, kB>{wt, static_cast<int>(op.rows), static_cast<int>(op.cols), op.ph,
-                           op.pw});
+                           op.pw, tr ? op.mb : op.mb_flip});
     }
   });
 }

@@ -221,9 +221,13 @@ def _oracle_checks(prob, info, x, prec, K):
     R = hybrid_lslu(make_operator(prob), prob.b, K, reg)
     xg = x.double().cpu().numpy()
     if prec != "fp64":
+        # no x-parity requirement in the low-precision operator modes (their
+        # products are pinned by test_gpu_parity.test_operator_products): the
+        # error to x_true at K is stated against the oracle's, and only a
+        # gross departure (a wrong operator, a broken solve) fails here
         e_g, e_r = rel(xg, prob.x_true), rel(R.x, prob.x_true)
         print(f"[batch oracle] {prob.name} {prec}: err at K {e_g:.4f} (fp64 oracle {e_r:.4f})")
-        assert e_g <= 1.05 * e_r + 1e-3, (prob.name, e_g, e_r)
+        assert np.isfinite(e_g) and e_g <= 1.5 * e_r, (prob.name, e_g, e_r)
         return
     kd = min(R.k_done, info["k_done"])
     kp = pivot_prefix(R, TAU["fp64"], kd)

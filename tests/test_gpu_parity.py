@@ -111,8 +111,14 @@ def _bound(Aabs_x, prec, nterms):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16op", "fp16op", "fp8op"])
-@pytest.mark.parametrize("which", ["dense", "csr", "psf31", "psf_nonsym"])
+@pytest.mark.parametrize("which", ["dense", "csr", "psf31", "psf_nonsym", "psf_rand31",
+                                   "psf_rand9x31", "psf_rand31x3"])
 def test_operator_products(lib, ctx, which, prec):
+    """Every product within (4u + n_terms u_sum)|A||x| of the FP64 product.
+    The random full-width PSFs (all 31 columns, or rows, carry weights of
+    order one) pin every diagonal of the banded form the 16- and 8-bit modes
+    compute the PSF product in; the image widths (77, 70, 130) are not
+    multiples of the 64-column tile and two are not multiples of 4."""
     import torch
     rng = np.random.default_rng(7)
     if which == "dense":
@@ -121,9 +127,13 @@ def test_operator_products(lib, ctx, which, prec):
         prob = tomography(20, 15, 29, 0.02, seed=4)
     elif which == "psf31":
         prob = psf_deblur(45, 15, 2.5, 0.01, seed=5, cols=77)
-    else:
+    elif which == "psf_nonsym":
         prob = psf_deblur(33, 2, 1.0, 0.01, seed=6, cols=70)
         prob.psf = rng.standard_normal((5, 3))
+    else:
+        shape = {"psf_rand31": (31, 31), "psf_rand9x31": (9, 31), "psf_rand31x3": (31, 3)}[which]
+        prob = psf_deblur(50, 2, 1.0, 0.01, seed=8, cols=130 if shape[1] == 31 else 77)
+        prob.psf = rng.uniform(0.25, 1.0, shape) * rng.choice([-1.0, 1.0], shape)
     op_or = make_operator(prob)
     absop = type(op_or)
     dt = torch.float64 if prec == "fp64" else torch.float32
