@@ -306,11 +306,15 @@ struct ProjParams {
   const double* gram;  // OPTIMAL, gradient: (K+1) x (K+1) Gram matrix of [L, x_true - x_0]
   double* dldl;        // nullptr, or K entries: d/dlambda ||x_k(lambda) - x_true||^2 at lambda_k
 };
+// The K problems go out in up to kProjGroups launches (consecutive k with
+// the same LDS placement), launch g on streams[g % nstreams]; the caller
+// orders the streams around the call.
+constexpr int kProjGroups = 4;
 void launch_projected(const double* H, const DevState* st, double beta_unused,
                       const ProjParams& p, double* Y, double* lam,
                       int* lam_idx, double* ghat, double* sep, double* smax,
                       double* smin, double* scratch, size_t lds_bytes,
-                      hipStream_t s);
+                      const hipStream_t* streams, int nstreams);
 // Scratch doubles of launch_projected for K problems with room for
 // grid_slots grid values each.
 size_t projected_scratch_doubles(int K, int grid_slots = kMaxGrid);

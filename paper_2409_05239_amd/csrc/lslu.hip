@@ -128,6 +128,11 @@ struct lslu_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // two more streams (default priority) and three events, made with the
+  // context: the independent launches of the projected problems run side by
+  // side, forked from and joined back into the context's stream
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
   std::string err;
   size_t lds_max = 0;
   // workspace
@@ -573,8 +578,18 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
     pp.gram = l.gram;
   }
   pp.dldl = grad ? l.dldl : nullptr;
-  launch_projected(l.H, st, 0.0, pp, l.Y, l.lam, l.lam_idx, l.ghat, l.sep,
-                   l.smax, l.smin, l.proj, c->lds_max, s);
+  {
+    // fork onto the side streams, one launch group each, then join
+    const hipStream_t ss[3] = {s, c->side[0], c->side[1]};
+    (void)hipEventRecord(c->fork, s);
+    for (int i = 0; i < 2; ++i) (void)hipStreamWaitEvent(c->side[i], c->fork, 0);
+    launch_projected(l.H, st, 0.0, pp, l.Y, l.lam, l.lam_idx, l.ghat, l.sep,
+                     l.smax, l.smin, l.proj, c->lds_max, ss, 3);
+    for (int i = 0; i < 2; ++i) {
+      (void)hipEventRecord(c->join[i], c->side[i]);
+      (void)hipStreamWaitEvent(s, c->join[i], 0);
+    }
+  }
   pe->mark(2, s);
   const double tol = o->stop_tol > 0.0 ? o->stop_tol : 1e-6;
   launch_stopping(l.ghat, st, tol, o->early_stop ? 1 : 0, l.sel, s);
@@ -841,6 +856,16 @@ lslu_status lslu_create(int device, void* hip_stream, lslu_ctx** out) {
       }
       c->own_stream = true;
     }
+    bool ok = true;
+    for (int i = 0; i < 2; ++i) {
+      ok = ok && hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking) == hipSuccess;
+      ok = ok && hipEventCreateWithFlags(&c->join[i], hipEventDisableTiming) == hipSuccess;
+    }
+    ok = ok && hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      lslu_destroy(c);
+      return LSLU_EDEVICE;
+    }
     *out = c;
     return LSLU_OK;
   } catch (const std::bad_alloc&) {
@@ -861,6 +886,12 @@ lslu_status lslu_destroy(lslu_ctx* c) {
   if (c->bat) (void)hipFree(c->bat);
   if (c->host) (void)hipHostFree(c->host);
   if (c->adj_host) (void)hipHostFree(c->adj_host);
+  for (int i = 0; i < 2; ++i) {
+    if (c->side[i]) (void)hipStreamSynchronize(c->side[i]);
+    if (c->side[i]) (void)hipStreamDestroy(c->side[i]);
+    if (c->join[i]) (void)hipEventDestroy(c->join[i]);
+  }
+  if (c->fork) (void)hipEventDestroy(c->fork);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return LSLU_OK;

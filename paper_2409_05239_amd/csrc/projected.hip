@@ -134,19 +134,19 @@ __device__ inline double elden_backward(const double* d, const double* e,
 
 // y = Q z in place, by one wavefront: the right reflectors j = k-3..0 with
 // vectors [1 at j+1; A(j, j+2:k-1)] and factors taur[j].
-__device__ inline void apply_q(const double* A, int lda, const double* taur, int k,
-                               double* z, int lane) {
+template <typename COL>
+__device__ inline void apply_q(COL colp, const double* taur, int k, double* z, int lane) {
   for (int j = k - 3; j >= 0; --j) {
     const double tau = taur[j];
     if (tau == 0.0) continue;
     double w = 0.0;
     for (int c = j + 1 + lane; c < k; c += kWave) {
-      const double u = (c == j + 1) ? 1.0 : A[(size_t)c * lda + j];
+      const double u = (c == j + 1) ? 1.0 : colp(c)[j];
       w = fma(u, z[c], w);
     }
     w = wave_sum_d(w) * tau;
     for (int c = j + 1 + lane; c < k; c += kWave) {
-      const double u = (c == j + 1) ? 1.0 : A[(size_t)c * lda + j];
+      const double u = (c == j + 1) ? 1.0 : colp(c)[j];
       z[c] = fma(-w, u, z[c]);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -155,15 +155,19 @@ __device__ inline void apply_q(const double* A, int lda, const double* taur, int
 }
 
 // Dynamic LDS: [A when a_in_lds][per-grid-value Elden scratch when l_in_lds],
-// sized for the largest k of the launch (k_last).
-template <bool a_in_lds, bool l_in_lds>
+// sized for the largest k of the launch (k_last).  a_split (with a_in_lds
+// false): A's first cs columns live in the problem's global scratch and the
+// others in LDS (a_room bytes), cs as small as the room allows.  Column c is
+// last changed by step c of the bidiagonalisation, so the global columns
+// are only touched in the first cs steps (and by y = Q z at the end).
+template <bool a_in_lds, bool l_in_lds, bool a_split>
 __global__ __launch_bounds__(kPT) void k_projected(
     const double* __restrict__ H, const DevState* __restrict__ st,
     ProjParams p, int k_first, int k_last, double* __restrict__ Y,
     double* __restrict__ lam_out, int* __restrict__ lam_idx_out,
     double* __restrict__ ghat_out, double* __restrict__ sep_out,
     double* __restrict__ smax_out, double* __restrict__ smin_out,
-    double* __restrict__ scratch) {
+    double* __restrict__ scratch, size_t a_room) {
   extern __shared__ double lds_a[];
   __shared__ double g[kMaxIter + 1], vb[kMaxIter + 1], taur[kMaxIter];
   __shared__ double d[kMaxIter], e[kMaxIter], ta[kMaxIter], tb[kMaxIter];
@@ -181,6 +185,18 @@ __global__ __launch_bounds__(kPT) void k_projected(
   double* blk = scratch + (size_t)(k - 1) * proj_scratch_per_k(K, p.grid_slots);
   double* A;
   if constexpr (a_in_lds) A = lds_a; else A = blk;
+  int cs = 0;  // a_split: columns 0..cs-1 in global scratch
+  if constexpr (a_split) {
+    const int lds_cols = static_cast<int>(a_room / (sizeof(double) * (size_t)lda));
+    cs = k > lds_cols ? k - lds_cols : 0;
+  }
+  // column c of the working matrix
+  auto colp = [&](int c) -> double* {
+    if constexpr (a_split)
+      return c < cs ? blk + (size_t)c * lda : lds_a + (size_t)(c - cs) * lda;
+    else
+      return A + (size_t)c * lda;
+  };
   double* lamscr;  // 3*K doubles per grid value
   if constexpr (l_in_lds)
     lamscr = lds_a + (a_in_lds ? proj_a_doubles(k_last) : 0);
@@ -190,7 +206,7 @@ __global__ __launch_bounds__(kPT) void k_projected(
   // 1. Load H (column-major, leading dimension K+1) into A; g = beta e_1.
   for (int idx = tid; idx < (k + 1) * k; idx += kPT) {
     const int c = idx / (k + 1), r = idx - c * (k + 1);
-    A[(size_t)c * lda + r] = H[(size_t)c * (K + 1) + r];
+    colp(c)[r] = H[(size_t)c * (K + 1) + r];
   }
   for (int r = tid; r <= k; r += kPT) g[r] = (r == 0) ? beta : 0.0;
   __syncthreads();
@@ -201,11 +217,11 @@ __global__ __launch_bounds__(kPT) void k_projected(
     if (wv == 0) {
       double s2 = 0.0;
       for (int r = j + 1 + lane; r <= k; r += kWave) {
-        const double x = A[(size_t)j * lda + r];
+        const double x = colp(j)[r];
         s2 = fma(x, x, s2);
       }
       s2 = wave_sum_d(s2);
-      const double alpha = A[(size_t)j * lda + j];
+      const double alpha = colp(j)[j];
       double tau = 0.0, bet = alpha, scal = 0.0;
       if (s2 != 0.0) {
         bet = -copysign(sqrt(alpha * alpha + s2), alpha);
@@ -213,11 +229,11 @@ __global__ __launch_bounds__(kPT) void k_projected(
         scal = 1.0 / (alpha - bet);
       }
       for (int r = j + 1 + lane; r <= k; r += kWave)
-        vb[r - j] = A[(size_t)j * lda + r] * scal;
+        vb[r - j] = colp(j)[r] * scal;
       if (lane == 0) {
         vb[0] = 1.0;
         s_tau = tau;
-        A[(size_t)j * lda + j] = bet;
+        colp(j)[j] = bet;
       }
     }
     __syncthreads();
@@ -229,7 +245,7 @@ __global__ __launch_bounds__(kPT) void k_projected(
       if (tau != 0.0) {
         const int li = tid % kBL;
         for (int t = tid / kBL; t <= ncol; t += kPT / kBL) {
-          double* col = (t < ncol) ? A + (size_t)(j + 1 + t) * lda : g;
+          double* col = (t < ncol) ? colp(j + 1 + t) : g;
           double d = 0.0;
           for (int r = j + li; r <= k; r += kBL) d = fma(vb[r - j], col[r], d);
           const double w = tau * group_sum<kBL>(d);
@@ -243,11 +259,11 @@ __global__ __launch_bounds__(kPT) void k_projected(
     if (wv == 0) {
       double s2 = 0.0;
       for (int c = j + 2 + lane; c < k; c += kWave) {
-        const double x = A[(size_t)c * lda + j];
+        const double x = colp(c)[j];
         s2 = fma(x, x, s2);
       }
       s2 = wave_sum_d(s2);
-      const double alpha = A[(size_t)(j + 1) * lda + j];
+      const double alpha = colp(j + 1)[j];
       double tau = 0.0, bet = alpha, scal = 0.0;
       if (s2 != 0.0) {
         bet = -copysign(sqrt(alpha * alpha + s2), alpha);
@@ -255,15 +271,16 @@ __global__ __launch_bounds__(kPT) void k_projected(
         scal = 1.0 / (alpha - bet);
       }
       for (int c = j + 2 + lane; c < k; c += kWave) {
-        const double v = A[(size_t)c * lda + j] * scal;
+        double* cc = colp(c);
+        const double v = cc[j] * scal;
         vb[c - j - 1] = v;
-        A[(size_t)c * lda + j] = v;  // kept for y = Q z
+        cc[j] = v;  // kept for y = Q z
       }
       if (lane == 0) {
         vb[0] = 1.0;
         s_tau = tau;
         taur[j] = tau;
-        A[(size_t)(j + 1) * lda + j] = bet;
+        colp(j + 1)[j] = bet;
       }
     }
     __syncthreads();
@@ -275,20 +292,21 @@ __global__ __launch_bounds__(kPT) void k_projected(
         const int li = tid % kBL;
         for (int t = tid / kBL; t < nrow; t += kPT / kBL) {
           const int r = j + 1 + t;
-          double* row = A + (size_t)(j + 1) * lda + r;  // A(r, j+1), stride lda
-          double d = 0.0;
-          for (int c = li; c < nc; c += kBL) d = fma(vb[c], row[(size_t)c * lda], d);
+          double d = 0.0;  // row r over columns j+1 .. k-1
+          for (int c = li; c < nc; c += kBL) d = fma(vb[c], colp(j + 1 + c)[r], d);
           const double w = tau * group_sum<kBL>(d);
-          for (int c = li; c < nc; c += kBL)
-            row[(size_t)c * lda] = fma(-w, vb[c], row[(size_t)c * lda]);
+          for (int c = li; c < nc; c += kBL) {
+            double* cp = colp(j + 1 + c) + r;
+            *cp = fma(-w, vb[c], *cp);
+          }
         }
       }
     }
     __syncthreads();
   }
   for (int i = tid; i < k; i += kPT) {
-    d[i] = A[(size_t)i * lda + i];
-    e[i] = (i + 1 < k) ? A[(size_t)(i + 1) * lda + i] : 0.0;
+    d[i] = colp(i)[i];
+    e[i] = (i + 1 < k) ? colp(i + 1)[i] : 0.0;
   }
   __syncthreads();
   for (int i = tid; i < k; i += kPT) {  // T = B^T B
@@ -395,7 +413,7 @@ __global__ __launch_bounds__(kPT) void k_projected(
     const double e0 = p.gram[(size_t)K * ldg + K];
     for (int gi = wv; gi < p.n_grid; gi += kPT / kWave) {
       double* y = lamscr + (size_t)gi * 3 * K + 2 * K;
-      apply_q(A, lda, taur, k, y, lane);
+      apply_q(colp, taur, k, y, lane);
       // y^T G y - 2 y^T h, h = G(0:k-1, K)
       double part = 0.0;
       for (int i = lane; i < k; i += kWave) {
@@ -464,8 +482,8 @@ __global__ __launch_bounds__(kPT) void k_projected(
   __syncthreads();
   double* dy = lamscr + 2 * K;  // -2 lambda Q w, when asked for
   if (wv == 0) {
-    apply_q(A, lda, taur, k, zy, lane);
-    if (p.dldl) apply_q(A, lda, taur, k, dy, lane);
+    apply_q(colp, taur, k, zy, lane);
+    if (p.dldl) apply_q(colp, taur, k, dy, lane);
   }
   __syncthreads();
   for (int r = tid; r < K; r += kPT)
@@ -499,56 +517,68 @@ size_t projected_scratch_doubles(int K, int grid_slots) {
   return proj_scratch_per_k(K, grid_slots) * (size_t)K;
 }
 
+namespace {
+// every variant launched by launch_projected
+const void* const kProjKernels[] = {
+    reinterpret_cast<const void*>(k_projected<true, true, false>),
+    reinterpret_cast<const void*>(k_projected<true, false, false>),
+    reinterpret_cast<const void*>(k_projected<false, false, true>)};
+}  // namespace
+
 void projected_init_attributes(size_t lds_bytes) {
   hipFuncAttributes fa{};
   size_t st = 0;
-  const void* kp[] = {reinterpret_cast<const void*>(k_projected<true, true>),
-                      reinterpret_cast<const void*>(k_projected<true, false>),
-                      reinterpret_cast<const void*>(k_projected<false, true>),
-                      reinterpret_cast<const void*>(k_projected<false, false>)};
-  for (const void* k : kp)
+  for (const void* k : kProjKernels)
     if (hipFuncGetAttributes(&fa, k) == hipSuccess) st = std::max(st, fa.sharedSizeBytes);
   if (st > 0) g_static_lds = st;
   if (lds_bytes <= g_static_lds) return;
   const int dyn = static_cast<int>(lds_bytes - g_static_lds);
-  const void* ks[] = {reinterpret_cast<const void*>(k_projected<true, true>),
-                      reinterpret_cast<const void*>(k_projected<true, false>),
-                      reinterpret_cast<const void*>(k_projected<false, true>),
-                      reinterpret_cast<const void*>(k_projected<false, false>)};
-  for (const void* k : ks)
+  for (const void* k : kProjKernels)
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
 }
 
 void launch_projected(const double* H, const DevState* st, double,
                       const ProjParams& p, double* Y, double* lam, int* lam_idx,
                       double* ghat, double* sep, double* smax, double* smin,
-                      double* scratch, size_t lds_bytes, hipStream_t s) {
+                      double* scratch, size_t lds_bytes, const hipStream_t* streams,
+                      int nstreams) {
   // Each problem keeps its working matrix and its per-grid-value Elden
   // scratch (3 K doubles per grid value, indexed with stride K) in LDS when
-  // they fit, else in its slice of global scratch.  Consecutive k with the
-  // same placement share one launch sized for the largest of them.
+  // both fit (placement 3), else the matrix in LDS and the Elden scratch in
+  // its slice of global scratch (1), else as many of the matrix's last
+  // columns as fit in LDS and the rest in global scratch (4).  Consecutive k
+  // with the same placement share one launch sized for the largest of them.
   const size_t room = lds_bytes > g_static_lds ? lds_bytes - g_static_lds : 0;
   const int G = (p.reg == kWGCV || p.reg == kGCV || p.reg == kOptimal)
                     ? std::max(p.n_grid, 1) : 1;
   const size_t lam_bytes = sizeof(double) * 3 * (size_t)p.K * G;
   auto place = [&](int k) {
     const size_t a = proj_a_doubles(k) * sizeof(double);
-    if (a + lam_bytes <= room) return 3;  // both
-    if (a <= room) return 1;              // the matrix (the bidiagonalisation)
-    if (lam_bytes <= room) return 2;      // grid scratch only
-    return 0;
+    if (a + lam_bytes <= room) return 3;
+    if (a <= room) return 1;
+    return 4;
   };
-  int k0 = 1;
+  int k0 = 1, group = 0;
   while (k0 <= p.K) {
     const int pl = place(k0);
     int k1 = k0;
     while (k1 + 1 <= p.K && place(k1 + 1) == pl) ++k1;
-    const int a_l = (pl & 1) ? 1 : 0, l_l = (pl & 2) ? 1 : 0;
-    const size_t dyn = (a_l ? proj_a_doubles(k1) * sizeof(double) : 0) + (l_l ? lam_bytes : 0);
-    auto kern = a_l ? (l_l ? k_projected<true, true> : k_projected<true, false>)
-                    : (l_l ? k_projected<false, true> : k_projected<false, false>);
-    kern<<<k1 - k0 + 1, kPT, dyn, s>>>(H, st, p, k0, k1, Y, lam, lam_idx, ghat, sep,
-                                       smax, smin, scratch);
+    // the groups are independent (disjoint k, outputs and scratch slices)
+    const hipStream_t s = streams[group++ % nstreams];
+    const int nblk = k1 - k0 + 1;
+    if (pl == 3) {
+      const size_t dyn = proj_a_doubles(k1) * sizeof(double) + lam_bytes;
+      k_projected<true, true, false><<<nblk, kPT, dyn, s>>>(H, st, p, k0, k1, Y, lam, lam_idx,
+                                                            ghat, sep, smax, smin, scratch, 0);
+    } else if (pl == 1) {
+      const size_t dyn = proj_a_doubles(k1) * sizeof(double);
+      k_projected<true, false, false><<<nblk, kPT, dyn, s>>>(H, st, p, k0, k1, Y, lam, lam_idx,
+                                                             ghat, sep, smax, smin, scratch, 0);
+    } else {
+      k_projected<false, false, true><<<nblk, kPT, room, s>>>(H, st, p, k0, k1, Y, lam, lam_idx,
+                                                              ghat, sep, smax, smin, scratch,
+                                                              room);
+    }
     k0 = k1 + 1;
   }
 }

@@ -629,3 +629,40 @@ def test_host_array_solve_matches_device_solve(lib, ctx, prec):
         assert ei.value.status == lib.LSLU_ENONFINITE
     finally:
         lib.lslu_op_destroy(op)
+
+
+@pytest.mark.parametrize("reg", ["wgcv", "fixed", "none"])
+def test_projected_problems_up_to_k200(lib, ctx, reg):
+    """The projected problems at large k, where the (k+1) x k working matrix
+    no longer fits in LDS and its first columns live in global scratch
+    (k > 134; at k = 200 most of them): lambda_k, Ghat(k) and y_k of the
+    library against the oracle's SVD solution of eq. TSP for the library's
+    own H and beta (Section 3.2.1), at every k from 120 to 200."""
+    from oracle.projected import ghat_value, projected_svd, select_lambda, tikhonov_coeffs
+    prob = random_dense(230, 215, seed=41, nu=0.01)
+    K = 200
+    grid = lambda_grid()
+    G = gpu_solve(lib, ctx, prob, "fp64", K, reg, lam=0.05, grid=grid, grid_relative=True,
+                  bases=False)
+    assert G["k_done"] == K
+    rp = RegParam(reg, lam=0.05, grid=grid, grid_relative=True)
+    worst_y = worst_g = 0.0
+    for k in range(120, K + 1):
+        s, c, V = projected_svd(G["H"][:k + 1, :k])
+        lam, li, sep, _ = select_lambda(rp, k, prob.m, G["beta"], s, c, V, None, None)
+        if sep > TAU["fp64"]:
+            assert G["lambda_idx"][k - 1] == li, k
+        y = tikhonov_coeffs(G["beta"], s, c, V, G["lambda_k"][k - 1])
+        worst_y = max(worst_y, rel(G["Y"][:k, k - 1], y))
+        gh = ghat_value(k, prob.n, prob.m, G["beta"], s, c, G["lambda_k"][k - 1])
+        worst_g = max(worst_g, abs(G["ghat"][k - 1] - gh) / abs(gh))
+        if reg == "wgcv":
+            assert np.isclose(G["lambda_k"][k - 1], s[0] * grid[G["lambda_idx"][k - 1]],
+                              rtol=1e-12)
+    kap = s[0] / s[-1]
+    print(f"[projected k<=200 {reg}] max y error {worst_y:.2e}, max Ghat error {worst_g:.2e}, "
+          f"kappa(H) at k=200 {kap:.1e}")
+    # y_k of a Tikhonov problem is as accurate as its conditioning allows:
+    # kappa(H) u for lambda = 0, less with damping
+    assert worst_y <= 1e-13 * max(kap, 1.0) and worst_y <= 1e-6
+    assert worst_g <= 1e-8
