@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LSLU_ABI_VERSION 12
+#define LSLU_ABI_VERSION 13
 
 typedef enum lslu_status {
   LSLU_OK = 0,
@@ -239,7 +239,24 @@ typedef enum lslu_flag {
    * rule.  0 where lambda_k = 0 (the derivative of the projected solution
    * vanishes there).  FP64 throughout, from the Gram matrix of
    * [L_k, x_true - x_0]. */
-  LSLU_FLAG_GRAD_LAMBDA = 8
+  LSLU_FLAG_GRAD_LAMBDA = 8,
+  /* Form only the returned iterate, x_out = x_0 + L_k y_k at the k the
+   * stopping rule selects (k_done, or k_stop with early_stop), instead of
+   * every x_k of Algorithm 5 followed by a copy of one of them: one pass over
+   * k columns of L instead of the product L Y.  Every other output is the
+   * same; x_out agrees with the all-iterates solve to the rounding of the
+   * order of the sum over j.  X_dev must be NULL (LSLU_EINVAL otherwise). */
+  LSLU_FLAG_FINAL_ONLY = 16,
+  /* Also return, for every pivot search, its separation (a1 - a2) / a1,
+   * where a1 and a2 are the largest and second largest magnitudes among the
+   * candidates (1 for a single candidate), in lslu_result.sep_t and sep_g:
+   * how far the choice is from a tie (Algorithm 4's infinity-norm pivot; for
+   * sampled searches, over the sampled candidates unless the search fell
+   * back to the full one).  Evaluated after the recurrence, from the
+   * normalised vector (a2/a1 = largest non-pivot |entry| of d_k or l_k), so
+   * it carries the rounding of the stored basis: about 1e-16 in FP64, 6e-8
+   * in the other modes.  One extra pass over both bases. */
+  LSLU_FLAG_PIVOT_SEP = 32
 } lslu_flag;
 
 typedef struct lslu_result {
@@ -273,6 +290,12 @@ typedef struct lslu_result {
   /* maxiter: with LSLU_FLAG_GRAD_LAMBDA, d/dlambda ||x_k(lambda) - x_true||^2
    * at lambda = lambda_k (NULL: not copied) */
   double* dloss_dlambda;
+  /* With LSLU_FLAG_PIVOT_SEP: the separation of each pivot search (see the
+   * flag); sep_t: maxiter+1 entries (search for t(1), t(2), ...), sep_g:
+   * maxiter (g(1), ...).  NaN for a search that was not made (breakdown,
+   * or the flag not set).  NULL: not copied. */
+  double* sep_t;
+  double* sep_g;
 } lslu_result;
 
 /* Run Hybrid LSLU (LSLU with LSLU_REG_NONE) for opts->maxiter iterations.

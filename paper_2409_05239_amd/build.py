@@ -38,6 +38,15 @@ COMMON = [
 ]
 
 
+# Per-file additions.  The iterate assembly keeps its FP64 matrix-core
+# accumulators in ordinary VGPRs: with the accumulator-register form the
+# compiler copies every accumulator tile in and out around each product of
+# its (uniformly) predicated tiles.
+EXTRA = {
+    "assemble.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def _sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
                   if f.endswith(".hip"))
@@ -45,7 +54,7 @@ def _sources():
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
+    cmd = [HIPCC, *COMMON, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{res.stdout}\n{res.stderr}")

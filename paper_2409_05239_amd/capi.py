@@ -74,6 +74,8 @@ LSLU_FLAG_EAGER = 1
 LSLU_FLAG_TIMING = 2
 LSLU_FLAG_ASYNC = 4
 LSLU_FLAG_GRAD_LAMBDA = 8
+LSLU_FLAG_FINAL_ONLY = 16
+LSLU_FLAG_PIVOT_SEP = 32
 
 
 class lslu_result(ctypes.Structure):
@@ -104,6 +106,8 @@ class lslu_result(ctypes.Structure):
         ("t_projected_ms", c_double),
         ("t_assemble_ms", c_double),
         ("dloss_dlambda", POINTER(c_double)),
+        ("sep_t", POINTER(c_double)),
+        ("sep_g", POINTER(c_double)),
     ]
 
 
@@ -352,7 +356,7 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
                stop_tol=0.0, early_stop=False, X=None, x_out=None,
                replay_piv_t=None, replay_piv_g=None, replay_lambda_idx=None,
                eager=False, timing=False, pivot_sample=None, asynchronous=False,
-               grad_lambda=False, static=False):
+               grad_lambda=False, static=False, final_only=False, pivot_sep=False):
     """Run the solver.  ``b``, ``x0``, ``X``, ``x_out`` are torch device
     tensors in the working precision (``x_out`` is allocated when None).
     ``pivot_sample = (rows, s)`` selects sampled pivots: ``rows`` is the
@@ -363,6 +367,9 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
     ``asynchronous=True`` enqueues the solve and returns a ``Pending``;
     ``lslu_wait(ctx, pending)`` completes it and returns the same triple.
     ``grad_lambda=True`` (needs ``x_true``) adds ``info["dloss_dlambda"]``.
+    ``final_only=True`` forms only the returned iterate (no ``X``).
+    ``pivot_sep=True`` adds ``info["sep_t"]`` and ``info["sep_g"]``, the
+    separation of every pivot search.
     With ``b`` (and ``x0``) given as NumPy arrays the call goes through
     ``lslu_solve_host`` (host arrays in FP64, synchronous) and ``x_out`` is a
     NumPy array.
@@ -385,6 +392,8 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
                  else torch.empty(n, dtype=_torch_dtype(prec), device=b.device))
     elif not host_io:
         _vec(x_out, n, prec, "x_out", dev)
+    if final_only and X is not None:
+        raise ValueError("final_only forms no iterates for X")
     _opt_vec(X, n * K, prec, "X", dev, at_least=True)
     _opt_vec(x_true, n, prec, "x_true", dev)
     o = lslu_opts()
@@ -405,7 +414,9 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
     o.X_dev = _dptr(X)
     o.flags = ((LSLU_FLAG_EAGER if eager else 0) | (LSLU_FLAG_TIMING if timing else 0)
                | (LSLU_FLAG_ASYNC if asynchronous else 0)
-               | (LSLU_FLAG_GRAD_LAMBDA if grad_lambda else 0))
+               | (LSLU_FLAG_GRAD_LAMBDA if grad_lambda else 0)
+               | (LSLU_FLAG_FINAL_ONLY if final_only else 0)
+               | (LSLU_FLAG_PIVOT_SEP if pivot_sep else 0))
     # the library reads K + 1, K and K entries of the replay arrays
     for name, arr, need in (("replay_piv_t", replay_piv_t, K + 1),
                             ("replay_piv_g", replay_piv_g, K),
@@ -431,6 +442,9 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
         sep_lambda=np.zeros(K), sigma_max=np.zeros(K), sigma_min=np.zeros(K))
     if grad_lambda:
         host["dloss_dlambda"] = np.zeros(K)
+    if pivot_sep:
+        host["sep_t"] = np.zeros(K + 1)
+        host["sep_g"] = np.zeros(K)
     for name, arr in host.items():
         ct = c_int32 if arr.dtype == np.int32 else c_double
         setattr(r, name, arr.ctypes.data_as(POINTER(ct)))
@@ -543,8 +557,9 @@ def _info(st, r, host, timing):
                 lambda_k=host["lambda_k"], lambda_idx=host["lambda_idx"],
                 ghat=host["ghat"], sep_lambda=host["sep_lambda"],
                 sigma_max=host["sigma_max"], sigma_min=host["sigma_min"])
-    if "dloss_dlambda" in host:
-        info["dloss_dlambda"] = host["dloss_dlambda"]
+    for name in ("dloss_dlambda", "sep_t", "sep_g"):
+        if name in host:
+            info[name] = host[name]
     if timing:
         info["timing"] = dict(t_recurrence_ms=r.t_recurrence_ms,
                               n_recurrence_launches=r.n_recurrence_launches,

@@ -279,7 +279,15 @@ void recurrence_init_attributes(size_t lds_bytes);
 // Basis recurrence helpers (basis.hip).
 template <typename T>
 void launch_fill(T* p, T v, int64_t count, hipStream_t s);
-void launch_state_reset(DevState* st, hipStream_t s);
+void launch_state_reset(DevState* st, double* nan_fill, int nan_count, hipStream_t s);
+// Pivot separations of the 2K+1 searches of a finished recurrence (basis.hip);
+// mx: 2K+1 words of scratch; samp: the sampled candidate rows or NULL.
+template <typename T>
+void launch_pivot_sep(const T* L, int64_t rsL, int64_t csL, int64_t n, const T* D,
+                      int64_t rsD, int64_t csD, int64_t m, const int* piv_t,
+                      const int* piv_g, const int* samp, int sample_s, int K,
+                      const DevState* st, unsigned long long* mx, double* sep_t,
+                      double* sep_g, hipStream_t s);
 template <typename T>
 void launch_sub(const T* a, const T* b, T* out, int64_t len, hipStream_t s);
 // Pivot candidates of v (no mask); returns the number of parts.
@@ -338,6 +346,11 @@ template <typename T>
 void launch_assemble(const T* L, int64_t rs, int64_t cs, int64_t n,
                      const double* Y, int K, const T* x0, T* X,
                      const DevState* st, hipStream_t s);
+// Only x_{k_sel} (k_sel[1], set by launch_stopping): x_out = x_0 + L y_{k_sel}.
+template <typename T>
+void launch_assemble_final(const T* L, int64_t rs, int64_t cs, int64_t n,
+                           const double* Y, int K, const T* x0, T* x_out,
+                           const int* k_sel, hipStream_t s);
 template <typename T>
 void launch_select_x(const T* X, int64_t n, const T* x0, T* x_out,
                      const DevState* st, const int* k_sel, hipStream_t s);

@@ -44,7 +44,8 @@ struct Layout {
   size_t res_bytes = 0;
   double *H = nullptr, *W = nullptr, *Y = nullptr, *lam = nullptr,
          *ghat = nullptr, *sep = nullptr, *smax = nullptr, *smin = nullptr,
-         *dldl = nullptr;
+         *dldl = nullptr, *psep = nullptr;  // psep: sep_t (K+1), then sep_g (K)
+  unsigned long long* psep_mx = nullptr;
   int *piv_t = nullptr, *piv_g = nullptr, *own_t = nullptr, *own_g = nullptr,
       *lam_idx = nullptr, *sel = nullptr;
   DevState* st = nullptr;
@@ -97,6 +98,7 @@ size_t carve(unsigned char* base, int64_t m, int64_t n, int K, size_t esz,
   l.mask_t = take(m);
   l.mask_g = take(n);
   l.parts = reinterpret_cast<ArgPart*>(take(sizeof(ArgPart) * 2 * kMaxParts));
+  l.psep_mx = reinterpret_cast<unsigned long long*>(take(sizeof(uint64_t) * (2 * K + 1)));
   // result block: doubles, then ints, then the state
   off = align_up(off, 256);
   const size_t res_start = off;
@@ -109,6 +111,7 @@ size_t carve(unsigned char* base, int64_t m, int64_t n, int K, size_t esz,
   l.smax = reinterpret_cast<double*>(take(sizeof(double) * K));
   l.smin = reinterpret_cast<double*>(take(sizeof(double) * K));
   l.dldl = reinterpret_cast<double*>(take(sizeof(double) * K));
+  l.psep = reinterpret_cast<double*>(take(sizeof(double) * (2 * K + 1)));
   l.piv_t = reinterpret_cast<int*>(take(sizeof(int) * (K + 1)));
   l.piv_g = reinterpret_cast<int*>(take(sizeof(int) * K));
   l.own_t = reinterpret_cast<int*>(take(sizeof(int) * (K + 1)));
@@ -407,7 +410,7 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
   const size_t lds = c->lds_max;
 
   if (part != 2) {
-  launch_state_reset(st, s);
+  launch_state_reset(st, l.psep, 2 * K + 1, s);
   launch_fill<unsigned char>(l.mask_t, 0, m, s);
   launch_fill<unsigned char>(l.mask_g, 0, n, s);
   launch_fill<int>(l.piv_t, -1, K + 1, s);
@@ -559,6 +562,11 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
   }
   if (part == 1) return;
 
+  if (o->flags & LSLU_FLAG_PIVOT_SEP)
+    launch_pivot_sep<T>(Lb, bs.rsL, bs.csL, n, Db, bs.rsD, bs.csD, m, l.piv_t, l.piv_g,
+                        o->sample_rows ? l.samp : nullptr, o->sample_s, K, st, l.psep_mx,
+                        l.psep, l.psep + (K + 1), s);
+
   ProjParams pp{};
   pp.K = K;
   pp.m = static_cast<int>(std::min<int64_t>(m, INT32_MAX));
@@ -593,8 +601,12 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
   pe->mark(2, s);
   const double tol = o->stop_tol > 0.0 ? o->stop_tol : 1e-6;
   launch_stopping(l.ghat, st, tol, o->early_stop ? 1 : 0, l.sel, s);
-  launch_assemble<T>(Lb, bs.rsL, bs.csL, n, l.Y, K, x0, X, st, s);
-  launch_select_x<T>(X, n, x0, x_out, st, l.sel, s);
+  if (o->flags & LSLU_FLAG_FINAL_ONLY) {
+    launch_assemble_final<T>(Lb, bs.rsL, bs.csL, n, l.Y, K, x0, x_out, l.sel, s);
+  } else {
+    launch_assemble<T>(Lb, bs.rsL, bs.csL, n, l.Y, K, x0, X, st, s);
+    launch_select_x<T>(X, n, x0, x_out, st, l.sel, s);
+  }
   pe->mark(3, s);
 }
 
@@ -610,6 +622,8 @@ lslu_status validate_opts(lslu_ctx* c, const lslu_op* op, const lslu_opts* o) {
     return fail(c, LSLU_EINVAL, "LSLU_REG_OPTIMAL needs x_true_dev");
   if ((o->flags & LSLU_FLAG_GRAD_LAMBDA) && !o->x_true_dev)
     return fail(c, LSLU_EINVAL, "LSLU_FLAG_GRAD_LAMBDA needs x_true_dev");
+  if ((o->flags & LSLU_FLAG_FINAL_ONLY) && o->X_dev)
+    return fail(c, LSLU_EINVAL, "LSLU_FLAG_FINAL_ONLY forms no iterates for X_dev");
   if (o->reg == LSLU_REG_FIXED && !(std::isfinite(o->lambda) && o->lambda >= 0.0))
     return fail(c, LSLU_EINVAL, "lambda must be finite and >= 0");
   if (o->reg == LSLU_REG_WGCV || o->reg == LSLU_REG_GCV || o->reg == LSLU_REG_OPTIMAL) {
@@ -1195,6 +1209,8 @@ static lslu_status complete_solve(lslu_ctx* c, int K, lslu_result* res,
       copy_out(res->sigma_max, reinterpret_cast<const double*>(hp(l.smax)), K);
       copy_out(res->sigma_min, reinterpret_cast<const double*>(hp(l.smin)), K);
       copy_out(res->dloss_dlambda, reinterpret_cast<const double*>(hp(l.dldl)), K);
+      copy_out(res->sep_t, reinterpret_cast<const double*>(hp(l.psep)), K + 1);
+      copy_out(res->sep_g, reinterpret_cast<const double*>(hp(l.psep)) + (K + 1), K);
       res->t_recurrence_ms = t_rec;
       res->n_recurrence_launches = pe.on ? pe.launches : 0;
       res->t_projected_ms = t_proj;
@@ -1314,7 +1330,9 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
           (double)o->grid_relative, o->omega, o->stop_tol, (double)o->early_stop,
           (double)rt, (double)rg, (double)rl, (double)(uintptr_t)o->x_true_dev,
           (double)(o->sample_rows != nullptr), (double)o->sample_s, (double)o->sample_len,
-          (double)(o->flags & LSLU_FLAG_GRAD_LAMBDA)};
+          (double)(o->flags & LSLU_FLAG_GRAD_LAMBDA),
+          (double)(o->flags & LSLU_FLAG_FINAL_ONLY),
+          (double)(o->flags & LSLU_FLAG_PIVOT_SEP)};
       hipGraphExec_t exec = nullptr;
       for (auto& g : c->graphs)
         if (g.key == key) exec = g.exec;
@@ -1462,7 +1480,9 @@ lslu_status lslu_solve_static(lslu_ctx* c, const lslu_op* op, const void* b,
           get(res->lambda_k, lay.lam, dK), get(res->lambda_idx, lay.lam_idx, iK),
           get(res->ghat, lay.ghat, dK), get(res->sep_lambda, lay.sep, dK),
           get(res->sigma_max, lay.smax, dK), get(res->sigma_min, lay.smin, dK),
-          get(res->dloss_dlambda, lay.dldl, dK)};
+          get(res->dloss_dlambda, lay.dldl, dK),
+          get(res->sep_t, lay.psep, dK + sizeof(double)),
+          get(res->sep_g, lay.psep + (K + 1), dK)};
       for (lslu_status g : gs)
         if (g != LSLU_OK) return g;
     }

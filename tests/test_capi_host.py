@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(capi):
 
 
 def test_abi_version_and_status_names(capi):
-    assert capi.lslu_abi_version() == 12
+    assert capi.lslu_abi_version() == 13
     assert capi.status_name(0) == "LSLU_OK"
     assert capi.status_name(2) == "LSLU_BREAKDOWN_U"
     assert capi.status_name(-4) == "LSLU_ENONFINITE"
