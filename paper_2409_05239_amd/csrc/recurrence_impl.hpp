@@ -231,44 +231,57 @@ __device__ __attribute__((always_inline)) inline void trisolve_wave(double* g, i
 
 // Sampled pivot search (the variant of Section 2.2): among the first
 // sample_s listed rows that are not earlier pivots, the entry of largest
-// magnitude (ties: smallest row), as a signed key; 0 when all are 0.  The
-// rank of a listed row among the eligible ones comes from a block-wide
-// ballot prefix count in list order.
+// magnitude (ties: smallest row), as a signed key; 0 when all are 0.  One
+// wavefront: every listed row, its eligibility and its value are loaded
+// first (kMaxSampleLen / 64 per lane), then the rank of each listed row among
+// the eligible ones is a ballot prefix count in list order.  The result is
+// returned to every thread of the block (one barrier).
 template <typename T>
 __device__ inline void sampled_search(const HalfArgs<T>& a, double& key, int& idx) {
-  __shared__ int wcount[kWaves];
+  __shared__ double s_key;
+  __shared__ int s_idx;
+  static_assert(kMaxSampleLen % kWave == 0, "sample lists fill whole wavefront rows");
+  constexpr int kPer = kMaxSampleLen / kWave;
   const PivotJob& job = a.job;
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-  key = 0.0;
-  idx = INT_MAX;
-  int base = 0;
-  for (int c0 = 0; c0 < job.sample_len; c0 += kThreads) {
-    const int li = c0 + tid;
-    const int row = li < job.sample_len ? job.sample[li] : -1;
-    bool elig = false;
-    double v = 0.0;
-    if (row >= 0) {
-      elig = job.mask[row] == 0;
-      v = static_cast<double>(a.up[row]);
-    }
-    const uint64_t bal = __ballot(elig);
-    const int below = __popcll(bal & ((1ull << lane) - 1ull));
-    if (lane == 0) wcount[w] = __popcll(bal);
-    __syncthreads();
-    int before = base, total = 0;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1);
+  if (tid < kWave) {
+    int row[kPer];
 #pragma unroll
-    for (int i = 0; i < kWaves; ++i) {
-      if (i < w) before += wcount[i];
-      total += wcount[i];
+    for (int u = 0; u < kPer; ++u) {
+      const int li = u * kWave + lane;
+      row[u] = li < job.sample_len ? job.sample[li] : -1;
     }
-    __syncthreads();
-    if (elig && before + below < job.sample_s && better(v, row, key, idx)) {
-      key = v;
-      idx = row;
+    unsigned char mk[kPer];
+    T v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int r = row[u] >= 0 ? row[u] : 0;
+      mk[u] = job.mask[r];
+      v[u] = a.up[r];
     }
-    base += total;
+    double bk = 0.0;
+    int bi = INT_MAX, base = 0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const bool elig = row[u] >= 0 && mk[u] == 0;
+      const uint64_t bal = __ballot(elig);
+      const int below = __popcll(bal & ((1ull << lane) - 1ull));
+      const double vv = static_cast<double>(v[u]);
+      if (elig && base + below < job.sample_s && better(vv, row[u], bk, bi)) {
+        bk = vv;
+        bi = row[u];
+      }
+      base += __popcll(bal);
+    }
+    wave_argmax(bk, bi);
+    if (lane == 0) {
+      s_key = bk;
+      s_idx = bi;
+    }
   }
-  block_argmax<kThreads>(key, idx);
+  __syncthreads();
+  key = s_key;
+  idx = s_idx;
 }
 
 // ------------------------------------------------------------ block 0 -----
@@ -289,37 +302,36 @@ __device__ void lead(const HalfArgs<T>& a, DevState* st, unsigned char* lds) {
   }
   double key = 0.0;
   int idx = INT_MAX;
-  constexpr int kHalf = kPartsPerThread / 2;
+  const PivotJob& job = a.job;
+  // A sampled search decides alone unless its entries are all 0; then (and
+  // always without a sample) the block candidates of the previous launch are
+  // reduced: the full search.
+  if (job.sample) sampled_search(a, key, idx);
+  if (!(fabs(key) > 0.0)) {
+    key = 0.0;
+    idx = INT_MAX;
+    constexpr int kHalf = kPartsPerThread / 2;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    int4 raw[kHalf];
+    for (int h = 0; h < 2; ++h) {
+      int4 raw[kHalf];
 #pragma unroll
-    for (int u = 0; u < kHalf; ++u) {
-      const int i = tid + (h * kHalf + u) * kThreads;
-      raw[u] = (i < a.nparts_in) ? reinterpret_cast<const int4*>(a.parts_in)[i]
-                                 : make_int4(0, 0, INT_MAX, 0);
-    }
+      for (int u = 0; u < kHalf; ++u) {
+        const int i = tid + (h * kHalf + u) * kThreads;
+        raw[u] = (i < a.nparts_in) ? reinterpret_cast<const int4*>(a.parts_in)[i]
+                                   : make_int4(0, 0, INT_MAX, 0);
+      }
 #pragma unroll
-    for (int u = 0; u < kHalf; ++u) {
-      const double k2 = __builtin_bit_cast(
-          double, (static_cast<uint64_t>(static_cast<uint32_t>(raw[u].y)) << 32) |
-                      static_cast<uint32_t>(raw[u].x));
-      if (better(k2, raw[u].z, key, idx)) {
-        key = k2;
-        idx = raw[u].z;
+      for (int u = 0; u < kHalf; ++u) {
+        const double k2 = __builtin_bit_cast(
+            double, (static_cast<uint64_t>(static_cast<uint32_t>(raw[u].y)) << 32) |
+                        static_cast<uint32_t>(raw[u].x));
+        if (better(k2, raw[u].z, key, idx)) {
+          key = k2;
+          idx = raw[u].z;
+        }
       }
     }
-  }
-  block_argmax<kThreads>(key, idx);
-  const PivotJob& job = a.job;
-  if (job.sample) {  // a sample whose entries are all 0 keeps the full search
-    double skey;
-    int sidx;
-    sampled_search(a, skey, sidx);
-    if (fabs(skey) > 0.0) {
-      key = skey;
-      idx = sidx;
-    }
+    block_argmax<kThreads>(key, idx);
   }
   const int own = (job.eligible && fabs(key) > 0.0) ? idx : -1;
   const int pick = job.replay ? (job.eligible ? job.replay[job.piv_pos] : -1) : own;
