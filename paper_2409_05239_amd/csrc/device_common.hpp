@@ -55,6 +55,15 @@ struct ValTraits<Half> {
   }
 };
 
+// The nearest binary16 value of a float (ties to even).  The float is pinned
+// in a register first: the compiler folds a float -> half conversion of a
+// value just rounded from double into one rounding from the double, which
+// differs at the float values that lie halfway between binary16 values.
+__device__ inline float fp16_round(float f) {
+  __asm__("" : "+v"(f));
+  return static_cast<float>(static_cast<_Float16>(f));
+}
+
 // Input rounding of the operator modes (kIn: kInNone, kInBf16, kInFp16, kInFp8):
 // in the 16-bit operator modes a product's input entries are rounded to the
 // operator's format, so every term is a product of two 16-bit numbers, exact
@@ -66,7 +75,7 @@ __device__ inline auto in_val(T v) {
   else if constexpr (kIn == kInFp8)
     return fp8_round(static_cast<float>(v));
   else if constexpr (kIn == kInFp16)
-    return static_cast<float>(static_cast<_Float16>(static_cast<float>(v)));
+    return fp16_round(static_cast<float>(v));
   else
     return v;
 }
@@ -225,6 +234,7 @@ template <typename V, typename AccT, int kIn>
 struct DenseRows {
   using Acc = AccT;
   using Val = V;
+  static constexpr int kInMode = kIn;
   const V* a;
   int64_t cols;
   template <int G, typename XF>
@@ -605,6 +615,72 @@ __host__ __device__ constexpr size_t psf_lds_bytes(int pw) {
   } else {
     return sizeof(Acc) * (psf_th<R>() + PH - 1) * (kPsfTW + pw - 1);
   }
+}
+
+// ------------------------------------------- dense rows on the matrix cores --
+// The 16-, 8-bit dense operators (stored values are the format's codes) on
+// the matrix cores: 16 rows r16 .. r16+15 of the row-major m x n matrix times
+// an input vector held as codes in LDS.  The rows are the A operand (lane l:
+// row l % 16, the kPer codes from column kK t + kPer (l / 16), one 8-byte
+// load); the input is column 0 of the B operand (lanes l % 16 == 0), the
+// other 15 columns zero, so lanes with l % 16 == 0 get rows 4 (l / 16) + r of
+// the product in element r.  A wave sums the column blocks t = t0, t0 + dt,
+// ... in increasing t.  Only 1/16 of each instruction's columns is used: the
+// product of one vector has no reuse, and the matrix cores take the codes
+// as they are stored (no conversion per element).  Needs n a multiple of kK
+// (rows then start at 8-byte boundaries); rows past m are read clamped and
+// their results are not used.
+template <typename RO>
+struct DenseMfma : std::false_type {};
+template <int kIn>
+struct DenseMfmaVal;
+template <>
+struct DenseMfmaVal<kInBf16> { using V = uint16_t; };
+template <>
+struct DenseMfmaVal<kInFp16> { using V = Half; };
+template <>
+struct DenseMfmaVal<kInFp8> { using V = Fp8; };
+template <typename V, int kIn>
+struct DenseMfma<DenseRows<V, float, kIn>>
+    : std::integral_constant<bool, psf_on_mfma<kIn>() &&
+                                       std::is_same_v<V, typename DenseMfmaVal<kIn>::V>> {};
+
+// Largest row length the matrix-core dense product takes (its input codes
+// sit in LDS).
+constexpr int kDenseMfmaMaxCols = 4096;
+
+template <int kIn>
+__host__ __device__ constexpr bool dense_mfma_fits(int64_t n) {
+  return n > 0 && n <= kDenseMfmaMaxCols && n % PsfMfma<kIn>::kK == 0;
+}
+
+// Codes of the input x(c) (rounded to the format) for c < n, by the block's
+// threads; the caller synchronises before use.
+template <int kIn, typename XF>
+__device__ inline void dense_mfma_stage_x(XF xf, int64_t n, typename PsfMfma<kIn>::E* xs,
+                                          int nthreads) {
+  for (int64_t c = threadIdx.x; c < n; c += nthreads)
+    xs[c] = PsfMfma<kIn>::enc(static_cast<float>(in_val<kIn>(xf(c))));
+}
+
+template <int kIn>
+__device__ inline mfma_f4 dense_mfma_rows16(const void* a, int64_t m, int64_t n, int64_t r16,
+                                            const typename PsfMfma<kIn>::E* xs, int t0, int dt) {
+  using M = PsfMfma<kIn>;
+  using E = typename M::E;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t row = r16 + (lane & 15) < m ? r16 + (lane & 15) : m - 1;
+  const E* arow = static_cast<const E*>(a) + row * n + M::kPer * (lane >> 4);
+  const E* xl = xs + M::kPer * (lane >> 4);
+  const bool bcol = (lane & 15) == 0;
+  mfma_f4 acc = {0.f, 0.f, 0.f, 0.f};
+  const int nt = static_cast<int>(n / M::kK);
+  for (int t = t0; t < nt; t += dt) {
+    const uint64_t aw = *reinterpret_cast<const uint64_t*>(arow + (int64_t)M::kK * t);
+    const uint64_t bw = bcol ? *reinterpret_cast<const uint64_t*>(xl + M::kK * t) : 0ull;
+    acc = M::mma(aw, bw, acc);
+  }
+  return acc;
 }
 
 // Copies the padded PSF rows into LDS (all threads of the block; every load

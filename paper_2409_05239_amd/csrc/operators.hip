@@ -11,8 +11,9 @@
 //   BF16OP: V = bfloat16, T = float,  Acc = float, input entries rounded to
 //           bfloat16 before the product (bf16 x bf16 is exact in float)
 //   FP16OP, FP8OP: as BF16OP with IEEE binary16, 8-bit E4M3 values
-// In the last three modes the PSF product runs on the matrix cores
-// (psf_tile_mfma in device_common.hpp).
+// In the last three modes the PSF product and the dense product (row
+// length a multiple of 16 or 32, up to 4096) run on the matrix cores
+// (psf_tile_mfma, dense_mfma_rows16 in device_common.hpp).
 //
 // Dense and CSR products are row-parallel (a group of 16 lanes per output
 // row, a fixed lane-stride partial sum and a fixed xor-butterfly reduction),
@@ -42,6 +43,29 @@ __global__ __launch_bounds__(kRowBlock) void k_rows(
   typename RowOp::Acc acc = op.template partial<kRowLanes>(r, sub, xf);
   acc = group_sum<kRowLanes>(acc);
   if (sub == 0) y[r] = static_cast<T>(acc);
+}
+
+// The 16- and 8-bit dense products on the matrix cores (dense_mfma_rows16):
+// the input's codes in LDS, a 16-row group per wavefront.
+template <typename T, int kIn>
+__global__ __launch_bounds__(kRowBlock) void k_rows_dense_mfma(
+    const void* __restrict__ a, int64_t rows, int64_t n, const T* __restrict__ x,
+    T* __restrict__ y, const int* stop) {
+  if (stop && *stop) return;
+  __shared__ typename PsfMfma<kIn>::E xs[kDenseMfmaMaxCols];
+  dense_mfma_stage_x<kIn>([x](int64_t c) { return x[c]; }, n, xs, kRowBlock);
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t r16 = ((int64_t)blockIdx.x * (kRowBlock / kWave) + threadIdx.x / kWave) * 16;
+  if (r16 >= rows) return;
+  const mfma_f4 acc = dense_mfma_rows16<kIn>(a, rows, n, r16, xs, 0, 1);
+  if ((lane & 15) == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r16 + 4 * (lane >> 4) + r;
+      if (row < rows) y[row] = static_cast<T>(acc[r]);
+    }
+  }
 }
 
 template <typename T, typename Acc, int PH, int kIn, int R>
@@ -114,6 +138,13 @@ void apply_t(const DeviceOp& op, int tr, const T* x, T* y, const int* stop,
     const int grid = static_cast<int>((rows + kRowsPerBlock - 1) / kRowsPerBlock);
     if (op.kind == 0) {
       DenseRows<V, Acc, kB> ro{static_cast<const V*>(tr ? op.AT : op.A), tr ? op.m : op.n};
+      if constexpr (DenseMfma<decltype(ro)>::value) {
+        if (dense_mfma_fits<kB>(ro.cols)) {
+          const int g16 = static_cast<int>((rows + 63) / 64);
+          k_rows_dense_mfma<T, kB><<<g16, kRowBlock, 0, s>>>(ro.a, rows, ro.cols, x, y, stop);
+          return;
+        }
+      }
       k_rows<<<grid, kRowBlock, 0, s>>>(ro, rows, x, y, stop);
     } else if (op.kind == 1) {
       CsrRows<V, Acc, kB> ro{tr ? op.rpT : op.rp, tr ? op.ciT : op.ci,

@@ -595,8 +595,13 @@ __device__ void consume_rows(const HalfArgs<T>& a, const RowOp& op, DevState* st
   const int64_t stride = (int64_t)ncons * kRows;
   const int64_t r0 = (int64_t)cb * kRows + rl;
   const bool has0 = r0 < a.rows;
+  // 16-, 8-bit dense rows on the matrix cores: the block's 16 rows of each
+  // pass as one row group (its 4 wavefronts take every 4th column block, the
+  // 4 partial sums added in wavefront order)
+  bool mf = false;
+  if constexpr (DenseMfma<RowOp>::value) mf = G == 16 && dense_mfma_fits<RowOp::kInMode>(op.cols);
   RowStage<typename RowOp::Val, T, kRowStage> sg;
-  if (has0) op.template stage<G, kRowStage>(r0, sub, a.up, sg);
+  if (has0 && !mf) op.template stage<G, kRowStage>(r0, sub, a.up, sg);
   NormStage<T> ns;
   normalise_stage(a, cb, ncons, ns);
   int pick;
@@ -606,14 +611,48 @@ __device__ void consume_rows(const HalfArgs<T>& a, const RowOp& op, DevState* st
   normalise_share(a, cb, ncons, pick, nz, ns);
   auto xf = [&](int64_t c) -> T { return nz(a.up[c]); };
   T q_first = T(0);
-  if (has0) {
-    Acc acc = op.template finish<G, kRowStage>(sg, nz, xf);
-    q_first = static_cast<T>(group_sum<G>(acc));
-  }
-  for (int64_t r = r0 + stride; r < a.rows; r += stride) {
-    Acc acc = op.template partial<G>(r, sub, xf);
-    acc = group_sum<G>(acc);
-    if (sub == 0) a.out[r] = static_cast<T>(acc);
+  if (mf) {
+    if constexpr (DenseMfma<RowOp>::value) {
+      constexpr int kB = RowOp::kInMode;
+      static_assert(kRows == 16, "one row group per pass");
+      __shared__ typename PsfMfma<kB>::E xs[kDenseMfmaMaxCols];
+      __shared__ float part[kWaves][16];
+      __shared__ float first[16];
+      dense_mfma_stage_x<kB>(xf, op.cols, xs, kThreads);
+      __syncthreads();
+      const int w = tid / kWave, lane = tid & (kWave - 1);
+      for (int64_t rb = (int64_t)cb * kRows; rb < a.rows; rb += stride) {
+        const mfma_f4 acc = dense_mfma_rows16<kB>(op.a, a.rows, op.cols, rb, xs, w, kWaves);
+        if ((lane & 15) == 0) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) part[w][4 * (lane >> 4) + r] = acc[r];
+        }
+        __syncthreads();
+        if (tid < 16) {
+          float v = part[0][tid];
+#pragma unroll
+          for (int i = 1; i < kWaves; ++i) v += part[i][tid];
+          if (rb + tid < a.rows) {
+            if (rb == (int64_t)cb * kRows)
+              first[tid] = v;
+            else
+              a.out[rb + tid] = static_cast<T>(v);
+          }
+        }
+        __syncthreads();
+      }
+      if (has0) q_first = static_cast<T>(first[rl]);
+    }
+  } else {
+    if (has0) {
+      Acc acc = op.template finish<G, kRowStage>(sg, nz, xf);
+      q_first = static_cast<T>(group_sum<G>(acc));
+    }
+    for (int64_t r = r0 + stride; r < a.rows; r += stride) {
+      Acc acc = op.template partial<G>(r, sub, xf);
+      acc = group_sum<G>(acc);
+      if (sub == 0) a.out[r] = static_cast<T>(acc);
+    }
   }
   if (a.rows == 0) return;
   // Elimination inputs of the first row, loaded before the coefficients.

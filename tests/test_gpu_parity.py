@@ -111,10 +111,12 @@ def _bound(Aabs_x, prec, nterms):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16op", "fp16op", "fp8op"])
-@pytest.mark.parametrize("which", ["dense", "csr", "psf31", "psf_nonsym", "psf_rand31",
-                                   "psf_rand9x31", "psf_rand31x3"])
+@pytest.mark.parametrize("which", ["dense", "dense96x64", "dense90x64", "csr", "psf31",
+                                   "psf_nonsym", "psf_rand31", "psf_rand9x31", "psf_rand31x3"])
 def test_operator_products(lib, ctx, which, prec):
     """Every product within (4u + n_terms u_sum)|A||x| of the FP64 product.
+    The dense 96 x 64 and 90 x 64 shapes take the matrix-core dense product
+    of the 16- and 8-bit modes (row lengths multiples of 16 and 32).
     The random full-width PSFs (all 31 columns, or rows, carry weights of
     order one) pin every diagonal of the banded form the 16- and 8-bit modes
     compute the PSF product in; the image widths (77, 70, 130) are not
@@ -123,6 +125,10 @@ def test_operator_products(lib, ctx, which, prec):
     rng = np.random.default_rng(7)
     if which == "dense":
         prob = random_dense(37, 53, seed=3)
+    elif which == "dense96x64":  # 16- and 8-bit modes: matrix cores both ways
+        prob = random_dense(96, 64, seed=31)
+    elif which == "dense90x64":  # A on the matrix cores (ragged row group), A^T not
+        prob = random_dense(90, 64, seed=32)
     elif which == "csr":
         prob = tomography(20, 15, 29, 0.02, seed=4)
     elif which == "psf31":
@@ -422,6 +428,46 @@ def test_8bit_operator_error(lib, ctx, name):
     print(f"[{name} fp8op] rel err vs x_true: min {e_lo.min():.4f} at k={int(e_lo.argmin()) + 1}, "
           f"final {e_lo[-1]:.4f} (fp64 oracle: min {e_64.min():.4f}, final {e_64[-1]:.4f})")
     assert e_lo.min() < 3.0 * e_64.min()
+
+
+@pytest.mark.parametrize("prec", ["fp16op", "fp8op", "bf16op"])
+def test_dense_matrix_core_modes(lib, ctx, prec):
+    """The dense operator of the 256 x 256 problem (K = 50) in the 16- and
+    8-bit modes, whose products run on the matrix cores (row lengths are
+    multiples of the instruction's 16 or 32).  Each product takes the
+    operator's rounded values and inputs rounded to the format, so the
+    Hessenberg relations hold for the rounded operator and the rounded
+    basis vectors to float rounding (every term exact in float):
+    A_r round(L_k) = D_{k+1} H and A_r^T round(D_k) = L_k W within
+    10 k 2^-24 of the magnitudes; the error to x_true is stated against the
+    FP64 oracle's."""
+    from gpu_helpers import e4m3
+    prob = config_problem("dense256")
+    K = 50
+    rnd = {"fp16op": lambda z: np.asarray(z, np.float64).astype(np.float16).astype(np.float64),
+           "fp8op": e4m3, "bf16op": _bf16}[prec]
+    G = gpu_solve(lib, ctx, prob, prec, K, "wgcv", grid=lambda_grid(), grid_relative=True)
+    check_basis_invariants(G, prob.m, prob.n)
+    k = min(G["n_l"], G["n_d"] - 1)
+    assert k >= 20
+    Ar = rnd(prob.A)
+    L, D = G["L"][:, :k], G["D"][:, :k + 1]
+    H, W = G["H"][:k + 1, :k], G["W"][:k, :k]
+    Lr, Dr = rnd(L), rnd(D[:, :k])
+    u = 2.0 ** -24
+    r1 = np.abs(Ar @ Lr - D @ H)
+    b1 = 10 * k * u * (np.abs(Ar) @ np.abs(Lr) + np.abs(D) @ np.abs(H))
+    r2 = np.abs(Ar.T @ Dr - L @ W)
+    b2 = 10 * k * u * (np.abs(Ar.T) @ np.abs(Dr) + np.abs(L) @ np.abs(W))
+    print(f"[dense256 {prec}] relations over k = {k}: max ratio to the bound "
+          f"{(r1 / b1).max():.3f}, {(r2 / b2).max():.3f}")
+    assert np.all(r1 <= b1) and np.all(r2 <= b2)
+    R = hybrid_lslu(make_operator(prob), prob.b, K, _reg("wgcv", True))
+    e_lo = np.array([rel(G["X"][:, j], prob.x_true) for j in range(G["k_done"])])
+    e_64 = np.array([rel(R.X[:, j], prob.x_true) for j in range(R.k_done)])
+    print(f"[dense256 {prec}] rel err vs x_true: min {e_lo.min():.4f} at k={int(e_lo.argmin()) + 1} "
+          f"(FP64 oracle: min {e_64.min():.4f} at k={int(e_64.argmin()) + 1})")
+    assert e_lo.min() < (3.0 if prec == "fp8op" else 1.5) * e_64.min()
 
 
 # -------------------------------------------------------------- edge cases
