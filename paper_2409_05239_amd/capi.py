@@ -179,6 +179,15 @@ def _check(ctx, status):
     return status
 
 
+def _torch_done(dev):
+    """Torch's work on its current stream of device ``dev`` (which may still
+    be writing the tensors passed in: inputs copied or filled there) must be
+    finished before the library's stream runs: the two are not ordered with
+    each other."""
+    import torch
+    torch.cuda.current_stream(0 if dev is None else dev).synchronize()
+
+
 def _dptr(t):
     return None if t is None else c_void_p(t.data_ptr())
 
@@ -315,7 +324,11 @@ def lslu_op_apply(ctx, op, transpose, x, y):
     dev = _CTX_DEVICE.get(ctx.value)
     px = _vec(x, nin, prec, "x", dev)
     py = _vec(y, nout, prec, "y", dev)
+    _torch_done(dev)
     _check(ctx, lib.lslu_op_apply(ctx, op, int(transpose), px, py))
+    # asynchronous on the library's stream: y is complete when this returns
+    import torch
+    torch.cuda.synchronize(0 if dev is None else dev)
 
 
 def lslu_op_tile(ctx, op, rows_per_lane=0):
@@ -462,6 +475,7 @@ def lslu_solve(ctx, op, b, maxiter, reg="none", lam=0.0, grid=None,
         _CTX_SHAPE[ctx.value] = (m, n, prec)  # the solve the context now holds
         return st, x_out, _info(st, r, host, timing)
     entry = lib.lslu_solve_static if static else lib.lslu_solve
+    _torch_done(dev)
     st = _check(ctx, entry(ctx, op, _dptr(b), _dptr(x0), ctypes.byref(o),
                            _dptr(x_out), ctypes.byref(r)))
     if static:
@@ -522,6 +536,7 @@ def lslu_solve_batch(ctxs, ops, bs, maxiter, reg="none", lam=0.0, grid=None,
     arr_b = (c_void_p * P)(*[b.data_ptr() for b in bs])
     arr_x = (c_void_p * P)(*[x.data_ptr() for x in xs])
     arr_r = (POINTER(lslu_result) * P)(*[ctypes.pointer(r) for r in rs])
+    _torch_done(_CTX_DEVICE.get(ctxs[0].value))
     st = _check(ctxs[0], lib.lslu_solve_batch(P, arr_c, arr_o, arr_b, ctypes.byref(o),
                                               arr_x, arr_r))
     for c, op in zip(ctxs, ops):
@@ -590,6 +605,7 @@ def lslu_vjp(ctx, op, k, xbar, bbar=None):
         bbar = torch.empty(m, dtype=_torch_dtype(prec), device=xbar.device)
     pb = _vec(bbar, m, prec, "bbar", dev)
     lb = c_double(0.0)
+    _torch_done(dev)
     _check(ctx, lib.lslu_vjp(ctx, op, int(k), px, pb, ctypes.byref(lb)))
     return bbar, lb.value
 
@@ -602,6 +618,9 @@ def lslu_get_basis(ctx, which, count, dst):
     if shape is None:
         raise ValueError("no solve was started on this context through this binding")
     m, n, prec = shape
-    p = _vec(dst, int(count) * (n if which == 0 else m), prec, "dst",
-             _CTX_DEVICE.get(ctx.value), at_least=True)
+    dev = _CTX_DEVICE.get(ctx.value)
+    p = _vec(dst, int(count) * (n if which == 0 else m), prec, "dst", dev, at_least=True)
+    _torch_done(dev)
     _check(ctx, lib.lslu_get_basis(ctx, int(which), int(count), p))
+    import torch
+    torch.cuda.synchronize(0 if dev is None else dev)

@@ -17,7 +17,7 @@
 //     trace((B^T B + lam^2 I)^-1) = ||R^-1||_F^2 from a recurrence of positive
 //     terms.  One thread per grid value of lambda.
 //  3. sigma_1 (for the relative grid and reports) and sigma_min by parallel
-//     multisection of Sturm counts of B^T B.
+//     multisection of Sturm counts of B^T B (both searches side by side).
 //  4. y_k = Q z_{lambda_k}.
 // In exact arithmetic these equal the SVD expressions of Section 3.2.1
 // (eq. gcv2, the SVD form of weighted GCV, eq. stop2 and the filtered SVD
@@ -32,10 +32,10 @@ namespace lslu {
 
 namespace {
 
-constexpr int kPT = 512;            // threads per projected problem
+constexpr int kPT = 1024;           // threads per projected problem
+constexpr int kSP = 512;            // of which run the eigenvalue-count searches
 constexpr int kBL = 8;              // lanes per column (row) of a reflector update
-constexpr int kSectRounds1 = 8;     // multisection rounds for sigma_1
-constexpr int kSectRoundsMin = 8;   // multisection rounds for sigma_min
+constexpr int kSectRounds = 9;      // multisection rounds (8 bits each)
 size_t g_static_lds = 32 * 1024;  // static LDS of k_projected, read at init
 
 // Working matrix A ((k+1) x k, leading dimension k+1).
@@ -48,15 +48,21 @@ __host__ __device__ inline size_t proj_scratch_per_k(int K, int G) {
 
 __device__ inline double wave_sum_d(double v) { return group_sum<kWave>(v); }
 
-// Number of eigenvalues of the tridiagonal T = B^T B (diagonal a,
-// off-diagonal b) below x, from the signs of its LDL^T pivots.
-__device__ inline int sturm_count(const double* a, const double* b, int k,
+// Number of eigenvalues of the tridiagonal T = B^T B (diagonal a, squared
+// off-diagonal b2) below x, from the signs of its LDL^T pivots.  The
+// quotient b2 / q is b2 times 1/q from the hardware reciprocal refined by two
+// Newton steps (a few ulps, as the count's usual error analysis allows, at
+// about half the latency of a correctly rounded division).
+__device__ inline int sturm_count(const double* a, const double* b2, int k,
                                   double x, double pivmin) {
   double q = a[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   int cnt = q < 0.0;
   for (int i = 1; i < k; ++i) {
-    q = (a[i] - x) - (b[i - 1] * b[i - 1]) / q;
+    double r = __builtin_amdgcn_rcp(q);
+    r = fma(fma(-q, r, 1.0), r, r);
+    r = fma(fma(-q, r, 1.0), r, r);
+    q = (a[i] - x) - b2[i - 1] * r;
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0.0;
   }
@@ -111,23 +117,40 @@ __device__ inline double elden_forward(const double* d, const double* e,
 }
 
 // Back substitution R z = q; returns ||g - B z||^2 (z stored when non-null).
+// Rows go in blocks of 8 whose operands are all loaded first (the factors may
+// sit in global scratch: one round trip per block, not per row).
 __device__ inline double elden_backward(const double* d, const double* e,
                                         const double* g, int k,
                                         const double* rho, const double* f,
                                         const double* q, double* z) {
+  constexpr int kB = 8;
   double znext = 0.0, mis = 0.0;
-  for (int i = k - 1; i >= 0; --i) {
-    double zi, ri;
-    if (i + 1 < k) {
-      zi = (q[i] - f[i] * znext) / rho[i];
-      ri = g[i] - d[i] * zi - e[i] * znext;
-    } else {
-      zi = q[i] / rho[i];
-      ri = g[i] - d[i] * zi;
+  for (int hi = k - 1; hi >= 0; hi -= kB) {
+    double qb[kB], fb[kB], rb[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int i = hi - u;
+      const int ic = i >= 0 ? i : 0;
+      qb[u] = q[ic];
+      fb[u] = f[ic];
+      rb[u] = rho[ic];
     }
-    mis += ri * ri;
-    if (z) z[i] = zi;
-    znext = zi;
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int i = hi - u;
+      if (i < 0) break;
+      double zi, ri;
+      if (i + 1 < k) {
+        zi = (qb[u] - fb[u] * znext) / rb[u];
+        ri = g[i] - d[i] * zi - e[i] * znext;
+      } else {
+        zi = qb[u] / rb[u];
+        ri = g[i] - d[i] * zi;
+      }
+      mis += ri * ri;
+      if (z) z[i] = zi;
+      znext = zi;
+    }
   }
   return mis;
 }
@@ -172,8 +195,7 @@ __global__ __launch_bounds__(kPT) void k_projected(
   __shared__ double g[kMaxIter + 1], vb[kMaxIter + 1], taur[kMaxIter];
   __shared__ double d[kMaxIter], e[kMaxIter], ta[kMaxIter], tb[kMaxIter];
   __shared__ double zy[kMaxIter], gv[kMaxGrid];
-  __shared__ int s_first;
-  __shared__ double s_tau, s_lo, s_hi, s_sig1, s_lam, s_sep;
+  __shared__ double s_tau, s_sig1, s_lam, s_sep;
   __shared__ int s_lidx;
 
   const int k = k_first + blockIdx.x;
@@ -316,47 +338,54 @@ __global__ __launch_bounds__(kPT) void k_projected(
   __syncthreads();
   const double gk1 = g[k];  // = +-beta c_{k+1}
 
-  // 3. sigma_1^2 and sigma_min^2 by multisection of the eigenvalue count.
+  // 3. sigma_1^2 and sigma_min^2 by multisection of the eigenvalue count,
+  // both at once: the first kSP / 2 threads bracket the first x with count k
+  // (the largest eigenvalue), the next kSP / 2 the first x with count 1 (the
+  // smallest), kSP / 2 + 1 intervals per round each (more threads would
+  // only share the vector units the counts are bound by).
   double pivmin = DBL_MIN, gers = 0.0;
   for (int i = 0; i < k; ++i) {
     const double bl = i > 0 ? fabs(tb[i - 1]) : 0.0, br = fabs(tb[i]);
     gers = fmax(gers, ta[i] + bl + br);
     pivmin = fmax(pivmin, DBL_MIN * tb[i] * tb[i]);
   }
-  for (int which = 0; which < 2; ++which) {
-    // which 0: first x with count k (largest); which 1: first x with count 1.
-    if (tid == 0) {
-      s_lo = 0.0;
-      s_hi = gers * (1.0 + 4.0 * DBL_EPSILON) + pivmin;
+  __syncthreads();  // every thread has read tb: square it in place
+  for (int i = tid; i < k; i += kPT) tb[i] = tb[i] * tb[i];
+  {
+    constexpr int kHP = kSP / 2;
+    __shared__ double s_lo2[2], s_hi2[2];
+    __shared__ int s_first2[2];
+    const int which = tid < kSP ? tid / kHP : 0, ht = tid - which * kHP;
+    const int target = which == 0 ? k : 1;
+    if (tid < 2) {
+      s_lo2[tid] = 0.0;
+      s_hi2[tid] = gers * (1.0 + 4.0 * DBL_EPSILON) + pivmin;
     }
     __syncthreads();
-    const int target = which == 0 ? k : 1;
-    const int rounds = which == 0 ? kSectRounds1 : kSectRoundsMin;
-    for (int rd = 0; rd < rounds; ++rd) {
-      const double lo = s_lo, hi = s_hi;
-      const double step = (hi - lo) / (double)(kPT + 1);
-      const int cnt = sturm_count(ta, tb, k, lo + step * (tid + 1), pivmin);
-      if (tid == 0) s_first = kPT;
+    for (int rd = 0; rd < kSectRounds; ++rd) {
+      const double lo = s_lo2[which], hi = s_hi2[which];
+      const double step = (hi - lo) / (double)(kHP + 1);
+      const int cnt = tid < kSP ? sturm_count(ta, tb, k, lo + step * (ht + 1), pivmin) : 0;
+      if (tid < 2) s_first2[tid] = kHP;
       __syncthreads();
       // the first point whose count reaches the target brackets it (the last
       // interval when none does); a minimum, so the choice is deterministic
-      if (cnt >= target) atomicMin(&s_first, tid);
+      if (tid < kSP && cnt >= target) atomicMin(&s_first2[which], ht);
       __syncthreads();
-      if (tid == 0) {
-        const int t = s_first;
-        s_lo = (t == 0) ? lo : lo + step * t;
-        s_hi = (t == kPT) ? hi : lo + step * (t + 1);
+      if (tid < 2) {
+        const int t = s_first2[tid];
+        const double l0 = s_lo2[tid], h0 = s_hi2[tid];
+        const double st2 = (h0 - l0) / (double)(kHP + 1);
+        s_lo2[tid] = (t == 0) ? l0 : l0 + st2 * t;
+        s_hi2[tid] = (t == kHP) ? h0 : l0 + st2 * (t + 1);
       }
       __syncthreads();
     }
     if (tid == 0) {
-      const double val = sqrt(0.5 * (s_lo + s_hi));
-      if (which == 0) {
-        smax_out[k - 1] = val;
-        s_sig1 = val;
-      } else {
-        smin_out[k - 1] = val;
-      }
+      const double v1 = sqrt(0.5 * (s_lo2[0] + s_hi2[0]));
+      smax_out[k - 1] = v1;
+      s_sig1 = v1;
+      smin_out[k - 1] = sqrt(0.5 * (s_lo2[1] + s_hi2[1]));
     }
     __syncthreads();
   }
@@ -373,7 +402,9 @@ __global__ __launch_bounds__(kPT) void k_projected(
       double* ff = rho + K;
       double* qq = ff + K;
       const double tr = elden_forward(d, e, g, k, lam, rho, ff, qq);
-      const double mis = elden_backward(d, e, g, k, rho, ff, qq, nullptr);
+      const double mis = elden_backward(d, e, g, k, rho, ff, qq, qq);  // z over q
+      ta[gi] = mis;  // kept for the chosen value (T is no longer needed)
+      tb[gi] = tr;
       const double num = (double)k * (mis + gk1 * gk1);
       // trace(I - omega H H_lam^+) = (k+1) - omega (k - lam^2 tr)
       const double den = (double)(k + 1) - omega * ((double)k - lam * lam * tr);
@@ -450,13 +481,27 @@ __global__ __launch_bounds__(kPT) void k_projected(
   __syncthreads();
 
   // 5. z for lambda_k and Ghat(k) (thread 0), then y = Q z (wavefront 0).
+  // On a grid (GCV, weighted GCV) they were formed for the chosen value
+  // already: its slot holds z and the factor R, ta/tb its residual and trace.
+  const bool on_grid = reg == kWGCV || reg == kGCV;
+  double* slot = lamscr + (size_t)(on_grid ? s_lidx : 0) * 3 * K;
+  if (on_grid) {
+    for (int i = tid; i < k; i += kPT) zy[i] = slot[2 * K + i];
+    __syncthreads();
+  }
   if (tid == 0) {
     const double lam = s_lam;
-    double* rho = lamscr;  // grid slot 0 is free again
+    double* rho = slot;
     double* ff = rho + K;
     double* qq = ff + K;
-    const double tr = elden_forward(d, e, g, k, lam, rho, ff, qq);
-    const double mis = elden_backward(d, e, g, k, rho, ff, qq, zy);
+    double tr, mis;
+    if (on_grid) {
+      tr = tb[s_lidx];
+      mis = ta[s_lidx];
+    } else {
+      tr = elden_forward(d, e, g, k, lam, rho, ff, qq);
+      mis = elden_backward(d, e, g, k, rho, ff, qq, zy);
+    }
     const double num = (double)p.n * (mis + gk1 * gk1);
     const double den = (double)(p.m - k) + lam * lam * tr;
     ghat_out[k - 1] = (den == 0.0) ? NAN : num / (den * den);
@@ -480,7 +525,7 @@ __global__ __launch_bounds__(kPT) void k_projected(
     }
   }
   __syncthreads();
-  double* dy = lamscr + 2 * K;  // -2 lambda Q w, when asked for
+  double* dy = slot + 2 * K;  // -2 lambda Q w, when asked for
   if (wv == 0) {
     apply_q(colp, taur, k, zy, lane);
     if (p.dldl) apply_q(colp, taur, k, dy, lane);
