@@ -44,8 +44,11 @@ PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 def _kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("recurrence.hip", "device_common.hpp", "internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2409_05239_amd", "csrc", f), "rb") as fh:
+    csrc = os.path.join(ROOT, "paper_2409_05239_amd", "csrc")
+    files = ["recurrence.hip", "recurrence_impl.hpp", "device_common.hpp", "internal.hpp"]
+    files += sorted(f for f in os.listdir(csrc) if f.startswith("recurrence_psf_"))
+    for f in files:
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -65,9 +68,11 @@ def _load_traffic(kernel, workload, prec):
 
 
 def csr_spmv_bytes(nnz, rows, cols, vsz, esz):
-    """Algorithmic bytes of one CSR product: values + column indices, row
+    """Algorithmic bytes of one CSR product: values + column indices (16-bit
+    when every index fits, as the library stores them: cols <= 65536), row
     pointers, the input vector once and the output once."""
-    return nnz * (vsz + 4) + 4 * (rows + 1) + esz * cols + esz * rows
+    isz = 2 if cols <= 65536 else 4
+    return nnz * (vsz + isz) + 4 * (rows + 1) + esz * cols + esz * rows
 
 
 def recurrence_bytes(prob, K, vsz, esz):

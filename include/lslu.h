@@ -120,7 +120,9 @@ lslu_status lslu_op_dense(lslu_ctx* ctx, int64_t m, int64_t n, const double* A,
  * indptr[m] = nnz), indices[nnz] (int32, strictly increasing within each row,
  * in [0, n)) and data[nnz] (double).  nnz must be < 2^31.  The library builds
  * the CSR of A^T on the host and keeps both on the device, so both products
- * are row-parallel with a fixed summation order (deterministic).
+ * are row-parallel with a fixed summation order (deterministic).  Column
+ * indices are stored in 16 bits when they fit (those of A when n <= 65536,
+ * those of A^T when m <= 65536), else in 32.
  * Errors: LSLU_EINVAL (shape, ordering or range violations), LSLU_ENONFINITE,
  * LSLU_ENOMEM. */
 lslu_status lslu_op_csr(lslu_ctx* ctx, int64_t m, int64_t n, int64_t nnz,

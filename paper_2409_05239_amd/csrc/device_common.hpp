@@ -323,20 +323,40 @@ struct Quad<Half> {
   }
 };
 
-// Row r of a CSR matrix (int32 row pointers and column indices; index and
-// value arrays 16-byte aligned and readable 3 entries past nnz).  The row is
+// Four column indices from a position that is a multiple of 4 (one 16-byte
+// load of int32, one 8-byte load of uint16).
+template <typename I>
+struct Idx4;
+template <>
+struct Idx4<int> {
+  __device__ static void load(const int* p, int (&c)[4]) {
+    const int4 c4 = *reinterpret_cast<const int4*>(p);
+    c[0] = c4.x; c[1] = c4.y; c[2] = c4.z; c[3] = c4.w;
+  }
+};
+template <>
+struct Idx4<uint16_t> {
+  __device__ static void load(const uint16_t* p, int (&c)[4]) {
+    const uint2 q = *reinterpret_cast<const uint2*>(p);
+    c[0] = static_cast<int>(q.x & 0xffffu); c[1] = static_cast<int>(q.x >> 16);
+    c[2] = static_cast<int>(q.y & 0xffffu); c[3] = static_cast<int>(q.y >> 16);
+  }
+};
+
+// Row r of a CSR matrix (int32 row pointers; int32 or uint16 column indices;
+// index and value arrays 16-byte aligned and readable 3 entries past nnz).  The row is
 // read in aligned chunks of 4 entries: lane `sub` of a group of G takes the
 // chunks that start at (beg & ~3) + 4 sub + 4 G i, with one vector load for
 // the indices and one for the values per chunk, then the gathers of its
 // entries inside [beg, end), kChunks chunks per batch so a row costs few
 // dependent round trips.  Each lane adds its entries in chunk order.
-template <typename V, typename AccT, int kIn>
+template <typename V, typename AccT, int kIn, typename I = int>
 struct CsrRows {
   using Acc = AccT;
   using Val = V;
   static constexpr int kChunks = 2;
   const int* rp;
-  const int* ci;
+  const I* ci;
   const V* val;
   // Chunks q, q + 4G, ... below end (entries outside [beg, end) skipped).
   template <int G, typename XF>
@@ -349,8 +369,7 @@ struct CsrRows {
       for (int h = 0; h < kChunks; ++h) {
         const int qh = q + h * 4 * G;
         if (qh < end) {
-          const int4 c4 = *reinterpret_cast<const int4*>(ci + qh);
-          c[h][0] = c4.x; c[h][1] = c4.y; c[h][2] = c4.z; c[h][3] = c4.w;
+          Idx4<I>::load(ci + qh, c[h]);
           Quad<V>::load(val + qh, v[h]);
         } else {
 #pragma unroll
@@ -400,8 +419,10 @@ struct CsrRows {
       const int qh = q + h * 4 * G;
       V vv[4];
       if (qh < end) {
-        const int4 c4 = *reinterpret_cast<const int4*>(ci + qh);
-        c[4 * h] = c4.x; c[4 * h + 1] = c4.y; c[4 * h + 2] = c4.z; c[4 * h + 3] = c4.w;
+        int cc[4];
+        Idx4<I>::load(ci + qh, cc);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) c[4 * h + e] = cc[e];
         Quad<V>::load(val + qh, vv);
       } else {
 #pragma unroll

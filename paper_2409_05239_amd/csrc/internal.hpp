@@ -176,9 +176,11 @@ struct DeviceOp {
   // dense: A (m x n) and AT (n x m), row-major, value type of prec
   void* A = nullptr;
   void* AT = nullptr;
-  // csr
-  int* rp = nullptr;  int* ci = nullptr;  void* val = nullptr;
-  int* rpT = nullptr; int* ciT = nullptr; void* valT = nullptr;
+  // csr: column indices as int32, or as uint16 when they all fit (idx16 bit
+  // 0: ci, bit 1: ciT), which cuts the bytes an entry streams by 2
+  int* rp = nullptr;  void* ci = nullptr;  void* val = nullptr;
+  int* rpT = nullptr; void* ciT = nullptr; void* valT = nullptr;
+  int idx16 = 0;
   int64_t nnz = 0;
   // psf
   int64_t rows = 0, cols = 0;

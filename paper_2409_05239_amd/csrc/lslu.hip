@@ -1005,11 +1005,19 @@ lslu_status lslu_op_csr(lslu_ctx* c, int64_t m, int64_t n, int64_t nnz,
     valT.resize(nnz + kCsrPad, 0.0);
     auto va = convert_values(dpad.data(), nnz + kCsrPad, prec);
     auto vt = convert_values(valT.data(), nnz + kCsrPad, prec);
+    // column indices in 16 bits when every one fits (A's are < n, A^T's < m)
+    auto upload_idx = [&](void** dst, const std::vector<int>& idx, bool narrow) -> lslu_status {
+      if (!narrow) return upload(c, dst, idx.data(), sizeof(int) * idx.size());
+      std::vector<uint16_t> v16(idx.begin(), idx.end());
+      return upload(c, dst, v16.data(), sizeof(uint16_t) * v16.size());
+    };
+    const bool n16 = n <= 65536, m16 = m <= 65536;
+    op->d.idx16 = (n16 ? 1 : 0) | (m16 ? 2 : 0);
     lslu_status st = upload(c, reinterpret_cast<void**>(&op->d.rp), rp.data(), sizeof(int) * (m + 1));
-    if (st == LSLU_OK) st = upload(c, reinterpret_cast<void**>(&op->d.ci), cpad.data(), sizeof(int) * cpad.size());
+    if (st == LSLU_OK) st = upload_idx(&op->d.ci, cpad, n16);
     if (st == LSLU_OK) st = upload(c, &op->d.val, va.data(), va.size());
     if (st == LSLU_OK) st = upload(c, reinterpret_cast<void**>(&op->d.rpT), rpT.data(), sizeof(int) * (n + 1));
-    if (st == LSLU_OK) st = upload(c, reinterpret_cast<void**>(&op->d.ciT), ciT.data(), sizeof(int) * ciT.size());
+    if (st == LSLU_OK) st = upload_idx(&op->d.ciT, ciT, m16);
     if (st == LSLU_OK) st = upload(c, &op->d.valT, vt.data(), vt.size());
     if (st != LSLU_OK) {
       free_op(op->d);

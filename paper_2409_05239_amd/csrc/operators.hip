@@ -147,9 +147,16 @@ void apply_t(const DeviceOp& op, int tr, const T* x, T* y, const int* stop,
       }
       k_rows<<<grid, kRowBlock, 0, s>>>(ro, rows, x, y, stop);
     } else if (op.kind == 1) {
-      CsrRows<V, Acc, kB> ro{tr ? op.rpT : op.rp, tr ? op.ciT : op.ci,
-                             static_cast<const V*>(tr ? op.valT : op.val)};
-      k_rows<<<grid, kRowBlock, 0, s>>>(ro, rows, x, y, stop);
+      const int* rp = tr ? op.rpT : op.rp;
+      const void* ci = tr ? op.ciT : op.ci;
+      const V* val = static_cast<const V*>(tr ? op.valT : op.val);
+      if (op.idx16 & (tr ? 2 : 1)) {
+        CsrRows<V, Acc, kB, uint16_t> ro{rp, static_cast<const uint16_t*>(ci), val};
+        k_rows<<<grid, kRowBlock, 0, s>>>(ro, rows, x, y, stop);
+      } else {
+        CsrRows<V, Acc, kB, int> ro{rp, static_cast<const int*>(ci), val};
+        k_rows<<<grid, kRowBlock, 0, s>>>(ro, rows, x, y, stop);
+      }
     } else {
       const int R = static_cast<int>(op.rows), C = static_cast<int>(op.cols);
       with_ph(op.ph, [&](auto phc) {

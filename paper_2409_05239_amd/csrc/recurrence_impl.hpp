@@ -1151,8 +1151,13 @@ void with_row_op(const DeviceOp& op, int tr, F&& f) {
     if (op.kind == 0) {
       f(DenseRows<V, Acc, kB>{static_cast<const V*>(tr ? op.AT : op.A), tr ? op.m : op.n});
     } else if (op.kind == 1) {
-      f(CsrRows<V, Acc, kB>{tr ? op.rpT : op.rp, tr ? op.ciT : op.ci,
-                            static_cast<const V*>(tr ? op.valT : op.val)});
+      const int* rp = tr ? op.rpT : op.rp;
+      const void* ci = tr ? op.ciT : op.ci;
+      const V* val = static_cast<const V*>(tr ? op.valT : op.val);
+      if (op.idx16 & (tr ? 2 : 1))
+        f(CsrRows<V, Acc, kB, uint16_t>{rp, static_cast<const uint16_t*>(ci), val});
+      else
+        f(CsrRows<V, Acc, kB, int>{rp, static_cast<const int*>(ci), val});
     } else {
       const Acc* wt;
       if constexpr (std::is_same_v<Acc, double>)
