@@ -311,6 +311,12 @@ CONFIGS = {
     "deblur1024": dict(make=lambda: psf_deblur(1024, 15, 2.5, 0.01, 1002),
                        iters=150, precision="fp64", reg="wgcv",
                        grid_relative=True),
+    # A 256 x 256 tomography sibling (180 angles, 362 bins): its CSR pair
+    # (about 336 MB in FP32 with 16-bit indices) exceeds the device's 256 MB
+    # last-level cache, so its products stream from HBM.
+    "tomo256": dict(make=lambda: tomography(256, 180, 362, 0.02, 1201),
+                    iters=100, precision="fp32", reg="wgcv",
+                    grid_relative=True),
     # The differentiable workload: d ||x_k - x_true||^2 / d (b, lambda) with a
     # fixed lambda (15 x 15 Gaussian PSF, sigma 2).
     "deblur512": dict(make=lambda: psf_deblur(512, 7, 2.0, 0.01, 1005),
