@@ -526,6 +526,7 @@ def run_batch(args):
 
     P, S, K = args.batch, args.contexts, 60
     probs = batch_problems(P, seed=0)
+    print(f"[batch] {P} problems generated", flush=True)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     grid = lambda_grid()
@@ -597,17 +598,21 @@ def run_batch(args):
 
     lo = prepare("bf16op", rr, probs)
     t_conc = timed(concurrent, lo)
+    print(f"[batch] concurrent on {S} contexts: {t_conc * 1e3:.3f} ms", flush=True)
     t_seq = timed(one_at_a_time, lo)
+    print(f"[batch] one at a time: {t_seq * 1e3:.3f} ms", flush=True)
     errs = errors(lo, probs)
     release(lo)
     hi = prepare("fp64", rr, probs)
     t_64 = timed(one_at_a_time, hi)
+    print(f"[batch] fp64 one at a time: {t_64 * 1e3:.3f} ms", flush=True)
     errs64 = errors(hi, probs)
     release(hi)
     tomo = [p for p in probs if p.kind == "csr"]
     own = [capi.lslu_create(0) for _ in tomo]  # the merged batch: one context each
     mo = prepare("bf16op", own, tomo)
     t_tm = timed(merged, mo)
+    print(f"[batch] tomography merged: {t_tm * 1e3:.3f} ms", flush=True)
     order = sorted(range(len(tomo)), key=lambda i: tomo[i].m)
     ng = 4
     groups = [[mo[i] for i in order[g::ng]] for g in range(ng)]  # interleaved by size

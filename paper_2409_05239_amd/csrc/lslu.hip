@@ -20,12 +20,24 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "internal.hpp"
 #include "lslu.h"
 
 using namespace lslu;
 
 namespace {
+
+// A named range on the profiler's host timeline (rocprofv3 --marker-trace)
+// from construction to the end of the scope; a no-op without a profiler.
+// The device work a range enqueues shows in the kernel trace beside it.
+struct Range {
+  explicit Range(const char* name) { roctxRangePush(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 struct Layout {
   void *L = nullptr, *D = nullptr, *q = nullptr, *u = nullptr, *r0 = nullptr,
@@ -410,6 +422,7 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
   const size_t lds = c->lds_max;
 
   if (part != 2) {
+  Range r_rec("lslu: set-up and recurrence (enqueue)");
   launch_state_reset(st, l.psep, 2 * K + 1, s);
   launch_fill<unsigned char>(l.mask_t, 0, m, s);
   launch_fill<unsigned char>(l.mask_g, 0, n, s);
@@ -587,6 +600,7 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
   }
   pp.dldl = grad ? l.dldl : nullptr;
   {
+    Range r_proj("lslu: projected problems (enqueue)");
     // fork onto the side streams, one launch group each, then join
     const hipStream_t ss[3] = {s, c->side[0], c->side[1]};
     (void)hipEventRecord(c->fork, s);
@@ -599,6 +613,7 @@ void enqueue_solve(lslu_ctx* c, const DeviceOp& op, const T* b, const T* x0,
     }
   }
   pe->mark(2, s);
+  Range r_asm("lslu: stopping rule and assembly (enqueue)");
   const double tol = o->stop_tol > 0.0 ? o->stop_tol : 1e-6;
   launch_stopping(l.ghat, st, tol, o->early_stop ? 1 : 0, l.sel, s);
   if (o->flags & LSLU_FLAG_FINAL_ONLY) {
@@ -920,6 +935,7 @@ lslu_status lslu_op_dense(lslu_ctx* c, int64_t m, int64_t n, const double* A,
   if (prec < LSLU_FP64 || prec > LSLU_FP8OP) return fail(c, LSLU_EINVAL, "bad precision");
   if (m > INT32_MAX || n > INT32_MAX) return fail(c, LSLU_EINVAL, "size too large");
   try {
+    Range r_call("lslu_op_dense");
     if (!finite_all(A, m * n)) return fail(c, LSLU_ENONFINITE, "A has NaN/Inf");
     LSLU_HIP(c, hipSetDevice(c->device));
     std::vector<double> AT(static_cast<size_t>(m * n));
@@ -960,6 +976,7 @@ lslu_status lslu_op_csr(lslu_ctx* c, int64_t m, int64_t n, int64_t nnz,
     return fail(c, LSLU_EINVAL, "sizes must be < 2^31");
   if (prec < LSLU_FP64 || prec > LSLU_FP8OP) return fail(c, LSLU_EINVAL, "bad precision");
   try {
+    Range r_call("lslu_op_csr");
     if (indptr[0] != 0 || indptr[m] != nnz)
       return fail(c, LSLU_EINVAL, "indptr[0] must be 0 and indptr[m] must be nnz");
     for (int64_t r = 0; r < m; ++r) {
@@ -1044,6 +1061,7 @@ lslu_status lslu_op_psf(lslu_ctx* c, int64_t rows, int64_t cols, int32_t ph,
   if (prec < LSLU_FP64 || prec > LSLU_FP8OP) return fail(c, LSLU_EINVAL, "bad precision");
   if (!finite_all(psf, (int64_t)ph * pw)) return fail(c, LSLU_ENONFINITE, "PSF has NaN/Inf");
   try {
+    Range r_call("lslu_op_psf");
     LSLU_HIP(c, hipSetDevice(c->device));
     const int np = ph * pw;
     std::vector<double> p(psf, psf + np), pf(np);
@@ -1116,6 +1134,7 @@ lslu_status lslu_op_tile(lslu_ctx* c, lslu_op* op, int32_t rows_per_lane, int32_
   if (rows_per_lane != 0 && rows_per_lane != 2 && rows_per_lane != 4 && rows_per_lane != 8)
     return fail(c, LSLU_EINVAL, "rows_per_lane must be 0 (measure), 2, 4 or 8");
   try {
+    Range r_call("lslu_op_tile");
     LSLU_HIP(c, hipSetDevice(c->device));
     int r = rows_per_lane;
     if (r == 0) {
@@ -1172,7 +1191,10 @@ static lslu_status complete_solve(lslu_ctx* c, int K, lslu_result* res,
                                   const PhaseEvents* pe_in) {
   const hipStream_t s = c->stream;
   const Layout& l = c->lay;
-  LSLU_HIP(c, hipStreamSynchronize(s));
+  {
+    Range r_wait("lslu: wait for the solve");
+    LSLU_HIP(c, hipStreamSynchronize(s));
+  }
   PhaseEvents none;
   const PhaseEvents& pe = pe_in ? *pe_in : none;
     // Unpack the result block (same layout as on the device).
@@ -1238,6 +1260,7 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
   if ((o->flags & LSLU_FLAG_ASYNC) && (o->flags & LSLU_FLAG_TIMING))
     return fail(c, LSLU_EINVAL, "LSLU_FLAG_TIMING needs a synchronous solve");
   try {
+    Range r_call("lslu_solve");
     lslu_status vs = validate_opts(c, op, o);
     if (vs != LSLU_OK) return vs;
     c->last_ok = false;
@@ -1349,6 +1372,7 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
           destroy_captured(c->graphs.front());
           c->graphs.erase(c->graphs.begin());
         }
+        Range r_cap("lslu_solve: graph capture");
         LSLU_HIP(c, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
         enqueue();
         lslu_ctx::Captured cap;
@@ -1366,6 +1390,7 @@ lslu_status lslu_solve(lslu_ctx* c, const lslu_op* op, const void* b,
         exec = cap.exec;
         c->graphs.push_back(std::move(cap));
       }
+      Range r_launch("lslu_solve: graph launch");
       LSLU_HIP(c, hipGraphLaunch(exec, s));
     }
     LSLU_HIP(c, hipGetLastError());
@@ -1538,6 +1563,7 @@ lslu_status lslu_solve_host(lslu_ctx* c, const lslu_op* op, const double* b,
   if (!finite_all(b, m) || (x0 && !finite_all(x0, n)))
     return fail(c, LSLU_ENONFINITE, "b or x0 has NaN/Inf");
   try {
+    Range r_call("lslu_solve_host");
     LSLU_HIP(c, hipSetDevice(c->device));
     const bool dbl = op->d.prec == kFP64;
     const size_t esz = dbl ? sizeof(double) : sizeof(float);
@@ -1615,6 +1641,7 @@ lslu_status lslu_solve_batch(int32_t count, lslu_ctx* const* ctxs, const lslu_op
     if (vs != LSLU_OK) return fail(c0, vs, "problem " + std::to_string(i) + ": " + c->err);
   }
   try {
+    Range r_call("lslu_solve_batch");
     LSLU_HIP(c0, hipSetDevice(c0->device));
     const int K = o->maxiter;
     const int P = count;
@@ -1802,6 +1829,7 @@ lslu_status lslu_vjp(lslu_ctx* c, const lslu_op* op, int32_t k, const void* xbar
   if (k < 1 || k > c->last_kdone)
     return fail(c, LSLU_EINVAL, "k must be in [1, k_done] of the last solve");
   try {
+    Range r_call("lslu_vjp");
     LSLU_HIP(c, hipSetDevice(c->device));
     const int K = c->K;
     const int64_t m = c->m, n = c->n;

@@ -17,8 +17,13 @@ def _bench():
 
 def test_csr_product_bytes():
     b = _bench()
-    # 10 nonzeros, float values: 10 * (4 + 4) + 4 * (3 + 1) + 4 * 5 + 4 * 3
-    assert b.csr_spmv_bytes(10, 3, 5, 4, 4) == 80 + 16 + 20 + 12
+    # 10 nonzeros, float values, 16-bit column indices (5 columns):
+    # 10 * (4 + 2) + 4 * (3 + 1) + 4 * 5 + 4 * 3
+    assert b.csr_spmv_bytes(10, 3, 5, 4, 4) == 60 + 16 + 20 + 12
+    # 70000 columns do not fit 16 bits: 32-bit indices
+    assert b.csr_spmv_bytes(10, 3, 70000, 4, 4) == 80 + 16 + 4 * 70000 + 12
+    # the boundary: 65536 columns (indices 0..65535) still fit
+    assert b.csr_spmv_bytes(10, 3, 65536, 4, 4) == 60 + 16 + 4 * 65536 + 12
 
 
 def test_recurrence_bytes_of_the_tomography_workload():
@@ -27,7 +32,7 @@ def test_recurrence_bytes_of_the_tomography_workload():
     prob = config_problem("tomo128")
     assert prob.nnz == 7043164
     total = b.recurrence_bytes(prob, 100, 4, 4)
-    assert total // 201 == 61466007
+    assert total // 201 == 47449760
 
 
 def test_vjp_bytes_grows_quadratically():

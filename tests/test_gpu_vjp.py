@@ -164,6 +164,80 @@ def test_vjp_deblur512_central_differences_fp64(lib, ctx):
         lib.lslu_op_destroy(op)
 
 
+def test_vjp_deblur512_central_differences_step_1e3(lib, ctx):
+    """Full size, the differentiable workload's own check: the loss
+    ||x_k - x_true||^2 by central differences with step 1e-3 (relative: b
+    moves by 1e-3 ||b|| along a unit direction, lambda by 1e-3 lambda),
+    against the FP64 and the FP32 reverse pass.  A direction is abandoned if
+    a perturbed solve picks another pivot; the differences are then taken
+    with the base pivots replayed (the fixed-pivot map the reverse pass
+    differentiates), and the test says so."""
+    import torch
+    prob = _deblur512()
+    K, lam, h = 40, 0.01, 1e-3
+    op64 = lib.make_operator(ctx, prob, lib.PRECISIONS["fp64"])
+    op32 = lib.make_operator(ctx, prob, lib.PRECISIONS["fp32"])
+    try:
+        print("[vjp] deblur512 central differences, step 1e-3", flush=True)
+        base = _solve(lib, ctx, op64, prob, "fp64", K, lam=lam)
+        k = base["k_done"]
+        assert k == K
+        pt, pg = _pivots(base)
+        xbar = 2.0 * (base["X"][:, k - 1] - prob.x_true)
+        g64, lb64 = _vjp(lib, ctx, op64, k, xbar, "fp64")
+        b32 = _solve(lib, ctx, op32, prob, "fp32", K, lam=lam)
+        same32 = _pivots(b32) == (pt, pg)
+        x32bar = 2.0 * (b32["X"][:, k - 1] - prob.x_true)
+        g32, lb32 = _vjp(lib, ctx, op32, k, x32bar, "fp32")
+
+        def loss(bv, lm, replay):
+            b = torch.tensor(bv, dtype=torch.float64, device="cuda")
+            kw = dict(replay_piv_t=base["piv_t"], replay_piv_g=base["piv_g"]) if replay else {}
+            st, x, info = lib.lslu_solve(ctx, op64, b, K, reg="fixed", lam=lm, **kw)
+            x = x.double().cpu().numpy()
+            flipped = (list(info["piv_t"][:k + 1]), list(info["piv_g"][:k])) != (pt, pg)
+            return float(np.sum((x - prob.x_true) ** 2)), flipped
+
+        hb = h * np.linalg.norm(prob.b)
+        kept = 0
+        for seed in (11, 12, 13):
+            v = np.random.default_rng(seed).standard_normal(prob.m)
+            v /= np.linalg.norm(v)
+            (lp, fp), (lm_, fm) = loss(prob.b + hb * v, lam, False), loss(prob.b - hb * v, lam, False)
+            replay = fp or fm
+            if replay:
+                print(f"[vjp] direction {seed}: a pivot flips at step 1e-3; abandoned "
+                      "(differences repeated with the base pivots replayed)")
+                (lp, _), (lm_, _) = (loss(prob.b + hb * v, lam, True),
+                                     loss(prob.b - hb * v, lam, True))
+            else:
+                kept += 1
+            fd = (lp - lm_) / (2 * hb)
+            e64 = abs(v @ g64 - fd) / np.linalg.norm(g64)
+            print(f"[vjp] direction {seed}: fd {fd:.6e}, fp64 {v @ g64:.6e} (rel {e64:.2e})"
+                  + (f", fp32 {v @ g32:.6e}" if same32 else ""))
+            assert e64 <= 1e-4, (seed, fd, v @ g64)
+            if same32:
+                # the FP32 pass differentiates at the FP32 iterate: xbar
+                # differs from the FP64 one by the FP32 iterate's error
+                # (about 1e-5 of x), amplified by ||x|| / ||x - x_true||
+                e32 = abs(v @ g32 - fd) / np.linalg.norm(g64)
+                assert e32 <= 1e-3, (seed, fd, v @ g32)
+        print(f"[vjp] {kept} of 3 directions kept without a pivot flip")
+        hl = h * lam
+        (lp, fp), (lm_, fm) = loss(prob.b, lam + hl, False), loss(prob.b, lam - hl, False)
+        if fp or fm:
+            (lp, _), (lm_, _) = loss(prob.b, lam + hl, True), loss(prob.b, lam - hl, True)
+        fdl = (lp - lm_) / (2 * hl)
+        print(f"[vjp] d loss / d lambda: fd {fdl:.6e}, fp64 {lb64:.6e}, fp32 {lb32:.6e}")
+        assert abs(lb64 - fdl) <= 1e-4 * abs(fdl), (lb64, fdl)
+        if same32:
+            assert abs(lb32 - fdl) <= 1e-3 * abs(fdl), (lb32, fdl)
+    finally:
+        lib.lslu_op_destroy(op64)
+        lib.lslu_op_destroy(op32)
+
+
 def test_vjp_deblur512_fp32_against_oracle(lib, ctx):
     """Full size, FP32 (the workload's precision): one random direction and
     lambda against the FP64 complex-step oracle with the GPU's pivots."""
