@@ -22,6 +22,7 @@
 
 #include <rocprofiler-sdk-roctx/roctx.h>
 
+#include "host_ops.hpp"
 #include "internal.hpp"
 #include "lslu.h"
 
@@ -245,31 +246,6 @@ bool finite_all(const double* p, int64_t count) {
 
 size_t prec_size(int prec) { return prec == kFP64 ? sizeof(double) : sizeof(float); }
 
-// Convert host doubles to the operator's stored value type.
-std::vector<unsigned char> convert_values(const double* v, int64_t count, int prec) {
-  std::vector<unsigned char> out;
-  if (prec == kFP64) {
-    out.resize(sizeof(double) * count);
-    std::memcpy(out.data(), v, out.size());
-  } else if (prec == kFP32) {
-    out.resize(sizeof(float) * count);
-    float* o = reinterpret_cast<float*>(out.data());
-    for (int64_t i = 0; i < count; ++i) o[i] = static_cast<float>(v[i]);
-  } else if (prec == kBF16) {
-    out.resize(sizeof(uint16_t) * count);
-    uint16_t* o = reinterpret_cast<uint16_t*>(out.data());
-    for (int64_t i = 0; i < count; ++i) o[i] = f32_to_bf16(static_cast<float>(v[i]));
-  } else if (prec == kFP8) {  // E4M3, rounded once from the given double
-    out.resize(count);
-    for (int64_t i = 0; i < count; ++i) out[i] = f64_to_fp8(v[i]);
-  } else {  // binary16, rounded once from the given double
-    out.resize(sizeof(uint16_t) * count);
-    uint16_t* o = reinterpret_cast<uint16_t*>(out.data());
-    for (int64_t i = 0; i < count; ++i) o[i] = f64_to_f16(v[i]);
-  }
-  return out;
-}
-
 lslu_status upload(lslu_ctx* c, void** dst, const void* src, size_t bytes) {
   LSLU_HIP(c, hipMalloc(dst, bytes > 0 ? bytes : 1));
   if (bytes) {
@@ -285,41 +261,6 @@ void free_op(DeviceOp& d) {
   for (void* p : ps)
     if (p) (void)hipFree(p);
   d = DeviceOp{};
-}
-
-// The correlation weights w (ph x pw, row-major) of one direction in the
-// form the matrix-core PSF product reads them (device_common.hpp,
-// psf_tile_mfma), in the operator's 16- or 8-bit format: for each PSF row a,
-// kPer copies s = 0..kPer-1 of the row, each RL codes long, copy s shifted
-// left by s codes: code j of copy s is w(a, j + s - 16 - dsh), 0 outside the
-// PSF, with dsh = 16 - pw / 2 (the staged tile starts 16 columns left of the
-// output tile).  kPer = 4, RL = 76 for bfloat16 and binary16; kPer = 8,
-// RL = 80 for E4M3.  Returned as 8-byte words.
-std::vector<uint64_t> psf_mfma_rows(const std::vector<double>& w, int ph, int pw, int prec) {
-  const bool f8 = prec == kFP8;
-  const int kPer = f8 ? 8 : 4, RL = f8 ? 80 : 76, esz = f8 ? 1 : 2;
-  const int dsh = 16 - pw / 2;
-  std::vector<unsigned char> bytes(static_cast<size_t>(ph) * kPer * RL * esz, 0);
-  for (int a = 0; a < ph; ++a)
-    for (int sft = 0; sft < kPer; ++sft)
-      for (int j = 0; j < RL; ++j) {
-        const int idx = j + sft - 16 - dsh;
-        if (idx < 0 || idx >= pw) continue;
-        const double v = w[static_cast<size_t>(a) * pw + idx];
-        const size_t at = ((static_cast<size_t>(a) * kPer + sft) * RL + j) * esz;
-        if (prec == kBF16) {
-          const uint16_t c = f32_to_bf16(static_cast<float>(v));
-          std::memcpy(&bytes[at], &c, 2);
-        } else if (prec == kFP16) {
-          const uint16_t c = f64_to_f16(v);
-          std::memcpy(&bytes[at], &c, 2);
-        } else {
-          bytes[at] = f64_to_fp8(v);
-        }
-      }
-  std::vector<uint64_t> out(bytes.size() / 8);
-  std::memcpy(out.data(), bytes.data(), bytes.size());
-  return out;
 }
 
 constexpr size_t kGraphCache = 64;
@@ -977,33 +918,14 @@ lslu_status lslu_op_csr(lslu_ctx* c, int64_t m, int64_t n, int64_t nnz,
   if (prec < LSLU_FP64 || prec > LSLU_FP8OP) return fail(c, LSLU_EINVAL, "bad precision");
   try {
     Range r_call("lslu_op_csr");
-    if (indptr[0] != 0 || indptr[m] != nnz)
-      return fail(c, LSLU_EINVAL, "indptr[0] must be 0 and indptr[m] must be nnz");
-    for (int64_t r = 0; r < m; ++r) {
-      if (indptr[r + 1] < indptr[r]) return fail(c, LSLU_EINVAL, "indptr decreases");
-      for (int64_t p = indptr[r]; p < indptr[r + 1]; ++p) {
-        if (indices[p] < 0 || indices[p] >= n)
-          return fail(c, LSLU_EINVAL, "column index out of range");
-        if (p > indptr[r] && indices[p] <= indices[p - 1])
-          return fail(c, LSLU_EINVAL, "column indices not strictly increasing");
-      }
-    }
+    if (const char* bad = csr_check(m, n, nnz, indptr, indices))
+      return fail(c, LSLU_EINVAL, bad);
     if (!finite_all(data, nnz)) return fail(c, LSLU_ENONFINITE, "data has NaN/Inf");
     LSLU_HIP(c, hipSetDevice(c->device));
-    // A^T in CSR: count per column, prefix sum, scatter in row order (so the
-    // column indices of A^T, i.e. rows of A, come out increasing).
-    std::vector<int> rp(m + 1), rpT(n + 1, 0), ciT(nnz);
-    std::vector<double> valT(nnz);
+    std::vector<int> rp(m + 1), rpT, ciT;
+    std::vector<double> valT;
     for (int64_t r = 0; r <= m; ++r) rp[r] = static_cast<int>(indptr[r]);
-    for (int64_t p = 0; p < nnz; ++p) rpT[indices[p] + 1] += 1;
-    for (int64_t j = 0; j < n; ++j) rpT[j + 1] += rpT[j];
-    std::vector<int> fillp(rpT.begin(), rpT.end() - 1);
-    for (int64_t r = 0; r < m; ++r)
-      for (int64_t p = indptr[r]; p < indptr[r + 1]; ++p) {
-        const int dst = fillp[indices[p]]++;
-        ciT[dst] = static_cast<int>(r);
-        valT[dst] = data[p];
-      }
+    csr_transpose(m, n, nnz, indptr, indices, data, rpT, ciT, valT);
     lslu_op* op = new lslu_op();
     op->serial = ++g_op_serial;
     op->ctx = c;
@@ -1025,7 +947,7 @@ lslu_status lslu_op_csr(lslu_ctx* c, int64_t m, int64_t n, int64_t nnz,
     // column indices in 16 bits when every one fits (A's are < n, A^T's < m)
     auto upload_idx = [&](void** dst, const std::vector<int>& idx, bool narrow) -> lslu_status {
       if (!narrow) return upload(c, dst, idx.data(), sizeof(int) * idx.size());
-      std::vector<uint16_t> v16(idx.begin(), idx.end());
+      const std::vector<uint16_t> v16 = narrow_indices(idx);
       return upload(c, dst, v16.data(), sizeof(uint16_t) * v16.size());
     };
     const bool n16 = n <= 65536, m16 = m <= 65536;

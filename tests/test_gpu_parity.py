@@ -579,6 +579,16 @@ def test_invalid_options_are_rejected(lib, ctx):
                 with pytest.raises(lib.LsluError) as ei:
                     make(bad)
                 assert ei.value.status == lib.LSLU_EINVAL
+        # malformed CSR structure, each rejected before any entry past nnz
+        # (or past a row's end) is read
+        ix = np.array([0, 1, 2, 3, 4], np.int32)
+        for ip, idx, why in (([0, 100, 5], ix, "exceeds nnz"),
+                             ([0, 2, 1, 5], ix, "decreases"),
+                             ([0, 2, 5], np.array([0, 9, 1, 2, 3], np.int32), "out of range"),
+                             ([0, 2, 5], np.array([1, 0, 1, 2, 3], np.int32), "increasing")):
+            with pytest.raises(lib.LsluError) as ei:
+                lib.lslu_op_csr(ctx, len(ip) - 1, 6, np.array(ip), idx, np.ones(5))
+            assert ei.value.status == lib.LSLU_EINVAL and why in str(ei.value), str(ei.value)
     finally:
         lib.lslu_op_destroy(op)
 
