@@ -374,8 +374,12 @@ def cpu_baseline(prob, cfg, grid, iters, K):
     what = ("the whole solve" if iters >= K else
             f"the first {iters} of {K} iterations (later iterations eliminate more "
             "basis vectors, so this overstates the oracle's rate over the whole solve)")
+    try:
+        host_cores = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        host_cores = os.cpu_count()
     return {"value": round(iters / el, 3), "unit": "iters/s", "cores": 1,
-            "kind": "oracle",
+            "host_cores": host_cores, "kind": "oracle",
             "sample": f"{what} of the same workload, {'median of 3 runs' if runs > 1 else 'one run'} "
                       f"of {el:.2f} s (FP64 NumPy/SciPy, one thread)"}
 
