@@ -308,7 +308,8 @@ def extra_workloads(capi, dev, args):
     """The other measured workloads, as extra keys of the JSON line:
     tomography (128^2, CSR, 100 iterations) in FP32 and FP64, and the dense
     256 x 256 blur (50 iterations, FP64) in microseconds per iteration, for
-    LSLU (lambda = 0) and Hybrid LSLU (weighted GCV)."""
+    LSLU (lambda = 0) and Hybrid LSLU (weighted GCV), beside the launch floor
+    (microseconds per launch of the same solve on a 64 x 64 problem)."""
     import torch
 
     from workloads import CONFIGS, lambda_grid
@@ -346,6 +347,18 @@ def extra_workloads(capi, dev, args):
                               rel_err_min=float(r["errs"].min()))
             capi.lslu_op_destroy(r["op"])
             print(f"[bench] dense256 {reg}: {r['ms'] * 1e3 / K:.2f} us/iter", flush=True)
+        # the launch floor: the same solve on a 64 x 64 dense problem, whose
+        # launches do almost no work
+        from workloads import random_dense
+        tiny = random_dense(64, 64, seed=7, nu=0.01)
+        r = measure(capi, ctx, tiny, dict(cfg, reg="none"), "fp64", K, max(args.steps, 20),
+                    args.warmup, grid, dev)
+        tm = r["timing"]
+        dense["launch_floor_us"] = round(tm["t_recurrence_ms"] * 1e3
+                                         / tm["n_recurrence_launches"], 3)
+        capi.lslu_op_destroy(r["op"])
+        print(f"[bench] launch floor (64 x 64 dense): {dense['launch_floor_us']:.2f} us/launch",
+              flush=True)
         out["dense256"] = dict(iters=K, precision="fp64", **dense)
     finally:
         capi.lslu_destroy(ctx)
