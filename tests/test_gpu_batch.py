@@ -293,3 +293,75 @@ def test_batched_solves_match_oracle(lib, prec):
             lib.lslu_op_destroy(op)
         for c in ctxs:
             lib.lslu_destroy(c)
+
+
+def test_merged_batches_from_several_threads(lib):
+    """Merged batches of size classes from several host threads at once, one
+    more thread capturing and replaying single solves meanwhile (the library
+    call releases the interpreter; no thread's copy may touch the legacy
+    stream while another captures): every result equals the problem's solve
+    alone."""
+    import threading
+
+    import torch
+    probs = sorted(_tomo_set(8, 11), key=lambda p: p.m)
+    solo_probs = _tomo_set(2, 12)
+    grid = lambda_grid()
+    ctxs = [lib.lslu_create(0) for _ in probs]
+    solo_ctx = lib.lslu_create(0)
+    ops, solo_ops = [], []
+    try:
+        for c, prob in zip(ctxs, probs):
+            ops.append(lib.make_operator(c, prob, lib.PRECISIONS["bf16op"]))
+        for prob in solo_probs:
+            solo_ops.append(lib.make_operator(solo_ctx, prob, lib.PRECISIONS["bf16op"]))
+        bs = [torch.tensor(p.b, dtype=torch.float32, device="cuda") for p in probs]
+        sbs = [torch.tensor(p.b, dtype=torch.float32, device="cuda") for p in solo_probs]
+        torch.cuda.synchronize()
+        groups = [list(range(g * 2, g * 2 + 2)) for g in range(4)]  # 4 size classes
+        results, errors = {}, []
+
+        def merged(g):
+            try:
+                for rep in range(2):
+                    st, out = lib.lslu_solve_batch([ctxs[i] for i in g], [ops[i] for i in g],
+                                                   [bs[i] for i in g], K, reg="wgcv", grid=grid,
+                                                   grid_relative=True)
+                    torch.cuda.synchronize()
+                    for i, (x, info) in zip(g, out):
+                        results[(i, rep)] = (x.clone(), info)
+            except Exception as e:  # reported below, in the test's thread
+                errors.append(e)
+
+        def solos():
+            try:
+                for rep in range(3):  # the first call captures, the others replay
+                    for op, b in zip(solo_ops, sbs):
+                        lib.lslu_solve(solo_ctx, op, b, K, reg="wgcv", grid=grid,
+                                       grid_relative=True)
+                torch.cuda.synchronize()
+            except Exception as e:
+                errors.append(e)
+
+        print("[batch] merged size classes from 4 threads, single solves on a fifth",
+              flush=True)
+        ths = [threading.Thread(target=merged, args=(g,)) for g in groups]
+        ths.append(threading.Thread(target=solos))
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        assert not errors, errors
+        for i, (c, op, b) in enumerate(zip(ctxs, ops, bs)):
+            st1, x1, i1 = lib.lslu_solve(c, op, b, K, reg="wgcv", grid=grid, grid_relative=True)
+            torch.cuda.synchronize()
+            for rep in range(2):
+                xb, ib = results[(i, rep)]
+                assert torch.equal(xb, x1), (i, rep)
+                assert np.array_equal(ib["piv_t"], i1["piv_t"])
+                assert np.array_equal(ib["H"], i1["H"]) and np.array_equal(ib["ghat"], i1["ghat"])
+    finally:
+        for op in ops + solo_ops:
+            lib.lslu_op_destroy(op)
+        for c in ctxs + [solo_ctx]:
+            lib.lslu_destroy(c)
