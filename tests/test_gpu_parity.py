@@ -87,15 +87,25 @@ def _compare(lib, ctx, prob, prec, K, kind, relative, lam=0.05, replay=True,
               f"{max(w[1] for w in worst):.3e} max residual gap "
               f"{max(w[2] for w in worst):.3e}")
         # The GPU's own H, W, L, D satisfy the Hessenberg relations to the
-        # rounding of its working precision; in FP64 H and W also match the
-        # oracle's entry by entry.
+        # rounding of its working precision; H and W also match the oracle's
+        # entry by entry (relative to their largest entry), in FP64 over the
+        # whole solve and in FP32 over the steps whose iterates were held to
+        # the stated tolerance above (the kappa cap)
         check_relations(G, op, prec)
         kd = G["k_done"]
-        if prec == "fp64":
+        if prec == "fp32" and kappa_cap is not None:
+            for k in range(1, kd + 1):
+                if G["sigma_max"][k - 1] / G["sigma_min"][k - 1] > kappa_cap:
+                    kd = k - 1
+                    break
+        if prec in ("fp64", "fp32") and kd > 0:
             Hs = np.abs(R.H[:kd + 1, :kd]).max()
             Ws = np.abs(R.W[:kd, :kd]).max()
-            assert np.abs(G["H"][:kd + 1, :kd] - R.H[:kd + 1, :kd]).max() <= tol * 10 * Hs
-            assert np.abs(G["W"][:kd, :kd] - R.W[:kd, :kd]).max() <= tol * 10 * Ws
+            dH = np.abs(G["H"][:kd + 1, :kd] - R.H[:kd + 1, :kd]).max()
+            dW = np.abs(G["W"][:kd, :kd] - R.W[:kd, :kd]).max()
+            print(f"[{prob.name} {prec} {kind}] H, W against the oracle over k <= {kd}: "
+                  f"{dH / Hs:.2e}, {dW / Ws:.2e} of their largest entries")
+            assert dH <= tol * 10 * Hs and dW <= tol * 10 * Ws
         return R, G
     return R, None
 
