@@ -729,43 +729,63 @@ __device__ inline void psf_mfma_stage_b(const uint64_t* __restrict__ mb, uint64_
 // PSF rows (psf_mfma_stage_b).  Every output is summed in the same order
 // (a, then t) whatever RB.  Ends with a barrier (the tile may be restaged
 // next).
-template <int kIn, int PH, int RB, typename CVT>
-__device__ inline void psf_tile_mfma(const float* __restrict__ u, CVT cvt, int rows, int cols,
-                                     int i0, int j0, const uint64_t* __restrict__ bl,
-                                     unsigned char* tile_raw, mfma_f4 (&acc)[RB]) {
-  using M = PsfMfma<kIn>;
-  using E = typename M::E;
-  constexpr int TCM = psf_mfma_cols<kIn>();
-  constexpr int TR = 16 * RB + PH - 1;
-  constexpr int NT = kPsfWaves * kWave;
-  constexpr int Q = kPsfMfmaStaged / 4;  // 16-byte loads per row
-  constexpr int PER = (TR * Q + NT - 1) / NT;
+// The raw (unnormalised) inputs of a thread's share of a matrix-core tile's
+// staged rows: they do not depend on the pivot, so a consumer loads its first
+// tile's before it waits (psf_tile_mfma_load), and converts them once the
+// pivot is known (psf_tile_mfma_from).
+template <int PH, int RB>
+struct MfmaTileIn {
+  static constexpr int kTR = 16 * RB + PH - 1;
+  static constexpr int kQ = kPsfMfmaStaged / 4;  // 16-byte loads per row
+  static constexpr int kPer = (kTR * kQ + kPsfWaves * kWave - 1) / (kPsfWaves * kWave);
+  float4 v[kPer];
+};
+
+// Columns j0 - 16 + 4 g .. + 3 come as one 16-byte load when they are in the
+// image (all or none of them when the row length is a multiple of 4); every
+// load of the share is issued before any value is used.
+template <int PH, int RB>
+__device__ inline void psf_tile_mfma_load(const float* __restrict__ u, int rows, int cols, int i0,
+                                          int j0, MfmaTileIn<PH, RB>& in) {
+  using In = MfmaTileIn<PH, RB>;
+  constexpr int NT = kPsfWaves * kWave, Q = In::kQ, TR = In::kTR;
   const int ch = PH / 2;
-  E* tile = reinterpret_cast<E*>(tile_raw);
   const bool vec = (cols & 3) == 0 && (reinterpret_cast<uintptr_t>(u) & 15) == 0;
-  {
-    // every input of the thread's share is loaded before any is converted;
-    // columns j0 - 16 + 4 g .. + 3 come as one 16-byte load when they are in
-    // the image (all or none of them when the row length is a multiple of 4)
-    float4 v[PER];
 #pragma unroll
-    for (int p = 0; p < PER; ++p) {
-      const int e = threadIdx.x + p * NT;
-      const int tr = e / Q, g = e - tr * Q;
-      const int gi = i0 - ch + tr, gj = j0 - 16 + 4 * g;
-      v[p] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (e < TR * Q && gi >= 0 && gi < rows) {
-        const float* src = u + (int64_t)gi * cols;
-        if (vec) {
-          if (gj >= 0 && gj < cols) v[p] = *reinterpret_cast<const float4*>(src + gj);
-        } else {
-          if (gj >= 0 && gj < cols) v[p].x = src[gj];
-          if (gj + 1 >= 0 && gj + 1 < cols) v[p].y = src[gj + 1];
-          if (gj + 2 >= 0 && gj + 2 < cols) v[p].z = src[gj + 2];
-          if (gj + 3 >= 0 && gj + 3 < cols) v[p].w = src[gj + 3];
-        }
+  for (int p = 0; p < In::kPer; ++p) {
+    const int e = threadIdx.x + p * NT;
+    const int tr = e / Q, g = e - tr * Q;
+    const int gi = i0 - ch + tr, gj = j0 - 16 + 4 * g;
+    in.v[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (e < TR * Q && gi >= 0 && gi < rows) {
+      const float* src = u + (int64_t)gi * cols;
+      if (vec) {
+        if (gj >= 0 && gj < cols) in.v[p] = *reinterpret_cast<const float4*>(src + gj);
+      } else {
+        if (gj >= 0 && gj < cols) in.v[p].x = src[gj];
+        if (gj + 1 >= 0 && gj + 1 < cols) in.v[p].y = src[gj + 1];
+        if (gj + 2 >= 0 && gj + 2 < cols) in.v[p].z = src[gj + 2];
+        if (gj + 3 >= 0 && gj + 3 < cols) in.v[p].w = src[gj + 3];
       }
     }
+  }
+}
+
+template <int kIn, int PH, int RB, typename CVT>
+__device__ inline void psf_tile_mfma_from(const MfmaTileIn<PH, RB>& in, CVT cvt,
+                                          const uint64_t* __restrict__ bl,
+                                          unsigned char* tile_raw, mfma_f4 (&acc)[RB]) {
+  using M = PsfMfma<kIn>;
+  using E = typename M::E;
+  using In = MfmaTileIn<PH, RB>;
+  constexpr int TCM = psf_mfma_cols<kIn>();
+  constexpr int TR = In::kTR;
+  constexpr int NT = kPsfWaves * kWave;
+  constexpr int Q = In::kQ;
+  constexpr int PER = In::kPer;
+  E* tile = reinterpret_cast<E*>(tile_raw);
+  {
+    const float4* v = in.v;
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
       const int e = threadIdx.x + p * NT;
@@ -816,6 +836,15 @@ __device__ inline void psf_tile_mfma(const float* __restrict__ u, CVT cvt, int r
     }
   }
   __syncthreads();
+}
+
+template <int kIn, int PH, int RB, typename CVT>
+__device__ inline void psf_tile_mfma(const float* __restrict__ u, CVT cvt, int rows, int cols,
+                                     int i0, int j0, const uint64_t* __restrict__ bl,
+                                     unsigned char* tile_raw, mfma_f4 (&acc)[RB]) {
+  MfmaTileIn<PH, RB> in;
+  psf_tile_mfma_load<PH, RB>(u, rows, cols, i0, j0, in);
+  psf_tile_mfma_from<kIn, PH, RB>(in, cvt, bl, tile_raw, acc);
 }
 
 // Output rows per lane for a rows x cols image: 8 when that still gives at

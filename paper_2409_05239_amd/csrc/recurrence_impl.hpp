@@ -206,10 +206,14 @@ __device__ __attribute__((always_inline)) inline void trisolve_wave(double* g, i
             const int64_t q = base[s] + i0 + u;
             t[s][u] = tp[q < P ? q : P - 1];
           }
+        // No early exit: a step past the last row (i >= nb) changes no row
+        // (j > i fails for every j < nb), and i - ib stays below 64 (i0 - ib
+        // is a multiple of 8 below ie - ib <= 64), so all 8 steps run
+        // unconditionally and the loads above are issued together instead
+        // of one before each step.
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int i = i0 + u;
-          if (i >= ie) break;
           const double wi = readlane_d(gr[s0], i - ib);
 #pragma unroll
           for (int s = s0; s < S; ++s) {
@@ -451,6 +455,47 @@ __device__ void pivot_entries(const HalfArgs<T>& a, const RowOp& op, DevState* s
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
   const int jr = (bid - 1) * kWaves + w;
   const bool act = jr < a.nb;
+  if constexpr (is_psf_pixels<RowOp>::value) {
+    // A PSF entry has at most 31 x 31 terms, 16 per lane: the weights and the
+    // unnormalised inputs of all of them are loaded before the wait (clamped
+    // in-bounds addresses, terms outside the image or the PSF masked), and
+    // each lane sums its terms t = lane, lane + 64, ... in increasing t, as
+    // the row policy's partial sum does.
+    using Acc = typename RowOp::Acc;
+    constexpr int kTaps = 16;
+    T u[kTaps];
+    Acc wv[kTaps];
+    bool in[kTaps];
+    if (act) {
+      const int64_t pix = a.piv[jr];
+      const int i = static_cast<int>(pix / op.cols);
+      const int j = static_cast<int>(pix - (int64_t)i * op.cols);
+      const int np = op.ph * op.pw, ch = op.ph / 2, cw = op.pw / 2;
+#pragma unroll
+      for (int q = 0; q < kTaps; ++q) {
+        const int t = lane + q * kWave;
+        const int aa = t / op.pw, bb = t - aa * op.pw;
+        const int gi = i + aa - ch, gj = j + bb - cw;
+        in[q] = t < np && gi >= 0 && gi < op.rows && gj >= 0 && gj < op.cols;
+        u[q] = a.up[in[q] ? (int64_t)gi * op.cols + gj : 0];
+        wv[q] = op.wt[t < np ? t : 0];
+      }
+    }
+    int pick;
+    double val;
+    if (!wait_pivot(a, st, pick, val)) return;
+    if (!act) return;
+    const Normaliser<T> nz(static_cast<T>(val));
+    Acc acc = 0;
+#pragma unroll
+    for (int q = 0; q < kTaps; ++q)
+      if (in[q]) acc = fma(wv[q], static_cast<Acc>(in_val<RowOp::kInMode>(nz(u[q]))), acc);
+    acc = group_sum<kWave>(acc);
+    if (lane == 0)
+      store_u64(reinterpret_cast<uint64_t*>(a.entries) + jr,
+                dbits(static_cast<double>(static_cast<T>(acc))));
+    return;
+  }
   RowStage<typename RowOp::Val, T, kEntryStage> sg;
   if (act) op.template stage<kWave, kEntryStage>(a.piv[jr], lane, a.up, sg);
   int pick;
@@ -781,8 +826,15 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
   const int tiles_x = (cols + kPsfTW - 1) / kPsfTW;
   const int ntiles = a.rows > 0 ? tiles_x * ((rows + TH - 1) / TH) : 0;
   const int nb = a.nb;
-  if constexpr (kMfma) {  // the operand blocks do not depend on the pivot
+  constexpr int kRB = kMfma ? TH / 16 : 1;
+  MfmaTileIn<PH, kRB> first_in;  // the first tile's raw inputs (matrix-core modes)
+  if constexpr (kMfma) {
+    // the operand blocks and the first tile's unnormalised inputs do not
+    // depend on the pivot
     if (ntiles > 0) psf_mfma_stage_b<kIn, PH>(mb, reinterpret_cast<uint64_t*>(lds));
+    if (cb < ntiles)
+      psf_tile_mfma_load<PH, kRB>(a.up, rows, cols, (cb / tiles_x) * TH, (cb % tiles_x) * kPsfTW,
+                                  first_in);
   }
   NormStage<T> ns;
   normalise_stage(a, cb, ncons, ns);
@@ -797,10 +849,13 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
       static_assert(TH % 16 == 0, "matrix-core tiles are 16-row blocks");
       constexpr int RB = TH / 16;
       mfma_f4 acc[RB];
-      psf_tile_mfma<kIn, PH, RB>(
-          a.up, [nz](float v) { return static_cast<float>(in_val<kIn>(nz(v))); }, rows, cols, i0,
-          j0, reinterpret_cast<const uint64_t*>(lds),
-          lds + sizeof(uint64_t) * psf_mfma_b_words<kIn, PH>(), acc);
+      const auto cvt = [nz](float v) { return static_cast<float>(in_val<kIn>(nz(v))); };
+      const uint64_t* bl = reinterpret_cast<const uint64_t*>(lds);
+      unsigned char* tl = lds + sizeof(uint64_t) * psf_mfma_b_words<kIn, PH>();
+      if (t == cb)  // block-uniform
+        psf_tile_mfma_from<kIn, PH, RB>(first_in, cvt, bl, tl, acc);
+      else
+        psf_tile_mfma<kIn, PH, RB>(a.up, cvt, rows, cols, i0, j0, bl, tl, acc);
       const int w = threadIdx.x / kWave;
       const int gj = j0 + 16 * w + (lane & 15);
 #pragma unroll
