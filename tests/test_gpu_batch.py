@@ -365,3 +365,60 @@ def test_merged_batches_from_several_threads(lib):
             lib.lslu_op_destroy(op)
         for c in ctxs + [solo_ctx]:
             lib.lslu_destroy(c)
+
+
+@pytest.mark.skip(reason="the graph-captured batch (one HIP graph over lane streams with every "
+                         "problem's solve and its result copy) was taken out of the library: "
+                         "its first capture ended the process with a host segmentation fault "
+                         "whose cause was not found; kept as the record of the case")
+def test_graph_batch_matches_single_solves(lib):
+    """LSLU_FLAG_BATCH_GRAPH: every problem's solve captured into one graph
+    over lane streams and replayed; tomography (CSR) and deblurring (PSF)
+    problems in two precisions mixed in one batch, more problems than lanes.
+    The replays reuse the cached graph; every result equals the problem's
+    solve alone, bit for bit."""
+    import torch
+    probs = batch_problems(12, seed=21)
+    precs = ["bf16op" if i % 3 else "fp32" for i in range(len(probs))]
+    grid = lambda_grid()
+    ctxs = [lib.lslu_create(0) for _ in probs]
+    ops = []
+    try:
+        for c, prob, pr in zip(ctxs, probs, precs):
+            ops.append(lib.make_operator(c, prob, lib.PRECISIONS[pr]))
+        bs = [torch.tensor(p.b, dtype=torch.float32, device="cuda") for p in probs]
+        xo = [torch.zeros(p.n, dtype=torch.float32, device="cuda") for p in probs]
+        torch.cuda.synchronize()
+        print("[batch] graph: " + ", ".join(f"{p.name}/{pr}" for p, pr in zip(probs, precs)),
+              flush=True)
+        outs = []
+        for rep in range(3):  # the first call captures, the others replay
+            xo_rep = [x.zero_() for x in xo]
+            st, out = lib.lslu_solve_batch(ctxs, ops, bs, K, reg="wgcv", grid=grid,
+                                           grid_relative=True, graph=True, x_outs=xo_rep)
+            torch.cuda.synchronize()
+            outs.append([(x.clone(), info) for x, info in out])
+        for i, (c, op, b) in enumerate(zip(ctxs, ops, bs)):
+            st1, x1, i1 = lib.lslu_solve(c, op, b, K, reg="wgcv", grid=grid, grid_relative=True)
+            torch.cuda.synchronize()
+            for rep in range(3):
+                xb, ib = outs[rep][i]
+                assert ib["k_done"] == i1["k_done"], (i, rep)
+                assert np.array_equal(ib["piv_t"], i1["piv_t"])
+                assert np.array_equal(ib["piv_g"], i1["piv_g"])
+                assert np.array_equal(ib["H"], i1["H"]) and np.array_equal(ib["ghat"], i1["ghat"])
+                assert torch.equal(xb, x1), (i, rep)
+        # a single solve refuses the batch-only flag
+        with pytest.raises(lib.LsluError) as ei:
+            o = lib.lslu_opts()
+            o.maxiter = K
+            o.flags = lib.LSLU_FLAG_BATCH_GRAPH
+            x = torch.zeros(probs[0].n, dtype=torch.float32, device="cuda")
+            lib._check(ctxs[0], lib.lib.lslu_solve(ctxs[0], ops[0], lib._dptr(bs[0]), None,
+                                                   o, lib._dptr(x), None))
+        assert ei.value.status == lib.LSLU_EINVAL
+    finally:
+        for op in ops:
+            lib.lslu_op_destroy(op)
+        for c in ctxs:
+            lib.lslu_destroy(c)
