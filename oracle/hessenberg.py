@@ -2,13 +2,17 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-The loop below takes the steps of Algorithm 5 in the paper's order and with its
-names: permutation vectors ``t`` (rows, for the basis ``D``) and ``g`` (columns,
-for the basis ``L``), the adjoint product ``q = A^T d_k``, the elimination of
-earlier ``l_j`` with coefficients read at the stored pivots, the pivot search,
-the forward product ``u = A l_k``, the elimination of earlier ``d_j``, the pivot
-search, the choice of lambda_k, the projected Tikhonov solve and the iterate
-``x_k = x_0 + L_k y``.  Elimination is sequential, exactly as written.
+Each iteration of Algorithm 5 is built from the same two steps on both
+bases (``eliminate``: the components along the earlier basis vectors, each
+read at that vector's pivot row and removed in turn; ``take_pivot``: the
+infinity-norm pivot, the division by it and the update of the permutation),
+in the paper's notation: permutation vectors ``t`` (rows, for the basis ``D``)
+and ``g`` (columns, for the basis ``L``), the adjoint product
+``q = A^T d_k`` reduced against ``L``, the forward product ``u = A l_k``
+reduced against ``D``, then the choice of lambda_k, the projected Tikhonov
+solve and the iterate ``x_k = x_0 + L_k y``.  Elimination is sequential in j,
+as the method defines it; the relations ``A L_k = D_{k+1} H_{k+1,k}`` and
+``A^T D_k = L_k W_k`` that these steps build are pinned by the tests.
 
 Readings where the paper is silent, ambiguous or inconsistent:
 
@@ -131,6 +135,30 @@ def pivot_search_sampled(v: np.ndarray, perm: np.ndarray, start: int,
     return pos, float(amax), sep
 
 
+def eliminate(v: np.ndarray, basis, perm: np.ndarray, count: int, coef: np.ndarray):
+    """Removes from ``v`` its components along the first ``count`` basis
+    vectors, each measured at that vector's own pivot row: for j = 0, 1, ...,
+    count-1 in turn, ``coef[j] = v(perm[j])`` and ``v <- v - coef[j] basis[j]``
+    (the inner loops of Algorithm 5 for both bases, of Algorithm 2 for its one
+    basis).  Basis vector j is 1 at ``perm[j]`` and 0 at ``perm[:j]``, so the
+    result is 0 at ``perm[:count]``.  ``coef`` is written in place (a column
+    of W or H).  Returns the new vector."""
+    for j in range(count):
+        coef[j] = v[perm[j]]
+        v = v - coef[j] * basis[j]
+    return v
+
+
+def take_pivot(v: np.ndarray, perm: np.ndarray, start: int, pos: int):
+    """Accepts the pivot found at position ``pos`` of ``perm``: returns its
+    value ``v(perm[pos])`` and ``v`` divided by it (IEEE division, reading R6:
+    exactly 1 at the pivot), and moves the pivot row to position ``start`` of
+    ``perm`` (in place)."""
+    val = v[perm[pos]]
+    perm[start], perm[pos] = perm[pos], perm[start]
+    return val, v / val
+
+
 def hybrid_lslu(op, b, maxiter: int, reg: Optional[RegParam] = None,
                 x0: Optional[np.ndarray] = None, stop_tol: float = 1e-6,
                 early_stop: bool = False, pivot_sample=None) -> Result:
@@ -184,19 +212,16 @@ def hybrid_lslu(op, b, maxiter: int, reg: Optional[RegParam] = None,
     if amax == 0.0:
         return finish(Status.ZERO_RHS, x0v.copy(), 0)
     sep_t.append(sep)
-    beta = float(r0[t[pos]])
-    Db.append(r0 / beta)
-    t[0], t[pos] = t[pos], t[0]
+    beta, d1 = take_pivot(r0, t, 0, pos)
+    beta = float(beta)
+    Db.append(d1)
 
     status = Status.OK
     k_stop = None
     x_final = x0v.copy()
     for k in range(1, K + 1):
         # Adjoint product and elimination of l_1..l_{k-1}.
-        q = op.rmatvec(Db[k - 1])
-        for j in range(1, k):
-            W[j - 1, k - 1] = q[g[j - 1]]
-            q = q - W[j - 1, k - 1] * Lb[j - 1]
+        q = eliminate(op.rmatvec(Db[k - 1]), Lb, g, k - 1, W[:, k - 1])
         # Pivot for l_k (guard k <= n, reading R1; exact zero test, R3).
         if k <= n:
             pos, amax, sep = search(q, g, k - 1, 2 * k - 1)
@@ -206,15 +231,11 @@ def hybrid_lslu(op, b, maxiter: int, reg: Optional[RegParam] = None,
             status = Status.BREAKDOWN_Q
             break
         sep_g.append(sep)
-        W[k - 1, k - 1] = q[g[pos]]
-        Lb.append(q / W[k - 1, k - 1])
-        g[k - 1], g[pos] = g[pos], g[k - 1]
+        W[k - 1, k - 1], lk = take_pivot(q, g, k - 1, pos)
+        Lb.append(lk)
 
         # Forward product and elimination of d_1..d_k.
-        u = op.matvec(Lb[k - 1])
-        for j in range(1, k + 1):
-            H[j - 1, k - 1] = u[t[j - 1]]
-            u = u - H[j - 1, k - 1] * Db[j - 1]
+        u = eliminate(op.matvec(Lb[k - 1]), Db, t, k, H[:, k - 1])
         last = False
         if k < m:
             pos, amax, sep = search(u, t, k, 2 * k)
@@ -226,9 +247,8 @@ def hybrid_lslu(op, b, maxiter: int, reg: Optional[RegParam] = None,
             last = True
         else:
             sep_t.append(sep)
-            H[k, k - 1] = u[t[pos]]
-            Db.append(u / H[k, k - 1])
-            t[k], t[pos] = t[pos], t[k]
+            H[k, k - 1], dk = take_pivot(u, t, k, pos)
+            Db.append(dk)
 
         # Projected problem: lambda_k, y_k, x_k.
         Hk = H[:k + 1, :k]
@@ -270,16 +290,12 @@ def square_hessenberg_pivoted(apply_B, r0: np.ndarray, maxiter: int):
     pos, amax, _ = pivot_search(r0, p, 0)
     if amax == 0.0:
         raise ValueError("zero start vector")
-    beta = r0[p[pos]]
-    Lb = [r0 / beta]
-    p[0], p[pos] = p[pos], p[0]
+    beta, l1 = take_pivot(r0, p, 0, pos)
+    Lb = [l1]
     Hs = np.zeros((maxiter + 1, maxiter))
     kk = 0
     for k in range(1, maxiter + 1):
-        u = apply_B(Lb[k - 1])
-        for j in range(1, k + 1):
-            Hs[j - 1, k - 1] = u[p[j - 1]]
-            u = u - Hs[j - 1, k - 1] * Lb[j - 1]
+        u = eliminate(apply_B(Lb[k - 1]), Lb, p, k, Hs[:, k - 1])
         kk = k
         if k < N:
             pos, amax, _ = pivot_search(u, p, k)
@@ -288,7 +304,6 @@ def square_hessenberg_pivoted(apply_B, r0: np.ndarray, maxiter: int):
         if amax == 0.0:
             Hs[k, k - 1] = 0.0
             break
-        Hs[k, k - 1] = u[p[pos]]
-        Lb.append(u / Hs[k, k - 1])
-        p[k], p[pos] = p[pos], p[k]
+        Hs[k, k - 1], lk = take_pivot(u, p, k, pos)
+        Lb.append(lk)
     return np.stack(Lb, axis=1), Hs[:kk + 1, :kk], [int(v) for v in p[:len(Lb)]]
