@@ -20,8 +20,10 @@ The JSON line also carries the roofline of the dominant kernel -- the
 half-iteration kernel of the recurrence (one launch per half-iteration), timed
 by the library with HIP events on the stream it launches on -- per mode, the
 FP64 CPU oracle timed on a bounded sample of the same workload, and as extra
-keys the 128x128 tomography workload (CSR, FP32 and FP64, 100 iterations) and
-the dense 256x256 blur (FP64, 50 iterations, microseconds per iteration).
+keys the 128x128 tomography workload (CSR, FP32 and FP64, 100 iterations),
+the dense 256x256 blur (FP64, 50 iterations, microseconds per iteration) and
+what plain streaming reaches on the same device (a device copy and the
+library's matrix-vector product at the shape of the basis).
 """
 
 from __future__ import annotations
@@ -362,7 +364,42 @@ def extra_workloads(capi, dev, args):
         out["dense256"] = dict(iters=K, precision="fp64", **dense)
     finally:
         capi.lslu_destroy(ctx)
+    out["stream_reference"] = stream_reference(dev)
     return out
+
+
+def stream_reference(dev, n=1 << 20, k=150, reps=20):
+    """What plain streaming reaches on this device, beside the roofline's
+    published peak: a 1 GiB device copy (bytes read + written) and the
+    library's matrix-vector product over an n x k column-major FP32 matrix,
+    the shape of the basis the elimination reads at 1024^2 and 150
+    iterations (bytes of the matrix)."""
+    import torch
+
+    def timed(f):
+        f()
+        torch.cuda.synchronize(dev)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(reps):
+            f()
+        t1.record()
+        torch.cuda.synchronize(dev)
+        return t0.elapsed_time(t1) * 1e-3 / reps
+
+    src = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    copy = 2 * src.numel() * 4 / timed(lambda: dst.copy_(src)) / 1e9
+    del src, dst
+    basis = torch.ones(k, n, dtype=torch.float32, device=dev)  # column j contiguous
+    coef = torch.ones(k, dtype=torch.float32, device=dev)
+    gemv = basis.numel() * 4 / timed(lambda: torch.mv(basis.t(), coef)) / 1e9
+    del basis, coef
+    ref = dict(copy_GBps=round(copy, 1), gemv_GBps=round(gemv, 1),
+               gemv_shape=f"{n} x {k} fp32 column-major", peak_GBps=HBM_PEAK_GBS)
+    print(f"[bench] stream reference: copy {copy:.0f} GB/s, gemv {gemv:.0f} GB/s", flush=True)
+    return ref
 
 
 def cpu_baseline(prob, cfg, grid, iters, K):
