@@ -179,9 +179,13 @@ __device__ __attribute__((always_inline)) inline void trisolve_inplace(
 // subtracts T(j,i) w_i, so each row sees the sequential order.  The entries
 // of the next 8 steps are loaded ahead (indices clamped into the triangle;
 // rows not updated by a step keep their value), so no step waits on LDS.
+// Rows of slot s are final once steps 0 .. 64 (s + 1) - 1 have run; each
+// slot's values are then stored to pub (the coefficient slots), so
+// consumers can start on the first coefficients while later ones are solved.
 template <typename T, int S>
 __device__ __attribute__((always_inline)) inline void trisolve_wave(double* g, int nb,
-                                                                    const T* __restrict__ tp) {
+                                                                    const T* __restrict__ tp,
+                                                                    uint64_t* pub) {
 #pragma clang fp contract(off)
   const int lane = threadIdx.x & (kWave - 1);
   if (threadIdx.x < kWave) {
@@ -223,6 +227,8 @@ __device__ __attribute__((always_inline)) inline void trisolve_wave(double* g, i
           }
         }
       }
+      const int j = lane + kWave * s0;
+      if (j < nb) store_u64(pub + j, dbits(gr[s0]));
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -427,23 +433,26 @@ __device__ void lead(const HalfArgs<T>& a, DevState* st, unsigned char* lds) {
     }
     return;
   }
+  uint64_t* cs = reinterpret_cast<uint64_t*>(a.cslot);
+  bool published = false;  // the solve stored the slots itself
   if constexpr (kTriLds) {
     const T* lt = reinterpret_cast<const T*>(lds);
+    published = nb >= 2 && nb <= 4 * kWave;
     if (nb >= 2 && nb <= kWave)
-      trisolve_wave<T, 1>(g, nb, lt);
+      trisolve_wave<T, 1>(g, nb, lt, cs);
     else if (nb > kWave && nb <= 2 * kWave)
-      trisolve_wave<T, 2>(g, nb, lt);
+      trisolve_wave<T, 2>(g, nb, lt, cs);
     else if (nb > 2 * kWave && nb <= 3 * kWave)
-      trisolve_wave<T, 3>(g, nb, lt);
+      trisolve_wave<T, 3>(g, nb, lt, cs);
     else if (nb > 3 * kWave && nb <= 4 * kWave)
-      trisolve_wave<T, 4>(g, nb, lt);
+      trisolve_wave<T, 4>(g, nb, lt, cs);
     else
       trisolve_inplace<T>(g, nb, lt);
   } else {
     trisolve_inplace<T>(g, nb, a.Tp);
   }
   for (int j = tid; j < nb; j += kThreads) {
-    store_u64(reinterpret_cast<uint64_t*>(a.cslot) + j, dbits(g[j]));
+    if (!published) store_u64(cs + j, dbits(g[j]));
     a.coef[j] = g[j];
   }
 }
@@ -606,6 +615,62 @@ __device__ inline bool fetch_coef(const HalfArgs<T>& a, DevState* st, double* cf
   }
   __syncthreads();
   return ok_s != 0;
+}
+
+// Waits until coefficients 0 .. need - 1 are published and stages every
+// coefficient of the published prefix in LDS (wavefront 0 polls); avail
+// (block-uniform) becomes the prefix length, at least need.  Called again
+// with a larger need when the elimination reaches past avail.  False when
+// the launch is to end, as fetch_coef.
+template <typename T>
+__device__ inline bool fetch_coef_prefix(const HalfArgs<T>& a, DevState* st, double* cf,
+                                         int need, int& avail) {
+  __shared__ int ok_s, avail_s;
+  const int nb = a.nb;
+  if (threadIdx.x < kWave) {
+    constexpr int kPer = kMaxIter / kWave;
+    const int lane = threadIdx.x;
+    const uint64_t* cs = reinterpret_cast<const uint64_t*>(a.cslot);
+    uint64_t bits[kPer];
+    bool ok = false, failed = false;
+    int have = avail;
+    for (int it = 0; it < kSpinLimit; ++it) {
+      // the published prefix: the first slot still empty, or nb
+      int first = nb;
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int j = lane + u * kWave;
+        bits[u] = (j >= have && j < nb) ? load_u64(cs + j) : 0;
+        const uint64_t empty = __ballot(j >= have && j < nb && bits[u] == kSentinel);
+        if (empty != 0 && first == nb) first = u * kWave + __builtin_ctzll(empty);
+      }
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int j = lane + u * kWave;
+        if (j >= have && j < first) cf[j] = __builtin_bit_cast(double, bits[u]);
+      }
+      have = first;
+      if (have >= need) {
+        ok = true;
+        break;
+      }
+      if (load_i(a.fail) != 0) {
+        failed = true;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (lane == 0) {
+      ok_s = ok ? 1 : 0;
+      avail_s = have;
+      if (!ok && !failed) atomicAdd(&st->spin_timeouts, 1);
+    }
+  }
+  __syncthreads();
+  avail = avail_s;
+  const bool ok = ok_s != 0;
+  __syncthreads();  // avail_s and ok_s are rewritten by the next call
+  return ok;
 }
 
 // --------------------------------------------------- row consumer blocks --
@@ -877,7 +942,11 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
     }
   }
   if (a.rows == 0) return;
-  if (!fetch_coef(a, st, cf)) return;
+  // The coefficients arrive in 64-slot chunks (the lead publishes each as
+  // its triangular solve finishes it): the first tile's elimination starts
+  // on the first chunk and waits for a later one only where it reaches it.
+  int avail = 0;
+  if (nb > 0 && !fetch_coef_prefix(a, st, cf, min(nb, kWave), avail)) return;
   double best = 0.0;
   int bidx = INT_MAX;
   {
@@ -913,26 +982,33 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
         // loads in flight per lane to keep HBM busy); each pixel still sums
         // the vectors in increasing j
         constexpr int U = sizeof(T) == 4 ? 4 : 2;
+        // Columns in chunks of 64 (ce: the chunk's end), each waited for
+        // only if not yet staged; U divides 64, so j reaches every chunk end
+        // but the last.
         int j = 0;
-        for (; j + U <= nb; j += U) {
-          T2 bq[U][RP];
+        for (int ce = min(nb, kWave);; ce = min(nb, ce + kWave)) {
+          if (ce > avail && !fetch_coef_prefix(a, st, cf, ce, avail)) return;
+          for (; j + U <= ce; j += U) {
+            T2 bq[U][RP];
 #pragma unroll
-          for (int uu = 0; uu < U; ++uu) {
-            const T* c0 = a.basis + (int64_t)(j + uu) * a.cs;
+            for (int uu = 0; uu < U; ++uu) {
+              const T* c0 = a.basis + (int64_t)(j + uu) * a.cs;
 #pragma unroll
-            for (int p = 0; p < RP; ++p) bq[uu][p] = *reinterpret_cast<const T2*>(c0 + pix[p]);
-          }
+              for (int p = 0; p < RP; ++p) bq[uu][p] = *reinterpret_cast<const T2*>(c0 + pix[p]);
+            }
 #pragma unroll
-          for (int uu = 0; uu < U; ++uu) {
-            const double w = cf[j + uu];
+            for (int uu = 0; uu < U; ++uu) {
+              const double w = cf[j + uu];
 #pragma unroll
-            for (int p = 0; p < RP; ++p) {
-              e0[p] = fma(w, static_cast<double>(bq[uu][p].x), e0[p]);
-              e1[p] = fma(w, static_cast<double>(bq[uu][p].y), e1[p]);
+              for (int p = 0; p < RP; ++p) {
+                e0[p] = fma(w, static_cast<double>(bq[uu][p].x), e0[p]);
+                e1[p] = fma(w, static_cast<double>(bq[uu][p].y), e1[p]);
+              }
             }
           }
+          if (ce == nb) break;
         }
-        for (; j < nb; ++j) {
+        for (; j < nb; ++j) {  // the last chunk's remainder, already staged
           const T* c0 = a.basis + (int64_t)j * a.cs;
           T2 bq[RP];
 #pragma unroll
@@ -985,23 +1061,27 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
 #pragma unroll
     for (int p = 0; p < R; ++p) e[p] = 0.0;
     int j = 0;
-    for (; j + 2 <= nb; j += 2) {
-      const T* c0 = a.basis + (int64_t)j * a.cs;
-      const T* c1 = c0 + a.cs;
-      T b0[R], b1[R];
+    for (int ce = min(nb, kWave);; ce = min(nb, ce + kWave)) {  // as above
+      if (ce > avail && !fetch_coef_prefix(a, st, cf, ce, avail)) return;
+      for (; j + 2 <= ce; j += 2) {
+        const T* c0 = a.basis + (int64_t)j * a.cs;
+        const T* c1 = c0 + a.cs;
+        T b0[R], b1[R];
 #pragma unroll
-      for (int p = 0; p < R; ++p) {
-        b0[p] = c0[pix[p]];
-        b1[p] = c1[pix[p]];
-      }
-      const double w0 = cf[j], w1 = cf[j + 1];
+        for (int p = 0; p < R; ++p) {
+          b0[p] = c0[pix[p]];
+          b1[p] = c1[pix[p]];
+        }
+        const double w0 = cf[j], w1 = cf[j + 1];
 #pragma unroll
-      for (int p = 0; p < R; ++p) {
-        e[p] = fma(w0, static_cast<double>(b0[p]), e[p]);
-        e[p] = fma(w1, static_cast<double>(b1[p]), e[p]);
+        for (int p = 0; p < R; ++p) {
+          e[p] = fma(w0, static_cast<double>(b0[p]), e[p]);
+          e[p] = fma(w1, static_cast<double>(b1[p]), e[p]);
+        }
       }
+      if (ce == nb) break;
     }
-    if (j < nb) {
+    if (j < nb) {  // the last chunk's remainder, already staged
       const T* c0 = a.basis + (int64_t)j * a.cs;
       const double w0 = cf[j];
 #pragma unroll

@@ -732,3 +732,49 @@ def test_projected_problems_up_to_k200(lib, ctx, reg):
     # kappa(H) u for lambda = 0, less with damping
     assert worst_y <= 1e-13 * max(kap, 1.0) and worst_y <= 1e-6
     assert worst_g <= 1e-8
+
+
+# ------------------------------------- coefficients published in chunks
+
+@pytest.mark.parametrize("cols", [46, 45])
+def test_psf_coefficient_chunks(lib, ctx, cols):
+    """140 iterations, so a launch eliminates up to 140 earlier basis
+    vectors: the lead publishes their coefficients in three 64-slot chunks
+    as its triangular solve finishes each, and a PSF consumer's elimination
+    waits chunk by chunk.  Even width (pixel pairs per lane) and odd width
+    (one pixel per lane): FP64 free (every pivot) and replayed and FP32
+    replayed against the oracle (x_k, H, W at every k); BF16-op (matrix-core
+    products) through the Hessenberg relations of its own bases (eq. nhr,
+    eq. nhr2), to the rounding of its bfloat16 products, which a coefficient
+    staged late or from the wrong slot would break by far."""
+    from oracle.operators import PsfOp
+    prob = psf_deblur(36, 2, 1.0, 0.01, seed=21, cols=cols)
+    K = 140
+    for prec in ("fp64", "fp32"):
+        # every pivot search is well separated here, so the free run is held
+        # to the oracle's pivots at every k
+        R, G = _compare(lib, ctx, prob, prec, K, "wgcv", True, check_free=(prec == "fp64"))
+        assert G["k_done"] == K
+    G = gpu_solve(lib, ctx, prob, "bf16op", K, "wgcv", grid=lambda_grid(), grid_relative=True)
+    check_basis_invariants(G, prob.m, prob.n)
+    op = make_operator(prob)
+    aop = PsfOp(np.abs(prob.psf), prob.image_shape)
+    k = min(G["n_l"], G["n_d"] - 1)
+    assert k >= 129
+    L, D = G["L"][:, :k], G["D"][:, :k + 1]
+    H, W = G["H"][:k + 1, :k], G["W"][:k, :k]
+    ub, uf = 2.0 ** -8, 2.0 ** -24
+    worst = 0.0
+    for j in range(k):
+        # column j of A L_k = D_{k+1} H and of A^T D_k = L_k W: the product
+        # rounds operator and input to bfloat16 (2 ub |A||x|), the sums and
+        # stored vectors are float
+        r1 = np.linalg.norm(op.matvec(L[:, j]) - D @ H[:, j])
+        b1 = 2.5 * ub * np.linalg.norm(aop.matvec(np.abs(L[:, j]))) \
+            + 10 * k * uf * np.linalg.norm(np.abs(D) @ np.abs(H[:, j]))
+        r2 = np.linalg.norm(op.rmatvec(D[:, j]) - L @ W[:, j])
+        b2 = 2.5 * ub * np.linalg.norm(aop.rmatvec(np.abs(D[:, j]))) \
+            + 10 * k * uf * np.linalg.norm(np.abs(L) @ np.abs(W[:, j]))
+        assert r1 <= b1 and r2 <= b2, (j, r1 / b1, r2 / b2)
+        worst = max(worst, r1 / b1, r2 / b2)
+    print(f"[chunks {prob.name}] bf16op relations at most {worst:.2f} of their rounding bound")
