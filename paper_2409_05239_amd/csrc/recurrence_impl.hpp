@@ -1104,8 +1104,10 @@ __device__ void consume_tiles(const HalfArgs<T>& a, const Acc* __restrict__ Wt,
   if (threadIdx.x == 0) write_part(a.parts_out, cb, best, bidx);
 }
 
+// Occupancy floor: 3 wavefronts per SIMD, so the 512 tiles of a 1024 x 1024
+// image fit beside the leading blocks and each consumer takes one tile.
 template <typename T, typename Acc, int PH, int kIn, bool kTriLds, int R>
-__global__ __launch_bounds__(kThreads) void k_half_psf(
+__global__ __launch_bounds__(kThreads, 3) void k_half_psf(
     HalfArgs<T> a, PsfPixels<Acc, kIn> op, const Acc* __restrict__ Wt) {
   extern __shared__ unsigned char lds[];
   DevState* st = a.job.st;
